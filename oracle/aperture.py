@@ -1,0 +1,103 @@
+"""Aperture selection by exhaustive enumeration, in float64.  Test infrastructure only.
+
+Sec. 2.1 and Sec. 2.2.2: from the beamlet prices, pick at an unoccupied
+control point the deliverable aperture with the best price.  Without the
+interdigitation constraint the MLC leaf rows are independent, so the best
+aperture is the best opening per row; the aperture price is the sum over rows
+and the chosen control point is the best over the unoccupied ones.
+
+Sign: the paper maximises the price pi = D^T(-grad F) (Eqs. 3-4).  Here the
+input is p = D^T grad F = -pi, so the best opening MINIMISES the sum of p.
+
+Readings where the paper is silent:
+* an opening of leaf row r is a half-open beamlet interval [L, R),
+  0 <= L <= R <= n_cols; the closed row is the empty interval, written (0, 0),
+  with sum 0;
+* ties: smallest sum, then shortest interval, then leftmost L; between
+  control points: smallest price, then lowest index;
+* an occupied control point gets L = R = 0 and price +inf;
+* there is no improving aperture (the column generation stops) when the best
+  price is >= 0; the selected index is then -1.
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+
+def all_intervals(n):
+    """Every opening of an n-beamlet row: the empty one first, then all [L, R)."""
+    out = [(0, 0)]
+    out += [(L, R) for L in range(n) for R in range(L + 1, n + 1)]
+    return out
+
+
+def best_intervals(rows):
+    """Best opening of each row of prices.  rows: [m, n].  Returns (L, R, sum)."""
+    rows = np.asarray(rows, np.float64)
+    m, n = rows.shape
+    ivs = all_intervals(n)
+    Ls = np.array([a for a, _ in ivs])
+    Rs = np.array([b for _, b in ivs])
+    cs = np.concatenate([np.zeros((m, 1)), np.cumsum(rows, axis=1)], axis=1)
+    sums = cs[:, Rs] - cs[:, Ls]                         # [m, n_int]
+    sums[:, 0] = 0.0                                     # the closed row
+    length = Rs - Ls
+    # lexicographic (sum, length, L): smallest wins
+    best = np.empty(m, np.int64)
+    for i in range(m):
+        order = np.lexsort((Ls, length, sums[i]))
+        best[i] = order[0]
+    return Ls[best].astype(np.int32), Rs[best].astype(np.int32), sums[np.arange(m), best]
+
+
+def select(p, n_cp, n_rows, n_cols, occupied):
+    """Aperture selection over all unoccupied control points.
+
+    p: [n_cp*n_rows*n_cols] beamlet prices (j = (k*n_rows + r)*n_cols + c).
+    Returns dict(L, R [n_cp, n_rows] int32, cp_price [n_cp] float64, best int,
+    best_price float)."""
+    P = np.asarray(p, np.float64).reshape(n_cp * n_rows, n_cols)
+    L, R, S = best_intervals(P)
+    L = L.reshape(n_cp, n_rows)
+    R = R.reshape(n_cp, n_rows)
+    cp_price = S.reshape(n_cp, n_rows).sum(axis=1)
+    occ = np.asarray(occupied, bool)
+    L[occ] = 0
+    R[occ] = 0
+    cp_price[occ] = np.inf
+    best = -1
+    best_price = np.inf
+    for k in range(n_cp):
+        if not occ[k] and cp_price[k] < best_price:
+            best, best_price = k, cp_price[k]
+    if best >= 0 and not best_price < 0.0:
+        best = -1
+    return dict(L=L, R=R, cp_price=cp_price, best=best, best_price=best_price)
+
+
+def best_aperture_bruteforce(p_cp):
+    """Best whole aperture of one control point by enumerating the Cartesian
+    product of every row's openings (tiny grids only).  p_cp: [n_rows, n_cols].
+
+    Returns (price, openings tuple).  Independent of the row decomposition,
+    so it checks that decomposition."""
+    p_cp = np.asarray(p_cp, np.float64)
+    n_rows, n_cols = p_cp.shape
+    ivs = all_intervals(n_cols)
+    row_sums = [[p_cp[r, a:b].sum() if b > a else 0.0 for (a, b) in ivs] for r in range(n_rows)]
+    best, arg = np.inf, None
+    for combo in itertools.product(range(len(ivs)), repeat=n_rows):
+        s = sum(row_sums[r][combo[r]] for r in range(n_rows))
+        if s < best:
+            best, arg = s, tuple(ivs[c] for c in combo)
+    return best, arg
+
+
+def aperture_members(cp, L, R, n_cp, n_rows, n_cols):
+    """bool[n_bl] membership of the aperture with openings [L_r, R_r) at control point cp."""
+    m = np.zeros((n_cp, n_rows, n_cols), bool)
+    for r in range(n_rows):
+        m[cp, r, int(L[r]):int(R[r])] = True
+    return m.ravel()

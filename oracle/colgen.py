@@ -1,0 +1,56 @@
+"""The column-generation loop of Sec. 2.1, in float64.  Test infrastructure only.
+
+Start from z = 0 and no apertures.  Each iteration solves the pricing problem
+(beamlet prices, Eq. 3, then the best aperture at an unoccupied control
+point) and, if that aperture can still lower F, adds it and re-solves the
+master problem (Eq. 6) for the fluence rates of all chosen apertures.
+
+Readings where the paper is silent: a new aperture starts at its lower bound
+and the other rates keep their values (warm start); the loop stops when the
+best aperture price is >= 0, when every control point is occupied, or after
+max_cg iterations; the prices used by the next pricing step are those at the
+master problem's final iterate.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import aperture as ap
+from . import bb
+from . import objective as obj
+from . import products
+
+
+def run(row, col, val, n_vox, n_cp, n_rows, n_cols, sid, table, max_cg,
+        params=bb.BBParams(), lo=0.0, hi=np.inf, form="D"):
+    """Returns dict(apertures=[(cp, L, R)], y, z, F, log=[per-iteration dicts])."""
+    n_bl = n_cp * n_rows * n_cols
+    apset = bb.ApertureSet(n_cp, n_rows, n_cols)
+    occupied = np.zeros(n_cp, bool)
+    y = np.zeros(0)
+    z = np.zeros(n_vox)
+    p = products.price(row, col, val, obj.gradient(z, sid, table), n_bl)
+    log = []
+    DA_cols = []
+    for it in range(max_cg):
+        sel = ap.select(p, n_cp, n_rows, n_cols, occupied)
+        if sel["best"] < 0:
+            break
+        k = sel["best"]
+        occupied[k] = True
+        apset.add(k, sel["L"][k], sel["R"][k])
+        y = np.append(y, lo)
+        if form == "DA":
+            member = apset.owner == apset.m - 1
+            DA_cols.append(products.aperture_ddc(row, col, val, member, n_vox))
+            apply, adjoint = bb.da_form_ops(np.stack(DA_cols, axis=1))
+        else:
+            apply, adjoint = bb.d_form_ops(row, col, val, n_vox, n_bl, apset)
+        m = apset.m
+        res = bb.solve(apply, adjoint, sid, table, y, np.full(m, lo), np.full(m, hi), params)
+        y, z = res["y"], res["z"]
+        p = products.price(row, col, val, obj.gradient(z, sid, table), n_bl)
+        log.append(dict(it=it, cp=k, best_price=sel["best_price"], F=res["F"],
+                        flags=res["flags"], bb_iters=res["iters"]))
+    return dict(apertures=list(zip(apset.cps, apset.L, apset.R)), y=y, z=z,
+                F=float(obj.objective(z, sid, table)), log=log, price=p)

@@ -1,0 +1,70 @@
+"""Invariants of the synthetic workload generator (inputs for both sides)."""
+import numpy as np
+import pytest
+
+from paper_1503_01721_amd import synth
+
+
+@pytest.mark.parametrize("name", ["tiny_cp4_bl3x4_vox8", "small_cp8_bl6x6_vox16", "cp20_bl20x20_vox32"])
+def test_generator_layout_and_values(name):
+    plan = synth.PLANS[name]
+    d = synth.generate_ddc(plan)
+    row, col, val = d["row"], d["col"], d["val"]
+    assert row.dtype == np.int32 and col.dtype == np.int32 and val.dtype == np.float32
+    assert row.min() >= 0 and row.max() < plan.n_vox
+    assert col.min() >= 0 and col.max() < plan.n_bl
+    # kept entries respect the cut and the kernel maximum of 1
+    assert val.min() >= np.float32(synth.CUTOFF) and val.max() <= 1.0
+    # unique pairs, sorted by (beamlet, voxel)
+    key = col.astype(np.int64) * plan.n_vox + row
+    assert np.all(np.diff(key) > 0)
+    # pointwise definition reproduces every stored value (and zeros elsewhere)
+    assert np.array_equal(synth.ddc_entries(plan, row, col), val)
+    rng = np.random.default_rng(0)
+    vox = rng.integers(0, plan.n_vox, 2000)
+    bl = rng.integers(0, plan.n_bl, 2000)
+    dense_pick = synth.ddc_entries(plan, vox, bl)
+    stored = dict(zip(key.tolist(), val.tolist()))
+    for v, b, e in zip(vox.tolist(), bl.tolist(), dense_pick.tolist()):
+        assert stored.get(b * plan.n_vox + v, 0.0) == e
+    # no entries outside the body cylinder
+    sid, table = synth.structures(plan)
+    assert np.all(sid[row] != synth.S_OUTSIDE)
+
+
+def test_plain_method_workload_size():
+    plan = synth.PLANS["cp20_bl20x20_vox32"]
+    d = synth.generate_ddc(plan)
+    assert plan.n_vox == 32768 and plan.n_bl == 8000
+    assert 4.5e6 < len(d["val"]) < 5.5e6       # ~5.07 M under this generator
+
+
+def test_structures_priority_and_table():
+    plan = synth.PLANS["cp20_bl20x20_vox32"]
+    sid, table = synth.structures(plan)
+    counts = np.bincount(sid, minlength=5)
+    assert counts[synth.S_PTV0] > 0 and counts[synth.S_OAR_A] > 0 and counts[synth.S_OAR_B] > 0
+    assert table.shape == (5, 3)
+    assert table[synth.S_PTV0].tolist() == [70.0, 1.0, 1.0]
+    assert table[synth.S_OUTSIDE].tolist() == [0.0, 0.0, 0.0]
+    # OAR weights: one-sided (no under-dose penalty)
+    assert table[synth.S_OAR_A, 2] == 0 and table[synth.S_BODY, 2] == 0
+
+
+def test_full_scale_control_point_is_reachable():
+    # One control point of the 180-angle, 128^3 workload reaches the PTV centre.
+    plan = synth.PLANS["cp180_bl40x40_vox128"]
+    r, c, v = synth.generate_cp(plan, 45)
+    N = plan.n_grid
+    centre = ((N // 2) * N + N // 2) * N + N // 2
+    assert np.any(r == centre)
+    assert 2.0e6 < len(v) < 3.5e6
+
+
+def test_random_apertures_and_boxes():
+    plan = synth.PLANS["cp20_bl20x20_vox32"]
+    cps, L, R = synth.random_apertures(plan, 8, 5)
+    assert len(set(cps.tolist())) == 8
+    assert np.all(L >= 0) and np.all(R <= plan.n_cols) and np.all(L < R)
+    lo, hi = synth.random_boxes(8, 5)
+    assert np.all(lo >= 0) and np.all(hi > lo)
