@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Benchmark: column-generation VMAT iterations on one MI355X.
+
+One step = one column-generation iteration of Sec. 2.1 on the full-scale
+single-arc workload (180 control points x 40x40 beamlets of 5 mm, 128^3
+voxels of 2.5 mm, ~5e8 non-zeros): price-based aperture selection, adding the
+aperture, then a 50-iteration Barzilai-Borwein master-problem solve, each
+iteration a dose product with the fused objective and a price product over
+the whole DDC matrix, plus one curvature product for the first step length.
+
+Output: one JSON line on stdout.  `value` is the effective HBM bandwidth of
+the whole timed job (algorithmic bytes of every product / wall time, inputs
+resident in HBM), `ms_per_step` the time per column-generation iteration.
+Progress goes to stderr.
+
+    python bench.py [--steps K] [--warmup W] [--storage f32|f16|bf16]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+METRIC = "effective HBM GB/s (and % peak) for D·x + Dᵀ·g; ms per column-gen iteration"
+HBM_PEAK_GBS = 8000.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(info, nrhs=1):
+    """Bytes each product must move: matrix once, row pointers, each vector once."""
+    n_vox, n_bl, nnz = info.n_vox, info.n_bl, info.nnz
+    mat = nnz * (info.value_bytes + 4)
+    scale = 4 * n_bl if info.value_bytes == 2 else 0
+    dose_obj = mat + 8 * (n_vox + 1) + 4 * nrhs * (n_bl + n_vox) + n_vox * (1 + 4 * nrhs) + scale
+    price = mat + 8 * (n_bl + 1) + 4 * nrhs * (n_vox + n_bl) + scale
+    curv = mat + 8 * (n_vox + 1) + 4 * n_bl + n_vox * (4 + 1) + scale
+    return dict(dose=dose_obj, price=price, curv=curv)
+
+
+def read_traffic(kernel, workload, storage):
+    """HBM traffic per launch from the committed counter summary, if it was taken
+    on the current kernel source; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}_{storage}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_1503_01721_amd", "csrc", "spmv.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if kv.get("spmv_source_sha256_16") != sha:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(d, plan, bytes_dose_plain, bytes_price):
+    """The FP64 oracle (NumPy bincount over COO, single-threaded) on one dose and
+    one price product over the whole matrix."""
+    import numpy as np
+    from oracle import products as oprod
+    from paper_1503_01721_amd import synth
+    x, g = synth.bench_vectors(plan.n_bl, plan.n_vox, 1002)
+    t0 = time.perf_counter()
+    oprod.dose(d["row"], d["col"], d["val"], x, plan.n_vox)
+    t1 = time.perf_counter()
+    oprod.price(d["row"], d["col"], d["val"], g, plan.n_bl)
+    t2 = time.perf_counter()
+    gbs = (bytes_dose_plain + bytes_price) / (t2 - t0) / 1e9
+    return {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": (f"one FP64 dose and one FP64 price product over the whole {plan.name} matrix "
+                       f"(NumPy bincount over COO; dose {t1 - t0:.2f} s, price {t2 - t1:.2f} s); "
+                       f"host {platform.processor() or platform.machine()}, os.cpu_count()={os.cpu_count()}"),
+            "seconds": round(t2 - t0, 3)}
+
+
+def copy_calibration():
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    n = 1 << 28                                     # 1 GiB of float32
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n,
+                      "launches": 5}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20, help="timed column-generation iterations")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed iterations before the timed ones")
+    ap.add_argument("--workload", default="cp180_bl40x40_vox128")
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--bb-steps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true", help=argparse.SUPPRESS)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the whole DDC matrix fits one MI355X's HBM); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    from paper_1503_01721_amd import dvmat, synth
+    from paper_1503_01721_amd.colgen import ColumnGeneration
+
+    plan = synth.PLANS[args.workload]
+    if args.warmup + args.steps > plan.n_cp:
+        raise SystemExit("more iterations than control points")
+    log(f"generating {plan.name}: {plan.n_vox} voxels x {plan.n_bl} beamlets")
+    t = time.perf_counter()
+    d = synth.generate_ddc(plan)
+    sid, table = synth.structures(plan)
+    t_gen = time.perf_counter() - t
+    log(f"generated nnz={len(d['val'])} in {t_gen:.1f} s")
+
+    t = time.perf_counter()
+    ddc = dvmat.DDC(d["row"], d["col"], d["val"], plan.n_vox, plan.n_bl, storage=args.storage)
+    obj = dvmat.Objective(sid, table)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t
+    info = ddc.info
+    log(f"built CSR(D) + CSR(D^T) and uploaded {info.workspace_bytes / 2**30:.2f} GiB in {t_build:.1f} s")
+
+    cg = ColumnGeneration(ddc, obj, plan.n_cp, plan.n_rows, plan.n_cols,
+                          max_apertures=args.warmup + args.steps, bb_steps=args.bb_steps)
+    cg.start()
+    for i in range(args.warmup):
+        rec = cg.iteration()
+        log(f"warmup iteration {i}: {rec}")
+    torch.cuda.synchronize()
+
+    cg.events = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        rec = cg.iteration()
+        if rec is None:
+            raise SystemExit("column generation stopped inside the timed region")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    log(f"timed {args.steps} iterations in {wall:.3f} s; last {cg.records[-1]}")
+
+    ab = algorithmic_bytes(info)
+    per_iter = args.bb_steps * (ab["dose"] + ab["price"]) + ab["curv"]
+    value = args.steps * per_iter / wall / 1e9
+    dose_ms = [e[0].elapsed_time(e[1]) for e in cg.events]
+    price_ms = [e[1].elapsed_time(e[2]) for e in cg.events]
+    mean_dose = sum(dose_ms) / len(dose_ms)
+    mean_price = sum(price_ms) / len(price_ms)
+    dom = "price" if mean_price >= mean_dose else "dose"
+    dom_ms = mean_price if dom == "price" else mean_dose
+    achieved = ab[dom] / (dom_ms * 1e-3) / 1e9
+    kname = "spmv_kernel (price, CSR of D^T)" if dom == "price" else "spmv_kernel (dose, CSR of D, objective epilogue)"
+    traffic = read_traffic(dom, plan.name, args.storage)
+    log(f"mean dose call {mean_dose:.3f} ms ({ab['dose'] / mean_dose / 1e6:.0f} GB/s), "
+        f"mean price call {mean_price:.3f} ms ({ab['price'] / mean_price / 1e6:.0f} GB/s)")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic",
+        "config": {
+            "workload": plan.name,
+            "n_vox": plan.n_vox, "n_beamlets": plan.n_bl, "nnz": int(info.nnz),
+            "storage": args.storage, "accumulate": "f32", "bb_steps_per_iteration": args.bb_steps,
+            "products_per_iteration": 2 * args.bb_steps + 1,
+            "algorithmic_bytes_per_iteration": per_iter,
+            "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
+            "mean_dose_call_ms": round(mean_dose, 4), "mean_price_call_ms": round(mean_price, 4),
+            "generate_s": round(t_gen, 2), "build_upload_s": round(t_build, 2),
+        },
+        "roofline": {
+            "bound": "hbm", "kernel": kname,
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": ab[dom], "mean_launch_ms": round(dom_ms, 4),
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on one dose and one price product (CPU baseline)")
+        bplain = ab["dose"] - info.n_vox * (1 + 4)
+        out["cpu_baseline"] = cpu_baseline(d, plan, bplain, ab["price"])
+        log(f"cpu baseline {out['cpu_baseline']['value']} GB/s in {out['cpu_baseline']['seconds']} s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

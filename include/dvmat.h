@@ -1,0 +1,249 @@
+/*
+ * dvmat.h -- C ABI of libdvmat: the dose-deposition-coefficient (DDC) products
+ * of column-generation VMAT optimisation on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Tian et al., "Multi-GPU implementation of a VMAT treatment plan
+ * optimization algorithm", arXiv:1503.01721.  Section 2.1 defines the model
+ * (objective Eq. 1, price Eqs. 3-4, aperture DDC Eq. 5, master problem Eq. 6,
+ * Barzilai-Borwein steps Eqs. 7-8 with the bound rules Eqs. 9-10); Section
+ * 2.2.2 describes the GPU steps (price by CSR SpMV of D^T, row-wise aperture
+ * selection, the four master-problem steps).
+ *
+ * Conventions for every call
+ * --------------------------
+ * - Return value: DVMAT_OK (0) or a negative dvmat_status; the message of the
+ *   last failure on the calling thread is dvmat_last_error() (never NULL).
+ *   Nothing throws, aborts or exits across this interface.
+ * - O(1) argument checks run before anything is enqueued; O(nnz) index and
+ *   finiteness checks run once, in dvmat_ddc_create.
+ * - Pointers documented "device" are device memory owned by the caller; the
+ *   library never allocates device memory.  Every handle that needs device
+ *   state keeps it in a caller-provided workspace whose size is queried first.
+ * - "stream" is a hipStream_t passed as void* (NULL = the null stream).  Hot
+ *   calls only enqueue work on it and return; results are valid after the
+ *   stream's work completes.  Calls that use one handle and overlap in time on
+ *   different streams race on that handle's scratch; serialise them.
+ * - Vectors with several right-hand sides (nrhs in 1..8) are row-major
+ *   [n][nrhs]: element (i, k) at i*nrhs + k.
+ * - Indices: voxel i in [0, n_vox), beamlet j in [0, n_bl); with a control-
+ *   point geometry, beamlet j = (k*n_rows + r)*n_cols + c for control point k,
+ *   MLC leaf row r and beamlet c along the row.
+ */
+#ifndef DVMAT_H
+#define DVMAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dvmat_status;
+#define DVMAT_OK        0
+#define DVMAT_E_ARG    (-1)   /* bad argument: null pointer, size, dtype, non-finite value */
+#define DVMAT_E_SHAPE  (-2)   /* inconsistent sizes (geometry, nrhs, workspace layout)     */
+#define DVMAT_E_INDEX  (-3)   /* COO row/column index out of range                          */
+#define DVMAT_E_NOMEM  (-4)   /* workspace smaller than the size query, or host alloc fail  */
+#define DVMAT_E_HIP    (-5)   /* a HIP runtime call failed                                  */
+#define DVMAT_E_STATE  (-6)   /* call out of order (unbound handle, occupied control point) */
+
+/* storage type of the DDC values; accumulation is always FP32 */
+#define DVMAT_F32   0
+#define DVMAT_F16   1   /* IEEE half, value/s_j with s_j = max_i |D_ij| kept in FP32 */
+#define DVMAT_BF16  2   /* bfloat16, same per-beamlet scale                           */
+
+typedef void* dvmat_stream;
+
+const char* dvmat_last_error(void);
+/* library version, e.g. 0x000100 for 0.1.0 */
+int32_t dvmat_version(void);
+
+/* ------------------------------------------------------------------------
+ * DDC matrix D (voxels x beamlets).
+ *
+ * The paper keeps D as COO on the host (Sec. 2.2.2) and D^T as CSR on the
+ * GPU for the price product Pi = D^T g (Eq. 3).  Here both orientations live
+ * in one GPU's memory: CSR of D ("dose matrix", rows = voxels) for z = D x,
+ * and CSR of D^T ("price matrix", rows = beamlets) for p = D^T g.  Row
+ * pointers are int64 (more than 2^31 non-zeros fit), column indices int32,
+ * every row is padded with explicit zeros to a multiple of 4 entries so that
+ * rows start on 16-byte boundaries.
+ * ---------------------------------------------------------------------- */
+typedef struct dvmat_ddc_s* dvmat_ddc;
+
+typedef struct {
+    int64_t n_vox, n_bl, nnz;            /* nnz after summing duplicate pairs   */
+    int64_t nnz_pad_dose, nnz_pad_price; /* stored entries incl. row padding     */
+    int64_t n_blocks_dose, n_blocks_price; /* row blocks (work units)            */
+    int64_t nonempty_rows_dose, nonempty_rows_price;
+    int32_t storage;                     /* DVMAT_F32 / F16 / BF16               */
+    int32_t value_bytes;                 /* 4 or 2                               */
+    size_t workspace_bytes;              /* device bytes needed by dvmat_ddc_bind */
+} dvmat_ddc_info_t;
+
+/* Validate host COO (row = voxel, col = beamlet, val; length nnz; read during
+ * the call only), sum duplicate pairs, build both CSR orientations, row blocks
+ * and (F16/BF16) the quantised values with per-beamlet scales, staged in host
+ * memory owned by the handle.  nnz may be 0.  Errors: DVMAT_E_ARG (null
+ * pointer with nnz > 0, sizes < 1 or >= 2^31, unknown storage, non-finite
+ * value), DVMAT_E_INDEX (index out of range), DVMAT_E_NOMEM (host memory). */
+dvmat_status dvmat_ddc_create(int64_t n_vox, int64_t n_bl, int64_t nnz,
+                              const int32_t* row_vox, const int32_t* col_bl,
+                              const float* val, int32_t storage, dvmat_ddc* out);
+/* Sizes and counts; valid right after create. */
+dvmat_status dvmat_ddc_info(dvmat_ddc ddc, dvmat_ddc_info_t* info);
+/* Copy the staged matrices into the caller's device workspace (>= info.
+ * workspace_bytes, 256-byte aligned), synchronise the stream and release the
+ * host staging.  Binding once is allowed; DVMAT_E_STATE on a second bind,
+ * DVMAT_E_NOMEM if bytes is too small, DVMAT_E_ARG if misaligned. */
+dvmat_status dvmat_ddc_bind(dvmat_ddc ddc, void* d_workspace, size_t bytes, dvmat_stream stream);
+/* Frees host memory only (the workspace stays the caller's). NULL is a no-op. */
+void dvmat_ddc_destroy(dvmat_ddc ddc);
+
+/* ------------------------------------------------------------------------
+ * Objective (Eq. 1): F(z) = sum_i w+_i max(0, z_i - T_i)^2 + w-_i max(0, T_i - z_i)^2
+ * with per-voxel (T, w+, w-) looked up from a structure id, the small
+ * replicated per-voxel parameters of Sec. 2.2.2.  w+ is the over-dose weight
+ * (Eq. 1 and the sentence after it).
+ * ---------------------------------------------------------------------- */
+typedef struct dvmat_obj_s* dvmat_obj;
+
+/* Device bytes needed by dvmat_obj_create for n_struct structures. */
+dvmat_status dvmat_obj_workspace_size(int32_t n_struct, size_t* bytes);
+/* d_struct_id: device uint8[n_vox], kept by reference (caller keeps it alive);
+ * table: host float[n_struct][3] of (T, w+, w-), copied into the workspace.
+ * n_struct in 1..256; ids >= n_struct read an all-zero row (no objective).
+ * Enqueues the table copy on stream. */
+dvmat_status dvmat_obj_create(int64_t n_vox, int32_t n_struct, const uint8_t* d_struct_id,
+                              const float* table, void* d_workspace, size_t bytes,
+                              dvmat_stream stream, dvmat_obj* out);
+void dvmat_obj_destroy(dvmat_obj obj);
+
+/* Standalone objective and gradient of an externally supplied dose.
+ * z: device [n_vox][nrhs]; g: device [n_vox][nrhs] = dF/dz (nullable);
+ * F: device float[nrhs] (nullable).  Eqs. (1) and (4) (g of Eq. 4 is -dF/dz). */
+dvmat_status dvmat_objective(dvmat_obj obj, const float* z, int32_t nrhs, float* g, float* F,
+                             dvmat_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Hot products.
+ * ---------------------------------------------------------------------- */
+
+/* Dose z = D x: the dose update of the master problem (Sec. 2.2.2 step 4;
+ * z = sum_k DA(A_k) y_k of Sec. 2.1 written per beamlet) and, for x the
+ * indicator of an aperture, the aperture DDC vector DA of Eq. (5).
+ * x: device [n_bl][nrhs]; z: device [n_vox][nrhs]; nrhs in 1..8.
+ * With obj != NULL the objective epilogue also writes g = dF/dz (if g != NULL)
+ * and F[nrhs] (if F != NULL), fused into the same pass over D. */
+dvmat_status dvmat_dose(dvmat_ddc ddc, const float* x, int32_t nrhs, float* z,
+                        dvmat_obj obj, float* g, float* F, dvmat_stream stream);
+
+/* Price p = D^T g (Eq. 3 with g = dF/dz; the paper's price is pi = -p).
+ * g: device [n_vox][nrhs]; p: device [n_bl][nrhs]; nrhs in 1..8. */
+dvmat_status dvmat_price(dvmat_ddc ddc, const float* g, int32_t nrhs, float* p,
+                         dvmat_stream stream);
+
+/* Curvature of F along a fluence direction, for the first step length of a
+ * master-problem solve: curv = sum_i w_i(z_ref) (D x_dir)_i^2 with w_i = w+
+ * where z_ref_i > T_i, w- where z_ref_i < T_i, 0 where equal.  x_dir: device
+ * float[n_bl]; z_ref: device float[n_vox]; d_out: device float[n_vox]
+ * receives D x_dir (nullable); curv: device double[1]. */
+dvmat_status dvmat_dose_curvature(dvmat_ddc ddc, const float* x_dir, dvmat_obj obj,
+                                  const float* z_ref, float* d_out, double* curv,
+                                  dvmat_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Aperture selection (pricing problem, second step; Sec. 2.1 and 2.2.2
+ * without the interdigitation constraint): per unoccupied control point and
+ * MLC leaf row, the opening [L, R) with the smallest sum of p (the paper
+ * maximises pi = -p); the aperture price is the sum over rows; the best
+ * control point has the smallest price.  Openings are half-open beamlet
+ * intervals, the closed row is (0, 0) with sum 0; ties: smaller sum, then
+ * shorter, then smaller L; between control points the lower index.
+ * ---------------------------------------------------------------------- */
+typedef struct { int32_t n_cp, n_rows, n_cols; } dvmat_geom;
+
+/* p: device float[n_cp*n_rows*n_cols]; occupied: device uint8[n_cp] (nonzero =
+ * occupied, nullable = none); L, R: device int32[n_cp][n_rows] (occupied
+ * control points get 0, 0); cp_price: device float[n_cp] (+inf if occupied);
+ * best: device int32[1] = the chosen control point, or -1 when no unoccupied
+ * control point has a price < 0 (the column generation stops, Sec. 2.1);
+ * best_price: device float[1] (the smallest price, +inf if all are occupied).
+ * Limits: n_cols <= 1024 and n_rows*(n_cols+1) <= 16384 (one control point's
+ * prices are staged in 64 KiB of LDS). */
+dvmat_status dvmat_aperture_select(dvmat_geom geom, const float* p, const uint8_t* occupied,
+                                   int32_t* L, int32_t* R, float* cp_price,
+                                   int32_t* best, float* best_price, dvmat_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Master problem (Eq. 6) by Barzilai-Borwein steps (Eqs. 7-8, alternating)
+ * with the subspace bound rules (Eqs. 9-10), state kept on the device.
+ *
+ * One solve: dvmat_bb_begin, optionally dvmat_bb_direction +
+ * dvmat_dose_curvature for the first step length, then per iteration
+ * dvmat_bb_step -> dvmat_dose (with objective) -> dvmat_price.
+ * Readings (the paper is silent): step length at the first iteration of a
+ * solve = <Gt,Gt>/(2 curv) (Cauchy step), later BB1 = <s,s>/<s,q> on odd and
+ * BB2 = <s,q>/<q,q> on even iterations, used as step along -Gt (Eqs. 7-8 are
+ * written with the negative gradient); if <s,q> <= 0 or the ratio is not
+ * finite and positive the previous length is reused (flag FALLBACK).
+ * Stopping: |F_{t-5} - F_t| <= eps_f |F_t|, max|y_t - y_{t-1}| <= eps_step
+ * max(1, max|y_t|), all masked gradient components zero, or max_iter steps.
+ * Once stopped, further steps leave y unchanged (the caller may keep a fixed
+ * number of steps).  Inner products are FP64, y and alpha FP32.
+ * ---------------------------------------------------------------------- */
+typedef struct dvmat_bb_s* dvmat_bb;
+
+typedef struct {
+    int32_t max_iter;    /* steps per solve (>= 1)             */
+    float   eps_f;       /* relative F change over five steps  */
+    float   eps_step;    /* step size relative to max(1,|y|)   */
+} dvmat_bb_params;
+
+#define DVMAT_BB_REL_F      1u
+#define DVMAT_BB_SMALL_STEP 2u
+#define DVMAT_BB_MAX_ITER   4u
+#define DVMAT_BB_FALLBACK   8u
+#define DVMAT_BB_CONVERGED 16u
+#define DVMAT_BB_NONFINITE 32u
+
+dvmat_status dvmat_bb_workspace_size(dvmat_geom geom, int32_t max_apertures, size_t* bytes);
+/* Initialises an empty aperture set in the caller's device workspace. */
+dvmat_status dvmat_bb_create(dvmat_geom geom, int32_t max_apertures, dvmat_bb_params params,
+                             void* d_workspace, size_t bytes, dvmat_stream stream, dvmat_bb* out);
+void dvmat_bb_destroy(dvmat_bb bb);
+/* Host-side count of apertures (-1 for a NULL handle). */
+int32_t dvmat_bb_count(dvmat_bb bb);
+/* Device uint8[n_cp] inside the workspace, 1 where a control point holds an
+ * aperture; maintained by dvmat_bb_add_aperture, suitable as the occupied
+ * argument of dvmat_aperture_select (the "unoccupied control points" of Sec. 2.1). */
+dvmat_status dvmat_bb_occupancy(dvmat_bb bb, const uint8_t** d_occupied);
+/* Add the aperture chosen at control point cp (host value, e.g. read back
+ * from dvmat_aperture_select's best): d_L, d_R device int32[n_rows] openings
+ * (e.g. L + cp*n_rows), box [lo, hi] (hi may be +inf), initial rate
+ * y0 (clamped to the box).  DVMAT_E_STATE if cp is occupied or the set is full. */
+dvmat_status dvmat_bb_add_aperture(dvmat_bb bb, int32_t cp, const int32_t* d_L, const int32_t* d_R,
+                                   float lo, float hi, float y0, dvmat_stream stream);
+/* Start a master-problem solve (iteration counter, flags and F history reset). */
+dvmat_status dvmat_bb_begin(dvmat_bb bb, dvmat_stream stream);
+/* From the price p = D^T dF/dz at the current rates: the gradient in the
+ * aperture domain G_k = sum_{j in A_k} p_j, masked by Eqs. (9)-(10), expanded
+ * to beamlets: x_dir_j = Gt_k for j in A_k, else 0.  x_dir: device float[n_bl]. */
+dvmat_status dvmat_bb_direction(dvmat_bb bb, const float* p, float* x_dir, dvmat_stream stream);
+/* One iteration: p = D^T dF/dz and F at the current rates (device), curv from
+ * dvmat_dose_curvature (device double[1], used on the first iteration of a
+ * solve; NULL = fall back to max|y|/max|Gt|); writes the new beamlet fluence
+ * x_next = B y (device float[n_bl]) and the solve's flags (device uint32[1],
+ * nullable). */
+dvmat_status dvmat_bb_step(dvmat_bb bb, const float* p, const float* F, const double* curv,
+                           float* x_next, uint32_t* flags, dvmat_stream stream);
+/* x = B y for the current rates (device float[n_bl]). */
+dvmat_status dvmat_bb_expand(dvmat_bb bb, float* x, dvmat_stream stream);
+/* Copy the current rates to device float[count]. */
+dvmat_status dvmat_bb_get_y(dvmat_bb bb, float* y, dvmat_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DVMAT_H */

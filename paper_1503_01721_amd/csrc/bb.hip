@@ -1,0 +1,417 @@
+// Master problem (Eq. 6) by Barzilai-Borwein steps with the subspace bound
+// rules, Eqs. (7)-(10); the four steps of Sec. 2.2.2 (gradient in the aperture
+// domain, step size, bounded update, dose update) with the dose update done by
+// the caller through dvmat_dose on the full matrix.
+//
+// Device state lives in the caller's workspace; each iteration is three small
+// launches: gather G_k = sum_{j in A_k} p_j (one workgroup per aperture, fixed
+// reduction order), the update (one workgroup: bound rules, FP64 inner
+// products, step length, stopping tests, clipped step), and the expansion of
+// the rates to the beamlet fluence x = B y (one thread per beamlet).
+#include "common.hpp"
+
+#include <cmath>
+#include <new>
+
+namespace dvmat {
+
+constexpr uint32_t kStopMask = DVMAT_BB_REL_F | DVMAT_BB_SMALL_STEP | DVMAT_BB_MAX_ITER | DVMAT_BB_CONVERGED |
+                               DVMAT_BB_NONFINITE;
+constexpr int kFHist = 8;
+
+struct BBState {
+    int32_t t;         // iteration counter of the current solve
+    uint32_t flags;
+    float alpha;       // last step length
+    float pad;
+    float F_hist[kFHist];
+};
+
+struct BBDev {
+    BBState* state;
+    int32_t* cp;       // [max_ap]
+    int32_t* L;        // [max_ap * n_rows]
+    int32_t* R;
+    float* lo;         // [max_ap]
+    float* hi;
+    float* y;
+    float* y_prev;
+    float* G;
+    float* Gt;
+    float* Gt_prev;
+    int32_t* cp_slot;  // [n_cp] aperture index or -1
+    uint8_t* occ;      // [n_cp] 1 where a control point holds an aperture
+};
+
+}  // namespace dvmat
+
+struct dvmat_bb_s {
+    dvmat_geom geom{};
+    int32_t max_ap = 0;
+    int32_t m = 0;
+    dvmat_bb_params params{};
+    std::vector<uint8_t> occupied;   // host mirror of control-point occupancy
+    dvmat::BBDev dev{};
+};
+
+namespace dvmat {
+
+static size_t bb_layout(const dvmat_geom& g, int32_t max_ap, BBDev* dev, char* base) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return base ? base + o : nullptr; };
+    char* p;
+    p = take(sizeof(BBState));                    if (dev) dev->state = reinterpret_cast<BBState*>(p);
+    p = take((size_t)max_ap * 4);                 if (dev) dev->cp = reinterpret_cast<int32_t*>(p);
+    p = take((size_t)max_ap * g.n_rows * 4);      if (dev) dev->L = reinterpret_cast<int32_t*>(p);
+    p = take((size_t)max_ap * g.n_rows * 4);      if (dev) dev->R = reinterpret_cast<int32_t*>(p);
+    float** fl[] = {dev ? &dev->lo : nullptr, dev ? &dev->hi : nullptr, dev ? &dev->y : nullptr,
+                    dev ? &dev->y_prev : nullptr, dev ? &dev->G : nullptr, dev ? &dev->Gt : nullptr,
+                    dev ? &dev->Gt_prev : nullptr};
+    for (float** f : fl) {
+        p = take((size_t)max_ap * 4);
+        if (f) *f = reinterpret_cast<float*>(p);
+    }
+    p = take((size_t)g.n_cp * 4);                 if (dev) dev->cp_slot = reinterpret_cast<int32_t*>(p);
+    p = take((size_t)g.n_cp);                     if (dev) dev->occ = reinterpret_cast<uint8_t*>(p);
+    return off;
+}
+
+__global__ void bb_init_kernel(BBDev B, int n_cp) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_cp; i += gridDim.x * blockDim.x) {
+        B.cp_slot[i] = -1;
+        B.occ[i] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        B.state->t = 0;
+        B.state->flags = 0;
+        B.state->alpha = 0.0f;
+        for (int i = 0; i < kFHist; ++i) B.state->F_hist[i] = 0.0f;
+    }
+}
+
+__global__ void bb_add_kernel(BBDev B, int slot, int cp, int n_rows, const int32_t* dL, const int32_t* dR, float lo,
+                              float hi, float y0) {
+    for (int r = threadIdx.x; r < n_rows; r += blockDim.x) {
+        B.L[(int64_t)slot * n_rows + r] = dL[r];
+        B.R[(int64_t)slot * n_rows + r] = dR[r];
+    }
+    if (threadIdx.x == 0) {
+        B.cp[slot] = cp;
+        B.cp_slot[cp] = slot;
+        B.occ[cp] = 1;
+        B.lo[slot] = lo;
+        B.hi[slot] = hi;
+        const float y = fminf(fmaxf(y0, lo), hi);
+        B.y[slot] = y;
+        B.y_prev[slot] = y;
+        B.G[slot] = 0.0f;
+        B.Gt[slot] = 0.0f;
+        B.Gt_prev[slot] = 0.0f;
+    }
+}
+
+__global__ void bb_begin_kernel(BBDev B) {
+    if (threadIdx.x == 0) {
+        B.state->t = 0;
+        B.state->flags = 0;
+        B.state->alpha = 0.0f;
+        for (int i = 0; i < kFHist; ++i) B.state->F_hist[i] = 0.0f;
+    }
+}
+
+// G_k = sum of p over the beamlets of aperture k (one workgroup per aperture).
+__global__ __launch_bounds__(256) void bb_gather_kernel(BBDev B, int n_rows, int n_cols, const float* __restrict__ p) {
+    __shared__ float s[256];
+    const int k = blockIdx.x;
+    const int cp = B.cp[k];
+    const int64_t base = (int64_t)cp * n_rows * n_cols;
+    const int per_cp = n_rows * n_cols;
+    float a = 0.0f;
+    for (int i = threadIdx.x; i < per_cp; i += 256) {
+        const int r = i / n_cols, c = i - r * n_cols;
+        if (c >= B.L[(int64_t)k * n_rows + r] && c < B.R[(int64_t)k * n_rows + r]) a += p[base + i];
+    }
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) B.G[k] = s[0];
+}
+
+enum { MODE_DIRECTION = 0, MODE_STEP = 1 };
+
+// Bound rules, step length, stopping tests and the clipped step (one workgroup).
+__global__ __launch_bounds__(256) void bb_update_kernel(BBDev B, int m, int mode, const float* Fp, const double* curv,
+                                                        uint32_t* flags_out, dvmat_bb_params prm) {
+    __shared__ double r_ss[256], r_sq[256], r_qq[256], r_gg[256];
+    __shared__ float r_ds[256], r_y[256], r_g[256];
+    __shared__ int r_nz[256];
+    __shared__ float s_alpha;
+    __shared__ uint32_t s_stop;
+    const int tid = threadIdx.x;
+    const int t = B.state->t;
+    uint32_t flags = B.state->flags;
+    if (mode == MODE_STEP && (flags & kStopMask)) {   // solve already stopped: rates stay
+        if (tid == 0 && flags_out) *flags_out = flags;
+        return;
+    }
+    // Eqs. (9)-(10) on G = dF/dy (the paper's g_A = -G)
+    double ss = 0.0, sq = 0.0, qq = 0.0, gg = 0.0;
+    float ds = 0.0f, ymax = 0.0f, gmax = 0.0f;
+    int nz = 0;
+    for (int k = tid; k < m; k += 256) {
+        const float lo = B.lo[k], hi = B.hi[k];
+        const float y = fminf(fmaxf(B.y[k], lo), hi);
+        const float G = B.G[k];
+        float gt = G;
+        if (y <= lo && G > 0.0f) gt = 0.0f;
+        if (y >= hi && G < 0.0f) gt = 0.0f;
+        B.y[k] = y;
+        B.Gt[k] = gt;
+        if (mode == MODE_STEP) {
+            nz += gt != 0.0f;
+            gg += (double)gt * (double)gt;
+            ymax = fmaxf(ymax, fabsf(y));
+            gmax = fmaxf(gmax, fabsf(gt));
+            if (t >= 1) {
+                const double s = (double)y - (double)B.y_prev[k];
+                const double q = (double)gt - (double)B.Gt_prev[k];
+                ss += s * s;
+                sq += s * q;
+                qq += q * q;
+                ds = fmaxf(ds, fabsf(y - B.y_prev[k]));
+            }
+        }
+    }
+    if (mode == MODE_DIRECTION) return;
+    r_ss[tid] = ss; r_sq[tid] = sq; r_qq[tid] = qq; r_gg[tid] = gg;
+    r_ds[tid] = ds; r_y[tid] = ymax; r_g[tid] = gmax; r_nz[tid] = nz;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+        if (tid < o) {
+            r_ss[tid] += r_ss[tid + o];
+            r_sq[tid] += r_sq[tid + o];
+            r_qq[tid] += r_qq[tid + o];
+            r_gg[tid] += r_gg[tid + o];
+            r_ds[tid] = fmaxf(r_ds[tid], r_ds[tid + o]);
+            r_y[tid] = fmaxf(r_y[tid], r_y[tid + o]);
+            r_g[tid] = fmaxf(r_g[tid], r_g[tid + o]);
+            r_nz[tid] += r_nz[tid + o];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const float F = *Fp;
+        B.state->F_hist[t % kFHist] = F;
+        uint32_t stop = 0;
+        if (!isfinite(F)) {
+            stop = DVMAT_BB_NONFINITE;
+        } else if (t >= 5 && fabs((double)B.state->F_hist[(t - 5) % kFHist] - (double)F) <=
+                                 (double)prm.eps_f * fabs((double)F)) {
+            stop = DVMAT_BB_REL_F;
+        } else if (t >= 1 && r_ds[0] <= prm.eps_step * fmaxf(1.0f, r_y[0])) {
+            stop = DVMAT_BB_SMALL_STEP;
+        } else if (r_nz[0] == 0) {
+            stop = DVMAT_BB_CONVERGED;
+        }
+        float alpha = B.state->alpha;
+        if (!stop) {
+            if (t == 0) {
+                const double den = curv ? 2.0 * (*curv) : 0.0;
+                if (den > 0.0 && isfinite(den)) {
+                    alpha = (float)(r_gg[0] / den);
+                } else {
+                    alpha = (r_y[0] > 0.0f ? r_y[0] : 1.0f) / r_g[0];
+                    flags |= DVMAT_BB_FALLBACK;
+                }
+            } else {
+                const double sqv = r_sq[0];
+                const double cand = (t & 1) ? r_ss[0] / sqv : sqv / r_qq[0];
+                if (sqv > 0.0 && isfinite(cand) && cand > 0.0) alpha = (float)cand;
+                else flags |= DVMAT_BB_FALLBACK;
+            }
+            if (!isfinite(alpha)) stop = DVMAT_BB_NONFINITE;
+        }
+        flags |= stop;
+        s_alpha = alpha;
+        s_stop = stop;
+        B.state->alpha = alpha;
+    }
+    __syncthreads();
+    const uint32_t stop = s_stop;
+    const float alpha = s_alpha;
+    if (!stop) {
+        for (int k = tid; k < m; k += 256) {
+            const float y = B.y[k];
+            const float gt = B.Gt[k];
+            B.y_prev[k] = y;
+            B.Gt_prev[k] = gt;
+            const double yn = (double)y - (double)alpha * (double)gt;
+            B.y[k] = fminf(fmaxf((float)yn, B.lo[k]), B.hi[k]);
+        }
+    }
+    if (tid == 0) {
+        if (!stop) {
+            if (t + 1 >= prm.max_iter) flags |= DVMAT_BB_MAX_ITER;
+            B.state->t = t + 1;
+        }
+        B.state->flags = flags;
+        if (flags_out) *flags_out = flags;
+    }
+}
+
+// x_j = src_k for beamlet j in aperture k, else 0.
+__global__ __launch_bounds__(256) void bb_expand_kernel(BBDev B, int n_rows, int n_cols, int64_t n_bl,
+                                                        const float* __restrict__ src, float* __restrict__ x) {
+    const int64_t per_cp = (int64_t)n_rows * n_cols;
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n_bl; j += (int64_t)gridDim.x * 256) {
+        const int cp = (int)(j / per_cp);
+        const int rc = (int)(j - (int64_t)cp * per_cp);
+        const int r = rc / n_cols, c = rc - r * n_cols;
+        const int slot = B.cp_slot[cp];
+        float v = 0.0f;
+        if (slot >= 0 && c >= B.L[(int64_t)slot * n_rows + r] && c < B.R[(int64_t)slot * n_rows + r]) v = src[slot];
+        x[j] = v;
+    }
+}
+
+__global__ void bb_copy_y_kernel(BBDev B, int m, float* y) {
+    for (int k = threadIdx.x; k < m; k += blockDim.x) y[k] = B.y[k];
+}
+
+static dvmat_status check_geom(const dvmat_geom& g, const char* fn) {
+    if (g.n_cp < 1 || g.n_rows < 1 || g.n_cols < 1)
+        return set_error(DVMAT_E_SHAPE, "%s: geometry %d x %d x %d", fn, g.n_cp, g.n_rows, g.n_cols);
+    if ((int64_t)g.n_cp * g.n_rows * g.n_cols >= (int64_t(1) << 31))
+        return set_error(DVMAT_E_SHAPE, "%s: more than 2^31 beamlets", fn);
+    return DVMAT_OK;
+}
+
+static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048)); }
+
+}  // namespace dvmat
+
+using namespace dvmat;
+
+extern "C" {
+
+dvmat_status dvmat_bb_workspace_size(dvmat_geom geom, int32_t max_ap, size_t* bytes) {
+    dvmat_status st = check_geom(geom, "dvmat_bb_workspace_size");
+    if (st) return st;
+    if (!bytes) return set_error(DVMAT_E_ARG, "dvmat_bb_workspace_size: bytes is NULL");
+    if (max_ap < 1 || max_ap > geom.n_cp)
+        return set_error(DVMAT_E_ARG, "dvmat_bb_workspace_size: max_apertures=%d not in 1..n_cp", max_ap);
+    *bytes = bb_layout(geom, max_ap, nullptr, nullptr);
+    return DVMAT_OK;
+}
+
+dvmat_status dvmat_bb_create(dvmat_geom geom, int32_t max_ap, dvmat_bb_params params, void* ws, size_t bytes,
+                             dvmat_stream stream, dvmat_bb* out) {
+    if (!out) return set_error(DVMAT_E_ARG, "dvmat_bb_create: out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    dvmat_status st = dvmat_bb_workspace_size(geom, max_ap, &need);
+    if (st) return st;
+    if (!ws) return set_error(DVMAT_E_ARG, "dvmat_bb_create: workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign) return set_error(DVMAT_E_ARG, "dvmat_bb_create: workspace misaligned");
+    if (bytes < need) return set_error(DVMAT_E_NOMEM, "dvmat_bb_create: workspace %zu < %zu bytes", bytes, need);
+    if (params.max_iter < 1 || !(params.eps_f >= 0.0f) || !(params.eps_step >= 0.0f))
+        return set_error(DVMAT_E_ARG, "dvmat_bb_create: bad parameters (max_iter=%d eps_f=%g eps_step=%g)",
+                         params.max_iter, params.eps_f, params.eps_step);
+    dvmat_bb_s* b = new (std::nothrow) dvmat_bb_s();
+    if (!b) return set_error(DVMAT_E_NOMEM, "dvmat_bb_create: host allocation failed");
+    b->geom = geom;
+    b->max_ap = max_ap;
+    b->params = params;
+    b->occupied.assign(geom.n_cp, 0);
+    bb_layout(geom, max_ap, &b->dev, static_cast<char*>(ws));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(bb_init_kernel, dim3(grid_for(geom.n_cp)), dim3(256), 0, s, b->dev, geom.n_cp);
+    st = check_hip(hipGetLastError(), "dvmat_bb_create launch");
+    if (st) { delete b; return st; }
+    *out = b;
+    return DVMAT_OK;
+}
+
+void dvmat_bb_destroy(dvmat_bb b) { delete b; }
+
+int32_t dvmat_bb_count(dvmat_bb b) { return b ? b->m : -1; }
+
+dvmat_status dvmat_bb_occupancy(dvmat_bb b, const uint8_t** d_occupied) {
+    if (!b || !d_occupied) return set_error(DVMAT_E_ARG, "dvmat_bb_occupancy: NULL argument");
+    *d_occupied = b->dev.occ;
+    return DVMAT_OK;
+}
+
+dvmat_status dvmat_bb_add_aperture(dvmat_bb b, int32_t cp, const int32_t* dL, const int32_t* dR, float lo, float hi,
+                                   float y0, dvmat_stream stream) {
+    if (!b || !dL || !dR) return set_error(DVMAT_E_ARG, "dvmat_bb_add_aperture: NULL argument");
+    if (cp < 0 || cp >= b->geom.n_cp)
+        return set_error(DVMAT_E_ARG, "dvmat_bb_add_aperture: control point %d not in [0,%d)", cp, b->geom.n_cp);
+    if (std::isnan(lo) || std::isnan(hi) || lo > hi || std::isinf(lo) || std::isnan(y0))
+        return set_error(DVMAT_E_ARG, "dvmat_bb_add_aperture: bad box [%g, %g] or y0 %g", lo, hi, y0);
+    if (b->occupied[cp]) return set_error(DVMAT_E_STATE, "dvmat_bb_add_aperture: control point %d already occupied", cp);
+    if (b->m >= b->max_ap) return set_error(DVMAT_E_STATE, "dvmat_bb_add_aperture: aperture set full (%d)", b->max_ap);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(bb_add_kernel, dim3(1), dim3(256), 0, s, b->dev, b->m, cp, b->geom.n_rows, dL, dR, lo, hi, y0);
+    dvmat_status st = check_hip(hipGetLastError(), "dvmat_bb_add_aperture launch");
+    if (st) return st;
+    b->occupied[cp] = 1;
+    b->m++;
+    return DVMAT_OK;
+}
+
+dvmat_status dvmat_bb_begin(dvmat_bb b, dvmat_stream stream) {
+    if (!b) return set_error(DVMAT_E_ARG, "dvmat_bb_begin: NULL handle");
+    hipLaunchKernelGGL(bb_begin_kernel, dim3(1), dim3(64), 0, reinterpret_cast<hipStream_t>(stream), b->dev);
+    return check_hip(hipGetLastError(), "dvmat_bb_begin launch");
+}
+
+dvmat_status dvmat_bb_direction(dvmat_bb b, const float* p, float* x_dir, dvmat_stream stream) {
+    if (!b || !p || !x_dir) return set_error(DVMAT_E_ARG, "dvmat_bb_direction: NULL argument");
+    if (b->m == 0) return set_error(DVMAT_E_STATE, "dvmat_bb_direction: no apertures");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const dvmat_geom& g = b->geom;
+    const int64_t n_bl = (int64_t)g.n_cp * g.n_rows * g.n_cols;
+    hipLaunchKernelGGL(bb_gather_kernel, dim3(b->m), dim3(256), 0, s, b->dev, g.n_rows, g.n_cols, p);
+    hipLaunchKernelGGL(bb_update_kernel, dim3(1), dim3(256), 0, s, b->dev, b->m, (int)MODE_DIRECTION,
+                       (const float*)nullptr, (const double*)nullptr, (uint32_t*)nullptr, b->params);
+    hipLaunchKernelGGL(bb_expand_kernel, dim3(grid_for(n_bl)), dim3(256), 0, s, b->dev, g.n_rows, g.n_cols, n_bl,
+                       (const float*)b->dev.Gt, x_dir);
+    return check_hip(hipGetLastError(), "dvmat_bb_direction launch");
+}
+
+dvmat_status dvmat_bb_step(dvmat_bb b, const float* p, const float* F, const double* curv, float* x_next,
+                           uint32_t* flags, dvmat_stream stream) {
+    if (!b || !p || !F || !x_next) return set_error(DVMAT_E_ARG, "dvmat_bb_step: NULL argument");
+    if (b->m == 0) return set_error(DVMAT_E_STATE, "dvmat_bb_step: no apertures");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const dvmat_geom& g = b->geom;
+    const int64_t n_bl = (int64_t)g.n_cp * g.n_rows * g.n_cols;
+    hipLaunchKernelGGL(bb_gather_kernel, dim3(b->m), dim3(256), 0, s, b->dev, g.n_rows, g.n_cols, p);
+    hipLaunchKernelGGL(bb_update_kernel, dim3(1), dim3(256), 0, s, b->dev, b->m, (int)MODE_STEP, F, curv, flags,
+                       b->params);
+    hipLaunchKernelGGL(bb_expand_kernel, dim3(grid_for(n_bl)), dim3(256), 0, s, b->dev, g.n_rows, g.n_cols, n_bl,
+                       (const float*)b->dev.y, x_next);
+    return check_hip(hipGetLastError(), "dvmat_bb_step launch");
+}
+
+dvmat_status dvmat_bb_expand(dvmat_bb b, float* x, dvmat_stream stream) {
+    if (!b || !x) return set_error(DVMAT_E_ARG, "dvmat_bb_expand: NULL argument");
+    const dvmat_geom& g = b->geom;
+    const int64_t n_bl = (int64_t)g.n_cp * g.n_rows * g.n_cols;
+    hipLaunchKernelGGL(bb_expand_kernel, dim3(grid_for(n_bl)), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
+                       b->dev, g.n_rows, g.n_cols, n_bl, (const float*)b->dev.y, x);
+    return check_hip(hipGetLastError(), "dvmat_bb_expand launch");
+}
+
+dvmat_status dvmat_bb_get_y(dvmat_bb b, float* y, dvmat_stream stream) {
+    if (!b || !y) return set_error(DVMAT_E_ARG, "dvmat_bb_get_y: NULL argument");
+    if (b->m == 0) return DVMAT_OK;
+    hipLaunchKernelGGL(bb_copy_y_kernel, dim3(1), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), b->dev, b->m, y);
+    return check_hip(hipGetLastError(), "dvmat_bb_get_y launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// Internal definitions shared by the libdvmat translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/dvmat.h"
+
+namespace dvmat {
+
+// Row padding of both CSR orientations (entries); rows start 16-byte aligned.
+constexpr int kRowPad = 4;
+// Device sub-buffer alignment inside caller workspaces.
+constexpr size_t kAlign = 256;
+// Workgroups of the SpMV launches are a multiple of the XCD count so that the
+// hardware's round-robin workgroup -> XCD dispatch gives each XCD an equal
+// share; each XCD then walks a contiguous range of row blocks.
+constexpr int kNumXcd = 8;
+constexpr int kWaveSize = 64;
+constexpr int kSpmvThreads = 256;                 // 4 waves per workgroup
+constexpr int kMaxSpmvWorkgroups = 8192;          // partial-sum slots in the objective workspace
+constexpr int kMaxRhs = 8;
+
+dvmat_status set_error(dvmat_status code, const char* fmt, ...);
+dvmat_status check_hip(hipError_t e, const char* what);
+
+inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+
+// One CSR orientation inside the device workspace.
+struct CsrDev {
+    int64_t n_rows = 0;
+    int64_t nnz_pad = 0;
+    int64_t n_blocks = 0;
+    int64_t nonempty = 0;
+    const int64_t* rowptr = nullptr;   // [n_rows + 1]
+    const int32_t* col = nullptr;      // [nnz_pad]
+    const void* val = nullptr;         // [nnz_pad] of value_bytes
+    const int32_t* blocks = nullptr;   // [n_blocks + 1] first row of each block
+};
+
+// Host staging of one orientation before bind.
+struct CsrHost {
+    int64_t n_rows = 0;
+    std::vector<int64_t> rowptr;
+    std::vector<int32_t> col;
+    std::vector<uint8_t> val;          // value_bytes per entry
+    std::vector<int32_t> blocks;
+    int64_t nonempty = 0;
+};
+
+}  // namespace dvmat
+
+struct dvmat_ddc_s {
+    int64_t n_vox = 0, n_bl = 0, nnz = 0;
+    int32_t storage = DVMAT_F32;
+    int32_t value_bytes = 4;
+    bool bound = false;
+    dvmat::CsrHost host_dose, host_price;
+    std::vector<float> host_scale;     // per-beamlet scale (16-bit storage)
+    dvmat::CsrDev dose, price;
+    const float* scale = nullptr;      // device [n_bl] (16-bit storage)
+    float* xs = nullptr;               // device [n_bl * kMaxRhs] scaled-x scratch (16-bit)
+    size_t ws_bytes = 0;
+    // workspace layout offsets
+    size_t off_dose_rowptr = 0, off_dose_col = 0, off_dose_val = 0, off_dose_blocks = 0;
+    size_t off_price_rowptr = 0, off_price_col = 0, off_price_val = 0, off_price_blocks = 0;
+    size_t off_scale = 0, off_xs = 0;
+};
+
+struct dvmat_obj_s {
+    int64_t n_vox = 0;
+    int32_t n_struct = 0;
+    const uint8_t* sid = nullptr;      // device [n_vox]
+    float* table = nullptr;            // device [256][4] (T, w+, w-, 0)
+    float* partial = nullptr;          // device [kMaxSpmvWorkgroups * kMaxRhs]
+    double* partial_d = nullptr;       // device [kMaxSpmvWorkgroups]
+};
+
+// Launch helpers implemented in spmv.hip, used by other units.
+namespace dvmat {
+dvmat_status launch_expand_scale(const dvmat_ddc_s* d, const float* x, int nrhs, hipStream_t s);
+}

@@ -1,0 +1,424 @@
+// Host side of the DDC handle: COO validation, the two CSR orientations
+// (counting sort by row, stable, multi-threaded), duplicate merging, row
+// padding, row blocks, 16-bit quantisation, and the upload into the caller's
+// device workspace.
+//
+// The paper converts each angle-group sub-matrix D_m to CSR of D_m^T at
+// initialisation (Sec. 2.2.2); here one GPU holds all of D, so both CSR(D)
+// and CSR(D^T) are built once from the host COO.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <thread>
+
+#include "common.hpp"
+
+namespace dvmat {
+
+static thread_local std::string g_last_error = "";
+
+dvmat_status set_error(dvmat_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+dvmat_status check_hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return DVMAT_OK;
+    return set_error(DVMAT_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+static int host_threads() {
+    int n = (int)std::thread::hardware_concurrency();
+    if (const char* s = std::getenv("DVMAT_HOST_THREADS")) n = std::atoi(s);
+    else if (const char* s2 = std::getenv("OMP_NUM_THREADS")) n = std::min(n, std::atoi(s2));
+    return std::max(1, std::min(n, 64));
+}
+
+template <class F>
+static void parallel_for(int64_t n, F&& f) {
+    int T = host_threads();
+    if (n < 1 << 16) T = 1;
+    T = (int)std::min<int64_t>(T, std::max<int64_t>(1, n));
+    std::vector<std::thread> th;
+    for (int t = 0; t < T; ++t) {
+        int64_t a = n * t / T, b = n * (t + 1) / T;
+        th.emplace_back([&, a, b, t] { f(a, b, t); });
+    }
+    for (auto& x : th) x.join();
+}
+
+static int64_t block_nnz_cap() {
+    if (const char* s = std::getenv("DVMAT_BLOCK_NNZ")) return std::max<int64_t>(kRowPad, std::atoll(s));
+    return 2048;
+}
+static int32_t block_row_cap() {
+    if (const char* s = std::getenv("DVMAT_BLOCK_ROWS")) return std::max(1, std::atoi(s));
+    return 64;
+}
+
+// IEEE binary16, round to nearest even (finite inputs; overflow -> inf).
+static uint16_t float_to_half_bits(float f) {
+    _Float16 h = (_Float16)f;
+    uint16_t b;
+    std::memcpy(&b, &h, 2);
+    return b;
+}
+// bfloat16, round to nearest even (finite inputs).
+static uint16_t float_to_bf16_bits(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7FFFu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+// Build one CSR orientation from COO keys (rk = row of this orientation,
+// ck = column).  Row padding to kRowPad, duplicates summed, columns sorted.
+static dvmat_status build_orientation(int64_t n_rows, int64_t nnz, const int32_t* rk,
+                                      const int32_t* ck, const float* v, CsrHost& out,
+                                      std::vector<float>& fval, std::vector<int64_t>& len_u) {
+    const int T = std::max(1, (int)std::min<int64_t>(host_threads(), nnz >= (1 << 16) ? 1 << 30 : 1));
+    try {
+        // per-thread histograms over contiguous entry chunks (stable scatter order)
+        std::vector<std::vector<int64_t>> hist(T, std::vector<int64_t>());
+        std::vector<std::thread> th;
+        for (int t = 0; t < T; ++t) {
+            th.emplace_back([&, t] {
+                hist[t].assign(n_rows, 0);
+                int64_t a = nnz * t / T, b = nnz * (t + 1) / T;
+                int64_t* h = hist[t].data();
+                for (int64_t k = a; k < b; ++k) h[rk[k]]++;
+            });
+        }
+        for (auto& x : th) x.join();
+        th.clear();
+        out.n_rows = n_rows;
+        out.rowptr.assign(n_rows + 1, 0);
+        std::vector<int64_t> len(n_rows, 0);
+        parallel_for(n_rows, [&](int64_t a, int64_t b, int) {
+            for (int64_t r = a; r < b; ++r) {
+                int64_t s = 0;
+                for (int t = 0; t < T; ++t) s += hist[t][r];
+                len[r] = s;
+            }
+        });
+        for (int64_t r = 0; r < n_rows; ++r)
+            out.rowptr[r + 1] = out.rowptr[r] + (len[r] + kRowPad - 1) / kRowPad * kRowPad;
+        const int64_t nnz_pad = out.rowptr[n_rows];
+        // thread-row start offsets, in place of the histograms
+        parallel_for(n_rows, [&](int64_t a, int64_t b, int) {
+            for (int64_t r = a; r < b; ++r) {
+                int64_t pos = out.rowptr[r];
+                for (int t = 0; t < T; ++t) {
+                    int64_t c = hist[t][r];
+                    hist[t][r] = pos;
+                    pos += c;
+                }
+            }
+        });
+        out.col.assign(nnz_pad, 0);
+        fval.assign(nnz_pad, 0.0f);
+        for (int t = 0; t < T; ++t) {
+            th.emplace_back([&, t] {
+                int64_t a = nnz * t / T, b = nnz * (t + 1) / T;
+                int64_t* h = hist[t].data();
+                for (int64_t k = a; k < b; ++k) {
+                    int64_t p = h[rk[k]]++;
+                    out.col[p] = ck[k];
+                    fval[p] = v[k];
+                }
+            });
+        }
+        for (auto& x : th) x.join();
+        th.clear();
+        hist.clear();
+        hist.shrink_to_fit();
+        // sort rows whose columns are out of order, merge duplicates, pad
+        len_u.assign(n_rows, 0);
+        parallel_for(n_rows, [&](int64_t a, int64_t b, int) {
+            std::vector<int64_t> perm;
+            std::vector<int32_t> tc;
+            std::vector<float> tv;
+            for (int64_t r = a; r < b; ++r) {
+                const int64_t s = out.rowptr[r], n = len[r];
+                int32_t* c = out.col.data() + s;
+                float* fv = fval.data() + s;
+                bool ok = true;
+                for (int64_t k = 1; k < n; ++k)
+                    if (c[k] <= c[k - 1]) { ok = false; break; }
+                int64_t m = n;
+                if (!ok) {
+                    perm.resize(n);
+                    std::iota(perm.begin(), perm.end(), 0);
+                    std::stable_sort(perm.begin(), perm.end(),
+                                     [&](int64_t x, int64_t y) { return c[x] < c[y]; });
+                    tc.resize(n);
+                    tv.resize(n);
+                    m = 0;
+                    for (int64_t k = 0; k < n; ++k) {
+                        int32_t cc = c[perm[k]];
+                        float vv = fv[perm[k]];
+                        if (m > 0 && tc[m - 1] == cc) tv[m - 1] += vv;
+                        else { tc[m] = cc; tv[m] = vv; ++m; }
+                    }
+                    std::copy(tc.begin(), tc.begin() + m, c);
+                    std::copy(tv.begin(), tv.begin() + m, fv);
+                }
+                len_u[r] = m;
+                const int64_t e = out.rowptr[r + 1];
+                const int32_t last = m > 0 ? c[m - 1] : 0;
+                for (int64_t k = s + m; k < e; ++k) { out.col[k] = last; fval[k] = 0.0f; }
+            }
+        });
+        // row blocks: consecutive rows up to a stored-entry budget and a row
+        // budget; a row longer than the budget forms a block of its own
+        const int64_t cap = block_nnz_cap();
+        const int32_t rcap = block_row_cap();
+        out.blocks.clear();
+        out.blocks.push_back(0);
+        int64_t acc = 0;
+        int32_t rows_in = 0;
+        out.nonempty = 0;
+        for (int64_t r = 0; r < n_rows; ++r) {
+            const int64_t lp = out.rowptr[r + 1] - out.rowptr[r];
+            if (len_u[r] > 0) out.nonempty++;
+            if (rows_in > 0 && (acc + lp > cap || rows_in >= rcap)) {
+                out.blocks.push_back((int32_t)r);
+                acc = 0;
+                rows_in = 0;
+            }
+            acc += lp;
+            rows_in++;
+        }
+        out.blocks.push_back((int32_t)n_rows);
+    } catch (const std::bad_alloc&) {
+        return set_error(DVMAT_E_NOMEM, "host allocation failed while building CSR (%lld rows, %lld nnz)",
+                         (long long)n_rows, (long long)nnz);
+    }
+    return DVMAT_OK;
+}
+
+// Store the float values of one orientation in the requested storage type.
+// beamlet_of_entry(k) gives the beamlet of stored entry k (for the scale).
+template <class BeamletOf>
+static void encode_values(CsrHost& h, const std::vector<float>& fval, int32_t storage,
+                          const std::vector<float>& scale, BeamletOf beamlet_of) {
+    const int64_t n = (int64_t)fval.size();
+    if (storage == DVMAT_F32) {
+        h.val.resize(n * 4);
+        std::memcpy(h.val.data(), fval.data(), n * 4);
+        return;
+    }
+    h.val.resize(n * 2);
+    uint16_t* q = reinterpret_cast<uint16_t*>(h.val.data());
+    parallel_for(h.n_rows, [&](int64_t a, int64_t b, int) {
+        for (int64_t r = a; r < b; ++r)
+            for (int64_t k = h.rowptr[r]; k < h.rowptr[r + 1]; ++k) {
+                const float s = scale[beamlet_of(r, k)];
+                const float x = fval[k] / s;
+                q[k] = storage == DVMAT_F16 ? float_to_half_bits(x) : float_to_bf16_bits(x);
+            }
+    });
+}
+
+}  // namespace dvmat
+
+using namespace dvmat;
+
+extern "C" {
+
+const char* dvmat_last_error(void) { return dvmat::g_last_error.c_str(); }
+
+int32_t dvmat_version(void) { return 0x000100; }
+
+dvmat_status dvmat_ddc_create(int64_t n_vox, int64_t n_bl, int64_t nnz, const int32_t* row_vox,
+                              const int32_t* col_bl, const float* val, int32_t storage,
+                              dvmat_ddc* out) {
+    if (!out) return set_error(DVMAT_E_ARG, "dvmat_ddc_create: out is NULL");
+    *out = nullptr;
+    if (n_vox < 1 || n_vox >= (int64_t(1) << 31) || n_bl < 1 || n_bl >= (int64_t(1) << 31))
+        return set_error(DVMAT_E_ARG, "dvmat_ddc_create: n_vox=%lld n_bl=%lld must be in [1, 2^31)",
+                         (long long)n_vox, (long long)n_bl);
+    if (nnz < 0) return set_error(DVMAT_E_ARG, "dvmat_ddc_create: nnz=%lld < 0", (long long)nnz);
+    if (nnz > 0 && (!row_vox || !col_bl || !val))
+        return set_error(DVMAT_E_ARG, "dvmat_ddc_create: NULL COO array with nnz=%lld", (long long)nnz);
+    if (storage != DVMAT_F32 && storage != DVMAT_F16 && storage != DVMAT_BF16)
+        return set_error(DVMAT_E_ARG, "dvmat_ddc_create: unknown storage %d", storage);
+    // O(nnz) validation
+    std::atomic<int64_t> bad_idx(-1), bad_val(-1);
+    parallel_for(nnz, [&](int64_t a, int64_t b, int) {
+        for (int64_t k = a; k < b; ++k) {
+            if (row_vox[k] < 0 || row_vox[k] >= n_vox || col_bl[k] < 0 || col_bl[k] >= n_bl) {
+                int64_t e = -1;
+                bad_idx.compare_exchange_strong(e, k);
+                return;
+            }
+            if (!std::isfinite(val[k])) {
+                int64_t e = -1;
+                bad_val.compare_exchange_strong(e, k);
+                return;
+            }
+        }
+    });
+    if (bad_idx.load() >= 0) {
+        int64_t k = bad_idx.load();
+        return set_error(DVMAT_E_INDEX, "dvmat_ddc_create: entry %lld has (row %d, col %d) outside [0,%lld)x[0,%lld)",
+                         (long long)k, row_vox[k], col_bl[k], (long long)n_vox, (long long)n_bl);
+    }
+    if (bad_val.load() >= 0)
+        return set_error(DVMAT_E_ARG, "dvmat_ddc_create: entry %lld has a non-finite value",
+                         (long long)bad_val.load());
+
+    dvmat_ddc_s* d = new (std::nothrow) dvmat_ddc_s();
+    if (!d) return set_error(DVMAT_E_NOMEM, "dvmat_ddc_create: host allocation failed");
+    d->n_vox = n_vox;
+    d->n_bl = n_bl;
+    d->storage = storage;
+    d->value_bytes = storage == DVMAT_F32 ? 4 : 2;
+    std::vector<float> fval;
+    std::vector<int64_t> len_u;
+    // dose orientation: rows = voxels, columns = beamlets
+    dvmat_status st = build_orientation(n_vox, nnz, row_vox, col_bl, val, d->host_dose, fval, len_u);
+    if (st != DVMAT_OK) { delete d; return st; }
+    int64_t nnz_u = 0;
+    for (int64_t x : len_u) nnz_u += x;
+    d->nnz = nnz_u;
+    if (storage != DVMAT_F32) {
+        // per-beamlet scale s_j = max_i |D_ij| (1 for an empty beamlet)
+        const int T = host_threads();
+        std::vector<std::vector<float>> mx(T);
+        parallel_for(n_vox, [&](int64_t a, int64_t b, int t) {
+            std::vector<float>& m = mx[t];
+            m.assign(n_bl, 0.0f);
+            for (int64_t r = a; r < b; ++r)
+                for (int64_t k = d->host_dose.rowptr[r]; k < d->host_dose.rowptr[r + 1]; ++k)
+                    m[d->host_dose.col[k]] = std::max(m[d->host_dose.col[k]], std::fabs(fval[k]));
+        });
+        d->host_scale.assign(n_bl, 0.0f);
+        for (auto& m : mx)
+            if (!m.empty())
+                for (int64_t j = 0; j < n_bl; ++j) d->host_scale[j] = std::max(d->host_scale[j], m[j]);
+        for (auto& s : d->host_scale)
+            if (!(s > 0.0f)) s = 1.0f;
+        const auto& hc = d->host_dose.col;
+        encode_values(d->host_dose, fval, storage, d->host_scale,
+                      [&](int64_t, int64_t k) { return hc[k]; });
+    } else {
+        encode_values(d->host_dose, fval, storage, d->host_scale, [](int64_t, int64_t) { return 0; });
+    }
+    std::vector<float>().swap(fval);
+    // price orientation: rows = beamlets, columns = voxels
+    st = build_orientation(n_bl, nnz, col_bl, row_vox, val, d->host_price, fval, len_u);
+    if (st != DVMAT_OK) { delete d; return st; }
+    encode_values(d->host_price, fval, storage, d->host_scale,
+                  [](int64_t r, int64_t) { return r; });
+    std::vector<float>().swap(fval);
+
+    // device workspace layout
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+    const CsrHost& hd = d->host_dose;
+    const CsrHost& hp = d->host_price;
+    d->off_dose_rowptr = take(hd.rowptr.size() * 8);
+    d->off_dose_col = take(hd.col.size() * 4);
+    d->off_dose_val = take(hd.col.size() * d->value_bytes);
+    d->off_dose_blocks = take(hd.blocks.size() * 4);
+    d->off_price_rowptr = take(hp.rowptr.size() * 8);
+    d->off_price_col = take(hp.col.size() * 4);
+    d->off_price_val = take(hp.col.size() * d->value_bytes);
+    d->off_price_blocks = take(hp.blocks.size() * 4);
+    if (storage != DVMAT_F32) {
+        d->off_scale = take(n_bl * 4);
+        d->off_xs = take(n_bl * 4 * kMaxRhs);
+    }
+    d->ws_bytes = std::max<size_t>(off, kAlign);
+    d->dose.n_rows = n_vox;
+    d->dose.nnz_pad = (int64_t)hd.col.size();
+    d->dose.n_blocks = (int64_t)hd.blocks.size() - 1;
+    d->dose.nonempty = hd.nonempty;
+    d->price.n_rows = n_bl;
+    d->price.nnz_pad = (int64_t)hp.col.size();
+    d->price.n_blocks = (int64_t)hp.blocks.size() - 1;
+    d->price.nonempty = hp.nonempty;
+    *out = d;
+    return DVMAT_OK;
+}
+
+dvmat_status dvmat_ddc_info(dvmat_ddc d, dvmat_ddc_info_t* info) {
+    if (!d || !info) return set_error(DVMAT_E_ARG, "dvmat_ddc_info: NULL argument");
+    info->n_vox = d->n_vox;
+    info->n_bl = d->n_bl;
+    info->nnz = d->nnz;
+    info->nnz_pad_dose = d->dose.nnz_pad;
+    info->nnz_pad_price = d->price.nnz_pad;
+    info->n_blocks_dose = d->dose.n_blocks;
+    info->n_blocks_price = d->price.n_blocks;
+    info->nonempty_rows_dose = d->dose.nonempty;
+    info->nonempty_rows_price = d->price.nonempty;
+    info->storage = d->storage;
+    info->value_bytes = d->value_bytes;
+    info->workspace_bytes = d->ws_bytes;
+    return DVMAT_OK;
+}
+
+dvmat_status dvmat_ddc_bind(dvmat_ddc d, void* ws, size_t bytes, dvmat_stream stream) {
+    if (!d || !ws) return set_error(DVMAT_E_ARG, "dvmat_ddc_bind: NULL argument");
+    if (d->bound) return set_error(DVMAT_E_STATE, "dvmat_ddc_bind: handle already bound");
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign)
+        return set_error(DVMAT_E_ARG, "dvmat_ddc_bind: workspace not %zu-byte aligned", kAlign);
+    if (bytes < d->ws_bytes)
+        return set_error(DVMAT_E_NOMEM, "dvmat_ddc_bind: workspace %zu bytes < required %zu", bytes, d->ws_bytes);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(ws);
+    auto up = [&](size_t off, const void* src, size_t n) -> dvmat_status {
+        if (n == 0) return DVMAT_OK;
+        return check_hip(hipMemcpyAsync(base + off, src, n, hipMemcpyHostToDevice, s), "dvmat_ddc_bind: copy");
+    };
+    const CsrHost& hd = d->host_dose;
+    const CsrHost& hp = d->host_price;
+    dvmat_status st = DVMAT_OK;
+    if ((st = up(d->off_dose_rowptr, hd.rowptr.data(), hd.rowptr.size() * 8))) return st;
+    if ((st = up(d->off_dose_col, hd.col.data(), hd.col.size() * 4))) return st;
+    if ((st = up(d->off_dose_val, hd.val.data(), hd.val.size()))) return st;
+    if ((st = up(d->off_dose_blocks, hd.blocks.data(), hd.blocks.size() * 4))) return st;
+    if ((st = up(d->off_price_rowptr, hp.rowptr.data(), hp.rowptr.size() * 8))) return st;
+    if ((st = up(d->off_price_col, hp.col.data(), hp.col.size() * 4))) return st;
+    if ((st = up(d->off_price_val, hp.val.data(), hp.val.size()))) return st;
+    if ((st = up(d->off_price_blocks, hp.blocks.data(), hp.blocks.size() * 4))) return st;
+    if (d->storage != DVMAT_F32)
+        if ((st = up(d->off_scale, d->host_scale.data(), d->host_scale.size() * 4))) return st;
+    if ((st = check_hip(hipStreamSynchronize(s), "dvmat_ddc_bind: synchronize"))) return st;
+    d->dose.rowptr = reinterpret_cast<const int64_t*>(base + d->off_dose_rowptr);
+    d->dose.col = reinterpret_cast<const int32_t*>(base + d->off_dose_col);
+    d->dose.val = base + d->off_dose_val;
+    d->dose.blocks = reinterpret_cast<const int32_t*>(base + d->off_dose_blocks);
+    d->price.rowptr = reinterpret_cast<const int64_t*>(base + d->off_price_rowptr);
+    d->price.col = reinterpret_cast<const int32_t*>(base + d->off_price_col);
+    d->price.val = base + d->off_price_val;
+    d->price.blocks = reinterpret_cast<const int32_t*>(base + d->off_price_blocks);
+    if (d->storage != DVMAT_F32) {
+        d->scale = reinterpret_cast<const float*>(base + d->off_scale);
+        d->xs = reinterpret_cast<float*>(base + d->off_xs);
+    }
+    // release the host staging
+    d->host_dose = CsrHost();
+    d->host_price = CsrHost();
+    d->bound = true;
+    return DVMAT_OK;
+}
+
+void dvmat_ddc_destroy(dvmat_ddc d) { delete d; }
+
+}  // extern "C"

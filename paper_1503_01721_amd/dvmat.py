@@ -1,0 +1,372 @@
+"""ctypes binding of libdvmat (argument marshalling only).
+
+Every step of the path runs in the HIP library; this module converts torch
+tensors to device pointers, owns the device workspaces the library asks for,
+and passes torch's current HIP stream.  If the library is not built the
+import fails: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "lib", "libdvmat.so")
+
+F32, F16, BF16 = 0, 1, 2
+STORAGE = {"f32": F32, "f16": F16, "bf16": BF16}
+
+BB_REL_F, BB_SMALL_STEP, BB_MAX_ITER, BB_FALLBACK, BB_CONVERGED, BB_NONFINITE = 1, 2, 4, 8, 16, 32
+BB_STOP_MASK = BB_REL_F | BB_SMALL_STEP | BB_MAX_ITER | BB_CONVERGED | BB_NONFINITE
+
+E_NAMES = {-1: "DVMAT_E_ARG", -2: "DVMAT_E_SHAPE", -3: "DVMAT_E_INDEX", -4: "DVMAT_E_NOMEM",
+           -5: "DVMAT_E_HIP", -6: "DVMAT_E_STATE"}
+
+
+class DvmatError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{E_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class DdcInfo(ctypes.Structure):
+    _fields_ = [("n_vox", ctypes.c_int64), ("n_bl", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("nnz_pad_dose", ctypes.c_int64), ("nnz_pad_price", ctypes.c_int64),
+                ("n_blocks_dose", ctypes.c_int64), ("n_blocks_price", ctypes.c_int64),
+                ("nonempty_rows_dose", ctypes.c_int64), ("nonempty_rows_price", ctypes.c_int64),
+                ("storage", ctypes.c_int32), ("value_bytes", ctypes.c_int32),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("n_cp", ctypes.c_int32), ("n_rows", ctypes.c_int32), ("n_cols", ctypes.c_int32)]
+
+
+class BBParams(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("eps_f", ctypes.c_float), ("eps_step", ctypes.c_float)]
+
+
+_P = ctypes.c_void_p
+_I32, _I64, _SZ, _F = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_float
+
+# name -> (restype, argtypes); must match include/dvmat.h
+_SIGNATURES = {
+    "dvmat_last_error": (ctypes.c_char_p, []),
+    "dvmat_version": (_I32, []),
+    "dvmat_ddc_create": (_I32, [_I64, _I64, _I64, _P, _P, _P, _I32, ctypes.POINTER(_P)]),
+    "dvmat_ddc_info": (_I32, [_P, ctypes.POINTER(DdcInfo)]),
+    "dvmat_ddc_bind": (_I32, [_P, _P, _SZ, _P]),
+    "dvmat_ddc_destroy": (None, [_P]),
+    "dvmat_obj_workspace_size": (_I32, [_I32, ctypes.POINTER(_SZ)]),
+    "dvmat_obj_create": (_I32, [_I64, _I32, _P, _P, _P, _SZ, _P, ctypes.POINTER(_P)]),
+    "dvmat_obj_destroy": (None, [_P]),
+    "dvmat_objective": (_I32, [_P, _P, _I32, _P, _P, _P]),
+    "dvmat_dose": (_I32, [_P, _P, _I32, _P, _P, _P, _P, _P]),
+    "dvmat_price": (_I32, [_P, _P, _I32, _P, _P]),
+    "dvmat_dose_curvature": (_I32, [_P, _P, _P, _P, _P, _P, _P]),
+    "dvmat_aperture_select": (_I32, [Geom, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "dvmat_bb_workspace_size": (_I32, [Geom, _I32, ctypes.POINTER(_SZ)]),
+    "dvmat_bb_create": (_I32, [Geom, _I32, BBParams, _P, _SZ, _P, ctypes.POINTER(_P)]),
+    "dvmat_bb_destroy": (None, [_P]),
+    "dvmat_bb_count": (_I32, [_P]),
+    "dvmat_bb_occupancy": (_I32, [_P, ctypes.POINTER(_P)]),
+    "dvmat_bb_add_aperture": (_I32, [_P, _I32, _P, _P, _F, _F, _F, _P]),
+    "dvmat_bb_begin": (_I32, [_P, _P]),
+    "dvmat_bb_direction": (_I32, [_P, _P, _P, _P]),
+    "dvmat_bb_step": (_I32, [_P, _P, _P, _P, _P, _P, _P]),
+    "dvmat_bb_expand": (_I32, [_P, _P, _P]),
+    "dvmat_bb_get_y": (_I32, [_P, _P, _P]),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libdvmat is not built ({LIB_PATH} missing); run __graft_entry__.build() "
+                          "or python -m paper_1503_01721_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(code):
+    if code != 0:
+        raise DvmatError(code, lib.dvmat_last_error().decode(errors="replace"))
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, numel, dtype=torch.float32, name="tensor", at_least=False):
+    """Shape/dtype guard: raw pointers cross the ABI, so sizes are checked here."""
+    if t is None:
+        return
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if (t.numel() < numel) if at_least else (t.numel() != numel):
+        raise ValueError(f"{name}: {t.numel()} elements, expected {'>= ' if at_least else ''}{numel}")
+
+
+def _nrhs(t, n, name):
+    nrhs = 1 if t.dim() == 1 else t.shape[1]
+    if t.dim() > 2 or t.shape[0] != n or not 1 <= nrhs <= 8:
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, expected [{n}] or [{n}, nrhs<=8]")
+    return nrhs
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    ws = torch.empty(max(int(nbytes), 256) + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + max(int(nbytes), 256)]
+
+
+class DDC:
+    """DDC matrix in both CSR orientations, resident in one GPU's memory."""
+
+    def __init__(self, row, col, val, n_vox: int, n_bl: int, storage: str = "f32", device="cuda"):
+        row = np.ascontiguousarray(row, dtype=np.int32)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float32)
+        if not (len(row) == len(col) == len(val)):
+            raise ValueError("COO arrays differ in length")
+        self.n_vox, self.n_bl = int(n_vox), int(n_bl)
+        self.storage = storage
+        h = _P()
+        _check(lib.dvmat_ddc_create(self.n_vox, self.n_bl, len(val),
+                                    row.ctypes.data_as(_P) if len(val) else None,
+                                    col.ctypes.data_as(_P) if len(val) else None,
+                                    val.ctypes.data_as(_P) if len(val) else None,
+                                    STORAGE[storage], ctypes.byref(h)))
+        self._h = h
+        info = DdcInfo()
+        _check(lib.dvmat_ddc_info(h, ctypes.byref(info)))
+        self.info = info
+        self.device = torch.device(device)
+        self.workspace = _workspace(info.workspace_bytes, self.device)
+        _check(lib.dvmat_ddc_bind(h, _ptr(self.workspace), self.workspace.numel(), _stream()))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib.dvmat_ddc_destroy(h)
+            self._h = None
+
+    # -- products -----------------------------------------------------------
+    def dose_(self, x, z, obj=None, g=None, F=None, stream=None):
+        nrhs = _nrhs(x, self.n_bl, "x")
+        _need(x, self.n_bl * nrhs, name="x")
+        _need(z, self.n_vox * nrhs, name="z")
+        _need(g, self.n_vox * nrhs, name="g")
+        _need(F, nrhs, name="F", at_least=True)
+        if obj is not None and obj.n_vox != self.n_vox:
+            raise ValueError("objective and matrix differ in voxel count")
+        _check(lib.dvmat_dose(self._h, _ptr(x), nrhs, _ptr(z), obj.handle if obj is not None else None,
+                              _ptr(g), _ptr(F), _stream(stream)))
+
+    def price_(self, g, p, stream=None):
+        nrhs = _nrhs(g, self.n_vox, "g")
+        _need(g, self.n_vox * nrhs, name="g")
+        _need(p, self.n_bl * nrhs, name="p")
+        _check(lib.dvmat_price(self._h, _ptr(g), nrhs, _ptr(p), _stream(stream)))
+
+    def dose(self, x, obj=None, with_grad=False):
+        """z = D x (x: [n_bl] or [n_bl, nrhs] float32 on the device).
+
+        With obj: returns (z, g = dF/dz or None, F[nrhs])."""
+        shape = (self.n_vox,) if x.dim() == 1 else (self.n_vox, x.shape[1])
+        z = torch.empty(shape, dtype=torch.float32, device=x.device)
+        if obj is None:
+            self.dose_(x, z)
+            return z
+        nrhs = 1 if x.dim() == 1 else x.shape[1]
+        g = torch.empty_like(z) if with_grad else None
+        F = torch.empty(nrhs, dtype=torch.float32, device=x.device)
+        self.dose_(x, z, obj, g, F)
+        return z, g, F
+
+    def price(self, g):
+        """p = D^T g (g: [n_vox] or [n_vox, nrhs] float32 on the device)."""
+        shape = (self.n_bl,) if g.dim() == 1 else (self.n_bl, g.shape[1])
+        p = torch.empty(shape, dtype=torch.float32, device=g.device)
+        self.price_(g, p)
+        return p
+
+    def curvature_(self, x_dir, obj, z_ref, curv, d_out=None, stream=None):
+        _need(x_dir, self.n_bl, name="x_dir")
+        _need(z_ref, self.n_vox, name="z_ref")
+        _need(curv, 1, torch.float64, name="curv", at_least=True)
+        _need(d_out, self.n_vox, name="d_out")
+        if obj.n_vox != self.n_vox:
+            raise ValueError("objective and matrix differ in voxel count")
+        _check(lib.dvmat_dose_curvature(self._h, _ptr(x_dir), obj.handle, _ptr(z_ref), _ptr(d_out),
+                                        _ptr(curv), _stream(stream)))
+
+
+class Objective:
+    """Per-voxel structure ids (device uint8) and the (T, w+, w-) table."""
+
+    def __init__(self, struct_id, table, device="cuda"):
+        table = np.ascontiguousarray(table, dtype=np.float32)
+        if table.ndim != 2 or table.shape[1] != 3:
+            raise ValueError("table must be [n_struct, 3]")
+        self.device = torch.device(device)
+        if isinstance(struct_id, np.ndarray):
+            if len(struct_id) and int(struct_id.max()) >= table.shape[0]:
+                raise ValueError("structure id beyond the table")
+            struct_id = torch.from_numpy(np.ascontiguousarray(struct_id, dtype=np.uint8)).to(self.device)
+        self.sid = struct_id.contiguous()
+        self.n_vox = self.sid.numel()
+        self.table = table
+        nbytes = _SZ()
+        _check(lib.dvmat_obj_workspace_size(table.shape[0], ctypes.byref(nbytes)))
+        self.workspace = _workspace(nbytes.value, self.device)
+        h = _P()
+        _check(lib.dvmat_obj_create(self.n_vox, table.shape[0], _ptr(self.sid), table.ctypes.data_as(_P),
+                                    _ptr(self.workspace), self.workspace.numel(), _stream(), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib.dvmat_obj_destroy(h)
+            self._h = None
+
+    def __call__(self, z, with_grad=True):
+        """(F[nrhs], g = dF/dz) of an external dose z."""
+        nrhs = _nrhs(z, self.n_vox, "z")
+        _need(z, self.n_vox * nrhs, name="z")
+        g = torch.empty_like(z) if with_grad else None
+        F = torch.empty(nrhs, dtype=torch.float32, device=z.device)
+        _check(lib.dvmat_objective(self._h, _ptr(z), nrhs, _ptr(g), _ptr(F), _stream()))
+        return F, g
+
+
+class ApertureSelector:
+    """Row-wise aperture selection over control points (preallocated outputs)."""
+
+    def __init__(self, n_cp, n_rows, n_cols, device="cuda"):
+        self.geom = Geom(n_cp, n_rows, n_cols)
+        dev = torch.device(device)
+        self.L = torch.empty((n_cp, n_rows), dtype=torch.int32, device=dev)
+        self.R = torch.empty((n_cp, n_rows), dtype=torch.int32, device=dev)
+        self.cp_price = torch.empty(n_cp, dtype=torch.float32, device=dev)
+        self.best = torch.empty(1, dtype=torch.int32, device=dev)
+        self.best_price = torch.empty(1, dtype=torch.float32, device=dev)
+
+    def __call__(self, p, occupied=None, stream=None):
+        g = self.geom
+        _need(p, g.n_cp * g.n_rows * g.n_cols, name="p")
+        if not isinstance(occupied, ctypes.c_void_p):
+            _need(occupied, g.n_cp, torch.uint8, name="occupied")
+        occ = occupied if isinstance(occupied, ctypes.c_void_p) else _ptr(occupied)
+        _check(lib.dvmat_aperture_select(self.geom, _ptr(p), occ, _ptr(self.L), _ptr(self.R),
+                                         _ptr(self.cp_price), _ptr(self.best), _ptr(self.best_price),
+                                         _stream(stream)))
+        return self
+
+
+def aperture_select(p, n_cp, n_rows, n_cols, occupied=None):
+    sel = ApertureSelector(n_cp, n_rows, n_cols, device=p.device)
+    sel(p, occupied)
+    return dict(L=sel.L, R=sel.R, cp_price=sel.cp_price, best=sel.best, best_price=sel.best_price)
+
+
+class BB:
+    """Device-resident master-problem state (aperture set, rates, BB history)."""
+
+    def __init__(self, n_cp, n_rows, n_cols, max_apertures, max_iter=50, eps_f=1e-5, eps_step=1e-7, device="cuda"):
+        self.geom = Geom(n_cp, n_rows, n_cols)
+        self.n_bl = n_cp * n_rows * n_cols
+        self.params = BBParams(max_iter, eps_f, eps_step)
+        nbytes = _SZ()
+        _check(lib.dvmat_bb_workspace_size(self.geom, max_apertures, ctypes.byref(nbytes)))
+        self.device = torch.device(device)
+        self.workspace = _workspace(nbytes.value, self.device)
+        h = _P()
+        _check(lib.dvmat_bb_create(self.geom, max_apertures, self.params, _ptr(self.workspace),
+                                   self.workspace.numel(), _stream(), ctypes.byref(h)))
+        self._h = h
+        self.flags = torch.zeros(1, dtype=torch.int32, device=self.device)
+
+    @property
+    def count(self):
+        return lib.dvmat_bb_count(self._h)
+
+    @property
+    def occupied_ptr(self):
+        """Device pointer of the control-point occupancy bytes (for aperture selection)."""
+        out = _P()
+        _check(lib.dvmat_bb_occupancy(self._h, ctypes.byref(out)))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib.dvmat_bb_destroy(h)
+            self._h = None
+
+    def add_aperture(self, cp, L_row, R_row, lo=0.0, hi=float("inf"), y0=None, stream=None):
+        y0 = lo if y0 is None else y0
+        _need(L_row, self.geom.n_rows, torch.int32, name="L")
+        _need(R_row, self.geom.n_rows, torch.int32, name="R")
+        _check(lib.dvmat_bb_add_aperture(self._h, int(cp), _ptr(L_row), _ptr(R_row), float(lo), float(hi),
+                                         float(y0), _stream(stream)))
+
+    def begin(self, stream=None):
+        _check(lib.dvmat_bb_begin(self._h, _stream(stream)))
+
+    def direction_(self, p, x_dir, stream=None):
+        _need(p, self.n_bl, name="p")
+        _need(x_dir, self.n_bl, name="x_dir")
+        _check(lib.dvmat_bb_direction(self._h, _ptr(p), _ptr(x_dir), _stream(stream)))
+
+    def step_(self, p, F, curv, x_next, stream=None):
+        _need(p, self.n_bl, name="p")
+        _need(F, 1, name="F", at_least=True)
+        _need(curv, 1, torch.float64, name="curv", at_least=True)
+        _need(x_next, self.n_bl, name="x_next")
+        _check(lib.dvmat_bb_step(self._h, _ptr(p), _ptr(F), _ptr(curv), _ptr(x_next), _ptr(self.flags),
+                                 _stream(stream)))
+
+    def expand_(self, x, stream=None):
+        _need(x, self.n_bl, name="x")
+        _check(lib.dvmat_bb_expand(self._h, _ptr(x), _stream(stream)))
+
+    def y(self):
+        out = torch.empty(max(self.count, 1), dtype=torch.float32, device=self.device)
+        _check(lib.dvmat_bb_get_y(self._h, _ptr(out), _stream()))
+        return out[:self.count]
+
+
+def exported_symbols():
+    """Names this binding binds (all entry points of include/dvmat.h)."""
+    return sorted(_SIGNATURES)

@@ -40,6 +40,8 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from typing import Dict, List, Optional, Tuple
 
 import numpy as np
@@ -178,13 +180,28 @@ def generate_cp(plan: Plan, a: int, xy=None):
     return (np.concatenate(rows_out), np.concatenate(cols_out), np.concatenate(vals_out))
 
 
-def generate_ddc(plan: Plan, cps: Optional[List[int]] = None):
+def _threads() -> int:
+    n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        n = min(n, int(env))
+    return max(1, min(n, 16))
+
+
+def generate_ddc(plan: Plan, cps: Optional[List[int]] = None, threads: Optional[int] = None):
     """COO of D (voxels x beamlets), sorted by (beamlet, voxel); unique pairs.
 
+    Control points are generated on a thread pool (NumPy releases the GIL in
+    its array loops); the result does not depend on the thread count.
     Returns dict(row=int32[nnz] voxel, col=int32[nnz] beamlet, val=float32[nnz])."""
     xy = body_xy(plan)
-    cps = range(plan.n_cp) if cps is None else cps
-    parts = [generate_cp(plan, a, xy) for a in cps]
+    cps = list(range(plan.n_cp) if cps is None else cps)
+    nt = threads or _threads()
+    if nt > 1 and len(cps) > 1:
+        with ThreadPoolExecutor(nt) as ex:
+            parts = list(ex.map(lambda a: generate_cp(plan, a, xy), cps))
+    else:
+        parts = [generate_cp(plan, a, xy) for a in cps]
     nnz = sum(len(p[0]) for p in parts)
     row = np.empty(nnz, np.int32)
     col = np.empty(nnz, np.int32)

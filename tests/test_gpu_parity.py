@@ -1,0 +1,376 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (FP32 storage, FP32 accumulation):
+* dose: max|z_gpu - z_ref| <= 1e-5 * max|z_ref|  (D >= 0, x >= 0: every term is
+  non-negative, so this is the relative-to-max-dose bound);
+* price: max|p_gpu - p_ref| <= 1e-5 * max_j (D^T |g|)_j, the scale of the sum
+  of absolute terms (g has mixed signs, so a plain relative bound on p would
+  measure cancellation, not the kernel);
+* integer results (openings, chosen control point) are compared exactly where
+  the inputs make every candidate sum exact in both precisions.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import aperture as oap
+from oracle import bb as obb
+from oracle import colgen as ocg
+from oracle import objective as oobj
+from oracle import products as oprod
+from paper_1503_01721_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+PLAN1 = synth.PLANS["cp20_bl20x20_vox32"]
+SMALL = synth.PLANS["small_cp8_bl6x6_vox16"]
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def dv():
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    from paper_1503_01721_amd import dvmat
+    return dvmat
+
+
+@pytest.fixture(scope="module")
+def plan1(dv):
+    d = synth.generate_ddc(PLAN1)
+    sid, table = synth.structures(PLAN1)
+    ddc = dv.DDC(d["row"], d["col"], d["val"], PLAN1.n_vox, PLAN1.n_bl)
+    obj = dv.Objective(sid, table)
+    return d, sid, table, ddc, obj
+
+
+def cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def price_scale(d, g, n_bl):
+    return np.abs(oprod.price(d["row"], d["col"], np.abs(d["val"]), np.abs(g), n_bl)).max(axis=0)
+
+
+# ---------------------------------------------------------------- products
+
+@pytest.mark.parametrize("nrhs", [1, 2, 3, 4, 8])
+def test_dose_and_price_plain_method_workload(dv, plan1, nrhs):
+    d, _, _, ddc, _ = plan1
+    x1, g1 = synth.bench_vectors(PLAN1.n_bl, PLAN1.n_vox, 1001 + nrhs)
+    rng = np.random.default_rng(nrhs)
+    x = x1 if nrhs == 1 else np.stack([x1] + [rng.random(PLAN1.n_bl, dtype=np.float32) for _ in range(nrhs - 1)], 1)
+    g = g1 if nrhs == 1 else np.stack([g1] + [rng.standard_normal(PLAN1.n_vox).astype(np.float32)
+                                              for _ in range(nrhs - 1)], 1)
+    z_ref = oprod.dose(d["row"], d["col"], d["val"], x, PLAN1.n_vox)
+    p_ref = oprod.price(d["row"], d["col"], d["val"], g, PLAN1.n_bl)
+    z = ddc.dose(cuda(x)).cpu().numpy()
+    p = ddc.price(cuda(g)).cpu().numpy()
+    assert np.abs(z - z_ref).max() <= TOL * np.abs(z_ref).max()
+    assert np.all(np.abs(p - p_ref).max(axis=0) <= TOL * price_scale(d, g, PLAN1.n_bl))
+
+
+def test_adjoint_identity_on_device(dv, plan1):
+    _, _, _, ddc, _ = plan1
+    x, g = synth.bench_vectors(PLAN1.n_bl, PLAN1.n_vox, 77)
+    z = ddc.dose(cuda(x)).double()
+    p = ddc.price(cuda(g)).double()
+    lhs = float((z * cuda(g).double()).sum())
+    rhs = float((cuda(x).double() * p).sum())
+    scale = float((z.abs() * cuda(g).double().abs()).sum())
+    assert abs(lhs - rhs) <= 1e-6 * scale
+
+
+def test_unstructured_ragged_matrix_with_empty_rows_and_duplicates(dv):
+    n_vox, n_bl = 3001, 517
+    d = synth.random_sparse(n_vox, n_bl, 0.02, 5, empty_rows=300, empty_cols=40)
+    # duplicates and a shuffled order exercise the builder's merge and sort
+    rng = np.random.default_rng(6)
+    dup = rng.choice(len(d["val"]), 500, replace=False)
+    row = np.concatenate([d["row"], d["row"][dup]])
+    col = np.concatenate([d["col"], d["col"][dup]])
+    val = np.concatenate([d["val"], rng.uniform(0.001, 1, 500).astype(np.float32)])
+    perm = rng.permutation(len(val))
+    row, col, val = row[perm], col[perm], val[perm]
+    ddc = dv.DDC(row, col, val, n_vox, n_bl)
+    assert ddc.info.nnz == len(d["val"])
+    x = rng.random(n_bl).astype(np.float32)
+    g = rng.standard_normal(n_vox).astype(np.float32)
+    z_ref = oprod.dose(row, col, val, x, n_vox)
+    p_ref = oprod.price(row, col, val, g, n_bl)
+    z = ddc.dose(cuda(x)).cpu().numpy()
+    p = ddc.price(cuda(g)).cpu().numpy()
+    assert np.abs(z - z_ref).max() <= TOL * np.abs(z_ref).max()
+    scale = oprod.price(row, col, np.abs(val), np.abs(g), n_bl).max()
+    assert np.abs(p - p_ref).max() <= TOL * scale
+    empty_rows = np.setdiff1d(np.arange(n_vox), row)
+    assert np.all(z[empty_rows] == 0.0)
+
+
+def test_long_rows_and_single_column(dv):
+    # rows much longer than one row block and a matrix with one beamlet
+    n_vox, n_bl = 64, 9000
+    rng = np.random.default_rng(8)
+    mask = rng.random((n_vox, n_bl)) < 0.6
+    r, c = np.nonzero(mask)
+    v = rng.uniform(0.001, 1, len(r)).astype(np.float32)
+    ddc = dv.DDC(r, c, v, n_vox, n_bl)
+    x = rng.random(n_bl).astype(np.float32)
+    z_ref = oprod.dose(r, c, v, x, n_vox)
+    assert np.abs(ddc.dose(cuda(x)).cpu().numpy() - z_ref).max() <= TOL * z_ref.max()
+    r1 = np.arange(0, 5000, 3, dtype=np.int32)
+    c1 = np.zeros_like(r1)
+    v1 = rng.uniform(0.001, 1, len(r1)).astype(np.float32)
+    ddc1 = dv.DDC(r1, c1, v1, 5000, 1)
+    g = rng.standard_normal(5000).astype(np.float32)
+    p_ref = oprod.price(r1, c1, v1, g, 1)
+    assert abs(float(ddc1.price(cuda(g)).cpu()[0]) - p_ref[0]) <= TOL * float(np.abs(v1 * g[r1]).sum())
+
+
+def test_empty_matrix_gives_zero(dv):
+    ddc = dv.DDC(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32), 100, 30)
+    assert torch.count_nonzero(ddc.dose(torch.ones(30, device="cuda"))) == 0
+    assert torch.count_nonzero(ddc.price(torch.ones(100, device="cuda"))) == 0
+
+
+def test_products_are_deterministic(dv, plan1):
+    _, _, _, ddc, obj = plan1
+    x, g = synth.bench_vectors(PLAN1.n_bl, PLAN1.n_vox, 3)
+    a = ddc.dose(cuda(x), obj, with_grad=True)
+    b = ddc.dose(cuda(x), obj, with_grad=True)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[2], b[2])
+    assert torch.equal(ddc.price(cuda(g)), ddc.price(cuda(g)))
+
+
+# ---------------------------------------------------------------- objective
+
+def test_dose_objective_epilogue_and_standalone_objective(dv, plan1):
+    d, sid, table, ddc, obj = plan1
+    x = synth.bench_vectors(PLAN1.n_bl, PLAN1.n_vox, 11)[0] * 4.0     # doses around the prescriptions
+    z_ref = oprod.dose(d["row"], d["col"], d["val"], x, PLAN1.n_vox)
+    F_ref = oobj.objective(z_ref, sid, table)
+    g_ref = oobj.gradient(z_ref, sid, table)
+    z, g, F = ddc.dose(cuda(x), obj, with_grad=True)
+    assert np.abs(z.cpu().numpy() - z_ref).max() <= TOL * np.abs(z_ref).max()
+    # gradient error follows from the dose error: |dg| <= 2 w |dz|
+    assert np.abs(g.cpu().numpy() - g_ref).max() <= 2 * 1.0 * TOL * np.abs(z_ref).max() + 1e-6
+    assert abs(float(F.cpu()[0]) - F_ref) <= 1e-5 * F_ref
+    # standalone on the oracle's own dose (rounded to FP32)
+    F2, g2 = obj(cuda(z_ref.astype(np.float32)))
+    z32 = z_ref.astype(np.float32).astype(np.float64)
+    assert abs(float(F2.cpu()[0]) - oobj.objective(z32, sid, table)) <= 1e-5 * F_ref
+    assert np.allclose(g2.cpu().numpy(), oobj.gradient(z32, sid, table), rtol=1e-6, atol=1e-5)
+
+
+def test_objective_multi_rhs(dv, plan1):
+    _, sid, table, _, obj = plan1
+    rng = np.random.default_rng(12)
+    z = rng.uniform(0, 90, (PLAN1.n_vox, 3)).astype(np.float32)
+    F, g = obj(cuda(z))
+    F_ref = oobj.objective(z.astype(np.float64), sid, table)
+    assert np.allclose(F.cpu().numpy(), F_ref, rtol=1e-5)
+    assert np.allclose(g.cpu().numpy(), oobj.gradient(z.astype(np.float64), sid, table), rtol=1e-6, atol=1e-5)
+
+
+def test_curvature(dv, plan1):
+    d, sid, table, ddc, obj = plan1
+    x, _ = synth.bench_vectors(PLAN1.n_bl, PLAN1.n_vox, 13)
+    xdir, _ = synth.bench_vectors(PLAN1.n_bl, PLAN1.n_vox, 14)
+    z_ref = oprod.dose(d["row"], d["col"], d["val"], 4.0 * x, PLAN1.n_vox).astype(np.float32)
+    dd_ref = oprod.dose(d["row"], d["col"], d["val"], xdir, PLAN1.n_vox)
+    c_ref = oobj.curvature(dd_ref, z_ref.astype(np.float64), sid, table)
+    curv = torch.zeros(1, dtype=torch.float64, device="cuda")
+    d_out = torch.empty(PLAN1.n_vox, device="cuda")
+    ddc.curvature_(cuda(xdir), obj, cuda(z_ref), curv, d_out)
+    assert abs(float(curv.cpu()[0]) - c_ref) <= 3e-5 * c_ref
+    assert np.abs(d_out.cpu().numpy() - dd_ref).max() <= TOL * dd_ref.max()
+
+
+# ---------------------------------------------------------------- aperture selection
+
+def test_aperture_select_exact_integer_prices(dv):
+    n_cp, n_rows, n_cols = 37, 11, 29
+    rng = np.random.default_rng(21)
+    p = rng.integers(-6, 7, size=(n_cp, n_rows, n_cols)).astype(np.float32)
+    p[rng.random(p.shape) < 0.4] = 0.0                       # exact zeros: ties resolved by the rule
+    occ = (rng.random(n_cp) < 0.3).astype(np.uint8)
+    ref = oap.select(p.ravel(), n_cp, n_rows, n_cols, occ.astype(bool))
+    out = dv.aperture_select(cuda(p.ravel()), n_cp, n_rows, n_cols, cuda(occ))
+    assert np.array_equal(out["L"].cpu().numpy(), ref["L"])
+    assert np.array_equal(out["R"].cpu().numpy(), ref["R"])
+    assert np.array_equal(out["cp_price"].cpu().numpy().astype(np.float64), ref["cp_price"])
+    assert int(out["best"].cpu()[0]) == ref["best"]
+    # all non-negative -> no improving aperture
+    out = dv.aperture_select(cuda(np.abs(p).ravel()), n_cp, n_rows, n_cols, None)
+    assert int(out["best"].cpu()[0]) == -1
+    # every control point occupied -> -1 and +inf prices
+    out = dv.aperture_select(cuda(p.ravel()), n_cp, n_rows, n_cols, torch.ones(n_cp, dtype=torch.uint8, device="cuda"))
+    assert int(out["best"].cpu()[0]) == -1 and torch.isinf(out["cp_price"]).all()
+
+
+def test_aperture_select_golden_rows(dv, golden_dir):
+    import json
+    import os
+    gold = json.load(open(os.path.join(golden_dir, "aperture_rows.json")))
+    for case in gold["rows"]:
+        p = np.array(case["p"], np.float32)
+        out = dv.aperture_select(cuda(p), 1, 1, len(p))
+        assert (int(out["L"].cpu()[0, 0]), int(out["R"].cpu()[0, 0])) == (case["L"], case["R"])
+        assert float(out["cp_price"].cpu()[0]) == case["sum"]
+    cp = gold["control_points"]
+    p = np.array(cp["p"], np.float32)
+    out = dv.aperture_select(cuda(p.ravel()), *p.shape)
+    assert int(out["best"].cpu()[0]) == cp["best_free"]
+    out = dv.aperture_select(cuda(p.ravel()), *p.shape, cuda(np.array([0, 1, 0], np.uint8)))
+    assert int(out["best"].cpu()[0]) == cp["best_cp1_occupied"]
+
+
+def test_aperture_select_real_prices(dv, plan1):
+    d, sid, table, ddc, obj = plan1
+    # prices at z = 0 (the first pricing problem)
+    z, g, F = ddc.dose(torch.zeros(PLAN1.n_bl, device="cuda"), obj, with_grad=True)
+    p = ddc.price(g)
+    p64 = p.cpu().numpy().astype(np.float64)
+    ref = oap.select(p64, PLAN1.n_cp, PLAN1.n_rows, PLAN1.n_cols, np.zeros(PLAN1.n_cp, bool))
+    out = dv.aperture_select(p, PLAN1.n_cp, PLAN1.n_rows, PLAN1.n_cols)
+    # the chosen openings' exact prices equal the oracle's best within FP32 summation error
+    L, R = out["L"].cpu().numpy(), out["R"].cpu().numpy()
+    P = p64.reshape(PLAN1.n_cp, PLAN1.n_rows, PLAN1.n_cols)
+    bound = 64 * 2.0 ** -24 * np.abs(P).sum(axis=2)
+    for k in range(PLAN1.n_cp):
+        for r in range(PLAN1.n_rows):
+            s = P[k, r, L[k, r]:R[k, r]].sum()
+            ref_s = P[k, r, ref["L"][k, r]:ref["R"][k, r]].sum()
+            assert abs(s - ref_s) <= bound[k, r]
+    best = int(out["best"].cpu()[0])
+    assert abs(ref["cp_price"][best] - ref["best_price"]) <= bound.sum(axis=1).max()
+
+
+# ---------------------------------------------------------------- master problem
+
+def _device_apertures(dv, plan, m, seed, lo, hi, max_iter, eps_f=0.0, eps_step=0.0):
+    cps, L, R = synth.random_apertures(plan, m, seed)
+    bb = dv.BB(plan.n_cp, plan.n_rows, plan.n_cols, m, max_iter=max_iter, eps_f=eps_f, eps_step=eps_step)
+    Ld, Rd = cuda(L), cuda(R)
+    for k in range(m):
+        bb.add_aperture(int(cps[k]), Ld[k], Rd[k], float(lo[k]), float(hi[k]))
+    apset = obb.ApertureSet(plan.n_cp, plan.n_rows, plan.n_cols)
+    for k in range(m):
+        apset.add(cps[k], L[k], R[k])
+    return bb, apset
+
+
+def _gpu_mp(dv, ddc, obj, bb, steps, n_vox, n_bl, record=True):
+    x = torch.zeros(n_bl, device="cuda")
+    xdir = torch.zeros(n_bl, device="cuda")
+    z = torch.empty(n_vox, device="cuda")
+    g = torch.empty(n_vox, device="cuda")
+    p = torch.empty(n_bl, device="cuda")
+    F = torch.empty(1, device="cuda")
+    curv = torch.empty(1, dtype=torch.float64, device="cuda")
+    bb.expand_(x)
+    ddc.dose_(x, z, obj, g, F)
+    ddc.price_(g, p)
+    bb.begin()
+    bb.direction_(p, xdir)
+    ddc.curvature_(xdir, obj, z, curv)
+    ys, Fs, flags = [], [float(F.cpu()[0])], []
+    for _ in range(steps):
+        bb.step_(p, F, curv, x)
+        ddc.dose_(x, z, obj, g, F)
+        ddc.price_(g, p)
+        if record:
+            ys.append(bb.y().cpu().numpy().astype(np.float64))
+            Fs.append(float(F.cpu()[0]))
+            flags.append(int(bb.flags.cpu()[0]))
+    return dict(y=ys, F=Fs, flags=flags, z=z, p=p)
+
+
+def test_bb_trajectory_matches_oracle(dv, plan1):
+    d, sid, table, ddc, obj = plan1
+    m = 4
+    lo, hi = np.zeros(m, np.float32), np.full(m, np.inf, np.float32)
+    bb, apset = _device_apertures(dv, PLAN1, m, 31, lo, hi, max_iter=30)
+    gpu = _gpu_mp(dv, ddc, obj, bb, 30, PLAN1.n_vox, PLAN1.n_bl)
+    apply, adjoint = obb.d_form_ops(d["row"], d["col"], d["val"], PLAN1.n_vox, PLAN1.n_bl, apset)
+    ref = obb.solve(apply, adjoint, sid, table, np.zeros(m), lo, hi,
+                    obb.BBParams(max_iter=30, eps_f=0.0, eps_step=0.0), record=True)
+    # oracle hist["y"][t] is y at the start of iteration t; the GPU records y after it
+    for t in range(8):
+        yr = ref["hist"]["y"][t + 1]
+        assert np.allclose(gpu["y"][t], yr, rtol=1e-4, atol=1e-4 * np.abs(yr).max()), t
+    assert gpu["F"][-1] == pytest.approx(ref["F"], rel=1e-4)
+    assert gpu["flags"][-1] & obb.FLAG_MAX_ITER
+
+
+def test_bb_box_bounds_and_stop_rule(dv, plan1):
+    d, sid, table, ddc, obj = plan1
+    m = 5
+    lo, hi = synth.random_boxes(m, 41)
+    bb, apset = _device_apertures(dv, PLAN1, m, 42, lo, hi, max_iter=50, eps_f=1e-5, eps_step=1e-7)
+    gpu = _gpu_mp(dv, ddc, obj, bb, 50, PLAN1.n_vox, PLAN1.n_bl)
+    y = gpu["y"][-1]
+    assert np.all(y >= lo - 1e-7) and np.all(y <= hi + 1e-7)
+    apply, adjoint = obb.d_form_ops(d["row"], d["col"], d["val"], PLAN1.n_vox, PLAN1.n_bl, apset)
+    ref = obb.solve(apply, adjoint, sid, table, lo.astype(np.float64), lo, hi,
+                    obb.BBParams(max_iter=50, eps_f=1e-5, eps_step=1e-7))
+    assert gpu["F"][-1] == pytest.approx(ref["F"], rel=1e-4)
+    # once a stop flag is raised the rates no longer change
+    stops = [i for i, f in enumerate(gpu["flags"]) if f & obb.STOP_MASK]
+    if stops:
+        s0 = stops[0]
+        for t in range(s0, len(gpu["y"])):
+            assert np.array_equal(gpu["y"][t], gpu["y"][s0])
+
+
+def test_column_generation_matches_oracle(dv, plan1):
+    from paper_1503_01721_amd.colgen import ColumnGeneration
+    d, sid, table, ddc, obj = plan1
+    n_it = 6
+    cg = ColumnGeneration(ddc, obj, PLAN1.n_cp, PLAN1.n_rows, PLAN1.n_cols, bb_steps=50, eps_f=0.0, eps_step=0.0)
+    recs = cg.run(n_it)
+    ref = ocg.run(d["row"], d["col"], d["val"], PLAN1.n_vox, PLAN1.n_cp, PLAN1.n_rows, PLAN1.n_cols,
+                  sid, table, max_cg=n_it, params=obb.BBParams(max_iter=50, eps_f=0.0, eps_step=0.0))
+    assert len(recs) == len(ref["log"]) == n_it
+    for a, b in zip(recs, ref["log"]):
+        assert a.cp == b["cp"]
+        assert a.F == pytest.approx(b["F"], rel=1e-3)
+    Fs = [r.F for r in recs]
+    assert all(b < a for a, b in zip(Fs, Fs[1:]))
+
+
+# ---------------------------------------------------------------- precision forms
+
+def _bf16_round(a):
+    """float32 -> bfloat16 -> float32, round to nearest even (finite values)."""
+    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32)
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_precision_forms(dv, plan1, storage):
+    d, _, _, _, _ = plan1
+    ddc = dv.DDC(d["row"], d["col"], d["val"], PLAN1.n_vox, PLAN1.n_bl, storage=storage)
+    assert ddc.info.value_bytes == 2
+    # dequantised matrix, computed here independently of the library
+    s = np.zeros(PLAN1.n_bl, np.float32)
+    np.maximum.at(s, d["col"], np.abs(d["val"]))
+    s[s == 0] = 1.0
+    q = d["val"] / s[d["col"]]
+    q = q.astype(np.float16).astype(np.float32) if storage == "f16" else _bf16_round(q)
+    deq = q.astype(np.float64) * s[d["col"]].astype(np.float64)
+    x, g = synth.bench_vectors(PLAN1.n_bl, PLAN1.n_vox, 51)
+    z = ddc.dose(cuda(x)).cpu().numpy()
+    p = ddc.price(cuda(g)).cpu().numpy()
+    # (i) arithmetic: kernel vs oracle on the dequantised values
+    z_deq = oprod.dose(d["row"], d["col"], deq, x, PLAN1.n_vox)
+    p_deq = oprod.price(d["row"], d["col"], deq, g, PLAN1.n_bl)
+    assert np.abs(z - z_deq).max() <= TOL * z_deq.max()
+    assert np.abs(p - p_deq).max() <= TOL * oprod.price(d["row"], d["col"], np.abs(deq), np.abs(g), PLAN1.n_bl).max()
+    # (ii) storage: against the FP32 original, relative to max dose
+    z_ref = oprod.dose(d["row"], d["col"], d["val"], x, PLAN1.n_vox)
+    err = np.abs(z - z_ref).max() / z_ref.max()
+    if storage == "f16":
+        assert err <= 2e-3            # provable: unit roundoff 2^-11 on non-negative terms
+    else:
+        assert err <= 2 ** -8         # worst-case bound of bfloat16 rounding
