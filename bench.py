@@ -108,6 +108,7 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--bb-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--copy-calibration", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
 
@@ -141,6 +142,12 @@ def main():
     t_build = time.perf_counter() - t
     info = ddc.info
     log(f"built CSR(D) + CSR(D^T) and uploaded {info.workspace_bytes / 2**30:.2f} GiB in {t_build:.1f} s")
+    if not args.no_autotune:
+        t = time.perf_counter()
+        info = ddc.autotune(reps=5)
+        log(f"autotuned in {time.perf_counter() - t:.1f} s: dose kernel {('row', 'stream')[info.dose_kernel]} "
+            f"x {info.dose_workgroups} wg ({info.dose_tuned_ms:.3f} ms), price kernel "
+            f"{('row', 'stream')[info.price_kernel]} x {info.price_workgroups} wg ({info.price_tuned_ms:.3f} ms)")
 
     cg = ColumnGeneration(ddc, obj, plan.n_cp, plan.n_rows, plan.n_cols,
                           max_apertures=args.warmup + args.steps, bb_steps=args.bb_steps)
@@ -199,6 +206,8 @@ def main():
             "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
             "mean_dose_call_ms": round(mean_dose, 4), "mean_price_call_ms": round(mean_price, 4),
             "generate_s": round(t_gen, 2), "build_upload_s": round(t_build, 2),
+            "dose_launch": {"kernel": ("row", "stream")[info.dose_kernel], "workgroups": info.dose_workgroups},
+            "price_launch": {"kernel": ("row", "stream")[info.price_kernel], "workgroups": info.price_workgroups},
         },
         "roofline": {
             "bound": "hbm", "kernel": kname,

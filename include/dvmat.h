@@ -80,6 +80,9 @@ typedef struct {
     int32_t storage;                     /* DVMAT_F32 / F16 / BF16               */
     int32_t value_bytes;                 /* 4 or 2                               */
     size_t workspace_bytes;              /* device bytes needed by dvmat_ddc_bind */
+    int32_t dose_kernel, dose_workgroups;   /* launch shape in use: kernel 0 = row, 1 = stream */
+    int32_t price_kernel, price_workgroups;
+    float dose_tuned_ms, price_tuned_ms;    /* autotuner's best times (0 before tuning) */
 } dvmat_ddc_info_t;
 
 /* Validate host COO (row = voxel, col = beamlet, val; length nnz; read during
@@ -144,6 +147,19 @@ dvmat_status dvmat_dose(dvmat_ddc ddc, const float* x, int32_t nrhs, float* z,
 dvmat_status dvmat_price(dvmat_ddc ddc, const float* g, int32_t nrhs, float* p,
                          dvmat_stream stream);
 
+/* Autotuner: times every candidate launch shape (block kernel "row" or
+ * "stream" x workgroup count) of the plain dose and of the price on the
+ * caller's vectors (x: device float[n_bl], z: float[n_vox], g: float[n_vox],
+ * p: float[n_bl], contents of z and p are overwritten), reps timed launches
+ * each after one warm-up, and keeps the fastest per orientation for all later
+ * calls on this handle.  Synchronises the stream.  Results are the same for
+ * every shape (each shape's reductions have a fixed order). */
+dvmat_status dvmat_ddc_autotune(dvmat_ddc ddc, const float* x, float* z, const float* g, float* p,
+                                int32_t reps, dvmat_stream stream);
+/* Set the launch shape by hand: orientation 0 = dose, 1 = price; kind 0 =
+ * row, 1 = stream; workgroups in [8, 8192] (rounded to a multiple of 8). */
+dvmat_status dvmat_ddc_set_kernel(dvmat_ddc ddc, int32_t orientation, int32_t kind, int32_t workgroups);
+
 /* Curvature of F along a fluence direction, for the first step length of a
  * master-problem solve: curv = sum_i w_i(z_ref) (D x_dir)_i^2 with w_i = w+
  * where z_ref_i > T_i, w- where z_ref_i < T_i, 0 where equal.  x_dir: device
@@ -189,7 +205,8 @@ dvmat_status dvmat_aperture_select(dvmat_geom geom, const float* p, const uint8_
  * written with the negative gradient); if <s,q> <= 0 or the ratio is not
  * finite and positive the previous length is reused (flag FALLBACK).
  * Stopping: |F_{t-5} - F_t| <= eps_f |F_t|, max|y_t - y_{t-1}| <= eps_step
- * max(1, max|y_t|), all masked gradient components zero, or max_iter steps.
+ * max(1, max|y_t|), all masked gradient components zero, or max_iter steps;
+ * a threshold of 0 switches its test off.
  * Once stopped, further steps leave y unchanged (the caller may keep a fixed
  * number of steps).  Inner products are FP64, y and alpha FP32.
  * ---------------------------------------------------------------------- */
@@ -238,10 +255,65 @@ dvmat_status dvmat_bb_direction(dvmat_bb bb, const float* p, float* x_dir, dvmat
  * nullable). */
 dvmat_status dvmat_bb_step(dvmat_bb bb, const float* p, const float* F, const double* curv,
                            float* x_next, uint32_t* flags, dvmat_stream stream);
+/* As dvmat_bb_direction and dvmat_bb_step, but with the gradient in the
+ * aperture domain supplied by the caller: G device float[count] = dF/dy_k
+ * (e.g. from automatic differentiation of F(D B y)); nothing is gathered. */
+dvmat_status dvmat_bb_direction_g(dvmat_bb bb, const float* G, float* x_dir, dvmat_stream stream);
+dvmat_status dvmat_bb_step_g(dvmat_bb bb, const float* G, const float* F, const double* curv,
+                             float* x_next, uint32_t* flags, dvmat_stream stream);
 /* x = B y for the current rates (device float[n_bl]). */
 dvmat_status dvmat_bb_expand(dvmat_bb bb, float* x, dvmat_stream stream);
 /* Copy the current rates to device float[count]. */
 dvmat_status dvmat_bb_get_y(dvmat_bb bb, float* y, dvmat_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Batched products over many plans in one launch: the row blocks of every
+ * plan form one work list that a single persistent grid walks, so plans of
+ * very different sizes share the GPU without a launch per plan.  (The paper
+ * suggests lending idle GPUs to another plan, Sec. 4; here the plans share
+ * one GPU.)  All plans must be bound and share a storage type; n <= 64.
+ * ---------------------------------------------------------------------- */
+typedef struct dvmat_batch_s* dvmat_batch;
+
+dvmat_status dvmat_batch_workspace_size(int32_t n, size_t* bytes);
+/* Records the plans' device layouts in the workspace (the ddc handles and
+ * their workspaces must outlive the batch).  Synchronises the stream. */
+dvmat_status dvmat_batch_create(const dvmat_ddc* ddcs, int32_t n, void* d_workspace, size_t bytes,
+                                dvmat_stream stream, dvmat_batch* out);
+void dvmat_batch_destroy(dvmat_batch batch);
+/* z_i = D_i x_i for every plan i in one launch.  xs, zs: host arrays of n
+ * device pointers ([n_bl_i][nrhs] and [n_vox_i][nrhs]); nrhs in {1,2,4,8}.
+ * The pointers are passed by value as kernel arguments, so a captured graph
+ * replays with the same buffers. */
+dvmat_status dvmat_batch_dose(dvmat_batch batch, const float* const* xs, int32_t nrhs, float* const* zs,
+                              dvmat_stream stream);
+/* p_i = D_i^T g_i for every plan i in one launch (layout as above). */
+dvmat_status dvmat_batch_price(dvmat_batch batch, const float* const* gs, int32_t nrhs, float* const* ps,
+                               dvmat_stream stream);
+/* Autotuner of the two batched launches (as dvmat_ddc_autotune; overwrites zs, ps). */
+dvmat_status dvmat_batch_autotune(dvmat_batch batch, const float* const* xs, float* const* zs,
+                                  const float* const* gs, float* const* ps, int32_t nrhs, int32_t reps,
+                                  dvmat_stream stream);
+/* Launch shape by hand (as dvmat_ddc_set_kernel). */
+dvmat_status dvmat_batch_set_kernel(dvmat_batch batch, int32_t orientation, int32_t kind, int32_t workgroups);
+/* Total row blocks of the dose and price work lists; cfg (nullable) receives
+ * {dose kernel, dose workgroups, price kernel, price workgroups}. */
+dvmat_status dvmat_batch_info(dvmat_batch batch, int64_t* dose_blocks, int64_t* price_blocks, int32_t* cfg);
+
+/* ------------------------------------------------------------------------
+ * Aperture maps for an explicit aperture list (no BB state): the fluence of
+ * the chosen apertures, x_j = y_k for beamlet j in aperture A_k (z = D x is
+ * then sum_k DA(A_k) y_k, Sec. 2.1 with Eq. 5), and its adjoint, the gradient
+ * in the aperture domain G_k = sum_{j in A_k} p_j (step 1 of the master
+ * problem, Sec. 2.2.2).  cps: device int32[m] distinct control points;
+ * L, R: device int32[m][n_rows] openings [L, R); y, G: device float[m];
+ * x, p: device float[n_cp*n_rows*n_cols].  expand writes every beamlet (0
+ * outside the apertures).
+ * ---------------------------------------------------------------------- */
+dvmat_status dvmat_aperture_expand(dvmat_geom geom, int32_t m, const int32_t* cps, const int32_t* L,
+                                   const int32_t* R, const float* y, float* x, dvmat_stream stream);
+dvmat_status dvmat_aperture_gather(dvmat_geom geom, int32_t m, const int32_t* cps, const int32_t* L,
+                                   const int32_t* R, const float* p, float* G, dvmat_stream stream);
 
 #ifdef __cplusplus
 }

@@ -25,7 +25,8 @@ the subspace, dose):
   4. y <- clip(y - alpha Gt, lo, hi); then the dose z at the new y.
 Stopping (Sec. 2.1): relative change of F over the last five iterations
 |F_{t-5} - F_t| <= eps_f |F_t|, step max|y_t - y_{t-1}| <= eps_step max(1, max|y_t|),
-an all-zero masked gradient, or max_iter iterations.
+an all-zero masked gradient, or max_iter iterations.  The paper gives no
+values for the two thresholds; a threshold of 0 switches its test off.
 
 The solver is written against two callables so the same steps run in the
 paper's DA-form (A = [DA_1 .. DA_m]) and in D-form (A = D B with B the
@@ -98,10 +99,11 @@ def solve(apply, adjoint, sid, table, y0, lo, hi, params=BBParams(), record=Fals
         if not np.isfinite(F):
             flags |= FLAG_NONFINITE
             break
-        if t >= 5 and abs(F_hist[t - 5] - F_hist[t]) <= params.eps_f * abs(F_hist[t]):
+        if params.eps_f > 0 and t >= 5 and abs(F_hist[t - 5] - F_hist[t]) <= params.eps_f * abs(F_hist[t]):
             flags |= FLAG_REL_F
             break
-        if t >= 1 and np.max(np.abs(y - y_prev)) <= params.eps_step * max(1.0, float(np.max(np.abs(y)))):
+        if (params.eps_step > 0 and t >= 1 and
+                np.max(np.abs(y - y_prev)) <= params.eps_step * max(1.0, float(np.max(np.abs(y))))):
             flags |= FLAG_SMALL_STEP
             break
         if not np.any(Gt != 0.0):

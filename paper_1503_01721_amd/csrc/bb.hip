@@ -144,7 +144,8 @@ enum { MODE_DIRECTION = 0, MODE_STEP = 1 };
 
 // Bound rules, step length, stopping tests and the clipped step (one workgroup).
 __global__ __launch_bounds__(256) void bb_update_kernel(BBDev B, int m, int mode, const float* Fp, const double* curv,
-                                                        uint32_t* flags_out, dvmat_bb_params prm) {
+                                                        uint32_t* flags_out, dvmat_bb_params prm,
+                                                        const float* __restrict__ G_ext) {
     __shared__ double r_ss[256], r_sq[256], r_qq[256], r_gg[256];
     __shared__ float r_ds[256], r_y[256], r_g[256];
     __shared__ int r_nz[256];
@@ -164,7 +165,7 @@ __global__ __launch_bounds__(256) void bb_update_kernel(BBDev B, int m, int mode
     for (int k = tid; k < m; k += 256) {
         const float lo = B.lo[k], hi = B.hi[k];
         const float y = fminf(fmaxf(B.y[k], lo), hi);
-        const float G = B.G[k];
+        const float G = G_ext ? G_ext[k] : B.G[k];
         float gt = G;
         if (y <= lo && G > 0.0f) gt = 0.0f;
         if (y >= hi && G < 0.0f) gt = 0.0f;
@@ -208,10 +209,10 @@ __global__ __launch_bounds__(256) void bb_update_kernel(BBDev B, int m, int mode
         uint32_t stop = 0;
         if (!isfinite(F)) {
             stop = DVMAT_BB_NONFINITE;
-        } else if (t >= 5 && fabs((double)B.state->F_hist[(t - 5) % kFHist] - (double)F) <=
-                                 (double)prm.eps_f * fabs((double)F)) {
+        } else if (prm.eps_f > 0.0f && t >= 5 &&
+                   fabs((double)B.state->F_hist[(t - 5) % kFHist] - (double)F) <= (double)prm.eps_f * fabs((double)F)) {
             stop = DVMAT_BB_REL_F;
-        } else if (t >= 1 && r_ds[0] <= prm.eps_step * fmaxf(1.0f, r_y[0])) {
+        } else if (prm.eps_step > 0.0f && t >= 1 && r_ds[0] <= prm.eps_step * fmaxf(1.0f, r_y[0])) {
             stop = DVMAT_BB_SMALL_STEP;
         } else if (r_nz[0] == 0) {
             stop = DVMAT_BB_CONVERGED;
@@ -279,6 +280,54 @@ __global__ __launch_bounds__(256) void bb_expand_kernel(BBDev B, int n_rows, int
 
 __global__ void bb_copy_y_kernel(BBDev B, int m, float* y) {
     for (int k = threadIdx.x; k < m; k += blockDim.x) y[k] = B.y[k];
+}
+
+// x = B y for an explicit aperture list: one workgroup per control point finds
+// the aperture sitting there (if any) and writes all of the point's beamlets.
+__global__ __launch_bounds__(256) void aperture_expand_kernel(int n_rows, int n_cols, int m,
+                                                              const int32_t* __restrict__ cps,
+                                                              const int32_t* __restrict__ L,
+                                                              const int32_t* __restrict__ R,
+                                                              const float* __restrict__ y, float* __restrict__ x) {
+    __shared__ int slot;
+    const int cp = blockIdx.x;
+    if (threadIdx.x == 0) slot = -1;
+    __syncthreads();
+    for (int k = threadIdx.x; k < m; k += blockDim.x)
+        if (cps[k] == cp) atomicMax(&slot, k);      // distinct control points: at most one match
+    __syncthreads();
+    const int s = slot;
+    const int per_cp = n_rows * n_cols;
+    float* xc = x + (int64_t)cp * per_cp;
+    for (int i = threadIdx.x; i < per_cp; i += blockDim.x) {
+        const int r = i / n_cols, c = i - r * n_cols;
+        float v = 0.0f;
+        if (s >= 0 && c >= L[(int64_t)s * n_rows + r] && c < R[(int64_t)s * n_rows + r]) v = y[s];
+        xc[i] = v;
+    }
+}
+
+// G_k = sum of p over the beamlets of aperture k (explicit aperture list).
+__global__ __launch_bounds__(256) void aperture_gather_kernel(int n_rows, int n_cols, const int32_t* __restrict__ cps,
+                                                              const int32_t* __restrict__ L,
+                                                              const int32_t* __restrict__ R,
+                                                              const float* __restrict__ p, float* __restrict__ G) {
+    __shared__ float s[256];
+    const int k = blockIdx.x;
+    const int64_t base = (int64_t)cps[k] * n_rows * n_cols;
+    const int per_cp = n_rows * n_cols;
+    float a = 0.0f;
+    for (int i = threadIdx.x; i < per_cp; i += 256) {
+        const int r = i / n_cols, c = i - r * n_cols;
+        if (c >= L[(int64_t)k * n_rows + r] && c < R[(int64_t)k * n_rows + r]) a += p[base + i];
+    }
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) G[k] = s[0];
 }
 
 static dvmat_status check_geom(const dvmat_geom& g, const char* fn) {
@@ -369,33 +418,62 @@ dvmat_status dvmat_bb_begin(dvmat_bb b, dvmat_stream stream) {
     return check_hip(hipGetLastError(), "dvmat_bb_begin launch");
 }
 
-dvmat_status dvmat_bb_direction(dvmat_bb b, const float* p, float* x_dir, dvmat_stream stream) {
-    if (!b || !p || !x_dir) return set_error(DVMAT_E_ARG, "dvmat_bb_direction: NULL argument");
-    if (b->m == 0) return set_error(DVMAT_E_STATE, "dvmat_bb_direction: no apertures");
+}  // extern "C"
+
+namespace dvmat {
+static dvmat_status bb_direction_impl(dvmat_bb b, const float* p, const float* G_ext, float* x_dir,
+                                      dvmat_stream stream, const char* fn) {
+    if (!b || !(p || G_ext) || !x_dir) return set_error(DVMAT_E_ARG, "%s: NULL argument", fn);
+    if (b->m == 0) return set_error(DVMAT_E_STATE, "%s: no apertures", fn);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const dvmat_geom& g = b->geom;
     const int64_t n_bl = (int64_t)g.n_cp * g.n_rows * g.n_cols;
-    hipLaunchKernelGGL(bb_gather_kernel, dim3(b->m), dim3(256), 0, s, b->dev, g.n_rows, g.n_cols, p);
+    if (!G_ext) hipLaunchKernelGGL(bb_gather_kernel, dim3(b->m), dim3(256), 0, s, b->dev, g.n_rows, g.n_cols, p);
     hipLaunchKernelGGL(bb_update_kernel, dim3(1), dim3(256), 0, s, b->dev, b->m, (int)MODE_DIRECTION,
-                       (const float*)nullptr, (const double*)nullptr, (uint32_t*)nullptr, b->params);
+                       (const float*)nullptr, (const double*)nullptr, (uint32_t*)nullptr, b->params, G_ext);
     hipLaunchKernelGGL(bb_expand_kernel, dim3(grid_for(n_bl)), dim3(256), 0, s, b->dev, g.n_rows, g.n_cols, n_bl,
                        (const float*)b->dev.Gt, x_dir);
-    return check_hip(hipGetLastError(), "dvmat_bb_direction launch");
+    return check_hip(hipGetLastError(), fn);
+}
+
+static dvmat_status bb_step_impl(dvmat_bb b, const float* p, const float* G_ext, const float* F, const double* curv,
+                                 float* x_next, uint32_t* flags, dvmat_stream stream, const char* fn) {
+    if (!b || !(p || G_ext) || !F || !x_next) return set_error(DVMAT_E_ARG, "%s: NULL argument", fn);
+    if (b->m == 0) return set_error(DVMAT_E_STATE, "%s: no apertures", fn);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const dvmat_geom& g = b->geom;
+    const int64_t n_bl = (int64_t)g.n_cp * g.n_rows * g.n_cols;
+    if (!G_ext) hipLaunchKernelGGL(bb_gather_kernel, dim3(b->m), dim3(256), 0, s, b->dev, g.n_rows, g.n_cols, p);
+    hipLaunchKernelGGL(bb_update_kernel, dim3(1), dim3(256), 0, s, b->dev, b->m, (int)MODE_STEP, F, curv, flags,
+                       b->params, G_ext);
+    hipLaunchKernelGGL(bb_expand_kernel, dim3(grid_for(n_bl)), dim3(256), 0, s, b->dev, g.n_rows, g.n_cols, n_bl,
+                       (const float*)b->dev.y, x_next);
+    return check_hip(hipGetLastError(), fn);
+}
+}  // namespace dvmat
+
+extern "C" {
+
+dvmat_status dvmat_bb_direction(dvmat_bb b, const float* p, float* x_dir, dvmat_stream stream) {
+    if (!p) return set_error(DVMAT_E_ARG, "dvmat_bb_direction: p is NULL");
+    return bb_direction_impl(b, p, nullptr, x_dir, stream, "dvmat_bb_direction");
+}
+
+dvmat_status dvmat_bb_direction_g(dvmat_bb b, const float* G, float* x_dir, dvmat_stream stream) {
+    if (!G) return set_error(DVMAT_E_ARG, "dvmat_bb_direction_g: G is NULL");
+    return bb_direction_impl(b, nullptr, G, x_dir, stream, "dvmat_bb_direction_g");
 }
 
 dvmat_status dvmat_bb_step(dvmat_bb b, const float* p, const float* F, const double* curv, float* x_next,
                            uint32_t* flags, dvmat_stream stream) {
-    if (!b || !p || !F || !x_next) return set_error(DVMAT_E_ARG, "dvmat_bb_step: NULL argument");
-    if (b->m == 0) return set_error(DVMAT_E_STATE, "dvmat_bb_step: no apertures");
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const dvmat_geom& g = b->geom;
-    const int64_t n_bl = (int64_t)g.n_cp * g.n_rows * g.n_cols;
-    hipLaunchKernelGGL(bb_gather_kernel, dim3(b->m), dim3(256), 0, s, b->dev, g.n_rows, g.n_cols, p);
-    hipLaunchKernelGGL(bb_update_kernel, dim3(1), dim3(256), 0, s, b->dev, b->m, (int)MODE_STEP, F, curv, flags,
-                       b->params);
-    hipLaunchKernelGGL(bb_expand_kernel, dim3(grid_for(n_bl)), dim3(256), 0, s, b->dev, g.n_rows, g.n_cols, n_bl,
-                       (const float*)b->dev.y, x_next);
-    return check_hip(hipGetLastError(), "dvmat_bb_step launch");
+    if (!p) return set_error(DVMAT_E_ARG, "dvmat_bb_step: p is NULL");
+    return bb_step_impl(b, p, nullptr, F, curv, x_next, flags, stream, "dvmat_bb_step");
+}
+
+dvmat_status dvmat_bb_step_g(dvmat_bb b, const float* G, const float* F, const double* curv, float* x_next,
+                             uint32_t* flags, dvmat_stream stream) {
+    if (!G) return set_error(DVMAT_E_ARG, "dvmat_bb_step_g: G is NULL");
+    return bb_step_impl(b, nullptr, G, F, curv, x_next, flags, stream, "dvmat_bb_step_g");
 }
 
 dvmat_status dvmat_bb_expand(dvmat_bb b, float* x, dvmat_stream stream) {
@@ -405,6 +483,29 @@ dvmat_status dvmat_bb_expand(dvmat_bb b, float* x, dvmat_stream stream) {
     hipLaunchKernelGGL(bb_expand_kernel, dim3(grid_for(n_bl)), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
                        b->dev, g.n_rows, g.n_cols, n_bl, (const float*)b->dev.y, x);
     return check_hip(hipGetLastError(), "dvmat_bb_expand launch");
+}
+
+dvmat_status dvmat_aperture_expand(dvmat_geom geom, int32_t m, const int32_t* cps, const int32_t* L, const int32_t* R,
+                                   const float* y, float* x, dvmat_stream stream) {
+    dvmat_status st = check_geom(geom, "dvmat_aperture_expand");
+    if (st) return st;
+    if (m < 0 || m > geom.n_cp) return set_error(DVMAT_E_ARG, "dvmat_aperture_expand: m=%d not in 0..n_cp", m);
+    if (!x || (m > 0 && (!cps || !L || !R || !y))) return set_error(DVMAT_E_ARG, "dvmat_aperture_expand: NULL argument");
+    hipLaunchKernelGGL(aperture_expand_kernel, dim3(geom.n_cp), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
+                       geom.n_rows, geom.n_cols, m, cps, L, R, y, x);
+    return check_hip(hipGetLastError(), "dvmat_aperture_expand launch");
+}
+
+dvmat_status dvmat_aperture_gather(dvmat_geom geom, int32_t m, const int32_t* cps, const int32_t* L, const int32_t* R,
+                                   const float* p, float* G, dvmat_stream stream) {
+    dvmat_status st = check_geom(geom, "dvmat_aperture_gather");
+    if (st) return st;
+    if (m < 0 || m > geom.n_cp) return set_error(DVMAT_E_ARG, "dvmat_aperture_gather: m=%d not in 0..n_cp", m);
+    if (m == 0) return DVMAT_OK;
+    if (!cps || !L || !R || !p || !G) return set_error(DVMAT_E_ARG, "dvmat_aperture_gather: NULL argument");
+    hipLaunchKernelGGL(aperture_gather_kernel, dim3(m), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
+                       geom.n_rows, geom.n_cols, cps, L, R, p, G);
+    return check_hip(hipGetLastError(), "dvmat_aperture_gather launch");
 }
 
 dvmat_status dvmat_bb_get_y(dvmat_bb b, float* y, dvmat_stream stream) {

@@ -24,6 +24,18 @@ constexpr int kWaveSize = 64;
 constexpr int kSpmvThreads = 256;                 // 4 waves per workgroup
 constexpr int kMaxSpmvWorkgroups = 8192;          // partial-sum slots in the objective workspace
 constexpr int kMaxRhs = 8;
+// Row blocks hold at most this many rows (the stream kernel stages them in LDS).
+constexpr int kBlockRowsMax = 64;
+// Plans per batched launch (their vector pointers travel as kernel arguments).
+constexpr int kMaxBatch = 64;
+
+// Launch shape of one SpMV orientation: block kernel (0 = row, 1 = stream)
+// and workgroup count.
+struct KernelCfg {
+    int kind;
+    int workgroups;
+};
+KernelCfg initial_kernel_cfg();
 
 dvmat_status set_error(dvmat_status code, const char* fmt, ...);
 dvmat_status check_hip(hipError_t e, const char* what);
@@ -65,6 +77,8 @@ struct dvmat_ddc_s {
     const float* scale = nullptr;      // device [n_bl] (16-bit storage)
     float* xs = nullptr;               // device [n_bl * kMaxRhs] scaled-x scratch (16-bit)
     size_t ws_bytes = 0;
+    dvmat::KernelCfg dose_cfg{0, 2048}, price_cfg{0, 2048};
+    float dose_tuned_ms = 0.0f, price_tuned_ms = 0.0f;
     // workspace layout offsets
     size_t off_dose_rowptr = 0, off_dose_col = 0, off_dose_val = 0, off_dose_blocks = 0;
     size_t off_price_rowptr = 0, off_price_col = 0, off_price_val = 0, off_price_blocks = 0;

@@ -64,8 +64,8 @@ static int64_t block_nnz_cap() {
     return 2048;
 }
 static int32_t block_row_cap() {
-    if (const char* s = std::getenv("DVMAT_BLOCK_ROWS")) return std::max(1, std::atoi(s));
-    return 64;
+    if (const char* s = std::getenv("DVMAT_BLOCK_ROWS")) return std::max(1, std::min(std::atoi(s), kBlockRowsMax));
+    return kBlockRowsMax;
 }
 
 // IEEE binary16, round to nearest even (finite inputs; overflow -> inf).
@@ -286,6 +286,8 @@ dvmat_status dvmat_ddc_create(int64_t n_vox, int64_t n_bl, int64_t nnz, const in
     d->n_vox = n_vox;
     d->n_bl = n_bl;
     d->storage = storage;
+    d->dose_cfg = initial_kernel_cfg();
+    d->price_cfg = initial_kernel_cfg();
     d->value_bytes = storage == DVMAT_F32 ? 4 : 2;
     std::vector<float> fval;
     std::vector<int64_t> len_u;
@@ -370,6 +372,12 @@ dvmat_status dvmat_ddc_info(dvmat_ddc d, dvmat_ddc_info_t* info) {
     info->storage = d->storage;
     info->value_bytes = d->value_bytes;
     info->workspace_bytes = d->ws_bytes;
+    info->dose_kernel = d->dose_cfg.kind;
+    info->dose_workgroups = d->dose_cfg.workgroups;
+    info->price_kernel = d->price_cfg.kind;
+    info->price_workgroups = d->price_cfg.workgroups;
+    info->dose_tuned_ms = d->dose_tuned_ms;
+    info->price_tuned_ms = d->price_tuned_ms;
     return DVMAT_OK;
 }
 

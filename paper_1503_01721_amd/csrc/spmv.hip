@@ -1,25 +1,33 @@
-// Dose z = D x and price p = D^T g on gfx950, plus the objective epilogue.
+// Dose z = D x and price p = D^T g on gfx950, the objective epilogue, the
+// batched multi-plan launch and the kernel autotuner.
 //
 // Both products are CSR row-times-vector kernels over the orientation that
-// makes the output a row: CSR(D) for the dose (rows = voxels, the "step 4"
-// dose update of Sec. 2.2.2 and Eq. 5 for aperture indicators) and CSR(D^T)
-// for the price (rows = beamlets, Eq. 3; the paper's GPU kernel assigns one
-// warp per beamlet row, Sec. 2.2.2).  The path is HBM-bound (2 flop per 8
-// bytes of matrix at FP32), so no matrix cores are used.
+// makes the output a row: CSR(D) for the dose (rows = voxels, the dose update
+// of the master problem, Sec. 2.2.2, and Eq. 5 for aperture indicators) and
+// CSR(D^T) for the price (rows = beamlets, Eq. 3; the paper assigns one warp
+// per beamlet row, Sec. 2.2.2).  The path is HBM-bound (2 flop per 8 bytes of
+// matrix at FP32), so no matrix cores are used.
 //
-// Mapping: rows are grouped on the host into blocks of consecutive rows with
-// a bounded number of stored entries.  One wave64 walks one block, one row at
-// a time: each lane streams 4 consecutive entries (16-byte value and column
-// loads, non-temporal so the matrix stream does not evict the gathered
-// vector from L2), gathers x[col], accumulates in FP32; a fixed butterfly
-// reduces the wave, lane 0 applies the epilogue.  The grid is a multiple of
-// the 8 XCDs; workgroup w runs on XCD w % 8 and each XCD owns a contiguous
-// range of blocks, so the waves sharing one L2 touch neighbouring rows.
-// Every reduction has a fixed order: results are bitwise reproducible.
+// Work units: rows are grouped on the host into blocks of consecutive rows
+// with a bounded number of stored entries (and at most kBlockRowsMax rows).
+// One wave64 processes one block at a time.  Two block kernels:
+//  - "row": row by row; each lane streams 4 consecutive entries (16-byte
+//    non-temporal value and column loads, so the matrix stream does not evict
+//    the gathered vector from L2), gathers x[col], FP32 accumulation, a fixed
+//    butterfly reduces the wave, lane 0 finishes the row;
+//  - "stream": the block's entries as one contiguous range, 256 per step with
+//    the next step's loads in flight, a segmented reduction across the wave,
+//    per-row sums in LDS, lane i finishes row i.
+// The grid is a multiple of the 8 XCDs; workgroup w runs on XCD w % 8 and each
+// XCD owns a contiguous range of blocks, so the waves sharing one L2 touch
+// neighbouring rows.  Every reduction has a fixed order: results are bitwise
+// reproducible run to run.
 #include "common.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <new>
 
 namespace dvmat {
 
@@ -37,14 +45,15 @@ struct SpmvParams {
     const int32_t* blocks;
     int64_t n_blocks;
     const float* x;
-    float* y;              // output rows (nullable for EPI_CURV)
-    const uint8_t* sid;    // objective epilogue
+    float* y;                // output rows (nullable for EPI_CURV)
+    const uint8_t* sid;      // objective epilogue
     const float* table;
     float* g;
     float* partial;
     double* partial_d;
     const float* zref;
-    const float* row_scale;  // EPI_SCALE
+    const float* row_scale;  // EPI_SCALE: y_r *= row_scale[r]
+    const float* x_scale;    // batched 16-bit dose: v *= x_scale[col]
 };
 
 template <int ST>
@@ -85,12 +94,18 @@ __device__ __forceinline__ void fma_gather(float (&acc)[NRHS], const float* __re
     }
 }
 
-template <int NRHS>
-__device__ __forceinline__ void fma4(float (&acc)[NRHS], const float* __restrict__ x, f32x4 v, i32x4 c) {
-    fma_gather<NRHS>(acc, x, v.x, c.x);
-    fma_gather<NRHS>(acc, x, v.y, c.y);
-    fma_gather<NRHS>(acc, x, v.z, c.z);
-    fma_gather<NRHS>(acc, x, v.w, c.w);
+template <int NRHS, bool SCALE_X>
+__device__ __forceinline__ void fma4(float (&acc)[NRHS], const SpmvParams& P, f32x4 v, i32x4 c) {
+    if constexpr (SCALE_X) {
+        v.x *= P.x_scale[c.x];
+        v.y *= P.x_scale[c.y];
+        v.z *= P.x_scale[c.z];
+        v.w *= P.x_scale[c.w];
+    }
+    fma_gather<NRHS>(acc, P.x, v.x, c.x);
+    fma_gather<NRHS>(acc, P.x, v.y, c.y);
+    fma_gather<NRHS>(acc, P.x, v.z, c.z);
+    fma_gather<NRHS>(acc, P.x, v.w, c.w);
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -99,86 +114,163 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
-template <int ST, int NRHS, int EPI>
-__global__ __launch_bounds__(kSpmvThreads) void spmv_kernel(SpmvParams P) {
-    constexpr int kWaves = kSpmvThreads / kWaveSize;
-    const int lane = threadIdx.x & (kWaveSize - 1);
-    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWaveSize);
-    const int wg = blockIdx.x;
-    const int xcd = wg % kNumXcd;
-    const int li = wg / kNumXcd;
-    const int waves_per_xcd = (gridDim.x / kNumXcd) * kWaves;
-    const int lw = li * kWaves + wid;
-    const int64_t b0 = P.n_blocks * xcd / kNumXcd;
-    const int64_t b1 = P.n_blocks * (xcd + 1) / kNumXcd;
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
 
-    float fpart[NRHS];
-#pragma unroll
-    for (int h = 0; h < NRHS; ++h) fpart[h] = 0.0f;
-    double cpart = 0.0;
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-    for (int64_t b = b0 + lw; b < b1; b += waves_per_xcd) {
-        const int r0 = P.blocks[b];
-        const int r1 = P.blocks[b + 1];
-        for (int r = r0; r < r1; ++r) {
-            const int64_t e0 = P.rowptr[r];
-            const int64_t e1 = P.rowptr[r + 1];
-            float acc[NRHS];
+// Row epilogue (one lane per row): plain, per-row scale, objective, curvature.
+template <int NRHS, int EPI>
+__device__ __forceinline__ void row_epilogue(const SpmvParams& P, int r, const float (&acc)[NRHS],
+                                             float (&fpart)[NRHS], double& cpart) {
+    if constexpr (EPI == EPI_PLAIN) {
 #pragma unroll
-            for (int h = 0; h < NRHS; ++h) acc[h] = 0.0f;
-            int64_t k = e0 + lane * 4;
-            for (; k + 256 < e1; k += 512) {
-                const f32x4 v0 = load_vals<ST>(P.val, k);
-                const i32x4 c0 = load_cols(P.col, k);
-                const f32x4 v1 = load_vals<ST>(P.val, k + 256);
-                const i32x4 c1 = load_cols(P.col, k + 256);
-                fma4<NRHS>(acc, P.x, v0, c0);
-                fma4<NRHS>(acc, P.x, v1, c1);
-            }
-            if (k < e1) {
-                const f32x4 v0 = load_vals<ST>(P.val, k);
-                const i32x4 c0 = load_cols(P.col, k);
-                fma4<NRHS>(acc, P.x, v0, c0);
-            }
+        for (int h = 0; h < NRHS; ++h) P.y[(int64_t)r * NRHS + h] = acc[h];
+    } else if constexpr (EPI == EPI_SCALE) {
+        const float s = P.row_scale[r];
 #pragma unroll
-            for (int h = 0; h < NRHS; ++h) acc[h] = wave_sum(acc[h]);
-            if (lane == 0) {
-                if constexpr (EPI == EPI_PLAIN) {
+        for (int h = 0; h < NRHS; ++h) P.y[(int64_t)r * NRHS + h] = acc[h] * s;
+    } else if constexpr (EPI == EPI_OBJ) {
+        const int s = P.sid[r];
+        const float T = P.table[s * 4 + 0];
+        const float wo = P.table[s * 4 + 1];
+        const float wu = P.table[s * 4 + 2];
 #pragma unroll
-                    for (int h = 0; h < NRHS; ++h) P.y[(int64_t)r * NRHS + h] = acc[h];
-                } else if constexpr (EPI == EPI_SCALE) {
-                    const float s = P.row_scale[r];
+        for (int h = 0; h < NRHS; ++h) {
+            const float z = acc[h];
+            P.y[(int64_t)r * NRHS + h] = z;
+            const float over = fmaxf(z - T, 0.0f);
+            const float under = fmaxf(T - z, 0.0f);
+            if (P.g) P.g[(int64_t)r * NRHS + h] = 2.0f * wo * over - 2.0f * wu * under;
+            fpart[h] += wo * over * over + wu * under * under;
+        }
+    } else {  // EPI_CURV
+        const float d = acc[0];
+        if (P.y) P.y[r] = d;
+        const int s = P.sid[r];
+        const float T = P.table[s * 4 + 0];
+        const float zr = P.zref[r];
+        const float w = zr > T ? P.table[s * 4 + 1] : (zr < T ? P.table[s * 4 + 2] : 0.0f);
+        cpart += (double)w * (double)d * (double)d;
+    }
+}
+
+// ---- block processors --------------------------------------------------------
+
+template <int ST, int NRHS, int EPI, bool SCALE_X>
+__device__ __forceinline__ void block_rows(const SpmvParams& P, int64_t b, int lane, float (&fpart)[NRHS],
+                                           double& cpart) {
+    const int r0 = P.blocks[b];
+    const int r1 = P.blocks[b + 1];
+    for (int r = r0; r < r1; ++r) {
+        const int64_t e0 = P.rowptr[r];
+        const int64_t e1 = P.rowptr[r + 1];
+        float acc[NRHS];
 #pragma unroll
-                    for (int h = 0; h < NRHS; ++h) P.y[(int64_t)r * NRHS + h] = acc[h] * s;
-                } else if constexpr (EPI == EPI_OBJ) {
-                    const int s = P.sid[r];
-                    const float T = P.table[s * 4 + 0];
-                    const float wo = P.table[s * 4 + 1];
-                    const float wu = P.table[s * 4 + 2];
+        for (int h = 0; h < NRHS; ++h) acc[h] = 0.0f;
+        int64_t k = e0 + lane * 4;
+        for (; k + 256 < e1; k += 512) {
+            const f32x4 v0 = load_vals<ST>(P.val, k);
+            const i32x4 c0 = load_cols(P.col, k);
+            const f32x4 v1 = load_vals<ST>(P.val, k + 256);
+            const i32x4 c1 = load_cols(P.col, k + 256);
+            fma4<NRHS, SCALE_X>(acc, P, v0, c0);
+            fma4<NRHS, SCALE_X>(acc, P, v1, c1);
+        }
+        if (k < e1) {
+            const f32x4 v0 = load_vals<ST>(P.val, k);
+            const i32x4 c0 = load_cols(P.col, k);
+            fma4<NRHS, SCALE_X>(acc, P, v0, c0);
+        }
 #pragma unroll
-                    for (int h = 0; h < NRHS; ++h) {
-                        const float z = acc[h];
-                        P.y[(int64_t)r * NRHS + h] = z;
-                        const float over = fmaxf(z - T, 0.0f);
-                        const float under = fmaxf(T - z, 0.0f);
-                        if (P.g) P.g[(int64_t)r * NRHS + h] = 2.0f * wo * over - 2.0f * wu * under;
-                        fpart[h] += wo * over * over + wu * under * under;
-                    }
-                } else {  // EPI_CURV
-                    const float d = acc[0];
-                    if (P.y) P.y[r] = d;
-                    const int s = P.sid[r];
-                    const float T = P.table[s * 4 + 0];
-                    const float zr = P.zref[r];
-                    const float w = zr > T ? P.table[s * 4 + 1] : (zr < T ? P.table[s * 4 + 2] : 0.0f);
-                    cpart += (double)w * (double)d * (double)d;
-                }
+        for (int h = 0; h < NRHS; ++h) acc[h] = wave_sum(acc[h]);
+        if (lane == 0) row_epilogue<NRHS, EPI>(P, r, acc, fpart, cpart);
+    }
+}
+
+// acc_l: this wave's LDS row accumulators [kBlockRowsMax * NRHS]; rel: [kBlockRowsMax + 1].
+template <int ST, int NRHS, int EPI, bool SCALE_X>
+__device__ __forceinline__ void block_stream(const SpmvParams& P, int64_t b, int lane, float* acc_l, int* rel,
+                                             float (&fpart)[NRHS], double& cpart) {
+    const int r0 = P.blocks[b];
+    const int nr = P.blocks[b + 1] - r0;               // 1 .. kBlockRowsMax
+    const int64_t e0 = P.rowptr[r0];
+    const int ne = (int)(P.rowptr[r0 + nr] - e0);
+    for (int i = lane; i <= nr; i += kWaveSize) rel[i] = (int)(P.rowptr[r0 + i] - e0);
+    for (int i = lane; i < nr * NRHS; i += kWaveSize) acc_l[i] = 0.0f;
+    wave_sync_lds();
+    int cur = 0;
+    f32x4 vn = {0.0f, 0.0f, 0.0f, 0.0f};
+    i32x4 cn = {0, 0, 0, 0};
+    if (lane * 4 < ne) {
+        vn = load_vals<ST>(P.val, e0 + lane * 4);
+        cn = load_cols(P.col, e0 + lane * 4);
+    }
+    for (int c0 = 0; c0 < ne; c0 += 256) {
+        const int k = c0 + lane * 4;
+        const f32x4 v = vn;
+        const i32x4 c = cn;
+        if (k + 256 < ne) {
+            vn = load_vals<ST>(P.val, e0 + k + 256);
+            cn = load_cols(P.col, e0 + k + 256);
+        }
+        float part[NRHS];
+#pragma unroll
+        for (int h = 0; h < NRHS; ++h) part[h] = 0.0f;
+        int row = -1;
+        if (k < ne) {
+            fma4<NRHS, SCALE_X>(part, P, v, c);
+            while (rel[cur + 1] <= k) ++cur;
+            row = cur;
+        }
+#pragma unroll
+        for (int d = 1; d < kWaveSize; d <<= 1) {
+            const int orow = __shfl_down(row, d);
+            float o[NRHS];
+#pragma unroll
+            for (int h = 0; h < NRHS; ++h) o[h] = __shfl_down(part[h], d);
+            if (lane + d < kWaveSize && orow == row) {
+#pragma unroll
+                for (int h = 0; h < NRHS; ++h) part[h] += o[h];
             }
         }
+        const int prow = __shfl_up(row, 1);
+        if (row >= 0 && (lane == 0 || prow != row)) {
+#pragma unroll
+            for (int h = 0; h < NRHS; ++h) acc_l[row * NRHS + h] += part[h];
+        }
     }
+    wave_sync_lds();
+    for (int i = lane; i < nr; i += kWaveSize) {
+        float a[NRHS];
+#pragma unroll
+        for (int h = 0; h < NRHS; ++h) a[h] = acc_l[i * NRHS + h];
+        row_epilogue<NRHS, EPI>(P, r0 + i, a, fpart, cpart);
+    }
+    wave_sync_lds();
+}
+
+// Per-workgroup partial of the objective / curvature (fixed order).
+template <int NRHS, int EPI>
+__device__ __forceinline__ void workgroup_partials(const SpmvParams& P, int lane, int wid, float (&fpart)[NRHS],
+                                                   double cpart) {
     if constexpr (EPI == EPI_OBJ || EPI == EPI_CURV) {
+        constexpr int kWaves = kSpmvThreads / kWaveSize;
         __shared__ float sp[kWaves][NRHS];
         __shared__ double sd[kWaves];
+        if constexpr (EPI == EPI_OBJ) {
+#pragma unroll
+            for (int h = 0; h < NRHS; ++h) fpart[h] = wave_sum(fpart[h]);
+        } else {
+            cpart = wave_sum_d(cpart);
+        }
         if (lane == 0) {
 #pragma unroll
             for (int h = 0; h < NRHS; ++h) sp[wid][h] = fpart[h];
@@ -191,16 +283,112 @@ __global__ __launch_bounds__(kSpmvThreads) void spmv_kernel(SpmvParams P) {
                 for (int h = 0; h < NRHS; ++h) {
                     float s = 0.0f;
                     for (int w = 0; w < kWaves; ++w) s += sp[w][h];
-                    P.partial[(int64_t)wg * NRHS + h] = s;
+                    P.partial[(int64_t)blockIdx.x * NRHS + h] = s;
                 }
             } else {
                 double s = 0.0;
                 for (int w = 0; w < kWaves; ++w) s += sd[w];
-                P.partial_d[wg] = s;
+                P.partial_d[blockIdx.x] = s;
             }
         }
     }
 }
+
+enum Kind { KIND_ROW = 0, KIND_STREAM = 1 };
+
+// Wave position: workgroup w on XCD w % 8; the XCD's waves share its block range.
+struct WaveSlot {
+    int lane, wid, lw, waves_per_xcd, xcd;
+};
+
+__device__ __forceinline__ WaveSlot wave_slot() {
+    constexpr int kWaves = kSpmvThreads / kWaveSize;
+    WaveSlot s;
+    s.lane = threadIdx.x & (kWaveSize - 1);
+    s.wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWaveSize);
+    s.xcd = blockIdx.x % kNumXcd;
+    s.lw = (blockIdx.x / kNumXcd) * kWaves + s.wid;
+    s.waves_per_xcd = (gridDim.x / kNumXcd) * kWaves;
+    return s;
+}
+
+template <int KIND, int ST, int NRHS, int EPI>
+__global__ __launch_bounds__(kSpmvThreads) void spmv_kernel(SpmvParams P) {
+    constexpr int kWaves = kSpmvThreads / kWaveSize;
+    const WaveSlot w = wave_slot();
+    const int64_t b0 = P.n_blocks * w.xcd / kNumXcd;
+    const int64_t b1 = P.n_blocks * (w.xcd + 1) / kNumXcd;
+    float fpart[NRHS];
+#pragma unroll
+    for (int h = 0; h < NRHS; ++h) fpart[h] = 0.0f;
+    double cpart = 0.0;
+    if constexpr (KIND == KIND_ROW) {
+        for (int64_t b = b0 + w.lw; b < b1; b += w.waves_per_xcd)
+            block_rows<ST, NRHS, EPI, false>(P, b, w.lane, fpart, cpart);
+    } else {
+        __shared__ float s_acc[kWaves][kBlockRowsMax * NRHS];
+        __shared__ int s_rel[kWaves][kBlockRowsMax + 1];
+        for (int64_t b = b0 + w.lw; b < b1; b += w.waves_per_xcd)
+            block_stream<ST, NRHS, EPI, false>(P, b, w.lane, s_acc[w.wid], s_rel[w.wid], fpart, cpart);
+    }
+    workgroup_partials<NRHS, EPI>(P, w.lane, w.wid, fpart, cpart);
+}
+
+// ---- batched launch over many plans ----------------------------------------
+
+struct PlanDev {
+    const int64_t* rowptr;
+    const int32_t* col;
+    const void* val;
+    const int32_t* blocks;
+    const float* scale;   // per-beamlet scale (16-bit storage) or nullptr
+    int64_t block_base;   // first global block of this plan
+    int64_t n_blocks;
+};
+
+struct BatchParams {
+    const PlanDev* plans;     // device [n_plans]
+    int n_plans;
+    int64_t total_blocks;
+    const float* x[kMaxBatch];
+    float* y[kMaxBatch];
+};
+
+template <int KIND, int ST, int NRHS, int EPI, bool SCALE_X>
+__global__ __launch_bounds__(kSpmvThreads) void spmv_batch_kernel(BatchParams B) {
+    constexpr int kWaves = kSpmvThreads / kWaveSize;
+    const WaveSlot w = wave_slot();
+    const int64_t b0 = B.total_blocks * w.xcd / kNumXcd;
+    const int64_t b1 = B.total_blocks * (w.xcd + 1) / kNumXcd;
+    float fpart[NRHS];
+#pragma unroll
+    for (int h = 0; h < NRHS; ++h) fpart[h] = 0.0f;
+    double cpart = 0.0;
+    __shared__ float s_acc[kWaves][(KIND == KIND_STREAM ? kBlockRowsMax : 1) * NRHS];
+    __shared__ int s_rel[kWaves][(KIND == KIND_STREAM ? kBlockRowsMax + 1 : 1)];
+    int p = 0;
+    for (int64_t b = b0 + w.lw; b < b1; b += w.waves_per_xcd) {
+        while (p + 1 < B.n_plans && B.plans[p + 1].block_base <= b) ++p;   // b only grows
+        const PlanDev& pd = B.plans[p];
+        SpmvParams P{};
+        P.rowptr = pd.rowptr;
+        P.col = pd.col;
+        P.val = pd.val;
+        P.blocks = pd.blocks;
+        P.n_blocks = pd.n_blocks;
+        P.x = B.x[p];
+        P.y = B.y[p];
+        P.row_scale = pd.scale;
+        P.x_scale = pd.scale;
+        if constexpr (KIND == KIND_ROW)
+            block_rows<ST, NRHS, EPI, SCALE_X>(P, b - pd.block_base, w.lane, fpart, cpart);
+        else
+            block_stream<ST, NRHS, EPI, SCALE_X>(P, b - pd.block_base, w.lane, s_acc[w.wid], s_rel[w.wid], fpart,
+                                                 cpart);
+    }
+}
+
+// ---- small kernels -----------------------------------------------------------
 
 // Sum of per-workgroup partials in a fixed order (FP64), one workgroup.
 __global__ __launch_bounds__(256) void finalize_f_kernel(const float* partial, int nwg, int nrhs, float* F) {
@@ -267,22 +455,30 @@ __global__ __launch_bounds__(256) void scale_x_kernel(const float* x, const floa
         xs[i] = x[i] * scale[i / nrhs];
 }
 
-static int spmv_workgroups(int64_t n_blocks) {
-    int want = 2048;
-    if (const char* s = std::getenv("DVMAT_SPMV_WG")) want = std::atoi(s);
-    int64_t need = (n_blocks + 3) / 4;
+// ---- launch plumbing ---------------------------------------------------------
+
+static int clamp_workgroups(int want, int64_t n_blocks) {
+    const int64_t need = (n_blocks + 3) / 4;
     int64_t w = std::min<int64_t>(want, need);
     w = (w + kNumXcd - 1) / kNumXcd * kNumXcd;
     w = std::max<int64_t>(kNumXcd, std::min<int64_t>(w, kMaxSpmvWorkgroups));
     return (int)w;
 }
 
-template <int ST, int EPI>
-static void launch_st(const SpmvParams& P, int nrhs, int nwg, hipStream_t s) {
+// Default launch shape; the autotuner overrides it per matrix orientation.
+static KernelCfg default_cfg() {
+    KernelCfg c{KIND_ROW, 2048};
+    if (const char* s = std::getenv("DVMAT_SPMV_KIND")) c.kind = s[0] == 's' ? KIND_STREAM : KIND_ROW;
+    if (const char* s = std::getenv("DVMAT_SPMV_WG")) c.workgroups = std::max(8, std::atoi(s));
+    return c;
+}
+
+template <int KIND, int ST, int EPI>
+static void launch_nrhs(const SpmvParams& P, int nrhs, int nwg, hipStream_t s) {
     dim3 grid(nwg), block(kSpmvThreads);
     switch (nrhs) {
 #define DVMAT_CASE(N) \
-    case N: hipLaunchKernelGGL((spmv_kernel<ST, N, EPI>), grid, block, 0, s, P); break;
+    case N: hipLaunchKernelGGL((spmv_kernel<KIND, ST, N, EPI>), grid, block, 0, s, P); break;
         DVMAT_CASE(1) DVMAT_CASE(2) DVMAT_CASE(3) DVMAT_CASE(4)
         DVMAT_CASE(5) DVMAT_CASE(6) DVMAT_CASE(7) DVMAT_CASE(8)
 #undef DVMAT_CASE
@@ -291,19 +487,32 @@ static void launch_st(const SpmvParams& P, int nrhs, int nwg, hipStream_t s) {
 }
 
 template <int EPI>
-static void launch_spmv(int storage, const SpmvParams& P, int nrhs, int nwg, hipStream_t s) {
-    if (storage == DVMAT_F32) launch_st<DVMAT_F32, EPI>(P, nrhs, nwg, s);
-    else if (storage == DVMAT_F16) launch_st<DVMAT_F16, EPI>(P, nrhs, nwg, s);
-    else launch_st<DVMAT_BF16, EPI>(P, nrhs, nwg, s);
+static void launch_spmv(const KernelCfg& cfg, int storage, const SpmvParams& P, int nrhs, hipStream_t s) {
+    const int nwg = clamp_workgroups(cfg.workgroups, P.n_blocks);
+    if (cfg.kind == KIND_STREAM) {
+        if (storage == DVMAT_F32) launch_nrhs<KIND_STREAM, DVMAT_F32, EPI>(P, nrhs, nwg, s);
+        else if (storage == DVMAT_F16) launch_nrhs<KIND_STREAM, DVMAT_F16, EPI>(P, nrhs, nwg, s);
+        else launch_nrhs<KIND_STREAM, DVMAT_BF16, EPI>(P, nrhs, nwg, s);
+    } else {
+        if (storage == DVMAT_F32) launch_nrhs<KIND_ROW, DVMAT_F32, EPI>(P, nrhs, nwg, s);
+        else if (storage == DVMAT_F16) launch_nrhs<KIND_ROW, DVMAT_F16, EPI>(P, nrhs, nwg, s);
+        else launch_nrhs<KIND_ROW, DVMAT_BF16, EPI>(P, nrhs, nwg, s);
+    }
 }
 
 // Curvature only needs one right-hand side.
-template <int EPI>
-static void launch_spmv1(int storage, const SpmvParams& P, int nwg, hipStream_t s) {
+static void launch_curv(const KernelCfg& cfg, int storage, const SpmvParams& P, hipStream_t s) {
+    const int nwg = clamp_workgroups(cfg.workgroups, P.n_blocks);
     dim3 grid(nwg), block(kSpmvThreads);
-    if (storage == DVMAT_F32) hipLaunchKernelGGL((spmv_kernel<DVMAT_F32, 1, EPI>), grid, block, 0, s, P);
-    else if (storage == DVMAT_F16) hipLaunchKernelGGL((spmv_kernel<DVMAT_F16, 1, EPI>), grid, block, 0, s, P);
-    else hipLaunchKernelGGL((spmv_kernel<DVMAT_BF16, 1, EPI>), grid, block, 0, s, P);
+    if (cfg.kind == KIND_STREAM) {
+        if (storage == DVMAT_F32) hipLaunchKernelGGL((spmv_kernel<KIND_STREAM, DVMAT_F32, 1, EPI_CURV>), grid, block, 0, s, P);
+        else if (storage == DVMAT_F16) hipLaunchKernelGGL((spmv_kernel<KIND_STREAM, DVMAT_F16, 1, EPI_CURV>), grid, block, 0, s, P);
+        else hipLaunchKernelGGL((spmv_kernel<KIND_STREAM, DVMAT_BF16, 1, EPI_CURV>), grid, block, 0, s, P);
+    } else {
+        if (storage == DVMAT_F32) hipLaunchKernelGGL((spmv_kernel<KIND_ROW, DVMAT_F32, 1, EPI_CURV>), grid, block, 0, s, P);
+        else if (storage == DVMAT_F16) hipLaunchKernelGGL((spmv_kernel<KIND_ROW, DVMAT_F16, 1, EPI_CURV>), grid, block, 0, s, P);
+        else hipLaunchKernelGGL((spmv_kernel<KIND_ROW, DVMAT_BF16, 1, EPI_CURV>), grid, block, 0, s, P);
+    }
 }
 
 static int elementwise_grid(int64_t n) {
@@ -311,15 +520,152 @@ static int elementwise_grid(int64_t n) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, 2048));
 }
 
-dvmat_status launch_expand_scale(const dvmat_ddc_s* d, const float* x, int nrhs, hipStream_t s) {
-    hipLaunchKernelGGL(scale_x_kernel, dim3(elementwise_grid(d->n_bl * nrhs)), dim3(256), 0, s, x, d->scale,
-                       d->n_bl, nrhs, d->xs);
-    return check_hip(hipGetLastError(), "scale_x_kernel launch");
-}
-
 static dvmat_status check_ddc(const dvmat_ddc_s* d, const char* fn) {
     if (!d) return set_error(DVMAT_E_ARG, "%s: ddc is NULL", fn);
     if (!d->bound) return set_error(DVMAT_E_STATE, "%s: ddc not bound to a device workspace", fn);
+    return DVMAT_OK;
+}
+
+static SpmvParams orientation_params(const CsrDev& c) {
+    SpmvParams P{};
+    P.rowptr = c.rowptr;
+    P.col = c.col;
+    P.val = c.val;
+    P.blocks = c.blocks;
+    P.n_blocks = c.n_blocks;
+    return P;
+}
+
+// Plain dose (no objective) on CSR(D), used by the public call and the autotuner.
+static dvmat_status dose_plain(dvmat_ddc_s* d, const KernelCfg& cfg, const float* x, int nrhs, float* z, hipStream_t s) {
+    const float* xin = x;
+    if (d->storage != DVMAT_F32) {
+        hipLaunchKernelGGL(scale_x_kernel, dim3(elementwise_grid(d->n_bl * nrhs)), dim3(256), 0, s, x, d->scale,
+                           d->n_bl, nrhs, d->xs);
+        xin = d->xs;
+    }
+    SpmvParams P = orientation_params(d->dose);
+    P.x = xin;
+    P.y = z;
+    launch_spmv<EPI_PLAIN>(cfg, d->storage, P, nrhs, s);
+    return check_hip(hipGetLastError(), "dose launch");
+}
+
+static dvmat_status price_any(dvmat_ddc_s* d, const KernelCfg& cfg, const float* g, int nrhs, float* p, hipStream_t s) {
+    SpmvParams P = orientation_params(d->price);
+    P.x = g;
+    P.y = p;
+    P.row_scale = d->scale;
+    if (d->storage == DVMAT_F32) launch_spmv<EPI_PLAIN>(cfg, d->storage, P, nrhs, s);
+    else launch_spmv<EPI_SCALE>(cfg, d->storage, P, nrhs, s);
+    return check_hip(hipGetLastError(), "price launch");
+}
+
+}  // namespace dvmat
+
+struct dvmat_batch_s {
+    int32_t n = 0;
+    int32_t storage = DVMAT_F32;
+    std::vector<int64_t> n_vox, n_bl;
+    dvmat::PlanDev* dose_plans = nullptr;    // device
+    dvmat::PlanDev* price_plans = nullptr;   // device
+    int64_t dose_blocks = 0, price_blocks = 0;
+    dvmat::KernelCfg dose_cfg{}, price_cfg{};
+};
+
+namespace dvmat {
+
+template <int KIND, int ST, int EPI, bool SCALE_X>
+static void launch_batch_nrhs(const BatchParams& B, int nrhs, int nwg, hipStream_t s) {
+    dim3 grid(nwg), block(kSpmvThreads);
+    switch (nrhs) {
+#define DVMAT_CASE(N) \
+    case N: hipLaunchKernelGGL((spmv_batch_kernel<KIND, ST, N, EPI, SCALE_X>), grid, block, 0, s, B); break;
+        DVMAT_CASE(1) DVMAT_CASE(2) DVMAT_CASE(4) DVMAT_CASE(8)
+#undef DVMAT_CASE
+        default: break;
+    }
+}
+
+// dose: plain epilogue, 16-bit scale applied to each gathered entry;
+// price: 16-bit scale applied per output row.
+template <bool DOSE>
+static void launch_batch(const dvmat_batch_s* bt, const KernelCfg& cfg, const BatchParams& B, int nrhs,
+                         hipStream_t s) {
+    const int nwg = clamp_workgroups(cfg.workgroups, B.total_blocks);
+    const int st = bt->storage;
+#define DVMAT_BATCH(KIND)                                                                                 \
+    if (st == DVMAT_F32) launch_batch_nrhs<KIND, DVMAT_F32, EPI_PLAIN, false>(B, nrhs, nwg, s);          \
+    else if (st == DVMAT_F16) {                                                                           \
+        if (DOSE) launch_batch_nrhs<KIND, DVMAT_F16, EPI_PLAIN, true>(B, nrhs, nwg, s);                   \
+        else launch_batch_nrhs<KIND, DVMAT_F16, EPI_SCALE, false>(B, nrhs, nwg, s);                       \
+    } else {                                                                                              \
+        if (DOSE) launch_batch_nrhs<KIND, DVMAT_BF16, EPI_PLAIN, true>(B, nrhs, nwg, s);                  \
+        else launch_batch_nrhs<KIND, DVMAT_BF16, EPI_SCALE, false>(B, nrhs, nwg, s);                      \
+    }
+    if (cfg.kind == KIND_STREAM) {
+        DVMAT_BATCH(KIND_STREAM)
+    } else {
+        DVMAT_BATCH(KIND_ROW)
+    }
+#undef DVMAT_BATCH
+}
+
+static dvmat_status batch_call(dvmat_batch_s* bt, bool dose, const KernelCfg& cfg, const float* const* in,
+                               int32_t nrhs, float* const* out, hipStream_t s, const char* fn) {
+    if (!bt || !in || !out) return set_error(DVMAT_E_ARG, "%s: NULL argument", fn);
+    if (nrhs != 1 && nrhs != 2 && nrhs != 4 && nrhs != 8)
+        return set_error(DVMAT_E_ARG, "%s: nrhs=%d not in {1,2,4,8}", fn, nrhs);
+    BatchParams B{};
+    B.plans = dose ? bt->dose_plans : bt->price_plans;
+    B.n_plans = bt->n;
+    B.total_blocks = dose ? bt->dose_blocks : bt->price_blocks;
+    for (int i = 0; i < bt->n; ++i) {
+        if (!in[i] || !out[i]) return set_error(DVMAT_E_ARG, "%s: NULL vector for plan %d", fn, i);
+        B.x[i] = in[i];
+        B.y[i] = out[i];
+    }
+    if (dose) launch_batch<true>(bt, cfg, B, nrhs, s);
+    else launch_batch<false>(bt, cfg, B, nrhs, s);
+    return check_hip(hipGetLastError(), fn);
+}
+
+// ---- autotuner ---------------------------------------------------------------
+
+static const int kTuneWorkgroups[] = {1024, 2048, 4096, 8192};
+
+template <class Run>
+static dvmat_status time_config(Run&& run, int reps, hipStream_t s, float* ms_out) {
+    hipEvent_t a, b;
+    dvmat_status st = check_hip(hipEventCreate(&a), "autotune event");
+    if (st) return st;
+    if ((st = check_hip(hipEventCreate(&b), "autotune event"))) { (void)hipEventDestroy(a); return st; }
+    st = run();                                              // warm-up
+    if (!st) st = check_hip(hipEventRecord(a, s), "autotune record");
+    for (int i = 0; i < reps && !st; ++i) st = run();
+    if (!st) st = check_hip(hipEventRecord(b, s), "autotune record");
+    if (!st) st = check_hip(hipEventSynchronize(b), "autotune sync");
+    float ms = 0.0f;
+    if (!st) st = check_hip(hipEventElapsedTime(&ms, a, b), "autotune elapsed");
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *ms_out = ms / std::max(reps, 1);
+    return st;
+}
+
+template <class RunCfg>
+static dvmat_status tune(RunCfg&& run_cfg, int reps, hipStream_t s, KernelCfg* best, float* best_ms) {
+    *best_ms = INFINITY;
+    for (int kind = 0; kind < 2; ++kind)
+        for (int wg : kTuneWorkgroups) {
+            KernelCfg c{kind, wg};
+            float ms = 0.0f;
+            dvmat_status st = time_config([&] { return run_cfg(c); }, reps, s, &ms);
+            if (st) return st;
+            if (std::getenv("DVMAT_AUTOTUNE_VERBOSE"))
+                fprintf(stderr, "[dvmat autotune] kernel=%s workgroups=%d %.4f ms\n", kind ? "stream" : "row", wg, ms);
+            if (ms < *best_ms) { *best_ms = ms; *best = c; }
+        }
     return DVMAT_OK;
 }
 
@@ -361,13 +707,12 @@ dvmat_status dvmat_obj_create(int64_t n_vox, int32_t n_struct, const uint8_t* d_
     o->partial = reinterpret_cast<float*>(base + align_up(256 * 4 * sizeof(float)));
     o->partial_d = reinterpret_cast<double*>(base + align_up(256 * 4 * sizeof(float)) +
                                              align_up((size_t)kMaxSpmvWorkgroups * kMaxRhs * sizeof(float)));
-    // padded 4-wide table; unused rows are zero (no objective)
-    static thread_local float host_tab[256 * 4];
-    for (int i = 0; i < 256 * 4; ++i) host_tab[i] = 0.0f;
+    // padded 4-wide table; rows past n_struct are zero (no objective)
+    std::vector<float> host_tab(256 * 4, 0.0f);
     for (int s = 0; s < n_struct; ++s)
         for (int c = 0; c < 3; ++c) host_tab[s * 4 + c] = table[s * 3 + c];
     hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
-    st = check_hip(hipMemcpyAsync(o->table, host_tab, sizeof host_tab, hipMemcpyHostToDevice, hs),
+    st = check_hip(hipMemcpyAsync(o->table, host_tab.data(), host_tab.size() * sizeof(float), hipMemcpyHostToDevice, hs),
                    "dvmat_obj_create: table copy");
     if (st == DVMAT_OK) st = check_hip(hipStreamSynchronize(hs), "dvmat_obj_create: synchronize");
     if (st) { delete o; return st; }
@@ -398,29 +743,24 @@ dvmat_status dvmat_dose(dvmat_ddc d, const float* x, int32_t nrhs, float* z, dvm
         return set_error(DVMAT_E_SHAPE, "dvmat_dose: objective has %lld voxels, matrix %lld",
                          (long long)obj->n_vox, (long long)d->n_vox);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (!obj) return dose_plain(d, d->dose_cfg, x, nrhs, z, s);
     const float* xin = x;
     if (d->storage != DVMAT_F32) {
-        if ((st = launch_expand_scale(d, x, nrhs, s))) return st;
+        hipLaunchKernelGGL(scale_x_kernel, dim3(elementwise_grid(d->n_bl * nrhs)), dim3(256), 0, s, x, d->scale,
+                           d->n_bl, nrhs, d->xs);
         xin = d->xs;
     }
-    SpmvParams P{};
-    P.rowptr = d->dose.rowptr;
-    P.col = d->dose.col;
-    P.val = d->dose.val;
-    P.blocks = d->dose.blocks;
-    P.n_blocks = d->dose.n_blocks;
+    SpmvParams P = orientation_params(d->dose);
     P.x = xin;
     P.y = z;
-    const int nwg = spmv_workgroups(d->dose.n_blocks);
-    if (obj) {
-        P.sid = obj->sid;
-        P.table = obj->table;
-        P.g = g;
-        P.partial = obj->partial;
-        launch_spmv<EPI_OBJ>(d->storage, P, nrhs, nwg, s);
-        if (F) hipLaunchKernelGGL(finalize_f_kernel, dim3(1), dim3(256), 0, s, obj->partial, nwg, nrhs, F);
-    } else {
-        launch_spmv<EPI_PLAIN>(d->storage, P, nrhs, nwg, s);
+    P.sid = obj->sid;
+    P.table = obj->table;
+    P.g = g;
+    P.partial = obj->partial;
+    launch_spmv<EPI_OBJ>(d->dose_cfg, d->storage, P, nrhs, s);
+    if (F) {
+        const int nwg = clamp_workgroups(d->dose_cfg.workgroups, P.n_blocks);
+        hipLaunchKernelGGL(finalize_f_kernel, dim3(1), dim3(256), 0, s, obj->partial, nwg, nrhs, F);
     }
     return check_hip(hipGetLastError(), "dvmat_dose launch");
 }
@@ -430,20 +770,7 @@ dvmat_status dvmat_price(dvmat_ddc d, const float* g, int32_t nrhs, float* p, dv
     if (st) return st;
     if (!g || !p) return set_error(DVMAT_E_ARG, "dvmat_price: g and p must be non-NULL");
     if (nrhs < 1 || nrhs > kMaxRhs) return set_error(DVMAT_E_ARG, "dvmat_price: nrhs=%d not in 1..8", nrhs);
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    SpmvParams P{};
-    P.rowptr = d->price.rowptr;
-    P.col = d->price.col;
-    P.val = d->price.val;
-    P.blocks = d->price.blocks;
-    P.n_blocks = d->price.n_blocks;
-    P.x = g;
-    P.y = p;
-    P.row_scale = d->scale;
-    const int nwg = spmv_workgroups(d->price.n_blocks);
-    if (d->storage == DVMAT_F32) launch_spmv<EPI_PLAIN>(d->storage, P, nrhs, nwg, s);
-    else launch_spmv<EPI_SCALE>(d->storage, P, nrhs, nwg, s);
-    return check_hip(hipGetLastError(), "dvmat_price launch");
+    return price_any(d, d->price_cfg, g, nrhs, p, reinterpret_cast<hipStream_t>(stream));
 }
 
 dvmat_status dvmat_dose_curvature(dvmat_ddc d, const float* x_dir, dvmat_obj obj, const float* z_ref, float* d_out,
@@ -455,25 +782,171 @@ dvmat_status dvmat_dose_curvature(dvmat_ddc d, const float* x_dir, dvmat_obj obj
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const float* xin = x_dir;
     if (d->storage != DVMAT_F32) {
-        if ((st = launch_expand_scale(d, x_dir, 1, s))) return st;
+        hipLaunchKernelGGL(scale_x_kernel, dim3(elementwise_grid(d->n_bl)), dim3(256), 0, s, x_dir, d->scale,
+                           d->n_bl, 1, d->xs);
         xin = d->xs;
     }
-    SpmvParams P{};
-    P.rowptr = d->dose.rowptr;
-    P.col = d->dose.col;
-    P.val = d->dose.val;
-    P.blocks = d->dose.blocks;
-    P.n_blocks = d->dose.n_blocks;
+    SpmvParams P = orientation_params(d->dose);
     P.x = xin;
     P.y = d_out;
     P.sid = obj->sid;
     P.table = obj->table;
     P.zref = z_ref;
     P.partial_d = obj->partial_d;
-    const int nwg = spmv_workgroups(d->dose.n_blocks);
-    launch_spmv1<EPI_CURV>(d->storage, P, nwg, s);
+    launch_curv(d->dose_cfg, d->storage, P, s);
+    const int nwg = clamp_workgroups(d->dose_cfg.workgroups, P.n_blocks);
     hipLaunchKernelGGL(finalize_d_kernel, dim3(1), dim3(256), 0, s, obj->partial_d, nwg, curv);
     return check_hip(hipGetLastError(), "dvmat_dose_curvature launch");
 }
 
+dvmat_status dvmat_ddc_autotune(dvmat_ddc d, const float* x, float* z, const float* g, float* p, int32_t reps,
+                                dvmat_stream stream) {
+    dvmat_status st = check_ddc(d, "dvmat_ddc_autotune");
+    if (st) return st;
+    if (!x || !z || !g || !p) return set_error(DVMAT_E_ARG, "dvmat_ddc_autotune: NULL argument");
+    if (reps < 1) return set_error(DVMAT_E_ARG, "dvmat_ddc_autotune: reps < 1");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    KernelCfg best{};
+    float ms = 0.0f;
+    st = tune([&](const KernelCfg& c) { return dose_plain(d, c, x, 1, z, s); }, reps, s, &best, &ms);
+    if (st) return st;
+    d->dose_cfg = best;
+    d->dose_tuned_ms = ms;
+    st = tune([&](const KernelCfg& c) { return price_any(d, c, g, 1, p, s); }, reps, s, &best, &ms);
+    if (st) return st;
+    d->price_cfg = best;
+    d->price_tuned_ms = ms;
+    return DVMAT_OK;
+}
+
+dvmat_status dvmat_ddc_set_kernel(dvmat_ddc d, int32_t orientation, int32_t kind, int32_t workgroups) {
+    if (!d) return set_error(DVMAT_E_ARG, "dvmat_ddc_set_kernel: NULL handle");
+    if (kind != 0 && kind != 1) return set_error(DVMAT_E_ARG, "dvmat_ddc_set_kernel: kind %d", kind);
+    if (workgroups < kNumXcd || workgroups > kMaxSpmvWorkgroups)
+        return set_error(DVMAT_E_ARG, "dvmat_ddc_set_kernel: workgroups %d not in [8, 8192]", workgroups);
+    KernelCfg c{kind, workgroups};
+    if (orientation == 0) d->dose_cfg = c;
+    else if (orientation == 1) d->price_cfg = c;
+    else return set_error(DVMAT_E_ARG, "dvmat_ddc_set_kernel: orientation %d", orientation);
+    return DVMAT_OK;
+}
+
+// ---- batched plans -------------------------------------------------------------
+
+dvmat_status dvmat_batch_workspace_size(int32_t n, size_t* bytes) {
+    if (!bytes) return set_error(DVMAT_E_ARG, "dvmat_batch_workspace_size: bytes is NULL");
+    if (n < 1 || n > kMaxBatch) return set_error(DVMAT_E_ARG, "dvmat_batch_workspace_size: n=%d not in 1..%d", n, kMaxBatch);
+    *bytes = 2 * align_up((size_t)n * sizeof(PlanDev));
+    return DVMAT_OK;
+}
+
+dvmat_status dvmat_batch_create(const dvmat_ddc* ddcs, int32_t n, void* ws, size_t bytes, dvmat_stream stream,
+                                dvmat_batch* out) {
+    if (!out) return set_error(DVMAT_E_ARG, "dvmat_batch_create: out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    dvmat_status st = dvmat_batch_workspace_size(n, &need);
+    if (st) return st;
+    if (!ddcs || !ws) return set_error(DVMAT_E_ARG, "dvmat_batch_create: NULL argument");
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign) return set_error(DVMAT_E_ARG, "dvmat_batch_create: workspace misaligned");
+    if (bytes < need) return set_error(DVMAT_E_NOMEM, "dvmat_batch_create: workspace %zu < %zu bytes", bytes, need);
+    std::vector<PlanDev> dp(n), pp(n);
+    int64_t bd = 0, bp = 0;
+    for (int i = 0; i < n; ++i) {
+        const dvmat_ddc_s* d = ddcs[i];
+        if ((st = check_ddc(d, "dvmat_batch_create"))) return st;
+        if (d->storage != ddcs[0]->storage)
+            return set_error(DVMAT_E_ARG, "dvmat_batch_create: plan %d has a different storage type", i);
+        dp[i] = PlanDev{d->dose.rowptr, d->dose.col, d->dose.val, d->dose.blocks, d->scale, bd, d->dose.n_blocks};
+        pp[i] = PlanDev{d->price.rowptr, d->price.col, d->price.val, d->price.blocks, d->scale, bp, d->price.n_blocks};
+        bd += d->dose.n_blocks;
+        bp += d->price.n_blocks;
+    }
+    dvmat_batch_s* bt = new (std::nothrow) dvmat_batch_s();
+    if (!bt) return set_error(DVMAT_E_NOMEM, "dvmat_batch_create: host allocation failed");
+    char* base = static_cast<char*>(ws);
+    bt->n = n;
+    bt->storage = ddcs[0]->storage;
+    bt->dose_plans = reinterpret_cast<PlanDev*>(base);
+    bt->price_plans = reinterpret_cast<PlanDev*>(base + align_up((size_t)n * sizeof(PlanDev)));
+    bt->dose_blocks = bd;
+    bt->price_blocks = bp;
+    bt->dose_cfg = default_cfg();
+    bt->price_cfg = default_cfg();
+    for (int i = 0; i < n; ++i) {
+        bt->n_vox.push_back(ddcs[i]->n_vox);
+        bt->n_bl.push_back(ddcs[i]->n_bl);
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    st = check_hip(hipMemcpyAsync(bt->dose_plans, dp.data(), n * sizeof(PlanDev), hipMemcpyHostToDevice, s),
+                   "dvmat_batch_create: copy");
+    if (!st) st = check_hip(hipMemcpyAsync(bt->price_plans, pp.data(), n * sizeof(PlanDev), hipMemcpyHostToDevice, s),
+                            "dvmat_batch_create: copy");
+    if (!st) st = check_hip(hipStreamSynchronize(s), "dvmat_batch_create: synchronize");
+    if (st) { delete bt; return st; }
+    *out = bt;
+    return DVMAT_OK;
+}
+
+void dvmat_batch_destroy(dvmat_batch b) { delete b; }
+
+dvmat_status dvmat_batch_dose(dvmat_batch b, const float* const* xs, int32_t nrhs, float* const* zs,
+                              dvmat_stream stream) {
+    return batch_call(b, true, b ? b->dose_cfg : KernelCfg{}, xs, nrhs, zs, reinterpret_cast<hipStream_t>(stream),
+                      "dvmat_batch_dose");
+}
+
+dvmat_status dvmat_batch_price(dvmat_batch b, const float* const* gs, int32_t nrhs, float* const* ps,
+                               dvmat_stream stream) {
+    return batch_call(b, false, b ? b->price_cfg : KernelCfg{}, gs, nrhs, ps, reinterpret_cast<hipStream_t>(stream),
+                      "dvmat_batch_price");
+}
+
+dvmat_status dvmat_batch_autotune(dvmat_batch b, const float* const* xs, float* const* zs, const float* const* gs,
+                                  float* const* ps, int32_t nrhs, int32_t reps, dvmat_stream stream) {
+    if (!b || !xs || !zs || !gs || !ps) return set_error(DVMAT_E_ARG, "dvmat_batch_autotune: NULL argument");
+    if (reps < 1) return set_error(DVMAT_E_ARG, "dvmat_batch_autotune: reps < 1");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    KernelCfg best{};
+    float ms = 0.0f;
+    dvmat_status st = tune([&](const KernelCfg& c) { return batch_call(b, true, c, xs, nrhs, zs, s, "dvmat_batch_autotune"); },
+                           reps, s, &best, &ms);
+    if (st) return st;
+    b->dose_cfg = best;
+    st = tune([&](const KernelCfg& c) { return batch_call(b, false, c, gs, nrhs, ps, s, "dvmat_batch_autotune"); },
+              reps, s, &best, &ms);
+    if (st) return st;
+    b->price_cfg = best;
+    return DVMAT_OK;
+}
+
+dvmat_status dvmat_batch_set_kernel(dvmat_batch b, int32_t orientation, int32_t kind, int32_t workgroups) {
+    if (!b) return set_error(DVMAT_E_ARG, "dvmat_batch_set_kernel: NULL handle");
+    if (kind != 0 && kind != 1) return set_error(DVMAT_E_ARG, "dvmat_batch_set_kernel: kind %d", kind);
+    if (workgroups < kNumXcd || workgroups > kMaxSpmvWorkgroups)
+        return set_error(DVMAT_E_ARG, "dvmat_batch_set_kernel: workgroups %d not in [8, 8192]", workgroups);
+    KernelCfg c{kind, workgroups};
+    if (orientation == 0) b->dose_cfg = c;
+    else if (orientation == 1) b->price_cfg = c;
+    else return set_error(DVMAT_E_ARG, "dvmat_batch_set_kernel: orientation %d", orientation);
+    return DVMAT_OK;
+}
+
+dvmat_status dvmat_batch_info(dvmat_batch b, int64_t* dose_blocks, int64_t* price_blocks, int32_t* cfg) {
+    if (!b) return set_error(DVMAT_E_ARG, "dvmat_batch_info: NULL handle");
+    if (dose_blocks) *dose_blocks = b->dose_blocks;
+    if (price_blocks) *price_blocks = b->price_blocks;
+    if (cfg) {
+        cfg[0] = b->dose_cfg.kind;
+        cfg[1] = b->dose_cfg.workgroups;
+        cfg[2] = b->price_cfg.kind;
+        cfg[3] = b->price_cfg.workgroups;
+    }
+    return DVMAT_OK;
+}
+
 }  // extern "C"
+
+namespace dvmat {
+KernelCfg initial_kernel_cfg() { return default_cfg(); }
+}  // namespace dvmat

@@ -39,7 +39,10 @@ class DdcInfo(ctypes.Structure):
                 ("n_blocks_dose", ctypes.c_int64), ("n_blocks_price", ctypes.c_int64),
                 ("nonempty_rows_dose", ctypes.c_int64), ("nonempty_rows_price", ctypes.c_int64),
                 ("storage", ctypes.c_int32), ("value_bytes", ctypes.c_int32),
-                ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t),
+                ("dose_kernel", ctypes.c_int32), ("dose_workgroups", ctypes.c_int32),
+                ("price_kernel", ctypes.c_int32), ("price_workgroups", ctypes.c_int32),
+                ("dose_tuned_ms", ctypes.c_float), ("price_tuned_ms", ctypes.c_float)]
 
 
 class Geom(ctypes.Structure):
@@ -68,6 +71,17 @@ _SIGNATURES = {
     "dvmat_dose": (_I32, [_P, _P, _I32, _P, _P, _P, _P, _P]),
     "dvmat_price": (_I32, [_P, _P, _I32, _P, _P]),
     "dvmat_dose_curvature": (_I32, [_P, _P, _P, _P, _P, _P, _P]),
+    "dvmat_ddc_autotune": (_I32, [_P, _P, _P, _P, _P, _I32, _P]),
+    "dvmat_ddc_set_kernel": (_I32, [_P, _I32, _I32, _I32]),
+    "dvmat_batch_workspace_size": (_I32, [_I32, ctypes.POINTER(_SZ)]),
+    "dvmat_batch_create": (_I32, [ctypes.POINTER(_P), _I32, _P, _SZ, _P, ctypes.POINTER(_P)]),
+    "dvmat_batch_destroy": (None, [_P]),
+    "dvmat_batch_dose": (_I32, [_P, ctypes.POINTER(_P), _I32, ctypes.POINTER(_P), _P]),
+    "dvmat_batch_price": (_I32, [_P, ctypes.POINTER(_P), _I32, ctypes.POINTER(_P), _P]),
+    "dvmat_batch_autotune": (_I32, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                    ctypes.POINTER(_P), _I32, _I32, _P]),
+    "dvmat_batch_set_kernel": (_I32, [_P, _I32, _I32, _I32]),
+    "dvmat_batch_info": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I32)]),
     "dvmat_aperture_select": (_I32, [Geom, _P, _P, _P, _P, _P, _P, _P, _P]),
     "dvmat_bb_workspace_size": (_I32, [Geom, _I32, ctypes.POINTER(_SZ)]),
     "dvmat_bb_create": (_I32, [Geom, _I32, BBParams, _P, _SZ, _P, ctypes.POINTER(_P)]),
@@ -78,6 +92,10 @@ _SIGNATURES = {
     "dvmat_bb_begin": (_I32, [_P, _P]),
     "dvmat_bb_direction": (_I32, [_P, _P, _P, _P]),
     "dvmat_bb_step": (_I32, [_P, _P, _P, _P, _P, _P, _P]),
+    "dvmat_bb_direction_g": (_I32, [_P, _P, _P, _P]),
+    "dvmat_bb_step_g": (_I32, [_P, _P, _P, _P, _P, _P, _P]),
+    "dvmat_aperture_expand": (_I32, [Geom, _I32, _P, _P, _P, _P, _P, _P]),
+    "dvmat_aperture_gather": (_I32, [Geom, _I32, _P, _P, _P, _P, _P, _P]),
     "dvmat_bb_expand": (_I32, [_P, _P, _P]),
     "dvmat_bb_get_y": (_I32, [_P, _P, _P]),
 }
@@ -215,6 +233,25 @@ class DDC:
         p = torch.empty(shape, dtype=torch.float32, device=g.device)
         self.price_(g, p)
         return p
+
+    def refresh_info(self):
+        _check(lib.dvmat_ddc_info(self._h, ctypes.byref(self.info)))
+        return self.info
+
+    def autotune(self, reps=5, seed=0):
+        """Pick the fastest launch shape per orientation (times every candidate)."""
+        gen = torch.Generator(device=self.device).manual_seed(seed)
+        x = torch.rand(self.n_bl, device=self.device, generator=gen)
+        g = torch.randn(self.n_vox, device=self.device, generator=gen)
+        z = torch.empty(self.n_vox, device=self.device)
+        p = torch.empty(self.n_bl, device=self.device)
+        _check(lib.dvmat_ddc_autotune(self._h, _ptr(x), _ptr(z), _ptr(g), _ptr(p), int(reps), _stream()))
+        return self.refresh_info()
+
+    def set_kernel(self, orientation: str, kind: str, workgroups: int):
+        _check(lib.dvmat_ddc_set_kernel(self._h, {"dose": 0, "price": 1}[orientation],
+                                        {"row": 0, "stream": 1}[kind], int(workgroups)))
+        return self.refresh_info()
 
     def curvature_(self, x_dir, obj, z_ref, curv, d_out=None, stream=None):
         _need(x_dir, self.n_bl, name="x_dir")
@@ -357,6 +394,19 @@ class BB:
         _check(lib.dvmat_bb_step(self._h, _ptr(p), _ptr(F), _ptr(curv), _ptr(x_next), _ptr(self.flags),
                                  _stream(stream)))
 
+    def direction_g_(self, G, x_dir, stream=None):
+        _need(G, self.count, name="G")
+        _need(x_dir, self.n_bl, name="x_dir")
+        _check(lib.dvmat_bb_direction_g(self._h, _ptr(G), _ptr(x_dir), _stream(stream)))
+
+    def step_g_(self, G, F, curv, x_next, stream=None):
+        _need(G, self.count, name="G")
+        _need(F, 1, name="F", at_least=True)
+        _need(curv, 1, torch.float64, name="curv", at_least=True)
+        _need(x_next, self.n_bl, name="x_next")
+        _check(lib.dvmat_bb_step_g(self._h, _ptr(G), _ptr(F), _ptr(curv), _ptr(x_next), _ptr(self.flags),
+                                   _stream(stream)))
+
     def expand_(self, x, stream=None):
         _need(x, self.n_bl, name="x")
         _check(lib.dvmat_bb_expand(self._h, _ptr(x), _stream(stream)))
@@ -365,6 +415,102 @@ class BB:
         out = torch.empty(max(self.count, 1), dtype=torch.float32, device=self.device)
         _check(lib.dvmat_bb_get_y(self._h, _ptr(out), _stream()))
         return out[:self.count]
+
+
+class Apertures:
+    """An explicit list of apertures (distinct control points) on the device,
+    with the fluence map x = B y and its adjoint G = B^T p."""
+
+    def __init__(self, n_cp, n_rows, n_cols, cps, L, R, device="cuda"):
+        self.geom = Geom(n_cp, n_rows, n_cols)
+        self.n_bl = n_cp * n_rows * n_cols
+        dev = torch.device(device)
+        cps = np.ascontiguousarray(cps, np.int32)
+        if len(set(cps.tolist())) != len(cps) or (len(cps) and (cps.min() < 0 or cps.max() >= n_cp)):
+            raise ValueError("apertures must sit at distinct control points in range")
+        L = np.ascontiguousarray(L, np.int32).reshape(len(cps), n_rows)
+        R = np.ascontiguousarray(R, np.int32).reshape(len(cps), n_rows)
+        if np.any(L < 0) or np.any(R > n_cols) or np.any(L > R):
+            raise ValueError("openings must satisfy 0 <= L <= R <= n_cols")
+        self.m = len(cps)
+        self.cps = torch.from_numpy(cps).to(dev)
+        self.L = torch.from_numpy(L).to(dev)
+        self.R = torch.from_numpy(R).to(dev)
+
+    def expand_(self, y, x, stream=None):
+        _need(y, self.m, name="y")
+        _need(x, self.n_bl, name="x")
+        _check(lib.dvmat_aperture_expand(self.geom, self.m, _ptr(self.cps), _ptr(self.L), _ptr(self.R), _ptr(y),
+                                         _ptr(x), _stream(stream)))
+
+    def gather_(self, p, G, stream=None):
+        _need(p, self.n_bl, name="p")
+        _need(G, self.m, name="G")
+        _check(lib.dvmat_aperture_gather(self.geom, self.m, _ptr(self.cps), _ptr(self.L), _ptr(self.R), _ptr(p),
+                                         _ptr(G), _stream(stream)))
+
+
+class Batch:
+    """Several plans' products in one launch each (dose, price)."""
+
+    def __init__(self, ddcs, device="cuda"):
+        self.ddcs = list(ddcs)
+        n = len(self.ddcs)
+        nbytes = _SZ()
+        _check(lib.dvmat_batch_workspace_size(n, ctypes.byref(nbytes)))
+        self.device = torch.device(device)
+        self.workspace = _workspace(nbytes.value, self.device)
+        arr = (_P * n)(*[d.handle.value for d in self.ddcs])
+        h = _P()
+        _check(lib.dvmat_batch_create(arr, n, _ptr(self.workspace), self.workspace.numel(), _stream(),
+                                      ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib.dvmat_batch_destroy(h)
+            self._h = None
+
+    def _ptrs(self, ts, sizes, name):
+        if len(ts) != len(self.ddcs):
+            raise ValueError(f"{name}: {len(ts)} tensors for {len(self.ddcs)} plans")
+        nrhs = 1 if ts[0].dim() == 1 else ts[0].shape[1]
+        for t, n in zip(ts, sizes):
+            _need(t, n * nrhs, name=name)
+            if (1 if t.dim() == 1 else t.shape[1]) != nrhs:
+                raise ValueError(f"{name}: mixed nrhs")
+        return (_P * len(ts))(*[t.data_ptr() for t in ts]), nrhs
+
+    def dose_(self, xs, zs, stream=None):
+        px, nrhs = self._ptrs(xs, [d.n_bl for d in self.ddcs], "x")
+        pz, _ = self._ptrs(zs, [d.n_vox for d in self.ddcs], "z")
+        _check(lib.dvmat_batch_dose(self._h, px, nrhs, pz, _stream(stream)))
+
+    def price_(self, gs, ps, stream=None):
+        pg, nrhs = self._ptrs(gs, [d.n_vox for d in self.ddcs], "g")
+        pp, _ = self._ptrs(ps, [d.n_bl for d in self.ddcs], "p")
+        _check(lib.dvmat_batch_price(self._h, pg, nrhs, pp, _stream(stream)))
+
+    def autotune(self, xs, zs, gs, ps, reps=3):
+        px, nrhs = self._ptrs(xs, [d.n_bl for d in self.ddcs], "x")
+        pz, _ = self._ptrs(zs, [d.n_vox for d in self.ddcs], "z")
+        pg, _ = self._ptrs(gs, [d.n_vox for d in self.ddcs], "g")
+        pp, _ = self._ptrs(ps, [d.n_bl for d in self.ddcs], "p")
+        _check(lib.dvmat_batch_autotune(self._h, px, pz, pg, pp, nrhs, int(reps), _stream()))
+        return self.info()
+
+    def set_kernel(self, orientation: str, kind: str, workgroups: int):
+        _check(lib.dvmat_batch_set_kernel(self._h, {"dose": 0, "price": 1}[orientation],
+                                          {"row": 0, "stream": 1}[kind], int(workgroups)))
+        return self.info()
+
+    def info(self):
+        nd, npb = _I64(), _I64()
+        cfg = (_I32 * 4)()
+        _check(lib.dvmat_batch_info(self._h, ctypes.byref(nd), ctypes.byref(npb), cfg))
+        return dict(dose_blocks=nd.value, price_blocks=npb.value, dose_kernel=cfg[0], dose_workgroups=cfg[1],
+                    price_kernel=cfg[2], price_workgroups=cfg[3])
 
 
 def exported_symbols():

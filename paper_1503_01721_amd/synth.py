@@ -95,6 +95,9 @@ PLANS: Dict[str, Plan] = {
     "cp20_bl20x20_vox32": Plan("cp20_bl20x20_vox32", 20, 20, 20, 5.0, 32, 2.5),
     "cp180_bl40x40_vox128": Plan("cp180_bl40x40_vox128", 180, 40, 40, 5.0, 128, 2.5),
     "cp360_bl60x60_vox160": Plan("cp360_bl60x60_vox160", 360, 60, 60, 3.3, 160, 2.0),
+    # two-arc pitches (3.3 mm beamlets, 2 mm voxels) at a size the oracle finishes quickly
+    "cp64_bl12x12_vox40": Plan("cp64_bl12x12_vox40", 64, 12, 12, 3.3, 40, 2.0,
+                               ((0.0, 0.0, 0.0, 12.0, 70.0),)),
 }
 
 

@@ -1,0 +1,109 @@
+"""Batched form: several plans of uneven size, several right-hand sides, one
+launch per product; checked per plan against the FP64 oracle, against
+one-plan-at-a-time calls, and under graph capture and replay."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import products as oprod
+from paper_1503_01721_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _plans():
+    names = ["tiny_cp4_bl3x4_vox8", "small_cp8_bl6x6_vox16", "cp20_bl20x20_vox32", "cp64_bl12x12_vox40"]
+    out = [(synth.PLANS[n].n_vox, synth.PLANS[n].n_bl, synth.generate_ddc(synth.PLANS[n])) for n in names]
+    out.append((3001, 517, synth.random_sparse(3001, 517, 0.02, 5, empty_rows=300, empty_cols=40)))
+    return out
+
+
+@pytest.fixture(scope="module")
+def plans():
+    assert torch.cuda.is_available()
+    return _plans()
+
+
+def _dequant(d, n_bl, storage):
+    if storage == "f32":
+        return d["val"].astype(np.float64)
+    s = np.zeros(n_bl, np.float32)
+    np.maximum.at(s, d["col"], np.abs(d["val"]))
+    s[s == 0] = 1.0
+    q = d["val"] / s[d["col"]]
+    if storage == "f16":
+        q = q.astype(np.float16).astype(np.float32)
+    else:
+        u = np.ascontiguousarray(q, np.float32).view(np.uint32).astype(np.uint64)
+        q = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16).astype(np.uint32).view(np.float32)
+    return q.astype(np.float64) * s[d["col"]]
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("nrhs", [1, 8])
+@pytest.mark.parametrize("kind", ["row", "stream"])
+def test_batch_matches_oracle_and_single_calls(plans, storage, nrhs, kind):
+    from paper_1503_01721_amd import dvmat
+    ddcs = [dvmat.DDC(d["row"], d["col"], d["val"], nv, nb, storage=storage) for nv, nb, d in plans]
+    batch = dvmat.Batch(ddcs)
+    info = batch.info()
+    assert info["dose_blocks"] == sum(x.info.n_blocks_dose for x in ddcs)
+    for orient in ("dose", "price"):
+        batch.set_kernel(orient, kind, 1024)
+        for x in ddcs:
+            x.set_kernel(orient, kind, 1024)
+    rng = np.random.default_rng(100 + nrhs)
+    xs = [rng.random((nb, nrhs) if nrhs > 1 else nb).astype(np.float32) for nv, nb, _ in plans]
+    gs = [rng.standard_normal((nv, nrhs) if nrhs > 1 else nv).astype(np.float32) for nv, nb, _ in plans]
+    xt = [torch.from_numpy(x).cuda() for x in xs]
+    gt = [torch.from_numpy(g).cuda() for g in gs]
+    zt = [torch.empty((nv, nrhs) if nrhs > 1 else nv, device="cuda") for nv, nb, _ in plans]
+    pt = [torch.empty((nb, nrhs) if nrhs > 1 else nb, device="cuda") for nv, nb, _ in plans]
+    batch.dose_(xt, zt)
+    batch.price_(gt, pt)
+    for (nv, nb, d), x, g, z, p, one in zip(plans, xs, gs, zt, pt, ddcs):
+        val = _dequant(d, nb, storage)
+        z_ref = oprod.dose(d["row"], d["col"], val, x, nv)
+        p_ref = oprod.price(d["row"], d["col"], val, g, nb)
+        assert np.abs(z.cpu().numpy() - z_ref).max() <= TOL * max(np.abs(z_ref).max(), 1e-30)
+        scale = oprod.price(d["row"], d["col"], np.abs(val), np.abs(g), nb).max()
+        assert np.abs(p.cpu().numpy() - p_ref).max() <= TOL * scale
+        # the batched launch equals the one-plan launch of the same kernel kind
+        assert torch.allclose(one.dose(torch.from_numpy(x).cuda()), z, rtol=1e-6, atol=1e-6 * float(z.abs().max()))
+
+
+def test_batch_graph_capture_replays(plans):
+    from paper_1503_01721_amd import dvmat
+    ddcs = [dvmat.DDC(d["row"], d["col"], d["val"], nv, nb, storage="f16") for nv, nb, d in plans]
+    batch = dvmat.Batch(ddcs)
+    rng = np.random.default_rng(7)
+    xt = [torch.from_numpy(rng.random((nb, 8)).astype(np.float32)).cuda() for nv, nb, _ in plans]
+    gt = [torch.from_numpy(rng.standard_normal((nv, 8)).astype(np.float32)).cuda() for nv, nb, _ in plans]
+    zt = [torch.empty((nv, 8), device="cuda") for nv, nb, _ in plans]
+    pt = [torch.empty((nb, 8), device="cuda") for nv, nb, _ in plans]
+    batch.dose_(xt, zt)
+    batch.price_(gt, pt)
+    torch.cuda.synchronize()
+    z_eager = [z.clone() for z in zt]
+    p_eager = [p.clone() for p in pt]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            batch.dose_(xt, zt)
+            batch.price_(gt, pt)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        for z in zt:
+            z.fill_(-1.0)
+        for p in pt:
+            p.fill_(-1.0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(zt, z_eager):
+            assert torch.equal(a, b), rep
+        for a, b in zip(pt, p_eager):
+            assert torch.equal(a, b), rep
