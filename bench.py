@@ -99,6 +99,161 @@ def copy_calibration():
                       "launches": 5}), flush=True)
 
 
+def plain_bytes(info, nrhs):
+    """Algorithmic bytes of a plain dose and a plain price product with nrhs vectors."""
+    n_vox, n_bl, nnz = info.n_vox, info.n_bl, info.nnz
+    mat = nnz * (info.value_bytes + 4)
+    scale = 4 * n_bl if info.value_bytes == 2 else 0
+    return (mat + 8 * (n_vox + 1) + 4 * nrhs * (n_bl + n_vox) + scale,
+            mat + 8 * (n_bl + 1) + 4 * nrhs * (n_vox + n_bl) + scale)
+
+
+def bench_batched(args):
+    """Many plans of uneven size, 8 right-hand sides each: one captured graph of
+    the batched dose and price launches vs one launch per plan."""
+    import torch
+    from paper_1503_01721_amd import dvmat, synth
+    storage = args.storage if args.storage != "f32" or "--storage" in sys.argv else "f16"
+    plans = synth.batched_plans(args.plans, 2005)
+    nrhs = 8
+    ddcs, t_gen, t_build = [], 0.0, 0.0
+    for i, p in enumerate(plans):
+        t = time.perf_counter()
+        d = synth.generate_ddc(p)
+        t_gen += time.perf_counter() - t
+        t = time.perf_counter()
+        ddcs.append(dvmat.DDC(d["row"], d["col"], d["val"], p.n_vox, p.n_bl, storage=storage))
+        t_build += time.perf_counter() - t
+        del d
+        if i % 8 == 7 or i == len(plans) - 1:
+            log(f"built {i + 1}/{len(plans)} plans (generate {t_gen:.1f} s, build {t_build:.1f} s)")
+    nnz = sum(x.info.nnz for x in ddcs)
+    gen = torch.Generator(device="cuda").manual_seed(2005)
+    X = [torch.rand((x.n_bl, nrhs), device="cuda", generator=gen) for x in ddcs]
+    G = [torch.randn((x.n_vox, nrhs), device="cuda", generator=gen) for x in ddcs]
+    Z = [torch.empty((x.n_vox, nrhs), device="cuda") for x in ddcs]
+    P = [torch.empty((x.n_bl, nrhs), device="cuda") for x in ddcs]
+    batch = dvmat.Batch(ddcs)
+    if not args.no_autotune:
+        binfo = batch.autotune(X, Z, G, P, reps=3)
+        for x in ddcs:
+            x.autotune(reps=3)
+        log(f"autotuned: batch {binfo}")
+    binfo = batch.info()
+    total = sum(sum(plain_bytes(x.info, nrhs)) for x in ddcs)
+    # batched: one captured graph holding the two launches
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        batch.dose_(X, Z)
+        batch.price_(G, P)
+        s.synchronize()
+        with torch.cuda.graph(graph, stream=s):
+            batch.dose_(X, Z)
+            batch.price_(G, P)
+    torch.cuda.current_stream().wait_stream(s)
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    t_batched = (time.perf_counter() - t0) / args.steps
+    # one plan at a time
+    for _ in range(args.warmup):
+        for x, xx, zz, gg, pp in zip(ddcs, X, Z, G, P):
+            x.dose_(xx, zz)
+            x.price_(gg, pp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for x, xx, zz, gg, pp in zip(ddcs, X, Z, G, P):
+            x.dose_(xx, zz)
+            x.price_(gg, pp)
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - t0) / args.steps
+    gbs_b, gbs_s = total / t_batched / 1e9, total / t_seq / 1e9
+    log(f"batched {t_batched * 1e3:.2f} ms ({gbs_b:.0f} GB/s) vs one-plan-at-a-time {t_seq * 1e3:.2f} ms "
+        f"({gbs_s:.0f} GB/s)")
+    print(json.dumps({
+        "metric": "aggregate effective HBM GB/s of dose + price over all plans (batched launch)",
+        "value": round(gbs_b, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(t_batched * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": storage, "data": "synthetic",
+        "config": {"workload": f"{len(plans)} uneven plans x {nrhs} right-hand sides", "nnz_total": int(nnz),
+                   "storage": storage, "nrhs": nrhs, "algorithmic_bytes_per_step": int(total),
+                   "one_plan_at_a_time_gbs": round(gbs_s, 2), "one_plan_at_a_time_ms": round(t_seq * 1e3, 3),
+                   "speedup_vs_one_plan_at_a_time": round(t_seq / t_batched, 3),
+                   "pct_hbm_peak": round(100.0 * gbs_b / HBM_PEAK_GBS, 2), "batch_launch": binfo,
+                   "generate_s": round(t_gen, 1), "build_upload_s": round(t_build, 1)},
+    }), flush=True)
+
+
+def bench_autograd(args):
+    """Differentiation form: F(D B y) and dF/dy by autograd (dose forward, price
+    backward) for 64 random apertures on the two-arc workload."""
+    import numpy as np
+    import torch
+    from paper_1503_01721_amd import dvmat, synth
+    from paper_1503_01721_amd.autograd import plan_objective
+    workload = args.workload if args.workload != "cp180_bl40x40_vox128" else "cp360_bl60x60_vox160"
+    storage = args.storage if "--storage" in sys.argv else "f16"
+    plan = synth.PLANS[workload]
+    t = time.perf_counter()
+    d = synth.generate_ddc(plan)
+    sid, table = synth.structures(plan)
+    t_gen = time.perf_counter() - t
+    log(f"generated {plan.name}: nnz={len(d['val'])} in {t_gen:.1f} s")
+    t = time.perf_counter()
+    ddc = dvmat.DDC(d["row"], d["col"], d["val"], plan.n_vox, plan.n_bl, storage=storage)
+    del d
+    obj = dvmat.Objective(sid, table)
+    t_build = time.perf_counter() - t
+    log(f"built and uploaded {ddc.info.workspace_bytes / 2**30:.1f} GiB in {t_build:.1f} s")
+    if not args.no_autotune:
+        ddc.autotune(reps=3)
+    cps, L, R = synth.random_apertures(plan, 64, 2004)
+    aps = dvmat.Apertures(plan.n_cp, plan.n_rows, plan.n_cols, cps, L, R)
+    # rates scaled so that the mean PTV dose is the prescription at y = 1
+    x1 = torch.empty(plan.n_bl, device="cuda")
+    aps.expand_(torch.ones(64, device="cuda"), x1)
+    z1 = ddc.dose(x1)
+    ptv = torch.from_numpy(sid == synth.S_PTV0).cuda()
+    scale = 70.0 / float(z1[ptv].mean())
+    rng = np.random.default_rng(2004)
+    y = torch.tensor(rng.uniform(0.5, 1.5, 64) * scale, dtype=torch.float32, device="cuda", requires_grad=True)
+
+    def step():
+        y.grad = None
+        F = plan_objective(y, aps, ddc, obj)
+        F.backward()
+        return F
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        F = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    bd, bp = plain_bytes(ddc.info, 1)
+    extra = plan.n_vox * (4 + 1 + 4) + 4 * plan.n_bl            # objective pass, fluence expansion
+    gbs = (bd + bp + extra) / dt / 1e9
+    log(f"F = {float(F):.6g}; forward+backward {dt * 1e3:.3f} ms ({gbs:.0f} GB/s)")
+    print(json.dumps({
+        "metric": "effective HBM GB/s of one autograd evaluation of F(D B y) and dF/dy",
+        "value": round(gbs, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": storage, "data": "synthetic",
+        "config": {"workload": plan.name, "n_vox": plan.n_vox, "n_beamlets": plan.n_bl, "nnz": int(ddc.info.nnz),
+                   "apertures": 64, "storage": storage, "pct_hbm_peak": round(100.0 * gbs / HBM_PEAK_GBS, 2),
+                   "generate_s": round(t_gen, 1), "build_upload_s": round(t_build, 1)},
+    }), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +264,11 @@ def main():
     ap.add_argument("--bb-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--mode", default="colgen", choices=["colgen", "batched", "autograd"],
+                    help="colgen: column-generation iterations (default); batched: many plans x 8 "
+                         "right-hand sides in one launch vs one plan at a time; autograd: F(D B y) "
+                         "forward + backward on the two-arc workload")
+    ap.add_argument("--plans", type=int, default=48, help="plans in --mode batched")
     ap.add_argument("--copy-calibration", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
 
@@ -124,6 +284,11 @@ def main():
 
     from paper_1503_01721_amd import dvmat, synth
     from paper_1503_01721_amd.colgen import ColumnGeneration
+
+    if args.mode == "batched":
+        return bench_batched(args)
+    if args.mode == "autograd":
+        return bench_autograd(args)
 
     plan = synth.PLANS[args.workload]
     if args.warmup + args.steps > plan.n_cp:

@@ -101,6 +101,34 @@ PLANS: Dict[str, Plan] = {
 }
 
 
+def batched_plans(n: int = 48, seed: int = 2005, max_cp: int = 180, max_grid: int = 40, max_vox: int = 128):
+    """n independent plans of uneven size: angles U{60..max_cp}, beamlet grids
+    U{20..max_grid} square at 5 mm, voxel cubes U{48..max_vox} at 2.5 mm, 1-3
+    non-overlapping spherical PTVs of radius U[12, 20] mm centred within
+    0.4 R_b, prescriptions drawn from {70, 59.4, 54} Gy (the three PTV levels
+    of the paper's head-and-neck case, Sec. 2.4)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(n):
+        n_cp = int(rng.integers(60, max_cp + 1))
+        grid = int(rng.integers(20, max_grid + 1))
+        nv = int(rng.integers(48, max_vox + 1))
+        R = min(0.45 * nv * 2.5, 115.0)
+        ptvs = []
+        want = int(rng.integers(1, 4))
+        tries = 0
+        while len(ptvs) < want and tries < 1000:
+            tries += 1
+            rad = float(rng.uniform(12.0, 20.0))
+            c = rng.uniform(-0.4 * R, 0.4 * R, 3)
+            if np.linalg.norm(c) > 0.4 * R:
+                continue
+            if all(np.linalg.norm(c - np.array(q[:3])) > rad + q[3] for q in ptvs):
+                ptvs.append((float(c[0]), float(c[1]), float(c[2]), rad, float(rng.choice([70.0, 59.4, 54.0]))))
+        out.append(Plan(f"batch{i:02d}_cp{n_cp}_bl{grid}x{grid}_vox{nv}", n_cp, grid, grid, 5.0, nv, 2.5, tuple(ptvs)))
+    return out
+
+
 def axis_centres(n: int, pitch: float) -> np.ndarray:
     return (np.arange(n, dtype=np.float64) - (n - 1) / 2.0) * pitch
 
@@ -210,10 +238,15 @@ def generate_ddc(plan: Plan, cps: Optional[List[int]] = None, threads: Optional[
     col = np.empty(nnz, np.int32)
     val = np.empty(nnz, np.float32)
     o = 0
-    for r_, c_, v_ in parts:
+    # copy part by part and drop each part once copied: the output's pages are
+    # committed as they are written, so the peak stays near one copy
+    parts.reverse()
+    while parts:
+        r_, c_, v_ = parts.pop()
         n = len(r_)
         row[o:o + n], col[o:o + n], val[o:o + n] = r_, c_, v_
         o += n
+        del r_, c_, v_
     return dict(row=row, col=col, val=val)
 
 
