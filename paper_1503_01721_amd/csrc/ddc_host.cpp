@@ -84,12 +84,38 @@ static uint16_t float_to_bf16_bits(float f) {
     return (uint16_t)(u >> 16);
 }
 
+// Within each 256-entry chunk of a row (the tail chunk: n entries, a multiple
+// of 4), store sorted entry l + q*(n/4) at position 4*l + q.  A wave's lane l
+// then loads entries l, l+n/4, l+2n/4, l+3n/4 with one 16-byte load, and each
+// of its four gather instructions covers n/4 consecutive sorted columns (a few
+// cache lines) instead of n/4 columns spaced 4 apart.  Sums are unchanged up to
+// the order of addition; every entry stays in its row.
+static bool interleave_enabled() {
+    const char* s = std::getenv("DVMAT_INTERLEAVE");
+    return !(s && s[0] == '0');
+}
+
+static void interleave_row(int32_t* c, float* v, int64_t len, std::vector<int32_t>& tc, std::vector<float>& tv) {
+    for (int64_t base = 0; base < len; base += 256) {
+        const int64_t n = std::min<int64_t>(256, len - base);
+        const int64_t w = n / 4;
+        tc.assign(c + base, c + base + n);
+        tv.assign(v + base, v + base + n);
+        for (int64_t l = 0; l < w; ++l)
+            for (int q = 0; q < 4; ++q) {
+                c[base + 4 * l + q] = tc[l + q * w];
+                v[base + 4 * l + q] = tv[l + q * w];
+            }
+    }
+}
+
 // Build one CSR orientation from COO keys (rk = row of this orientation,
 // ck = column).  Row padding to kRowPad, duplicates summed, columns sorted.
 static dvmat_status build_orientation(int64_t n_rows, int64_t nnz, const int32_t* rk,
                                       const int32_t* ck, const float* v, CsrHost& out,
                                       std::vector<float>& fval, std::vector<int64_t>& len_u) {
-    const int T = std::max(1, (int)std::min<int64_t>(host_threads(), nnz >= (1 << 16) ? 1 << 30 : 1));
+    const int T = nnz >= (1 << 16) ? host_threads() : 1;
+    const bool interleave = interleave_enabled();
     try {
         // per-thread histograms over contiguous entry chunks (stable scatter order)
         std::vector<std::vector<int64_t>> hist(T, std::vector<int64_t>());
@@ -180,6 +206,7 @@ static dvmat_status build_orientation(int64_t n_rows, int64_t nnz, const int32_t
                 const int64_t e = out.rowptr[r + 1];
                 const int32_t last = m > 0 ? c[m - 1] : 0;
                 for (int64_t k = s + m; k < e; ++k) { out.col[k] = last; fval[k] = 0.0f; }
+                if (interleave) interleave_row(out.col.data() + s, fval.data() + s, e - s, tc, tv);
             }
         });
         // row blocks: consecutive rows up to a stored-entry budget and a row
