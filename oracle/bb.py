@@ -116,9 +116,9 @@ def solve(apply, adjoint, sid, table, y0, lo, hi, params=BBParams(), record=Fals
         else:
             s = y - y_prev
             q = Gt - Gt_prev
-            ss, sq, qq = float(np.dot(s, s)), float(np.dot(s, q)), float(np.dot(q, q))
+            ss, sq, qq = np.dot(s, s), np.dot(s, q), np.dot(q, q)     # float64 scalars: x/0 is inf/nan
             with np.errstate(divide="ignore", invalid="ignore"):
-                cand = ss / sq if (t % 2 == 1) else sq / qq
+                cand = float(ss / sq if (t % 2 == 1) else sq / qq)
             if sq > 0.0 and np.isfinite(cand) and cand > 0.0:
                 alpha = cand
             else:
