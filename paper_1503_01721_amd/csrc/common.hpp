@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/dvmat.h"
+#include "dvmat.h"
 
 namespace dvmat {
 
