@@ -67,8 +67,8 @@ int32_t dvmat_version(void);
  * in one GPU's memory: CSR of D ("dose matrix", rows = voxels) for z = D x,
  * and CSR of D^T ("price matrix", rows = beamlets) for p = D^T g.  Row
  * pointers are int64 (more than 2^31 non-zeros fit), column indices int32,
- * every row is padded with explicit zeros to a multiple of 4 entries so that
- * rows start on 16-byte boundaries.
+ * every (block) row is padded with explicit zeros to a multiple of 4 entries
+ * so that rows start on 16-byte boundaries.
  * ---------------------------------------------------------------------- */
 typedef struct dvmat_ddc_s* dvmat_ddc;
 
@@ -83,7 +83,27 @@ typedef struct {
     int32_t dose_kernel, dose_workgroups;   /* launch shape in use: kernel 0 = row, 1 = stream */
     int32_t price_kernel, price_workgroups;
     float dose_tuned_ms, price_tuned_ms;    /* autotuner's best times (0 before tuning) */
+    int32_t dose_block_rows, price_block_rows;  /* rows sharing one column index (build option) */
 } dvmat_ddc_info_t;
+
+/* Build options of the device layout.  block_rows B in {1, 2, 4}: B
+ * consecutive rows form a block row that stores the union of their columns
+ * once, with B values per column (zeros where a row lacks it), so one index
+ * load and one gather of the input vector serve B rows.  Neighbouring voxels
+ * see almost the same beamlets (the dose matrix gains; default B = 4 there);
+ * neighbouring beamlets overlap less (default B = 1 for the price matrix).
+ * interleave (0/1, default 1): store the entries of each 256-entry chunk of a
+ * block row interleaved so that each gather instruction of a wave covers
+ * consecutive columns.  unit_entries: stored values per work unit (default 2048). */
+typedef struct {
+    int32_t dose_block_rows;
+    int32_t price_block_rows;
+    int32_t interleave;
+    int32_t unit_entries;
+} dvmat_build_opts;
+
+/* Fill opts with the defaults. */
+dvmat_status dvmat_ddc_default_opts(dvmat_build_opts* opts);
 
 /* Validate host COO (row = voxel, col = beamlet, val; length nnz; read during
  * the call only), sum duplicate pairs, build both CSR orientations, row blocks
@@ -94,6 +114,12 @@ typedef struct {
 dvmat_status dvmat_ddc_create(int64_t n_vox, int64_t n_bl, int64_t nnz,
                               const int32_t* row_vox, const int32_t* col_bl,
                               const float* val, int32_t storage, dvmat_ddc* out);
+/* As dvmat_ddc_create with explicit build options (NULL = defaults);
+ * DVMAT_E_ARG for options out of range. */
+dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz,
+                                 const int32_t* row_vox, const int32_t* col_bl,
+                                 const float* val, int32_t storage,
+                                 const dvmat_build_opts* opts, dvmat_ddc* out);
 /* Sizes and counts; valid right after create. */
 dvmat_status dvmat_ddc_info(dvmat_ddc ddc, dvmat_ddc_info_t* info);
 /* Copy the staged matrices into the caller's device workspace (>= info.

@@ -44,22 +44,25 @@ inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a
 
 // One CSR orientation inside the device workspace.
 struct CsrDev {
-    int64_t n_rows = 0;
+    int64_t n_rows = 0;                // rows of the orientation (voxels or beamlets)
+    int B = 1;                         // rows per block row
     int64_t nnz_pad = 0;
     int64_t n_blocks = 0;
     int64_t nonempty = 0;
-    const int64_t* rowptr = nullptr;   // [n_rows + 1]
-    const int32_t* col = nullptr;      // [nnz_pad]
-    const void* val = nullptr;         // [nnz_pad] of value_bytes
-    const int32_t* blocks = nullptr;   // [n_blocks + 1] first row of each block
+    const int64_t* rowptr = nullptr;   // [n_block_rows + 1], in block entries
+    const int32_t* col = nullptr;      // [block entries]
+    const void* val = nullptr;         // [block entries * B] of value_bytes
+    const int32_t* blocks = nullptr;   // [n_blocks + 1] first block row of each work unit
 };
 
 // Host staging of one orientation before bind.
 struct CsrHost {
     int64_t n_rows = 0;
+    int B = 1;
+    int64_t n_brows = 0;
     std::vector<int64_t> rowptr;
     std::vector<int32_t> col;
-    std::vector<uint8_t> val;          // value_bytes per entry
+    std::vector<uint8_t> val;          // value_bytes per value, B values per block entry
     std::vector<int32_t> blocks;
     int64_t nonempty = 0;
 };
@@ -78,6 +81,7 @@ struct dvmat_ddc_s {
     float* xs = nullptr;               // device [n_bl * kMaxRhs] scaled-x scratch (16-bit)
     size_t ws_bytes = 0;
     dvmat::KernelCfg dose_cfg{0, 2048}, price_cfg{0, 2048};
+    dvmat_build_opts opts{};
     float dose_tuned_ms = 0.0f, price_tuned_ms = 0.0f;
     // workspace layout offsets
     size_t off_dose_rowptr = 0, off_dose_col = 0, off_dose_val = 0, off_dose_blocks = 0;

@@ -59,14 +59,6 @@ static void parallel_for(int64_t n, F&& f) {
     for (auto& x : th) x.join();
 }
 
-static int64_t block_nnz_cap() {
-    if (const char* s = std::getenv("DVMAT_BLOCK_NNZ")) return std::max<int64_t>(kRowPad, std::atoll(s));
-    return 2048;
-}
-static int32_t block_row_cap() {
-    if (const char* s = std::getenv("DVMAT_BLOCK_ROWS")) return std::max(1, std::min(std::atoi(s), kBlockRowsMax));
-    return kBlockRowsMax;
-}
 
 // IEEE binary16, round to nearest even (finite inputs; overflow -> inf).
 static uint16_t float_to_half_bits(float f) {
@@ -84,179 +76,238 @@ static uint16_t float_to_bf16_bits(float f) {
     return (uint16_t)(u >> 16);
 }
 
-// Within each 256-entry chunk of a row (the tail chunk: n entries, a multiple
-// of 4), store sorted entry l + q*(n/4) at position 4*l + q.  A wave's lane l
-// then loads entries l, l+n/4, l+2n/4, l+3n/4 with one 16-byte load, and each
-// of its four gather instructions covers n/4 consecutive sorted columns (a few
-// cache lines) instead of n/4 columns spaced 4 apart.  Sums are unchanged up to
-// the order of addition; every entry stays in its row.
-static bool interleave_enabled() {
-    const char* s = std::getenv("DVMAT_INTERLEAVE");
-    return !(s && s[0] == '0');
-}
+// Rows of one orientation, sorted by column with duplicates summed: row r's
+// entries sit at [start[r], start[r] + len[r]) of col/val.
+struct SortedRows {
+    std::vector<int64_t> start;
+    std::vector<int64_t> len;
+    std::vector<int32_t> col;
+    std::vector<float> val;
+};
 
-static void interleave_row(int32_t* c, float* v, int64_t len, std::vector<int32_t>& tc, std::vector<float>& tv) {
-    for (int64_t base = 0; base < len; base += 256) {
-        const int64_t n = std::min<int64_t>(256, len - base);
-        const int64_t w = n / 4;
-        tc.assign(c + base, c + base + n);
-        tv.assign(v + base, v + base + n);
-        for (int64_t l = 0; l < w; ++l)
-            for (int q = 0; q < 4; ++q) {
-                c[base + 4 * l + q] = tc[l + q * w];
-                v[base + 4 * l + q] = tv[l + q * w];
-            }
-    }
-}
-
-// Build one CSR orientation from COO keys (rk = row of this orientation,
-// ck = column).  Row padding to kRowPad, duplicates summed, columns sorted.
-static dvmat_status build_orientation(int64_t n_rows, int64_t nnz, const int32_t* rk,
-                                      const int32_t* ck, const float* v, CsrHost& out,
-                                      std::vector<float>& fval, std::vector<int64_t>& len_u) {
+// Stable counting sort of COO by row key rk (per-thread histograms over
+// contiguous entry chunks keep the input order inside a row), then per row:
+// sort by column if needed and sum duplicate pairs.
+static dvmat_status sort_rows(int64_t n_rows, int64_t nnz, const int32_t* rk, const int32_t* ck, const float* v,
+                              SortedRows& out) {
     const int T = nnz >= (1 << 16) ? host_threads() : 1;
-    const bool interleave = interleave_enabled();
     try {
-        // per-thread histograms over contiguous entry chunks (stable scatter order)
-        std::vector<std::vector<int64_t>> hist(T, std::vector<int64_t>());
+        std::vector<std::vector<int64_t>> hist(T);
         std::vector<std::thread> th;
         for (int t = 0; t < T; ++t) {
             th.emplace_back([&, t] {
                 hist[t].assign(n_rows, 0);
-                int64_t a = nnz * t / T, b = nnz * (t + 1) / T;
+                const int64_t a = nnz * t / T, b = nnz * (t + 1) / T;
                 int64_t* h = hist[t].data();
                 for (int64_t k = a; k < b; ++k) h[rk[k]]++;
             });
         }
         for (auto& x : th) x.join();
         th.clear();
-        out.n_rows = n_rows;
-        out.rowptr.assign(n_rows + 1, 0);
-        std::vector<int64_t> len(n_rows, 0);
+        out.start.assign(n_rows + 1, 0);
+        out.len.assign(n_rows, 0);
         parallel_for(n_rows, [&](int64_t a, int64_t b, int) {
             for (int64_t r = a; r < b; ++r) {
-                int64_t s = 0;
-                for (int t = 0; t < T; ++t) s += hist[t][r];
-                len[r] = s;
+                int64_t c = 0;
+                for (int t = 0; t < T; ++t) c += hist[t][r];
+                out.len[r] = c;
             }
         });
-        for (int64_t r = 0; r < n_rows; ++r)
-            out.rowptr[r + 1] = out.rowptr[r] + (len[r] + kRowPad - 1) / kRowPad * kRowPad;
-        const int64_t nnz_pad = out.rowptr[n_rows];
-        // thread-row start offsets, in place of the histograms
+        for (int64_t r = 0; r < n_rows; ++r) out.start[r + 1] = out.start[r] + out.len[r];
         parallel_for(n_rows, [&](int64_t a, int64_t b, int) {
             for (int64_t r = a; r < b; ++r) {
-                int64_t pos = out.rowptr[r];
+                int64_t pos = out.start[r];
                 for (int t = 0; t < T; ++t) {
-                    int64_t c = hist[t][r];
+                    const int64_t c = hist[t][r];
                     hist[t][r] = pos;
                     pos += c;
                 }
             }
         });
-        out.col.assign(nnz_pad, 0);
-        fval.assign(nnz_pad, 0.0f);
+        out.col.resize(nnz);
+        out.val.resize(nnz);
         for (int t = 0; t < T; ++t) {
             th.emplace_back([&, t] {
-                int64_t a = nnz * t / T, b = nnz * (t + 1) / T;
+                const int64_t a = nnz * t / T, b = nnz * (t + 1) / T;
                 int64_t* h = hist[t].data();
                 for (int64_t k = a; k < b; ++k) {
-                    int64_t p = h[rk[k]]++;
+                    const int64_t p = h[rk[k]]++;
                     out.col[p] = ck[k];
-                    fval[p] = v[k];
+                    out.val[p] = v[k];
                 }
             });
         }
         for (auto& x : th) x.join();
-        th.clear();
         hist.clear();
         hist.shrink_to_fit();
-        // sort rows whose columns are out of order, merge duplicates, pad
-        len_u.assign(n_rows, 0);
         parallel_for(n_rows, [&](int64_t a, int64_t b, int) {
             std::vector<int64_t> perm;
             std::vector<int32_t> tc;
             std::vector<float> tv;
             for (int64_t r = a; r < b; ++r) {
-                const int64_t s = out.rowptr[r], n = len[r];
-                int32_t* c = out.col.data() + s;
-                float* fv = fval.data() + s;
+                const int64_t s0 = out.start[r], n = out.len[r];
+                int32_t* c = out.col.data() + s0;
+                float* fv = out.val.data() + s0;
                 bool ok = true;
                 for (int64_t k = 1; k < n; ++k)
                     if (c[k] <= c[k - 1]) { ok = false; break; }
-                int64_t m = n;
-                if (!ok) {
-                    perm.resize(n);
-                    std::iota(perm.begin(), perm.end(), 0);
-                    std::stable_sort(perm.begin(), perm.end(),
-                                     [&](int64_t x, int64_t y) { return c[x] < c[y]; });
-                    tc.resize(n);
-                    tv.resize(n);
-                    m = 0;
-                    for (int64_t k = 0; k < n; ++k) {
-                        int32_t cc = c[perm[k]];
-                        float vv = fv[perm[k]];
-                        if (m > 0 && tc[m - 1] == cc) tv[m - 1] += vv;
-                        else { tc[m] = cc; tv[m] = vv; ++m; }
-                    }
-                    std::copy(tc.begin(), tc.begin() + m, c);
-                    std::copy(tv.begin(), tv.begin() + m, fv);
+                if (ok) continue;
+                perm.resize(n);
+                std::iota(perm.begin(), perm.end(), 0);
+                std::stable_sort(perm.begin(), perm.end(), [&](int64_t x, int64_t y) { return c[x] < c[y]; });
+                tc.resize(n);
+                tv.resize(n);
+                int64_t m = 0;
+                for (int64_t k = 0; k < n; ++k) {
+                    const int32_t cc = c[perm[k]];
+                    const float vv = fv[perm[k]];
+                    if (m > 0 && tc[m - 1] == cc) tv[m - 1] += vv;
+                    else { tc[m] = cc; tv[m] = vv; ++m; }
                 }
-                len_u[r] = m;
-                const int64_t e = out.rowptr[r + 1];
-                const int32_t last = m > 0 ? c[m - 1] : 0;
-                for (int64_t k = s + m; k < e; ++k) { out.col[k] = last; fval[k] = 0.0f; }
-                if (interleave) interleave_row(out.col.data() + s, fval.data() + s, e - s, tc, tv);
+                std::copy(tc.begin(), tc.begin() + m, c);
+                std::copy(tv.begin(), tv.begin() + m, fv);
+                out.len[r] = m;
             }
         });
-        // row blocks: consecutive rows up to a stored-entry budget and a row
-        // budget; a row longer than the budget forms a block of its own
-        const int64_t cap = block_nnz_cap();
-        const int32_t rcap = block_row_cap();
+    } catch (const std::bad_alloc&) {
+        return set_error(DVMAT_E_NOMEM, "host allocation failed while sorting %lld entries", (long long)nnz);
+    }
+    return DVMAT_OK;
+}
+
+// Block-row layout of one orientation.  B consecutive rows form a block row;
+// its stored entries are the union of the rows' columns, each with B values
+// (zero where a row lacks the column), so one column index and one gather of
+// the vector serve B rows.  Block rows are padded with zero entries to a
+// multiple of 4, and within every 256-entry chunk of a block row (the tail
+// chunk: n entries) sorted entry l + q*(n/4) is stored at position 4*l + q: a
+// lane's 16-byte column load then holds entries l, l+n/4, l+2n/4, l+3n/4 and
+// each gather instruction of a wave covers n/4 consecutive sorted columns.
+static dvmat_status build_blocked(const SortedRows& sr, int64_t n_rows, int B, bool interleave, int64_t unit_cap,
+                                  CsrHost& out, std::vector<float>& fvalb) {
+    try {
+        const int64_t n_br = (n_rows + B - 1) / B;
+        out.n_rows = n_rows;
+        out.B = B;
+        out.n_brows = n_br;
+        std::vector<int64_t> uni(n_br, 0);
+        // union size of each block row (B-way merge of sorted column lists)
+        parallel_for(n_br, [&](int64_t a, int64_t b, int) {
+            int64_t pos[4], end[4];
+            for (int64_t br = a; br < b; ++br) {
+                const int nb = (int)std::min<int64_t>(B, n_rows - br * B);
+                for (int q = 0; q < nb; ++q) {
+                    pos[q] = sr.start[br * B + q];
+                    end[q] = pos[q] + sr.len[br * B + q];
+                }
+                int64_t u = 0;
+                for (;;) {
+                    int32_t cmin = INT32_MAX;
+                    for (int q = 0; q < nb; ++q)
+                        if (pos[q] < end[q]) cmin = std::min(cmin, sr.col[pos[q]]);
+                    if (cmin == INT32_MAX) break;
+                    for (int q = 0; q < nb; ++q)
+                        if (pos[q] < end[q] && sr.col[pos[q]] == cmin) pos[q]++;
+                    ++u;
+                }
+                uni[br] = u;
+            }
+        });
+        out.rowptr.assign(n_br + 1, 0);
+        for (int64_t br = 0; br < n_br; ++br) out.rowptr[br + 1] = out.rowptr[br] + (uni[br] + kRowPad - 1) / kRowPad * kRowPad;
+        const int64_t ne = out.rowptr[n_br];
+        out.col.assign(ne, 0);
+        fvalb.assign(ne * B, 0.0f);
+        parallel_for(n_br, [&](int64_t a, int64_t b, int) {
+            int64_t pos[4], end[4];
+            std::vector<int32_t> tc;
+            std::vector<float> tv;
+            for (int64_t br = a; br < b; ++br) {
+                const int nb = (int)std::min<int64_t>(B, n_rows - br * B);
+                for (int q = 0; q < nb; ++q) {
+                    pos[q] = sr.start[br * B + q];
+                    end[q] = pos[q] + sr.len[br * B + q];
+                }
+                const int64_t s0 = out.rowptr[br], e0 = out.rowptr[br + 1];
+                int32_t* c = out.col.data() + s0;
+                float* fv = fvalb.data() + s0 * B;
+                int64_t u = 0;
+                for (;;) {
+                    int32_t cmin = INT32_MAX;
+                    for (int q = 0; q < nb; ++q)
+                        if (pos[q] < end[q]) cmin = std::min(cmin, sr.col[pos[q]]);
+                    if (cmin == INT32_MAX) break;
+                    c[u] = cmin;
+                    for (int q = 0; q < nb; ++q)
+                        if (pos[q] < end[q] && sr.col[pos[q]] == cmin) fv[u * B + q] = sr.val[pos[q]++];
+                    ++u;
+                }
+                const int32_t last = u > 0 ? c[u - 1] : 0;
+                for (int64_t k = u; k < e0 - s0; ++k) c[k] = last;      // padding: valid column, zero values
+                if (!interleave) continue;
+                const int64_t len = e0 - s0;
+                for (int64_t base = 0; base < len; base += 256) {
+                    const int64_t n = std::min<int64_t>(256, len - base);
+                    const int64_t w = n / 4;
+                    tc.assign(c + base, c + base + n);
+                    tv.assign(fv + base * B, fv + (base + n) * B);
+                    for (int64_t l = 0; l < w; ++l)
+                        for (int q = 0; q < 4; ++q) {
+                            c[base + 4 * l + q] = tc[l + q * w];
+                            for (int bb = 0; bb < B; ++bb) fv[(base + 4 * l + q) * B + bb] = tv[(l + q * w) * B + bb];
+                        }
+                }
+            }
+        });
+        // work units: consecutive block rows up to a stored-value budget and
+        // kBlockRowsMax block rows; a longer block row is a unit of its own
         out.blocks.clear();
         out.blocks.push_back(0);
         int64_t acc = 0;
         int32_t rows_in = 0;
-        out.nonempty = 0;
-        for (int64_t r = 0; r < n_rows; ++r) {
-            const int64_t lp = out.rowptr[r + 1] - out.rowptr[r];
-            if (len_u[r] > 0) out.nonempty++;
-            if (rows_in > 0 && (acc + lp > cap || rows_in >= rcap)) {
-                out.blocks.push_back((int32_t)r);
+        for (int64_t br = 0; br < n_br; ++br) {
+            const int64_t lp = (out.rowptr[br + 1] - out.rowptr[br]) * B;
+            if (rows_in > 0 && (acc + lp > unit_cap || rows_in >= kBlockRowsMax)) {
+                out.blocks.push_back((int32_t)br);
                 acc = 0;
                 rows_in = 0;
             }
             acc += lp;
             rows_in++;
         }
-        out.blocks.push_back((int32_t)n_rows);
+        out.blocks.push_back((int32_t)n_br);
+        out.nonempty = 0;
+        for (int64_t r = 0; r < n_rows; ++r) out.nonempty += sr.len[r] > 0;
     } catch (const std::bad_alloc&) {
-        return set_error(DVMAT_E_NOMEM, "host allocation failed while building CSR (%lld rows, %lld nnz)",
-                         (long long)n_rows, (long long)nnz);
+        return set_error(DVMAT_E_NOMEM, "host allocation failed while building block rows (%lld rows)",
+                         (long long)n_rows);
     }
     return DVMAT_OK;
 }
 
-// Store the float values of one orientation in the requested storage type.
-// beamlet_of_entry(k) gives the beamlet of stored entry k (for the scale).
-template <class BeamletOf>
-static void encode_values(CsrHost& h, const std::vector<float>& fval, int32_t storage,
-                          const std::vector<float>& scale, BeamletOf beamlet_of) {
-    const int64_t n = (int64_t)fval.size();
+// Store the values in the requested type.  16-bit storage keeps v / s_j with
+// s_j the scale of the value's beamlet: the column for the dose orientation,
+// the row for the price orientation.
+static void encode_values(CsrHost& h, const std::vector<float>& fvalb, int32_t storage,
+                          const std::vector<float>& scale, bool beamlet_is_row) {
+    const int64_t ne = (int64_t)h.col.size();
+    const int B = h.B;
     if (storage == DVMAT_F32) {
-        h.val.resize(n * 4);
-        std::memcpy(h.val.data(), fval.data(), n * 4);
+        h.val.resize(ne * B * 4);
+        std::memcpy(h.val.data(), fvalb.data(), ne * B * 4);
         return;
     }
-    h.val.resize(n * 2);
+    h.val.resize(ne * B * 2);
     uint16_t* q = reinterpret_cast<uint16_t*>(h.val.data());
-    parallel_for(h.n_rows, [&](int64_t a, int64_t b, int) {
-        for (int64_t r = a; r < b; ++r)
-            for (int64_t k = h.rowptr[r]; k < h.rowptr[r + 1]; ++k) {
-                const float s = scale[beamlet_of(r, k)];
-                const float x = fval[k] / s;
-                q[k] = storage == DVMAT_F16 ? float_to_half_bits(x) : float_to_bf16_bits(x);
-            }
+    parallel_for(h.n_brows, [&](int64_t a, int64_t b, int) {
+        for (int64_t br = a; br < b; ++br)
+            for (int64_t k = h.rowptr[br]; k < h.rowptr[br + 1]; ++k)
+                for (int bb = 0; bb < B; ++bb) {
+                    const int64_t r = std::min<int64_t>(br * B + bb, h.n_rows - 1);
+                    const float s = scale[beamlet_is_row ? r : h.col[k]];
+                    const float x = fvalb[k * B + bb] / s;
+                    q[k * B + bb] = storage == DVMAT_F16 ? float_to_half_bits(x) : float_to_bf16_bits(x);
+                }
     });
 }
 
@@ -270,10 +321,36 @@ const char* dvmat_last_error(void) { return dvmat::g_last_error.c_str(); }
 
 int32_t dvmat_version(void) { return 0x000100; }
 
+dvmat_status dvmat_ddc_default_opts(dvmat_build_opts* opts) {
+    if (!opts) return set_error(DVMAT_E_ARG, "dvmat_ddc_default_opts: NULL argument");
+    opts->dose_block_rows = 4;
+    opts->price_block_rows = 1;
+    opts->interleave = 1;
+    opts->unit_entries = 2048;
+    if (const char* e = std::getenv("DVMAT_DOSE_B")) opts->dose_block_rows = std::atoi(e);
+    if (const char* e = std::getenv("DVMAT_PRICE_B")) opts->price_block_rows = std::atoi(e);
+    if (const char* e = std::getenv("DVMAT_INTERLEAVE")) opts->interleave = std::atoi(e);
+    if (const char* e = std::getenv("DVMAT_BLOCK_NNZ")) opts->unit_entries = std::atoi(e);
+    return DVMAT_OK;
+}
+
 dvmat_status dvmat_ddc_create(int64_t n_vox, int64_t n_bl, int64_t nnz, const int32_t* row_vox,
-                              const int32_t* col_bl, const float* val, int32_t storage,
-                              dvmat_ddc* out) {
+                              const int32_t* col_bl, const float* val, int32_t storage, dvmat_ddc* out) {
+    return dvmat_ddc_create_ex(n_vox, n_bl, nnz, row_vox, col_bl, val, storage, nullptr, out);
+}
+
+dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const int32_t* row_vox,
+                                 const int32_t* col_bl, const float* val, int32_t storage,
+                                 const dvmat_build_opts* opts, dvmat_ddc* out) {
     if (!out) return set_error(DVMAT_E_ARG, "dvmat_ddc_create: out is NULL");
+    dvmat_build_opts o;
+    dvmat_ddc_default_opts(&o);
+    if (opts) o = *opts;
+    auto okB = [](int b) { return b == 1 || b == 2 || b == 4; };
+    if (!okB(o.dose_block_rows) || !okB(o.price_block_rows) || (o.interleave != 0 && o.interleave != 1) ||
+        o.unit_entries < 4 || o.unit_entries > (1 << 24))
+        return set_error(DVMAT_E_ARG, "dvmat_ddc_create: bad build options (block rows %d/%d, interleave %d, unit %d)",
+                         o.dose_block_rows, o.price_block_rows, o.interleave, o.unit_entries);
     *out = nullptr;
     if (n_vox < 1 || n_vox >= (int64_t(1) << 31) || n_bl < 1 || n_bl >= (int64_t(1) << 31))
         return set_error(DVMAT_E_ARG, "dvmat_ddc_create: n_vox=%lld n_bl=%lld must be in [1, 2^31)",
@@ -316,44 +393,57 @@ dvmat_status dvmat_ddc_create(int64_t n_vox, int64_t n_bl, int64_t nnz, const in
     d->dose_cfg = initial_kernel_cfg();
     d->price_cfg = initial_kernel_cfg();
     d->value_bytes = storage == DVMAT_F32 ? 4 : 2;
-    std::vector<float> fval;
-    std::vector<int64_t> len_u;
-    // dose orientation: rows = voxels, columns = beamlets
-    dvmat_status st = build_orientation(n_vox, nnz, row_vox, col_bl, val, d->host_dose, fval, len_u);
-    if (st != DVMAT_OK) { delete d; return st; }
-    int64_t nnz_u = 0;
-    for (int64_t x : len_u) nnz_u += x;
-    d->nnz = nnz_u;
-    if (storage != DVMAT_F32) {
-        // per-beamlet scale s_j = max_i |D_ij| (1 for an empty beamlet)
-        const int T = host_threads();
-        std::vector<std::vector<float>> mx(T);
-        parallel_for(n_vox, [&](int64_t a, int64_t b, int t) {
-            std::vector<float>& m = mx[t];
-            m.assign(n_bl, 0.0f);
-            for (int64_t r = a; r < b; ++r)
-                for (int64_t k = d->host_dose.rowptr[r]; k < d->host_dose.rowptr[r + 1]; ++k)
-                    m[d->host_dose.col[k]] = std::max(m[d->host_dose.col[k]], std::fabs(fval[k]));
-        });
-        d->host_scale.assign(n_bl, 0.0f);
-        for (auto& m : mx)
-            if (!m.empty())
-                for (int64_t j = 0; j < n_bl; ++j) d->host_scale[j] = std::max(d->host_scale[j], m[j]);
-        for (auto& s : d->host_scale)
-            if (!(s > 0.0f)) s = 1.0f;
-        const auto& hc = d->host_dose.col;
-        encode_values(d->host_dose, fval, storage, d->host_scale,
-                      [&](int64_t, int64_t k) { return hc[k]; });
-    } else {
-        encode_values(d->host_dose, fval, storage, d->host_scale, [](int64_t, int64_t) { return 0; });
+    d->opts = o;
+    dvmat_status st = DVMAT_OK;
+    {
+        // dose orientation: rows = voxels, columns = beamlets
+        SortedRows sr;
+        std::vector<float> fvalb;
+        if ((st = sort_rows(n_vox, nnz, row_vox, col_bl, val, sr))) { delete d; return st; }
+        int64_t nnz_u = 0;
+        for (int64_t x : sr.len) nnz_u += x;
+        d->nnz = nnz_u;
+        if (storage != DVMAT_F32) {
+            // per-beamlet scale s_j = max_i |D_ij| (1 for an empty beamlet)
+            const int T = host_threads();
+            std::vector<std::vector<float>> mx(T);
+            parallel_for(n_vox, [&](int64_t a, int64_t b, int t) {
+                std::vector<float>& m = mx[t];
+                m.assign(n_bl, 0.0f);
+                for (int64_t r = a; r < b; ++r)
+                    for (int64_t k = sr.start[r]; k < sr.start[r] + sr.len[r]; ++k)
+                        m[sr.col[k]] = std::max(m[sr.col[k]], std::fabs(sr.val[k]));
+            });
+            d->host_scale.assign(n_bl, 0.0f);
+            for (auto& m : mx)
+                if (!m.empty())
+                    for (int64_t j = 0; j < n_bl; ++j) d->host_scale[j] = std::max(d->host_scale[j], m[j]);
+            for (auto& s : d->host_scale)
+                if (!(s > 0.0f)) s = 1.0f;
+        }
+        if ((st = build_blocked(sr, n_vox, o.dose_block_rows, o.interleave != 0, o.unit_entries, d->host_dose, fvalb))) {
+            delete d;
+            return st;
+        }
+        std::vector<int64_t>().swap(sr.start);
+        std::vector<int64_t>().swap(sr.len);
+        std::vector<int32_t>().swap(sr.col);
+        std::vector<float>().swap(sr.val);
+        encode_values(d->host_dose, fvalb, storage, d->host_scale, false);
     }
-    std::vector<float>().swap(fval);
-    // price orientation: rows = beamlets, columns = voxels
-    st = build_orientation(n_bl, nnz, col_bl, row_vox, val, d->host_price, fval, len_u);
-    if (st != DVMAT_OK) { delete d; return st; }
-    encode_values(d->host_price, fval, storage, d->host_scale,
-                  [](int64_t r, int64_t) { return r; });
-    std::vector<float>().swap(fval);
+    {
+        // price orientation: rows = beamlets, columns = voxels
+        SortedRows sr;
+        std::vector<float> fvalb;
+        if ((st = sort_rows(n_bl, nnz, col_bl, row_vox, val, sr))) { delete d; return st; }
+        if ((st = build_blocked(sr, n_bl, o.price_block_rows, o.interleave != 0, o.unit_entries, d->host_price, fvalb))) {
+            delete d;
+            return st;
+        }
+        std::vector<int32_t>().swap(sr.col);
+        std::vector<float>().swap(sr.val);
+        encode_values(d->host_price, fvalb, storage, d->host_scale, true);
+    }
 
     // device workspace layout
     size_t off = 0;
@@ -362,11 +452,11 @@ dvmat_status dvmat_ddc_create(int64_t n_vox, int64_t n_bl, int64_t nnz, const in
     const CsrHost& hp = d->host_price;
     d->off_dose_rowptr = take(hd.rowptr.size() * 8);
     d->off_dose_col = take(hd.col.size() * 4);
-    d->off_dose_val = take(hd.col.size() * d->value_bytes);
+    d->off_dose_val = take(hd.val.size());
     d->off_dose_blocks = take(hd.blocks.size() * 4);
     d->off_price_rowptr = take(hp.rowptr.size() * 8);
     d->off_price_col = take(hp.col.size() * 4);
-    d->off_price_val = take(hp.col.size() * d->value_bytes);
+    d->off_price_val = take(hp.val.size());
     d->off_price_blocks = take(hp.blocks.size() * 4);
     if (storage != DVMAT_F32) {
         d->off_scale = take(n_bl * 4);
@@ -374,11 +464,13 @@ dvmat_status dvmat_ddc_create(int64_t n_vox, int64_t n_bl, int64_t nnz, const in
     }
     d->ws_bytes = std::max<size_t>(off, kAlign);
     d->dose.n_rows = n_vox;
-    d->dose.nnz_pad = (int64_t)hd.col.size();
+    d->dose.B = hd.B;
+    d->dose.nnz_pad = (int64_t)hd.col.size() * hd.B;
     d->dose.n_blocks = (int64_t)hd.blocks.size() - 1;
     d->dose.nonempty = hd.nonempty;
     d->price.n_rows = n_bl;
-    d->price.nnz_pad = (int64_t)hp.col.size();
+    d->price.B = hp.B;
+    d->price.nnz_pad = (int64_t)hp.col.size() * hp.B;
     d->price.n_blocks = (int64_t)hp.blocks.size() - 1;
     d->price.nonempty = hp.nonempty;
     *out = d;
@@ -405,6 +497,8 @@ dvmat_status dvmat_ddc_info(dvmat_ddc d, dvmat_ddc_info_t* info) {
     info->price_workgroups = d->price_cfg.workgroups;
     info->dose_tuned_ms = d->dose_tuned_ms;
     info->price_tuned_ms = d->price_tuned_ms;
+    info->dose_block_rows = d->dose.B;
+    info->price_block_rows = d->price.B;
     return DVMAT_OK;
 }
 

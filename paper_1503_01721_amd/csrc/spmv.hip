@@ -39,6 +39,7 @@ typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 enum Epi { EPI_PLAIN = 0, EPI_OBJ = 1, EPI_CURV = 2, EPI_SCALE = 3 };
 
 struct SpmvParams {
+    int64_t n_rows;          // rows of the orientation (the last block row may be partial)
     const int64_t* rowptr;
     const int32_t* col;
     const void* val;
@@ -164,34 +165,103 @@ __device__ __forceinline__ void row_epilogue(const SpmvParams& P, int r, const f
 
 // ---- block processors --------------------------------------------------------
 
-template <int ST, int NRHS, int EPI, bool SCALE_X>
+// 4 block entries x B values from value index 4*B*k/4 on: V[t] holds values
+// 4t..4t+3 of the 4B consecutive values; entry q's value b is element q*B + b.
+template <int ST, int B>
+__device__ __forceinline__ void load_block_vals(const void* base, int64_t k, f32x4 (&V)[B]) {
+#pragma unroll
+    for (int t = 0; t < B; ++t) V[t] = load_vals<ST>(base, k * B + 4 * t);
+}
+
+template <int NRHS, int B, bool SCALE_X>
+__device__ __forceinline__ void fma4_blocked(float (&acc)[B][NRHS], const SpmvParams& P, const f32x4 (&V)[B], i32x4 c) {
+    const int cc[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        float xv[NRHS];
+        if constexpr (NRHS == 8) {
+            const f32x4 a = *reinterpret_cast<const f32x4*>(P.x + (int64_t)cc[q] * 8);
+            const f32x4 b = *reinterpret_cast<const f32x4*>(P.x + (int64_t)cc[q] * 8 + 4);
+            xv[0] = a.x; xv[1] = a.y; xv[2] = a.z; xv[3] = a.w;
+            xv[4] = b.x; xv[5] = b.y; xv[6] = b.z; xv[7] = b.w;
+        } else if constexpr (NRHS == 4) {
+            const f32x4 a = *reinterpret_cast<const f32x4*>(P.x + (int64_t)cc[q] * 4);
+            xv[0] = a.x; xv[1] = a.y; xv[2] = a.z; xv[3] = a.w;
+        } else {
+#pragma unroll
+            for (int h = 0; h < NRHS; ++h) xv[h] = P.x[(int64_t)cc[q] * NRHS + h];
+        }
+        if constexpr (SCALE_X) {
+            const float sc = P.x_scale[cc[q]];
+#pragma unroll
+            for (int h = 0; h < NRHS; ++h) xv[h] *= sc;
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int e = q * B + b;
+            const float v = V[e / 4][e % 4];
+#pragma unroll
+            for (int h = 0; h < NRHS; ++h) acc[b][h] += v * xv[h];
+        }
+    }
+}
+
+// Kernel body "row": block rows in order; per block row each lane streams 4
+// consecutive block entries per step (16-byte column load, B 16-byte value
+// loads at FP32), two steps in flight; the wave's butterfly reduces each of
+// the B rows, lane 0 finishes them.
+template <int ST, int NRHS, int EPI, bool SCALE_X, int B>
 __device__ __forceinline__ void block_rows(const SpmvParams& P, int64_t b, int lane, float (&fpart)[NRHS],
                                            double& cpart) {
     const int r0 = P.blocks[b];
     const int r1 = P.blocks[b + 1];
-    for (int r = r0; r < r1; ++r) {
-        const int64_t e0 = P.rowptr[r];
-        const int64_t e1 = P.rowptr[r + 1];
-        float acc[NRHS];
+    for (int br = r0; br < r1; ++br) {
+        const int64_t e0 = P.rowptr[br];
+        const int64_t e1 = P.rowptr[br + 1];
+        float acc[B][NRHS];
 #pragma unroll
-        for (int h = 0; h < NRHS; ++h) acc[h] = 0.0f;
+        for (int q = 0; q < B; ++q)
+#pragma unroll
+            for (int h = 0; h < NRHS; ++h) acc[q][h] = 0.0f;
         int64_t k = e0 + lane * 4;
-        for (; k + 256 < e1; k += 512) {
-            const f32x4 v0 = load_vals<ST>(P.val, k);
-            const i32x4 c0 = load_cols(P.col, k);
-            const f32x4 v1 = load_vals<ST>(P.val, k + 256);
-            const i32x4 c1 = load_cols(P.col, k + 256);
-            fma4<NRHS, SCALE_X>(acc, P, v0, c0);
-            fma4<NRHS, SCALE_X>(acc, P, v1, c1);
+        // two steps in flight unless a step already holds 64 bytes of values
+        // per lane (FP32 with 4 rows per block row): registers, not bytes, bind there
+        constexpr bool kTwoSteps = (ST == DVMAT_F32 ? 4 : 2) * B < 16;
+        if constexpr (kTwoSteps) {
+            for (; k + 256 < e1; k += 512) {
+                f32x4 V0[B], V1[B];
+                load_block_vals<ST, B>(P.val, k, V0);
+                const i32x4 c0 = load_cols(P.col, k);
+                load_block_vals<ST, B>(P.val, k + 256, V1);
+                const i32x4 c1 = load_cols(P.col, k + 256);
+                fma4_blocked<NRHS, B, SCALE_X>(acc, P, V0, c0);
+                fma4_blocked<NRHS, B, SCALE_X>(acc, P, V1, c1);
+            }
+        } else {
+            for (; k + 256 < e1; k += 256) {
+                f32x4 V0[B];
+                load_block_vals<ST, B>(P.val, k, V0);
+                const i32x4 c0 = load_cols(P.col, k);
+                fma4_blocked<NRHS, B, SCALE_X>(acc, P, V0, c0);
+            }
         }
         if (k < e1) {
-            const f32x4 v0 = load_vals<ST>(P.val, k);
+            f32x4 V0[B];
+            load_block_vals<ST, B>(P.val, k, V0);
             const i32x4 c0 = load_cols(P.col, k);
-            fma4<NRHS, SCALE_X>(acc, P, v0, c0);
+            fma4_blocked<NRHS, B, SCALE_X>(acc, P, V0, c0);
         }
 #pragma unroll
-        for (int h = 0; h < NRHS; ++h) acc[h] = wave_sum(acc[h]);
-        if (lane == 0) row_epilogue<NRHS, EPI>(P, r, acc, fpart, cpart);
+        for (int q = 0; q < B; ++q)
+#pragma unroll
+            for (int h = 0; h < NRHS; ++h) acc[q][h] = wave_sum(acc[q][h]);
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < B; ++q) {
+                const int64_t r = (int64_t)br * B + q;
+                if (r < P.n_rows) row_epilogue<NRHS, EPI>(P, (int)r, acc[q], fpart, cpart);
+            }
+        }
     }
 }
 
@@ -312,7 +382,7 @@ __device__ __forceinline__ WaveSlot wave_slot() {
     return s;
 }
 
-template <int KIND, int ST, int NRHS, int EPI>
+template <int KIND, int ST, int NRHS, int EPI, int B>
 __global__ __launch_bounds__(kSpmvThreads) void spmv_kernel(SpmvParams P) {
     constexpr int kWaves = kSpmvThreads / kWaveSize;
     const WaveSlot w = wave_slot();
@@ -322,9 +392,9 @@ __global__ __launch_bounds__(kSpmvThreads) void spmv_kernel(SpmvParams P) {
 #pragma unroll
     for (int h = 0; h < NRHS; ++h) fpart[h] = 0.0f;
     double cpart = 0.0;
-    if constexpr (KIND == KIND_ROW) {
+    if constexpr (KIND == KIND_ROW || B != 1) {
         for (int64_t b = b0 + w.lw; b < b1; b += w.waves_per_xcd)
-            block_rows<ST, NRHS, EPI, false>(P, b, w.lane, fpart, cpart);
+            block_rows<ST, NRHS, EPI, false, B>(P, b, w.lane, fpart, cpart);
     } else {
         __shared__ float s_acc[kWaves][kBlockRowsMax * NRHS];
         __shared__ int s_rel[kWaves][kBlockRowsMax + 1];
@@ -342,6 +412,7 @@ struct PlanDev {
     const void* val;
     const int32_t* blocks;
     const float* scale;   // per-beamlet scale (16-bit storage) or nullptr
+    int64_t n_rows;       // rows of the orientation
     int64_t block_base;   // first global block of this plan
     int64_t n_blocks;
 };
@@ -354,7 +425,7 @@ struct BatchParams {
     float* y[kMaxBatch];
 };
 
-template <int KIND, int ST, int NRHS, int EPI, bool SCALE_X>
+template <int KIND, int ST, int NRHS, int EPI, bool SCALE_X, int BR>
 __global__ __launch_bounds__(kSpmvThreads) void spmv_batch_kernel(BatchParams B) {
     constexpr int kWaves = kSpmvThreads / kWaveSize;
     const WaveSlot w = wave_slot();
@@ -371,6 +442,7 @@ __global__ __launch_bounds__(kSpmvThreads) void spmv_batch_kernel(BatchParams B)
         while (p + 1 < B.n_plans && B.plans[p + 1].block_base <= b) ++p;   // b only grows
         const PlanDev& pd = B.plans[p];
         SpmvParams P{};
+        P.n_rows = pd.n_rows;
         P.rowptr = pd.rowptr;
         P.col = pd.col;
         P.val = pd.val;
@@ -380,8 +452,8 @@ __global__ __launch_bounds__(kSpmvThreads) void spmv_batch_kernel(BatchParams B)
         P.y = B.y[p];
         P.row_scale = pd.scale;
         P.x_scale = pd.scale;
-        if constexpr (KIND == KIND_ROW)
-            block_rows<ST, NRHS, EPI, SCALE_X>(P, b - pd.block_base, w.lane, fpart, cpart);
+        if constexpr (KIND == KIND_ROW || BR != 1)
+            block_rows<ST, NRHS, EPI, SCALE_X, BR>(P, b - pd.block_base, w.lane, fpart, cpart);
         else
             block_stream<ST, NRHS, EPI, SCALE_X>(P, b - pd.block_base, w.lane, s_acc[w.wid], s_rel[w.wid], fpart,
                                                  cpart);
@@ -473,12 +545,12 @@ static KernelCfg default_cfg() {
     return c;
 }
 
-template <int KIND, int ST, int EPI>
+template <int KIND, int ST, int EPI, int B>
 static void launch_nrhs(const SpmvParams& P, int nrhs, int nwg, hipStream_t s) {
     dim3 grid(nwg), block(kSpmvThreads);
     switch (nrhs) {
 #define DVMAT_CASE(N) \
-    case N: hipLaunchKernelGGL((spmv_kernel<KIND, ST, N, EPI>), grid, block, 0, s, P); break;
+    case N: hipLaunchKernelGGL((spmv_kernel<KIND, ST, N, EPI, B>), grid, block, 0, s, P); break;
         DVMAT_CASE(1) DVMAT_CASE(2) DVMAT_CASE(3) DVMAT_CASE(4)
         DVMAT_CASE(5) DVMAT_CASE(6) DVMAT_CASE(7) DVMAT_CASE(8)
 #undef DVMAT_CASE
@@ -486,33 +558,37 @@ static void launch_nrhs(const SpmvParams& P, int nrhs, int nwg, hipStream_t s) {
     }
 }
 
+template <int ST, int EPI>
+static void launch_st(const KernelCfg& cfg, int B, const SpmvParams& P, int nrhs, int nwg, hipStream_t s) {
+    if (B == 4) launch_nrhs<KIND_ROW, ST, EPI, 4>(P, nrhs, nwg, s);
+    else if (B == 2) launch_nrhs<KIND_ROW, ST, EPI, 2>(P, nrhs, nwg, s);
+    else if (cfg.kind == KIND_STREAM) launch_nrhs<KIND_STREAM, ST, EPI, 1>(P, nrhs, nwg, s);
+    else launch_nrhs<KIND_ROW, ST, EPI, 1>(P, nrhs, nwg, s);
+}
+
 template <int EPI>
-static void launch_spmv(const KernelCfg& cfg, int storage, const SpmvParams& P, int nrhs, hipStream_t s) {
+static void launch_spmv(const KernelCfg& cfg, int storage, int B, const SpmvParams& P, int nrhs, hipStream_t s) {
     const int nwg = clamp_workgroups(cfg.workgroups, P.n_blocks);
-    if (cfg.kind == KIND_STREAM) {
-        if (storage == DVMAT_F32) launch_nrhs<KIND_STREAM, DVMAT_F32, EPI>(P, nrhs, nwg, s);
-        else if (storage == DVMAT_F16) launch_nrhs<KIND_STREAM, DVMAT_F16, EPI>(P, nrhs, nwg, s);
-        else launch_nrhs<KIND_STREAM, DVMAT_BF16, EPI>(P, nrhs, nwg, s);
-    } else {
-        if (storage == DVMAT_F32) launch_nrhs<KIND_ROW, DVMAT_F32, EPI>(P, nrhs, nwg, s);
-        else if (storage == DVMAT_F16) launch_nrhs<KIND_ROW, DVMAT_F16, EPI>(P, nrhs, nwg, s);
-        else launch_nrhs<KIND_ROW, DVMAT_BF16, EPI>(P, nrhs, nwg, s);
-    }
+    if (storage == DVMAT_F32) launch_st<DVMAT_F32, EPI>(cfg, B, P, nrhs, nwg, s);
+    else if (storage == DVMAT_F16) launch_st<DVMAT_F16, EPI>(cfg, B, P, nrhs, nwg, s);
+    else launch_st<DVMAT_BF16, EPI>(cfg, B, P, nrhs, nwg, s);
 }
 
 // Curvature only needs one right-hand side.
-static void launch_curv(const KernelCfg& cfg, int storage, const SpmvParams& P, hipStream_t s) {
-    const int nwg = clamp_workgroups(cfg.workgroups, P.n_blocks);
+template <int ST>
+static void launch_curv_st(const KernelCfg& cfg, int B, const SpmvParams& P, int nwg, hipStream_t s) {
     dim3 grid(nwg), block(kSpmvThreads);
-    if (cfg.kind == KIND_STREAM) {
-        if (storage == DVMAT_F32) hipLaunchKernelGGL((spmv_kernel<KIND_STREAM, DVMAT_F32, 1, EPI_CURV>), grid, block, 0, s, P);
-        else if (storage == DVMAT_F16) hipLaunchKernelGGL((spmv_kernel<KIND_STREAM, DVMAT_F16, 1, EPI_CURV>), grid, block, 0, s, P);
-        else hipLaunchKernelGGL((spmv_kernel<KIND_STREAM, DVMAT_BF16, 1, EPI_CURV>), grid, block, 0, s, P);
-    } else {
-        if (storage == DVMAT_F32) hipLaunchKernelGGL((spmv_kernel<KIND_ROW, DVMAT_F32, 1, EPI_CURV>), grid, block, 0, s, P);
-        else if (storage == DVMAT_F16) hipLaunchKernelGGL((spmv_kernel<KIND_ROW, DVMAT_F16, 1, EPI_CURV>), grid, block, 0, s, P);
-        else hipLaunchKernelGGL((spmv_kernel<KIND_ROW, DVMAT_BF16, 1, EPI_CURV>), grid, block, 0, s, P);
-    }
+    if (B == 4) hipLaunchKernelGGL((spmv_kernel<KIND_ROW, ST, 1, EPI_CURV, 4>), grid, block, 0, s, P);
+    else if (B == 2) hipLaunchKernelGGL((spmv_kernel<KIND_ROW, ST, 1, EPI_CURV, 2>), grid, block, 0, s, P);
+    else if (cfg.kind == KIND_STREAM) hipLaunchKernelGGL((spmv_kernel<KIND_STREAM, ST, 1, EPI_CURV, 1>), grid, block, 0, s, P);
+    else hipLaunchKernelGGL((spmv_kernel<KIND_ROW, ST, 1, EPI_CURV, 1>), grid, block, 0, s, P);
+}
+
+static void launch_curv(const KernelCfg& cfg, int storage, int B, const SpmvParams& P, hipStream_t s) {
+    const int nwg = clamp_workgroups(cfg.workgroups, P.n_blocks);
+    if (storage == DVMAT_F32) launch_curv_st<DVMAT_F32>(cfg, B, P, nwg, s);
+    else if (storage == DVMAT_F16) launch_curv_st<DVMAT_F16>(cfg, B, P, nwg, s);
+    else launch_curv_st<DVMAT_BF16>(cfg, B, P, nwg, s);
 }
 
 static int elementwise_grid(int64_t n) {
@@ -528,6 +604,7 @@ static dvmat_status check_ddc(const dvmat_ddc_s* d, const char* fn) {
 
 static SpmvParams orientation_params(const CsrDev& c) {
     SpmvParams P{};
+    P.n_rows = c.n_rows;
     P.rowptr = c.rowptr;
     P.col = c.col;
     P.val = c.val;
@@ -547,7 +624,7 @@ static dvmat_status dose_plain(dvmat_ddc_s* d, const KernelCfg& cfg, const float
     SpmvParams P = orientation_params(d->dose);
     P.x = xin;
     P.y = z;
-    launch_spmv<EPI_PLAIN>(cfg, d->storage, P, nrhs, s);
+    launch_spmv<EPI_PLAIN>(cfg, d->storage, d->dose.B, P, nrhs, s);
     return check_hip(hipGetLastError(), "dose launch");
 }
 
@@ -556,8 +633,8 @@ static dvmat_status price_any(dvmat_ddc_s* d, const KernelCfg& cfg, const float*
     P.x = g;
     P.y = p;
     P.row_scale = d->scale;
-    if (d->storage == DVMAT_F32) launch_spmv<EPI_PLAIN>(cfg, d->storage, P, nrhs, s);
-    else launch_spmv<EPI_SCALE>(cfg, d->storage, P, nrhs, s);
+    if (d->storage == DVMAT_F32) launch_spmv<EPI_PLAIN>(cfg, d->storage, d->price.B, P, nrhs, s);
+    else launch_spmv<EPI_SCALE>(cfg, d->storage, d->price.B, P, nrhs, s);
     return check_hip(hipGetLastError(), "price launch");
 }
 
@@ -571,20 +648,29 @@ struct dvmat_batch_s {
     dvmat::PlanDev* price_plans = nullptr;   // device
     int64_t dose_blocks = 0, price_blocks = 0;
     dvmat::KernelCfg dose_cfg{}, price_cfg{};
+    int dose_B = 1, price_B = 1;
 };
 
 namespace dvmat {
 
-template <int KIND, int ST, int EPI, bool SCALE_X>
+template <int KIND, int ST, int EPI, bool SCALE_X, int BR>
 static void launch_batch_nrhs(const BatchParams& B, int nrhs, int nwg, hipStream_t s) {
     dim3 grid(nwg), block(kSpmvThreads);
     switch (nrhs) {
 #define DVMAT_CASE(N) \
-    case N: hipLaunchKernelGGL((spmv_batch_kernel<KIND, ST, N, EPI, SCALE_X>), grid, block, 0, s, B); break;
+    case N: hipLaunchKernelGGL((spmv_batch_kernel<KIND, ST, N, EPI, SCALE_X, BR>), grid, block, 0, s, B); break;
         DVMAT_CASE(1) DVMAT_CASE(2) DVMAT_CASE(4) DVMAT_CASE(8)
 #undef DVMAT_CASE
         default: break;
     }
+}
+
+template <int ST, int EPI, bool SCALE_X>
+static void launch_batch_st(int kind, int BR, const BatchParams& B, int nrhs, int nwg, hipStream_t s) {
+    if (BR == 4) launch_batch_nrhs<KIND_ROW, ST, EPI, SCALE_X, 4>(B, nrhs, nwg, s);
+    else if (BR == 2) launch_batch_nrhs<KIND_ROW, ST, EPI, SCALE_X, 2>(B, nrhs, nwg, s);
+    else if (kind == KIND_STREAM) launch_batch_nrhs<KIND_STREAM, ST, EPI, SCALE_X, 1>(B, nrhs, nwg, s);
+    else launch_batch_nrhs<KIND_ROW, ST, EPI, SCALE_X, 1>(B, nrhs, nwg, s);
 }
 
 // dose: plain epilogue, 16-bit scale applied to each gathered entry;
@@ -594,21 +680,15 @@ static void launch_batch(const dvmat_batch_s* bt, const KernelCfg& cfg, const Ba
                          hipStream_t s) {
     const int nwg = clamp_workgroups(cfg.workgroups, B.total_blocks);
     const int st = bt->storage;
-#define DVMAT_BATCH(KIND)                                                                                 \
-    if (st == DVMAT_F32) launch_batch_nrhs<KIND, DVMAT_F32, EPI_PLAIN, false>(B, nrhs, nwg, s);          \
-    else if (st == DVMAT_F16) {                                                                           \
-        if (DOSE) launch_batch_nrhs<KIND, DVMAT_F16, EPI_PLAIN, true>(B, nrhs, nwg, s);                   \
-        else launch_batch_nrhs<KIND, DVMAT_F16, EPI_SCALE, false>(B, nrhs, nwg, s);                       \
-    } else {                                                                                              \
-        if (DOSE) launch_batch_nrhs<KIND, DVMAT_BF16, EPI_PLAIN, true>(B, nrhs, nwg, s);                  \
-        else launch_batch_nrhs<KIND, DVMAT_BF16, EPI_SCALE, false>(B, nrhs, nwg, s);                      \
-    }
-    if (cfg.kind == KIND_STREAM) {
-        DVMAT_BATCH(KIND_STREAM)
+    const int BR = DOSE ? bt->dose_B : bt->price_B;
+    if (st == DVMAT_F32) launch_batch_st<DVMAT_F32, EPI_PLAIN, false>(cfg.kind, BR, B, nrhs, nwg, s);
+    else if (st == DVMAT_F16) {
+        if (DOSE) launch_batch_st<DVMAT_F16, EPI_PLAIN, true>(cfg.kind, BR, B, nrhs, nwg, s);
+        else launch_batch_st<DVMAT_F16, EPI_SCALE, false>(cfg.kind, BR, B, nrhs, nwg, s);
     } else {
-        DVMAT_BATCH(KIND_ROW)
+        if (DOSE) launch_batch_st<DVMAT_BF16, EPI_PLAIN, true>(cfg.kind, BR, B, nrhs, nwg, s);
+        else launch_batch_st<DVMAT_BF16, EPI_SCALE, false>(cfg.kind, BR, B, nrhs, nwg, s);
     }
-#undef DVMAT_BATCH
 }
 
 static dvmat_status batch_call(dvmat_batch_s* bt, bool dose, const KernelCfg& cfg, const float* const* in,
@@ -654,9 +734,9 @@ static dvmat_status time_config(Run&& run, int reps, hipStream_t s, float* ms_ou
 }
 
 template <class RunCfg>
-static dvmat_status tune(RunCfg&& run_cfg, int reps, hipStream_t s, KernelCfg* best, float* best_ms) {
+static dvmat_status tune(RunCfg&& run_cfg, int reps, hipStream_t s, KernelCfg* best, float* best_ms, int B) {
     *best_ms = INFINITY;
-    for (int kind = 0; kind < 2; ++kind)
+    for (int kind = 0; kind < (B == 1 ? 2 : 1); ++kind)
         for (int wg : kTuneWorkgroups) {
             KernelCfg c{kind, wg};
             float ms = 0.0f;
@@ -757,7 +837,7 @@ dvmat_status dvmat_dose(dvmat_ddc d, const float* x, int32_t nrhs, float* z, dvm
     P.table = obj->table;
     P.g = g;
     P.partial = obj->partial;
-    launch_spmv<EPI_OBJ>(d->dose_cfg, d->storage, P, nrhs, s);
+    launch_spmv<EPI_OBJ>(d->dose_cfg, d->storage, d->dose.B, P, nrhs, s);
     if (F) {
         const int nwg = clamp_workgroups(d->dose_cfg.workgroups, P.n_blocks);
         hipLaunchKernelGGL(finalize_f_kernel, dim3(1), dim3(256), 0, s, obj->partial, nwg, nrhs, F);
@@ -793,7 +873,7 @@ dvmat_status dvmat_dose_curvature(dvmat_ddc d, const float* x_dir, dvmat_obj obj
     P.table = obj->table;
     P.zref = z_ref;
     P.partial_d = obj->partial_d;
-    launch_curv(d->dose_cfg, d->storage, P, s);
+    launch_curv(d->dose_cfg, d->storage, d->dose.B, P, s);
     const int nwg = clamp_workgroups(d->dose_cfg.workgroups, P.n_blocks);
     hipLaunchKernelGGL(finalize_d_kernel, dim3(1), dim3(256), 0, s, obj->partial_d, nwg, curv);
     return check_hip(hipGetLastError(), "dvmat_dose_curvature launch");
@@ -808,11 +888,11 @@ dvmat_status dvmat_ddc_autotune(dvmat_ddc d, const float* x, float* z, const flo
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     KernelCfg best{};
     float ms = 0.0f;
-    st = tune([&](const KernelCfg& c) { return dose_plain(d, c, x, 1, z, s); }, reps, s, &best, &ms);
+    st = tune([&](const KernelCfg& c) { return dose_plain(d, c, x, 1, z, s); }, reps, s, &best, &ms, d->dose.B);
     if (st) return st;
     d->dose_cfg = best;
     d->dose_tuned_ms = ms;
-    st = tune([&](const KernelCfg& c) { return price_any(d, c, g, 1, p, s); }, reps, s, &best, &ms);
+    st = tune([&](const KernelCfg& c) { return price_any(d, c, g, 1, p, s); }, reps, s, &best, &ms, d->price.B);
     if (st) return st;
     d->price_cfg = best;
     d->price_tuned_ms = ms;
@@ -825,9 +905,12 @@ dvmat_status dvmat_ddc_set_kernel(dvmat_ddc d, int32_t orientation, int32_t kind
     if (workgroups < kNumXcd || workgroups > kMaxSpmvWorkgroups)
         return set_error(DVMAT_E_ARG, "dvmat_ddc_set_kernel: workgroups %d not in [8, 8192]", workgroups);
     KernelCfg c{kind, workgroups};
+    if (orientation != 0 && orientation != 1)
+        return set_error(DVMAT_E_ARG, "dvmat_ddc_set_kernel: orientation %d", orientation);
+    if (kind == KIND_STREAM && (orientation == 0 ? d->dose.B : d->price.B) != 1)
+        return set_error(DVMAT_E_ARG, "dvmat_ddc_set_kernel: the stream kernel needs one row per block row");
     if (orientation == 0) d->dose_cfg = c;
-    else if (orientation == 1) d->price_cfg = c;
-    else return set_error(DVMAT_E_ARG, "dvmat_ddc_set_kernel: orientation %d", orientation);
+    else d->price_cfg = c;
     return DVMAT_OK;
 }
 
@@ -857,8 +940,12 @@ dvmat_status dvmat_batch_create(const dvmat_ddc* ddcs, int32_t n, void* ws, size
         if ((st = check_ddc(d, "dvmat_batch_create"))) return st;
         if (d->storage != ddcs[0]->storage)
             return set_error(DVMAT_E_ARG, "dvmat_batch_create: plan %d has a different storage type", i);
-        dp[i] = PlanDev{d->dose.rowptr, d->dose.col, d->dose.val, d->dose.blocks, d->scale, bd, d->dose.n_blocks};
-        pp[i] = PlanDev{d->price.rowptr, d->price.col, d->price.val, d->price.blocks, d->scale, bp, d->price.n_blocks};
+        if (d->dose.B != ddcs[0]->dose.B || d->price.B != ddcs[0]->price.B)
+            return set_error(DVMAT_E_ARG, "dvmat_batch_create: plan %d has a different block-row layout", i);
+        dp[i] = PlanDev{d->dose.rowptr, d->dose.col, d->dose.val, d->dose.blocks, d->scale, d->dose.n_rows, bd,
+                        d->dose.n_blocks};
+        pp[i] = PlanDev{d->price.rowptr, d->price.col, d->price.val, d->price.blocks, d->scale, d->price.n_rows, bp,
+                        d->price.n_blocks};
         bd += d->dose.n_blocks;
         bp += d->price.n_blocks;
     }
@@ -867,6 +954,8 @@ dvmat_status dvmat_batch_create(const dvmat_ddc* ddcs, int32_t n, void* ws, size
     char* base = static_cast<char*>(ws);
     bt->n = n;
     bt->storage = ddcs[0]->storage;
+    bt->dose_B = ddcs[0]->dose.B;
+    bt->price_B = ddcs[0]->price.B;
     bt->dose_plans = reinterpret_cast<PlanDev*>(base);
     bt->price_plans = reinterpret_cast<PlanDev*>(base + align_up((size_t)n * sizeof(PlanDev)));
     bt->dose_blocks = bd;
@@ -910,11 +999,11 @@ dvmat_status dvmat_batch_autotune(dvmat_batch b, const float* const* xs, float* 
     KernelCfg best{};
     float ms = 0.0f;
     dvmat_status st = tune([&](const KernelCfg& c) { return batch_call(b, true, c, xs, nrhs, zs, s, "dvmat_batch_autotune"); },
-                           reps, s, &best, &ms);
+                           reps, s, &best, &ms, b->dose_B);
     if (st) return st;
     b->dose_cfg = best;
     st = tune([&](const KernelCfg& c) { return batch_call(b, false, c, gs, nrhs, ps, s, "dvmat_batch_autotune"); },
-              reps, s, &best, &ms);
+              reps, s, &best, &ms, b->price_B);
     if (st) return st;
     b->price_cfg = best;
     return DVMAT_OK;

@@ -42,7 +42,13 @@ class DdcInfo(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_size_t),
                 ("dose_kernel", ctypes.c_int32), ("dose_workgroups", ctypes.c_int32),
                 ("price_kernel", ctypes.c_int32), ("price_workgroups", ctypes.c_int32),
-                ("dose_tuned_ms", ctypes.c_float), ("price_tuned_ms", ctypes.c_float)]
+                ("dose_tuned_ms", ctypes.c_float), ("price_tuned_ms", ctypes.c_float),
+                ("dose_block_rows", ctypes.c_int32), ("price_block_rows", ctypes.c_int32)]
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("dose_block_rows", ctypes.c_int32), ("price_block_rows", ctypes.c_int32),
+                ("interleave", ctypes.c_int32), ("unit_entries", ctypes.c_int32)]
 
 
 class Geom(ctypes.Structure):
@@ -61,6 +67,9 @@ _SIGNATURES = {
     "dvmat_last_error": (ctypes.c_char_p, []),
     "dvmat_version": (_I32, []),
     "dvmat_ddc_create": (_I32, [_I64, _I64, _I64, _P, _P, _P, _I32, ctypes.POINTER(_P)]),
+    "dvmat_ddc_create_ex": (_I32, [_I64, _I64, _I64, _P, _P, _P, _I32, ctypes.POINTER(BuildOpts),
+                                   ctypes.POINTER(_P)]),
+    "dvmat_ddc_default_opts": (_I32, [ctypes.POINTER(BuildOpts)]),
     "dvmat_ddc_info": (_I32, [_P, ctypes.POINTER(DdcInfo)]),
     "dvmat_ddc_bind": (_I32, [_P, _P, _SZ, _P]),
     "dvmat_ddc_destroy": (None, [_P]),
@@ -162,7 +171,8 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 class DDC:
     """DDC matrix in both CSR orientations, resident in one GPU's memory."""
 
-    def __init__(self, row, col, val, n_vox: int, n_bl: int, storage: str = "f32", device="cuda"):
+    def __init__(self, row, col, val, n_vox: int, n_bl: int, storage: str = "f32", device="cuda",
+                 dose_block_rows=None, price_block_rows=None, interleave=None, unit_entries=None):
         row = np.ascontiguousarray(row, dtype=np.int32)
         col = np.ascontiguousarray(col, dtype=np.int32)
         val = np.ascontiguousarray(val, dtype=np.float32)
@@ -170,12 +180,18 @@ class DDC:
             raise ValueError("COO arrays differ in length")
         self.n_vox, self.n_bl = int(n_vox), int(n_bl)
         self.storage = storage
+        opts = BuildOpts()
+        _check(lib.dvmat_ddc_default_opts(ctypes.byref(opts)))
+        for name, v in (("dose_block_rows", dose_block_rows), ("price_block_rows", price_block_rows),
+                        ("interleave", interleave), ("unit_entries", unit_entries)):
+            if v is not None:
+                setattr(opts, name, int(v))
         h = _P()
-        _check(lib.dvmat_ddc_create(self.n_vox, self.n_bl, len(val),
-                                    row.ctypes.data_as(_P) if len(val) else None,
-                                    col.ctypes.data_as(_P) if len(val) else None,
-                                    val.ctypes.data_as(_P) if len(val) else None,
-                                    STORAGE[storage], ctypes.byref(h)))
+        _check(lib.dvmat_ddc_create_ex(self.n_vox, self.n_bl, len(val),
+                                       row.ctypes.data_as(_P) if len(val) else None,
+                                       col.ctypes.data_as(_P) if len(val) else None,
+                                       val.ctypes.data_as(_P) if len(val) else None,
+                                       STORAGE[storage], ctypes.byref(opts), ctypes.byref(h)))
         self._h = h
         info = DdcInfo()
         _check(lib.dvmat_ddc_info(h, ctypes.byref(info)))

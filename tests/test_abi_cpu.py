@@ -102,8 +102,10 @@ def test_row_blocks_cover_rows(dv):
     dv.lib.dvmat_ddc_info(h, ctypes.byref(info))
     assert info.nnz == len(d["val"])
     assert info.n_blocks_dose >= 1 and info.n_blocks_price >= 1
-    # padding adds fewer than 4 entries per non-empty row
-    assert info.nnz <= info.nnz_pad_dose < info.nnz + 4 * info.nonempty_rows_dose
+    # with one row per block row, padding adds fewer than 4 entries per non-empty row
+    assert info.price_block_rows == 1
+    assert info.nnz <= info.nnz_pad_price < info.nnz + 4 * info.nonempty_rows_price
+    assert info.nnz_pad_dose >= info.nnz
     dv.lib.dvmat_ddc_destroy(h)
 
 
@@ -119,3 +121,30 @@ def test_bb_and_select_argument_checks(dv):
     assert dv.lib.dvmat_obj_workspace_size(0, ctypes.byref(n)) == -1
     assert dv.lib.dvmat_obj_workspace_size(5, ctypes.byref(n)) == 0
     assert dv.lib.dvmat_bb_count(None) == -1
+
+
+def test_build_options(dv):
+    from paper_1503_01721_amd import synth
+    opts = dv.BuildOpts()
+    assert dv.lib.dvmat_ddc_default_opts(ctypes.byref(opts)) == 0
+    assert opts.dose_block_rows in (1, 2, 4) and opts.price_block_rows in (1, 2, 4) and opts.interleave in (0, 1)
+    plan = synth.PLANS["small_cp8_bl6x6_vox16"]
+    d = synth.generate_ddc(plan)
+    row = np.ascontiguousarray(d["row"]); col = np.ascontiguousarray(d["col"]); val = np.ascontiguousarray(d["val"])
+    P = ctypes.c_void_p
+    for bd, bp in ((1, 1), (2, 4), (4, 2), (3, 1), (1, 0)):
+        o = dv.BuildOpts(bd, bp, 1, 2048)
+        h = ctypes.c_void_p()
+        code = dv.lib.dvmat_ddc_create_ex(plan.n_vox, plan.n_bl, len(val), row.ctypes.data_as(P), col.ctypes.data_as(P),
+                                          val.ctypes.data_as(P), 0, ctypes.byref(o), ctypes.byref(h))
+        if bd not in (1, 2, 4) or bp not in (1, 2, 4):
+            assert code == -1
+            continue
+        assert code == 0
+        info = dv.DdcInfo()
+        dv.lib.dvmat_ddc_info(h, ctypes.byref(info))
+        assert info.nnz == len(val) and info.dose_block_rows == bd and info.price_block_rows == bp
+        # stored value slots: at least the non-zeros, block rows hold B values per stored column
+        assert info.nnz_pad_dose >= info.nnz and info.nnz_pad_dose % bd == 0
+        assert info.nnz_pad_price >= info.nnz and info.nnz_pad_price % bp == 0
+        dv.lib.dvmat_ddc_destroy(h)

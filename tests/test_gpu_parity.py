@@ -411,9 +411,10 @@ def test_precision_forms(dv, plan1, storage):
 
 # ---------------------------------------------------------------- launch shapes and autotuner
 
-@pytest.mark.parametrize("kind", ["row", "stream"])
+@pytest.mark.parametrize("kind,B", [("row", 1), ("stream", 1), ("row", 2), ("row", 4)])
 @pytest.mark.parametrize("wg", [8, 1000, 8192])
-def test_launch_shapes_match_oracle(dv, kind, wg):
+@pytest.mark.parametrize("interleave", [0, 1])
+def test_launch_shapes_match_oracle(dv, kind, B, wg, interleave):
     # ragged unstructured matrix with empty rows, a dense band of long rows and
     # short rows: exercises multi-row blocks, single-row blocks longer than the
     # block budget, and the segmented reduction across row boundaries
@@ -425,12 +426,13 @@ def test_launch_shapes_match_oracle(dv, kind, wg):
     mask[:, 50:80] = False                                # empty columns
     r, c = np.nonzero(mask)
     v = rng.uniform(0.001, 1, len(r)).astype(np.float32)
-    ddc = dv.DDC(r, c, v, n_vox, n_bl)
+    ddc = dv.DDC(r, c, v, n_vox, n_bl, dose_block_rows=B, price_block_rows=B, interleave=interleave)
+    assert ddc.info.dose_block_rows == B and ddc.info.price_block_rows == B
     ddc.set_kernel("dose", kind, wg)
     ddc.set_kernel("price", kind, wg)
     X = rng.random((n_bl, 4)).astype(np.float32)
     G = rng.standard_normal((n_vox, 4)).astype(np.float32)
-    for x, g in ((X[:, 0].copy(), G[:, 0].copy()), (X, G)):
+    for x, g in ((X[:, 0].copy(), G[:, 0].copy()), (X, G), (X[:, :3].copy(), G[:, :3].copy())):
         z_ref = oprod.dose(r, c, v, x, n_vox)
         p_ref = oprod.price(r, c, v, g, n_bl)
         z = ddc.dose(cuda(x)).cpu().numpy()
@@ -467,3 +469,38 @@ def test_autotune_keeps_results_within_tolerance(dv, plan1):
     assert np.abs(ddc.dose(cuda(x)).cpu().numpy() - z_ref).max() <= TOL * z_ref.max()
     p_ref = oprod.price(d["row"], d["col"], d["val"], g, PLAN1.n_bl)
     assert np.abs(ddc.price(cuda(g)).cpu().numpy() - p_ref).max() <= TOL * price_scale(d, g, PLAN1.n_bl)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("B", [1, 2, 4])
+def test_block_rows_plain_method_workload(dv, plan1, storage, B):
+    """Every block-row layout and storage type on the 20-angle workload, with
+    the objective epilogue, the curvature pass and 8 right-hand sides."""
+    d, sid, table, _, obj = plan1
+    ddc = dv.DDC(d["row"], d["col"], d["val"], PLAN1.n_vox, PLAN1.n_bl, storage=storage,
+                 dose_block_rows=B, price_block_rows=B)
+    val = d["val"].astype(np.float64)
+    if storage != "f32":
+        s = np.zeros(PLAN1.n_bl, np.float32)
+        np.maximum.at(s, d["col"], np.abs(d["val"]))
+        s[s == 0] = 1.0
+        q = d["val"] / s[d["col"]]
+        q = q.astype(np.float16).astype(np.float32) if storage == "f16" else _bf16_round(q)
+        val = q.astype(np.float64) * s[d["col"]]
+    x = synth.bench_vectors(PLAN1.n_bl, PLAN1.n_vox, 300 + B)[0] * 4.0
+    z_ref = oprod.dose(d["row"], d["col"], val, x, PLAN1.n_vox)
+    z, g, F = ddc.dose(cuda(x), obj, with_grad=True)
+    assert np.abs(z.cpu().numpy() - z_ref).max() <= TOL * z_ref.max()
+    F_ref = oobj.objective(z_ref, sid, table)
+    assert abs(float(F.cpu()[0]) - F_ref) <= 1e-5 * F_ref
+    gz = g.cpu().numpy().astype(np.float64)
+    p_ref = oprod.price(d["row"], d["col"], val, gz, PLAN1.n_bl)
+    p = ddc.price(g).cpu().numpy()
+    assert np.abs(p - p_ref).max() <= TOL * oprod.price(d["row"], d["col"], np.abs(val), np.abs(gz), PLAN1.n_bl).max()
+    curv = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ddc.curvature_(cuda(x), obj, z, curv)
+    c_ref = oobj.curvature(z_ref, z.cpu().numpy().astype(np.float64), sid, table)
+    assert abs(float(curv.cpu()[0]) - c_ref) <= 3e-5 * c_ref
+    X = np.random.default_rng(B).random((PLAN1.n_bl, 8)).astype(np.float32)
+    Z_ref = oprod.dose(d["row"], d["col"], val, X, PLAN1.n_vox)
+    assert np.abs(ddc.dose(cuda(X)).cpu().numpy() - Z_ref).max() <= TOL * Z_ref.max()
