@@ -269,6 +269,9 @@ def main():
                          "right-hand sides in one launch vs one plan at a time; autograd: F(D B y) "
                          "forward + backward on the two-arc workload")
     ap.add_argument("--plans", type=int, default=48, help="plans in --mode batched")
+    ap.add_argument("--form", default="D", choices=["D", "DA"],
+                    help="master problem over the whole matrix (D, default: every BB iteration runs "
+                         "a dose and a price product) or over the aperture dose vectors (DA)")
     ap.add_argument("--copy-calibration", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
 
@@ -315,7 +318,7 @@ def main():
             f"{('row', 'stream')[info.price_kernel]} x {info.price_workgroups} wg ({info.price_tuned_ms:.3f} ms)")
 
     cg = ColumnGeneration(ddc, obj, plan.n_cp, plan.n_rows, plan.n_cols,
-                          max_apertures=args.warmup + args.steps, bb_steps=args.bb_steps)
+                          max_apertures=args.warmup + args.steps, bb_steps=args.bb_steps, form=args.form)
     cg.start()
     for i in range(args.warmup):
         rec = cg.iteration()
@@ -335,10 +338,17 @@ def main():
     log(f"timed {args.steps} iterations in {wall:.3f} s; last {cg.records[-1]}")
 
     ab = algorithmic_bytes(info)
-    per_iter = args.bb_steps * (ab["dose"] + ab["price"]) + ab["curv"]
+    if args.form == "D":
+        per_iter = args.bb_steps * (ab["dose"] + ab["price"]) + ab["curv"]
+    else:
+        # one price product and one dose product (the new aperture's column) per
+        # iteration; the BB iterations read the DA columns, not the matrix
+        per_iter = ab["price"] + ab["dose"]
     value = args.steps * per_iter / wall / 1e9
-    dose_ms = [e[0].elapsed_time(e[1]) for e in cg.events]
-    price_ms = [e[1].elapsed_time(e[2]) for e in cg.events]
+    if not cg.events:
+        cg.events = []
+    dose_ms = [e[0].elapsed_time(e[1]) for e in cg.events] or [float("nan")]
+    price_ms = [e[1].elapsed_time(e[2]) for e in cg.events] or [float("nan")]
     mean_dose = sum(dose_ms) / len(dose_ms)
     mean_price = sum(price_ms) / len(price_ms)
     dom = "price" if mean_price >= mean_dose else "dose"
@@ -366,7 +376,8 @@ def main():
             "workload": plan.name,
             "n_vox": plan.n_vox, "n_beamlets": plan.n_bl, "nnz": int(info.nnz),
             "storage": args.storage, "accumulate": "f32", "bb_steps_per_iteration": args.bb_steps,
-            "products_per_iteration": 2 * args.bb_steps + 1,
+            "master_problem_form": args.form,
+            "products_per_iteration": 2 * args.bb_steps + 1 if args.form == "D" else 2,
             "algorithmic_bytes_per_iteration": per_iter,
             "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
             "mean_dose_call_ms": round(mean_dose, 4), "mean_price_call_ms": round(mean_price, 4),

@@ -281,6 +281,10 @@ dvmat_status dvmat_bb_direction(dvmat_bb bb, const float* p, float* x_dir, dvmat
  * nullable). */
 dvmat_status dvmat_bb_step(dvmat_bb bb, const float* p, const float* F, const double* curv,
                            float* x_next, uint32_t* flags, dvmat_stream stream);
+/* Device pointers into the workspace: the current rates y (float[count]) and
+ * the masked gradient of the last dvmat_bb_direction/step (float[count]);
+ * valid while the handle lives, contents change with each call. */
+dvmat_status dvmat_bb_state(dvmat_bb bb, const float** y, const float** gt);
 /* As dvmat_bb_direction and dvmat_bb_step, but with the gradient in the
  * aperture domain supplied by the caller: G device float[count] = dF/dy_k
  * (e.g. from automatic differentiation of F(D B y)); nothing is gathered. */
@@ -340,6 +344,36 @@ dvmat_status dvmat_aperture_expand(dvmat_geom geom, int32_t m, const int32_t* cp
                                    const int32_t* R, const float* y, float* x, dvmat_stream stream);
 dvmat_status dvmat_aperture_gather(dvmat_geom geom, int32_t m, const int32_t* cps, const int32_t* L,
                                    const int32_t* R, const float* p, float* G, dvmat_stream stream);
+
+/* ------------------------------------------------------------------------
+ * DA-form master problem (Eq. 6 as written in the paper): the dose vector of
+ * each chosen aperture, DA(A_k) = sum_{j in A_k} D_:j (Eq. 5), is formed once
+ * on the device as a dense column; z = sum_k DA_k y_k and the gradient in the
+ * aperture domain G_k = <DA_k, dF/dz> then need only the m columns, not the
+ * whole matrix (Sec. 2.2.2 forms DA on the CPU; here one dose product of the
+ * aperture's indicator fluence does it on the GPU).
+ * ---------------------------------------------------------------------- */
+typedef struct dvmat_da_s* dvmat_da;
+
+dvmat_status dvmat_da_workspace_size(int64_t n_vox, int32_t max_apertures, size_t* bytes);
+dvmat_status dvmat_da_create(int64_t n_vox, int32_t max_apertures, void* d_workspace, size_t bytes,
+                             dvmat_da* out);
+void dvmat_da_destroy(dvmat_da da);
+int32_t dvmat_da_count(dvmat_da da);
+/* Append DA = D x_ind for the next aperture: x_ind device float[n_bl], the
+ * aperture's indicator fluence (e.g. dvmat_aperture_expand with rate 1).
+ * DVMAT_E_STATE when max_apertures columns exist. */
+dvmat_status dvmat_da_append(dvmat_da da, dvmat_ddc ddc, const float* x_ind, dvmat_stream stream);
+/* y: device float[count]; z, g (nullable): device float[n_vox] receive the dose
+ * and dF/dz; G: device float[count] = dF/dy; F (nullable): device float[1]. */
+dvmat_status dvmat_da_eval(dvmat_da da, dvmat_obj obj, const float* y, float* z, float* g, float* G,
+                           float* F, dvmat_stream stream);
+/* curv = sum_i w_i(z_ref) (sum_k DA_k dir_k)_i^2 (weights as dvmat_dose_curvature);
+ * dir: device float[count]; curv: device double[1]. */
+dvmat_status dvmat_da_curvature(dvmat_da da, dvmat_obj obj, const float* dir, const float* z_ref,
+                                double* curv, dvmat_stream stream);
+/* Device pointer of column k (float[n_vox]). */
+dvmat_status dvmat_da_column(dvmat_da da, int32_t k, const float** col);
 
 #ifdef __cplusplus
 }

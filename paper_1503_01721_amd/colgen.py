@@ -8,6 +8,12 @@ D^T on the devices for the price and forms each aperture's DDC vector on the
 CPU (Sec. 2.2.2); here the whole DDC sits in HBM and every master-problem
 iteration runs the dose and price products on it.
 
+Two forms of the master problem: "D" runs every BB iteration through the
+dose and price products over the whole DDC matrix; "DA" is the paper's own
+form (Eq. 6): each chosen aperture's dose vector DA_k = D 1_{A_k} (Eq. 5) is
+formed once and the iterations read only those m columns.  Both compute the
+same iterates up to rounding.
+
 Per iteration the host reads back one small record (chosen control point,
 its price, the solve's flags and F); all other data stays on the device.
 """
@@ -35,7 +41,10 @@ class ColumnGeneration:
 
     def __init__(self, ddc: dvmat.DDC, obj: dvmat.Objective, n_cp: int, n_rows: int, n_cols: int,
                  max_apertures: Optional[int] = None, bb_steps: int = 50, eps_f: float = 1e-5,
-                 eps_step: float = 1e-7, lo: float = 0.0, hi: float = float("inf")):
+                 eps_step: float = 1e-7, lo: float = 0.0, hi: float = float("inf"), form: str = "D"):
+        if form not in ("D", "DA"):
+            raise ValueError("form must be 'D' or 'DA'")
+        self.form = form
         if n_cp * n_rows * n_cols != ddc.n_bl:
             raise ValueError("control-point geometry does not match the number of beamlets")
         dev = ddc.device
@@ -55,6 +64,12 @@ class ColumnGeneration:
         self.g = torch.empty(ddc.n_vox, **f32)
         self.F = torch.empty(1, **f32)
         self.curv = torch.empty(1, dtype=torch.float64, device=dev)
+        if form == "DA":
+            self.da = dvmat.DAColumns(ddc.n_vox, self.max_apertures, device=dev)
+            self.G = torch.empty(self.max_apertures, dtype=torch.float32, device=dev)
+            self.one = torch.ones(1, dtype=torch.float32, device=dev)
+            self.cp_dev = torch.empty(1, dtype=torch.int32, device=dev)
+            self.x_ind = torch.empty(ddc.n_bl, dtype=torch.float32, device=dev)
         self.records: List[IterationRecord] = []
         # optional HIP-event log of (dose start, dose end = price start, price end)
         # per master-problem iteration; events are recorded on torch's current
@@ -73,10 +88,34 @@ class ColumnGeneration:
         """Pricing problem, second step (device); returns the selector."""
         return self.sel(self.p, self.bb.occupied_ptr)
 
+    def _master_problem_da(self, steps):
+        m = self.bb.count
+        G = self.G[:m]
+        y_ptr, gt_ptr = self.bb.state_ptrs()
+        self.bb.begin()
+        self.da.eval_(self.obj, y_ptr, G, z=self.z, g=self.g, F=self.F)
+        self.bb.direction_g_(G, self.x_dir)
+        self.da.curvature_(self.obj, gt_ptr, self.z, self.curv)
+        for _ in range(steps):
+            self.bb.step_g_(G, self.F, self.curv, self.x)
+            self.da.eval_(self.obj, y_ptr, G, z=self.z, g=self.g, F=self.F)
+        self.ddc.price_(self.g, self.p)
+
+    def _append_da_column(self, cp):
+        """DA of the new aperture: dose of its indicator fluence (Eq. 5)."""
+        self.cp_dev.fill_(cp)
+        dvmat._check(dvmat.lib.dvmat_aperture_expand(self.sel.geom, 1, dvmat._ptr(self.cp_dev),
+                                                     dvmat._ptr(self.sel.L[cp]), dvmat._ptr(self.sel.R[cp]),
+                                                     dvmat._ptr(self.one), dvmat._ptr(self.x_ind),
+                                                     dvmat._stream()))
+        self.da.append_(self.ddc, self.x_ind)
+
     def master_problem(self, steps: Optional[int] = None):
         """BB solve over the current aperture set: begin, the first step
         length's curvature product, then `steps` x (step, dose+objective, price)."""
         steps = self.bb_steps if steps is None else steps
+        if self.form == "DA":
+            return self._master_problem_da(steps)
         self.bb.begin()
         self.bb.direction_(self.p, self.x_dir)
         self.ddc.curvature_(self.x_dir, self.obj, self.z, self.curv)
@@ -105,6 +144,8 @@ class ColumnGeneration:
             self.done = True
             return None
         self.bb.add_aperture(best, self.sel.L[best], self.sel.R[best], self.lo, self.hi)
+        if self.form == "DA":
+            self._append_da_column(best)
         self.master_problem()
         rec = IterationRecord(self.iterations, best, best_price, float(self.F.item()), int(self.bb.flags.item()))
         self.records.append(rec)

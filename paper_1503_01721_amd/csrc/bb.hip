@@ -388,6 +388,13 @@ void dvmat_bb_destroy(dvmat_bb b) { delete b; }
 
 int32_t dvmat_bb_count(dvmat_bb b) { return b ? b->m : -1; }
 
+dvmat_status dvmat_bb_state(dvmat_bb b, const float** y, const float** gt) {
+    if (!b) return set_error(DVMAT_E_ARG, "dvmat_bb_state: NULL handle");
+    if (y) *y = b->dev.y;
+    if (gt) *gt = b->dev.Gt;
+    return DVMAT_OK;
+}
+
 dvmat_status dvmat_bb_occupancy(dvmat_bb b, const uint8_t** d_occupied) {
     if (!b || !d_occupied) return set_error(DVMAT_E_ARG, "dvmat_bb_occupancy: NULL argument");
     *d_occupied = b->dev.occ;

@@ -1,0 +1,258 @@
+// DA-form master problem (Eq. 6 as the paper writes it).
+//
+// The paper solves the master problem on the aperture DDC vectors
+// DA(A_k) = sum_{j in A_k} D_:j (Eq. 5), computed once per chosen aperture,
+// with z = sum_k DA_k y_k and the gradient in the aperture domain
+// G_k = <DA_k, dF/dz> (Sec. 2.1, Sec. 2.2.2).  Here each DA_k is a dense
+// device column of n_vox floats, produced by one dose product of the
+// aperture's indicator fluence; a BB iteration then reads the m columns
+// instead of the whole matrix twice.
+//
+// dvmat_da_eval is one pass over the columns: a workgroup owns a contiguous
+// chunk of voxels, forms z and dF/dz for it (columns streamed from HBM), keeps
+// dF/dz in LDS, then re-reads its chunk of every column (now in L2) to form
+// its share of each G_k; per-workgroup shares are summed in a fixed order.
+#include "common.hpp"
+
+#include <cmath>
+#include <new>
+
+namespace dvmat {
+
+constexpr int kDaThreads = 256;
+constexpr int kDaPerThread = 16;
+constexpr int kDaChunk = kDaThreads * kDaPerThread;   // voxels per workgroup
+
+}  // namespace dvmat
+
+struct dvmat_da_s {
+    int64_t n_vox = 0;
+    int32_t max_ap = 0;
+    int32_t m = 0;
+    int32_t n_chunks = 0;
+    float* cols = nullptr;       // [max_ap][n_vox]
+    float* partial = nullptr;    // [max_ap + 1][n_chunks]: G shares, then F shares
+    double* partial_d = nullptr; // [n_chunks]
+    float* gbuf = nullptr;       // [n_vox] dF/dz when the caller does not keep it
+};
+
+namespace dvmat {
+
+static size_t da_layout(int64_t n_vox, int32_t max_ap, dvmat_da_s* d, char* base) {
+    const int64_t chunks = (n_vox + kDaChunk - 1) / kDaChunk;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return base ? base + o : nullptr; };
+    char* p;
+    p = take((size_t)max_ap * n_vox * 4);           if (d) d->cols = reinterpret_cast<float*>(p);
+    p = take((size_t)(max_ap + 1) * chunks * 4);    if (d) d->partial = reinterpret_cast<float*>(p);
+    p = take((size_t)chunks * 8);                   if (d) d->partial_d = reinterpret_cast<double*>(p);
+    p = take((size_t)n_vox * 4);                    if (d) d->gbuf = reinterpret_cast<float*>(p);
+    if (d) d->n_chunks = (int32_t)chunks;
+    return off;
+}
+
+__device__ __forceinline__ float block_sum(float v, float* red) {
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    float s = 0.0f;
+    for (int w = 0; w < kDaThreads / 64; ++w) s += red[w];
+    return s;
+}
+
+__global__ __launch_bounds__(kDaThreads) void da_eval_kernel(const float* __restrict__ cols, int64_t n_vox, int m,
+                                                             const float* __restrict__ y, const uint8_t* __restrict__ sid,
+                                                             const float* __restrict__ table, float* __restrict__ z,
+                                                             float* __restrict__ g, float* __restrict__ partial,
+                                                             int n_chunks) {
+    __shared__ float sy[1024];
+    __shared__ float sg[kDaChunk];
+    __shared__ float red[kDaThreads / 64];
+    const int64_t c0 = (int64_t)blockIdx.x * kDaChunk;
+    for (int k = threadIdx.x; k < m; k += kDaThreads) sy[k] = y[k];
+    __syncthreads();
+    float fpart = 0.0f;
+    for (int u = 0; u < kDaPerThread; ++u) {
+        const int li = u * kDaThreads + threadIdx.x;
+        const int64_t i = c0 + li;
+        float gi = 0.0f;
+        if (i < n_vox) {
+            float zi = 0.0f;
+            for (int k = 0; k < m; ++k) zi += cols[(int64_t)k * n_vox + i] * sy[k];
+            const int s = sid[i];
+            const float T = table[s * 4 + 0], wo = table[s * 4 + 1], wu = table[s * 4 + 2];
+            const float over = fmaxf(zi - T, 0.0f), under = fmaxf(T - zi, 0.0f);
+            gi = 2.0f * wo * over - 2.0f * wu * under;
+            fpart += wo * over * over + wu * under * under;
+            if (z) z[i] = zi;
+            g[i] = gi;
+        }
+        sg[li] = gi;
+    }
+    // G_k shares: this chunk of every column (just streamed, so in L2)
+    for (int k = 0; k < m; ++k) {
+        float a = 0.0f;
+        for (int u = 0; u < kDaPerThread; ++u) {
+            const int li = u * kDaThreads + threadIdx.x;
+            const int64_t i = c0 + li;
+            if (i < n_vox) a += cols[(int64_t)k * n_vox + i] * sg[li];
+        }
+        const float s = block_sum(a, red);
+        if (threadIdx.x == 0) partial[(int64_t)k * n_chunks + blockIdx.x] = s;
+    }
+    const float fs = block_sum(fpart, red);
+    if (threadIdx.x == 0) partial[(int64_t)m * n_chunks + blockIdx.x] = fs;
+}
+
+// G[k] = sum of the chunk shares (k < m), F = sum of the F shares; fixed order, FP64.
+__global__ __launch_bounds__(256) void da_finalize_kernel(const float* __restrict__ partial, int m, int n_chunks,
+                                                          float* __restrict__ G, float* __restrict__ F) {
+    __shared__ double s[256];
+    for (int k = 0; k <= m; ++k) {
+        double a = 0.0;
+        for (int c = threadIdx.x; c < n_chunks; c += 256) a += (double)partial[(int64_t)k * n_chunks + c];
+        s[threadIdx.x] = a;
+        __syncthreads();
+        for (int o = 128; o >= 1; o >>= 1) {
+            if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            if (k < m) G[k] = (float)s[0];
+            else if (F) F[0] = (float)s[0];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kDaThreads) void da_curv_kernel(const float* __restrict__ cols, int64_t n_vox, int m,
+                                                             const float* __restrict__ dirv,
+                                                             const uint8_t* __restrict__ sid,
+                                                             const float* __restrict__ table,
+                                                             const float* __restrict__ zref,
+                                                             double* __restrict__ partial_d) {
+    __shared__ float sd[1024];
+    __shared__ double red[kDaThreads / 64];
+    const int64_t c0 = (int64_t)blockIdx.x * kDaChunk;
+    for (int k = threadIdx.x; k < m; k += kDaThreads) sd[k] = dirv[k];
+    __syncthreads();
+    double a = 0.0;
+    for (int u = 0; u < kDaPerThread; ++u) {
+        const int64_t i = c0 + u * kDaThreads + threadIdx.x;
+        if (i >= n_vox) continue;
+        float di = 0.0f;
+        for (int k = 0; k < m; ++k) di += cols[(int64_t)k * n_vox + i] * sd[k];
+        const int s = sid[i];
+        const float T = table[s * 4 + 0];
+        const float zr = zref[i];
+        const float w = zr > T ? table[s * 4 + 1] : (zr < T ? table[s * 4 + 2] : 0.0f);
+        a += (double)w * (double)di * (double)di;
+    }
+    for (int o = 32; o >= 1; o >>= 1) a += __shfl_xor(a, o);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kDaThreads / 64; ++w) t += red[w];
+        partial_d[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(256) void da_finalize_d_kernel(const double* __restrict__ partial, int n, double* out) {
+    __shared__ double s[256];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) a += partial[i];
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+        if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0];
+}
+
+}  // namespace dvmat
+
+using namespace dvmat;
+
+extern "C" {
+
+dvmat_status dvmat_da_workspace_size(int64_t n_vox, int32_t max_ap, size_t* bytes) {
+    if (!bytes) return set_error(DVMAT_E_ARG, "dvmat_da_workspace_size: bytes is NULL");
+    if (n_vox < 1 || max_ap < 1 || max_ap > 1024)
+        return set_error(DVMAT_E_ARG, "dvmat_da_workspace_size: n_vox=%lld max_apertures=%d (1..1024)",
+                         (long long)n_vox, max_ap);
+    *bytes = da_layout(n_vox, max_ap, nullptr, nullptr);
+    return DVMAT_OK;
+}
+
+dvmat_status dvmat_da_create(int64_t n_vox, int32_t max_ap, void* ws, size_t bytes, dvmat_da* out) {
+    if (!out) return set_error(DVMAT_E_ARG, "dvmat_da_create: out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    dvmat_status st = dvmat_da_workspace_size(n_vox, max_ap, &need);
+    if (st) return st;
+    if (!ws) return set_error(DVMAT_E_ARG, "dvmat_da_create: workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign) return set_error(DVMAT_E_ARG, "dvmat_da_create: workspace misaligned");
+    if (bytes < need) return set_error(DVMAT_E_NOMEM, "dvmat_da_create: workspace %zu < %zu bytes", bytes, need);
+    dvmat_da_s* d = new (std::nothrow) dvmat_da_s();
+    if (!d) return set_error(DVMAT_E_NOMEM, "dvmat_da_create: host allocation failed");
+    d->n_vox = n_vox;
+    d->max_ap = max_ap;
+    da_layout(n_vox, max_ap, d, static_cast<char*>(ws));
+    *out = d;
+    return DVMAT_OK;
+}
+
+void dvmat_da_destroy(dvmat_da d) { delete d; }
+
+int32_t dvmat_da_count(dvmat_da d) { return d ? d->m : -1; }
+
+dvmat_status dvmat_da_append(dvmat_da d, dvmat_ddc ddc, const float* x_ind, dvmat_stream stream) {
+    if (!d || !ddc || !x_ind) return set_error(DVMAT_E_ARG, "dvmat_da_append: NULL argument");
+    if (d->m >= d->max_ap) return set_error(DVMAT_E_STATE, "dvmat_da_append: %d columns already", d->m);
+    dvmat_ddc_info_t info;
+    dvmat_status st = dvmat_ddc_info(ddc, &info);
+    if (st) return st;
+    if (info.n_vox != d->n_vox) return set_error(DVMAT_E_SHAPE, "dvmat_da_append: voxel count mismatch");
+    st = dvmat_dose(ddc, x_ind, 1, d->cols + (int64_t)d->m * d->n_vox, nullptr, nullptr, nullptr, stream);
+    if (st) return st;
+    d->m++;
+    return DVMAT_OK;
+}
+
+dvmat_status dvmat_da_eval(dvmat_da d, dvmat_obj obj, const float* y, float* z, float* g, float* G, float* F,
+                           dvmat_stream stream) {
+    if (!d || !obj || !y || !G) return set_error(DVMAT_E_ARG, "dvmat_da_eval: NULL argument");
+    if (obj->n_vox != d->n_vox) return set_error(DVMAT_E_SHAPE, "dvmat_da_eval: voxel count mismatch");
+    if (d->m == 0) return set_error(DVMAT_E_STATE, "dvmat_da_eval: no columns");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(da_eval_kernel, dim3(d->n_chunks), dim3(kDaThreads), 0, s, d->cols, d->n_vox, d->m, y,
+                       obj->sid, obj->table, z, g ? g : d->gbuf, d->partial, d->n_chunks);
+    hipLaunchKernelGGL(da_finalize_kernel, dim3(1), dim3(256), 0, s, d->partial, d->m, d->n_chunks, G, F);
+    return check_hip(hipGetLastError(), "dvmat_da_eval launch");
+}
+
+dvmat_status dvmat_da_curvature(dvmat_da d, dvmat_obj obj, const float* dir, const float* z_ref, double* curv,
+                                dvmat_stream stream) {
+    if (!d || !obj || !dir || !z_ref || !curv) return set_error(DVMAT_E_ARG, "dvmat_da_curvature: NULL argument");
+    if (obj->n_vox != d->n_vox) return set_error(DVMAT_E_SHAPE, "dvmat_da_curvature: voxel count mismatch");
+    if (d->m == 0) return set_error(DVMAT_E_STATE, "dvmat_da_curvature: no columns");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(da_curv_kernel, dim3(d->n_chunks), dim3(kDaThreads), 0, s, d->cols, d->n_vox, d->m, dir,
+                       obj->sid, obj->table, z_ref, d->partial_d);
+    hipLaunchKernelGGL(da_finalize_d_kernel, dim3(1), dim3(256), 0, s, d->partial_d, d->n_chunks, curv);
+    return check_hip(hipGetLastError(), "dvmat_da_curvature launch");
+}
+
+dvmat_status dvmat_da_column(dvmat_da d, int32_t k, const float** col) {
+    if (!d || !col) return set_error(DVMAT_E_ARG, "dvmat_da_column: NULL argument");
+    if (k < 0 || k >= d->m) return set_error(DVMAT_E_ARG, "dvmat_da_column: column %d of %d", k, d->m);
+    *col = d->cols + (int64_t)k * d->n_vox;
+    return DVMAT_OK;
+}
+
+}  // extern "C"

@@ -103,6 +103,15 @@ _SIGNATURES = {
     "dvmat_bb_step": (_I32, [_P, _P, _P, _P, _P, _P, _P]),
     "dvmat_bb_direction_g": (_I32, [_P, _P, _P, _P]),
     "dvmat_bb_step_g": (_I32, [_P, _P, _P, _P, _P, _P, _P]),
+    "dvmat_bb_state": (_I32, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P)]),
+    "dvmat_da_workspace_size": (_I32, [_I64, _I32, ctypes.POINTER(_SZ)]),
+    "dvmat_da_create": (_I32, [_I64, _I32, _P, _SZ, ctypes.POINTER(_P)]),
+    "dvmat_da_destroy": (None, [_P]),
+    "dvmat_da_count": (_I32, [_P]),
+    "dvmat_da_append": (_I32, [_P, _P, _P, _P]),
+    "dvmat_da_eval": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P]),
+    "dvmat_da_curvature": (_I32, [_P, _P, _P, _P, _P, _P]),
+    "dvmat_da_column": (_I32, [_P, _I32, ctypes.POINTER(_P)]),
     "dvmat_aperture_expand": (_I32, [Geom, _I32, _P, _P, _P, _P, _P, _P]),
     "dvmat_aperture_gather": (_I32, [Geom, _I32, _P, _P, _P, _P, _P, _P]),
     "dvmat_bb_expand": (_I32, [_P, _P, _P]),
@@ -374,6 +383,12 @@ class BB:
     def count(self):
         return lib.dvmat_bb_count(self._h)
 
+    def state_ptrs(self):
+        """(y, masked gradient) device pointers inside the workspace."""
+        y, gt = _P(), _P()
+        _check(lib.dvmat_bb_state(self._h, ctypes.byref(y), ctypes.byref(gt)))
+        return y, gt
+
     @property
     def occupied_ptr(self):
         """Device pointer of the control-point occupancy bytes (for aperture selection)."""
@@ -431,6 +446,57 @@ class BB:
         out = torch.empty(max(self.count, 1), dtype=torch.float32, device=self.device)
         _check(lib.dvmat_bb_get_y(self._h, _ptr(out), _stream()))
         return out[:self.count]
+
+
+class DAColumns:
+    """Dense aperture dose vectors DA_k (Eq. 5) for the DA-form master problem."""
+
+    def __init__(self, n_vox, max_apertures, device="cuda"):
+        self.n_vox = int(n_vox)
+        nbytes = _SZ()
+        _check(lib.dvmat_da_workspace_size(self.n_vox, int(max_apertures), ctypes.byref(nbytes)))
+        self.device = torch.device(device)
+        self.workspace = _workspace(nbytes.value, self.device)
+        h = _P()
+        _check(lib.dvmat_da_create(self.n_vox, int(max_apertures), _ptr(self.workspace), self.workspace.numel(),
+                                   ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib.dvmat_da_destroy(h)
+            self._h = None
+
+    @property
+    def count(self):
+        return lib.dvmat_da_count(self._h)
+
+    def append_(self, ddc, x_ind, stream=None):
+        _need(x_ind, ddc.n_bl, name="x_ind")
+        _check(lib.dvmat_da_append(self._h, ddc.handle, _ptr(x_ind), _stream(stream)))
+
+    def eval_(self, obj, y, G, z=None, g=None, F=None, stream=None):
+        """y, G: device pointers (c_void_p) or tensors of count floats."""
+        yp = y if isinstance(y, ctypes.c_void_p) else _ptr(y)
+        if not isinstance(y, ctypes.c_void_p):
+            _need(y, self.count, name="y")
+        _need(G, self.count, name="G")
+        _need(z, self.n_vox, name="z")
+        _need(g, self.n_vox, name="g")
+        _need(F, 1, name="F", at_least=True)
+        _check(lib.dvmat_da_eval(self._h, obj.handle, yp, _ptr(z), _ptr(g), _ptr(G), _ptr(F), _stream(stream)))
+
+    def curvature_(self, obj, direction, z_ref, curv, stream=None):
+        dp = direction if isinstance(direction, ctypes.c_void_p) else _ptr(direction)
+        _need(z_ref, self.n_vox, name="z_ref")
+        _need(curv, 1, torch.float64, name="curv", at_least=True)
+        _check(lib.dvmat_da_curvature(self._h, obj.handle, dp, _ptr(z_ref), _ptr(curv), _stream(stream)))
+
+    def column(self, k):
+        p = _P()
+        _check(lib.dvmat_da_column(self._h, int(k), ctypes.byref(p)))
+        return p
 
 
 class Apertures:

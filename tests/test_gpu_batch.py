@@ -42,10 +42,11 @@ def _dequant(d, n_bl, storage):
 
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 @pytest.mark.parametrize("nrhs", [1, 8])
-@pytest.mark.parametrize("kind", ["row", "stream"])
-def test_batch_matches_oracle_and_single_calls(plans, storage, nrhs, kind):
+@pytest.mark.parametrize("kind,B", [("row", 1), ("stream", 1), ("row", 2), ("row", 4)])
+def test_batch_matches_oracle_and_single_calls(plans, storage, nrhs, kind, B):
     from paper_1503_01721_amd import dvmat
-    ddcs = [dvmat.DDC(d["row"], d["col"], d["val"], nv, nb, storage=storage) for nv, nb, d in plans]
+    ddcs = [dvmat.DDC(d["row"], d["col"], d["val"], nv, nb, storage=storage, dose_block_rows=B,
+                      price_block_rows=B) for nv, nb, d in plans]
     batch = dvmat.Batch(ddcs)
     info = batch.info()
     assert info["dose_blocks"] == sum(x.info.n_blocks_dose for x in ddcs)

@@ -322,7 +322,8 @@ def test_bb_box_bounds_and_stop_rule(dv, plan1):
             assert np.array_equal(gpu["y"][t], gpu["y"][s0])
 
 
-def test_column_generation_matches_oracle(dv, plan1):
+@pytest.mark.parametrize("form", ["D", "DA"])
+def test_column_generation_matches_oracle(dv, plan1, form):
     """Each GPU column-generation iteration checked against the oracle from
     the same state: the prices the selection sees, the selection's optimality
     (within the price error bound: near-ties between control points make an
@@ -331,7 +332,7 @@ def test_column_generation_matches_oracle(dv, plan1):
     from paper_1503_01721_amd.colgen import ColumnGeneration
     d, sid, table, ddc, obj = plan1
     n_cp, n_rows, n_cols = PLAN1.n_cp, PLAN1.n_rows, PLAN1.n_cols
-    cg = ColumnGeneration(ddc, obj, n_cp, n_rows, n_cols, bb_steps=50, eps_f=0.0, eps_step=0.0)
+    cg = ColumnGeneration(ddc, obj, n_cp, n_rows, n_cols, bb_steps=50, eps_f=0.0, eps_step=0.0, form=form)
     cg.start()
     apset = obb.ApertureSet(n_cp, n_rows, n_cols)
     occupied = np.zeros(n_cp, bool)
@@ -504,3 +505,50 @@ def test_block_rows_plain_method_workload(dv, plan1, storage, B):
     X = np.random.default_rng(B).random((PLAN1.n_bl, 8)).astype(np.float32)
     Z_ref = oprod.dose(d["row"], d["col"], val, X, PLAN1.n_vox)
     assert np.abs(ddc.dose(cuda(X)).cpu().numpy() - Z_ref).max() <= TOL * Z_ref.max()
+
+
+def test_da_columns_and_eval(dv, plan1):
+    """DA-form pieces: the columns equal Eq. (5) and one evaluation gives the
+    oracle's z = sum_k DA_k y_k, F and G_k = <DA_k, dF/dz>."""
+    d, sid, table, ddc, obj = plan1
+    m = 6
+    cps, L, R = synth.random_apertures(PLAN1, m, 55)
+    da = dv.DAColumns(PLAN1.n_vox, 8)
+    apset = obb.ApertureSet(PLAN1.n_cp, PLAN1.n_rows, PLAN1.n_cols)
+    for k in range(m):
+        one = dv.Apertures(PLAN1.n_cp, PLAN1.n_rows, PLAN1.n_cols, cps[k:k + 1], L[k:k + 1], R[k:k + 1])
+        x_ind = torch.empty(PLAN1.n_bl, device="cuda")
+        one.expand_(torch.ones(1, device="cuda"), x_ind)
+        da.append_(ddc, x_ind)
+        apset.add(cps[k], L[k], R[k])
+    assert da.count == m
+    DA = np.stack([oprod.aperture_ddc(d["row"], d["col"], d["val"], apset.owner == k, PLAN1.n_vox)
+                   for k in range(m)], axis=1)
+    # each column (Eq. 5), read back through an evaluation at a unit rate vector
+    z1 = torch.empty(PLAN1.n_vox, device="cuda")
+    Gk = torch.empty(m, device="cuda")
+    for k in range(m):
+        e = torch.zeros(m, device="cuda")
+        e[k] = 1.0
+        da.eval_(obj, e, Gk, z=z1)
+        assert np.abs(z1.cpu().numpy() - DA[:, k]).max() <= TOL * DA[:, k].max()
+    # evaluate at random rates
+    y = np.random.default_rng(56).uniform(0.5, 4.0, m).astype(np.float32)
+    G = torch.empty(m, device="cuda")
+    z = torch.empty(PLAN1.n_vox, device="cuda")
+    g = torch.empty(PLAN1.n_vox, device="cuda")
+    F = torch.empty(1, device="cuda")
+    da.eval_(obj, torch.tensor(y, device="cuda"), G, z=z, g=g, F=F)
+    z_ref = DA @ y.astype(np.float64)
+    assert np.abs(z.cpu().numpy() - z_ref).max() <= TOL * z_ref.max()
+    F_ref = oobj.objective(z_ref, sid, table)
+    assert abs(float(F.cpu()[0]) - F_ref) <= 1e-5 * F_ref
+    G_ref = DA.T @ oobj.gradient(z_ref, sid, table)
+    G_scale = np.abs(DA).T @ np.abs(oobj.gradient(z_ref, sid, table))
+    assert np.all(np.abs(G.cpu().numpy() - G_ref) <= 1e-5 * G_scale.max())
+    # curvature along a direction
+    dirv = np.random.default_rng(57).standard_normal(m).astype(np.float32)
+    curv = torch.empty(1, dtype=torch.float64, device="cuda")
+    da.curvature_(obj, torch.tensor(dirv, device="cuda"), z, curv)
+    c_ref = oobj.curvature(DA @ dirv.astype(np.float64), z.cpu().numpy().astype(np.float64), sid, table)
+    assert abs(float(curv.cpu()[0]) - c_ref) <= 3e-5 * c_ref
