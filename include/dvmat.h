@@ -84,6 +84,7 @@ typedef struct {
     int32_t price_kernel, price_workgroups;
     float dose_tuned_ms, price_tuned_ms;    /* autotuner's best times (0 before tuning) */
     int32_t dose_block_rows, price_block_rows;  /* rows sharing one column index (build option) */
+    int32_t dose_row_order, price_row_order;    /* row order of the layout (build option) */
 } dvmat_ddc_info_t;
 
 /* Build options of the device layout.  block_rows B in {1, 2, 4}: B
@@ -94,12 +95,18 @@ typedef struct {
  * neighbouring beamlets overlap less (default B = 1 for the price matrix).
  * interleave (0/1, default 1): store the entries of each 256-entry chunk of a
  * block row interleaved so that each gather instruction of a wave covers
- * consecutive columns.  unit_entries: stored values per work unit (default 2048). */
+ * consecutive columns.  unit_entries: stored values per work unit (default 2048).
+ * row_order: 0 = natural; 1 = rows stored in order of their first column
+ * (empty rows last), so rows that read the same part of the input vector run
+ * together (for the price matrix: beamlets covering the same slab of voxels,
+ * from every angle); outputs are still written in natural order. */
 typedef struct {
     int32_t dose_block_rows;
     int32_t price_block_rows;
     int32_t interleave;
     int32_t unit_entries;
+    int32_t dose_row_order;
+    int32_t price_row_order;
 } dvmat_build_opts;
 
 /* Fill opts with the defaults. */

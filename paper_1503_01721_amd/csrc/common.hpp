@@ -53,6 +53,7 @@ struct CsrDev {
     const int32_t* col = nullptr;      // [block entries]
     const void* val = nullptr;         // [block entries * B] of value_bytes
     const int32_t* blocks = nullptr;   // [n_blocks + 1] first block row of each work unit
+    const int32_t* perm = nullptr;     // [n_rows] row stored at each position, or nullptr (natural order)
 };
 
 // Host staging of one orientation before bind.
@@ -64,6 +65,7 @@ struct CsrHost {
     std::vector<int32_t> col;
     std::vector<uint8_t> val;          // value_bytes per value, B values per block entry
     std::vector<int32_t> blocks;
+    std::vector<int32_t> perm;         // empty: natural row order
     int64_t nonempty = 0;
 };
 
@@ -84,8 +86,8 @@ struct dvmat_ddc_s {
     dvmat_build_opts opts{};
     float dose_tuned_ms = 0.0f, price_tuned_ms = 0.0f;
     // workspace layout offsets
-    size_t off_dose_rowptr = 0, off_dose_col = 0, off_dose_val = 0, off_dose_blocks = 0;
-    size_t off_price_rowptr = 0, off_price_col = 0, off_price_val = 0, off_price_blocks = 0;
+    size_t off_dose_rowptr = 0, off_dose_col = 0, off_dose_val = 0, off_dose_blocks = 0, off_dose_perm = 0;
+    size_t off_price_rowptr = 0, off_price_col = 0, off_price_val = 0, off_price_blocks = 0, off_price_perm = 0;
     size_t off_scale = 0, off_xs = 0;
 };
 

@@ -184,12 +184,23 @@ static dvmat_status sort_rows(int64_t n_rows, int64_t nnz, const int32_t* rk, co
 // lane's 16-byte column load then holds entries l, l+n/4, l+2n/4, l+3n/4 and
 // each gather instruction of a wave covers n/4 consecutive sorted columns.
 static dvmat_status build_blocked(const SortedRows& sr, int64_t n_rows, int B, bool interleave, int64_t unit_cap,
-                                  CsrHost& out, std::vector<float>& fvalb) {
+                                  bool order_by_first_col, CsrHost& out, std::vector<float>& fvalb) {
     try {
         const int64_t n_br = (n_rows + B - 1) / B;
         out.n_rows = n_rows;
         out.B = B;
         out.n_brows = n_br;
+        // optional row order: position p holds row perm[p]; rows sorted by their
+        // first column (empty rows last), so rows touching the same part of the
+        // input vector are processed together
+        out.perm.clear();
+        if (order_by_first_col) {
+            out.perm.resize(n_rows);
+            std::iota(out.perm.begin(), out.perm.end(), 0);
+            auto key = [&](int32_t r) -> int64_t { return sr.len[r] > 0 ? sr.col[sr.start[r]] : INT64_MAX; };
+            std::stable_sort(out.perm.begin(), out.perm.end(), [&](int32_t a, int32_t b) { return key(a) < key(b); });
+        }
+        auto row_at = [&](int64_t pos) -> int64_t { return out.perm.empty() ? pos : out.perm[pos]; };
         std::vector<int64_t> uni(n_br, 0);
         // union size of each block row (B-way merge of sorted column lists)
         parallel_for(n_br, [&](int64_t a, int64_t b, int) {
@@ -197,8 +208,8 @@ static dvmat_status build_blocked(const SortedRows& sr, int64_t n_rows, int B, b
             for (int64_t br = a; br < b; ++br) {
                 const int nb = (int)std::min<int64_t>(B, n_rows - br * B);
                 for (int q = 0; q < nb; ++q) {
-                    pos[q] = sr.start[br * B + q];
-                    end[q] = pos[q] + sr.len[br * B + q];
+                    pos[q] = sr.start[row_at(br * B + q)];
+                    end[q] = pos[q] + sr.len[row_at(br * B + q)];
                 }
                 int64_t u = 0;
                 for (;;) {
@@ -225,8 +236,8 @@ static dvmat_status build_blocked(const SortedRows& sr, int64_t n_rows, int B, b
             for (int64_t br = a; br < b; ++br) {
                 const int nb = (int)std::min<int64_t>(B, n_rows - br * B);
                 for (int q = 0; q < nb; ++q) {
-                    pos[q] = sr.start[br * B + q];
-                    end[q] = pos[q] + sr.len[br * B + q];
+                    pos[q] = sr.start[row_at(br * B + q)];
+                    end[q] = pos[q] + sr.len[row_at(br * B + q)];
                 }
                 const int64_t s0 = out.rowptr[br], e0 = out.rowptr[br + 1];
                 int32_t* c = out.col.data() + s0;
@@ -303,7 +314,8 @@ static void encode_values(CsrHost& h, const std::vector<float>& fvalb, int32_t s
         for (int64_t br = a; br < b; ++br)
             for (int64_t k = h.rowptr[br]; k < h.rowptr[br + 1]; ++k)
                 for (int bb = 0; bb < B; ++bb) {
-                    const int64_t r = std::min<int64_t>(br * B + bb, h.n_rows - 1);
+                    const int64_t pos = std::min<int64_t>(br * B + bb, h.n_rows - 1);
+                    const int64_t r = h.perm.empty() ? pos : h.perm[pos];
                     const float s = scale[beamlet_is_row ? r : h.col[k]];
                     const float x = fvalb[k * B + bb] / s;
                     q[k * B + bb] = storage == DVMAT_F16 ? float_to_half_bits(x) : float_to_bf16_bits(x);
@@ -327,6 +339,10 @@ dvmat_status dvmat_ddc_default_opts(dvmat_build_opts* opts) {
     opts->price_block_rows = 1;
     opts->interleave = 1;
     opts->unit_entries = 2048;
+    opts->dose_row_order = 0;
+    opts->price_row_order = 0;
+    if (const char* e = std::getenv("DVMAT_DOSE_ORDER")) opts->dose_row_order = std::atoi(e);
+    if (const char* e = std::getenv("DVMAT_PRICE_ORDER")) opts->price_row_order = std::atoi(e);
     if (const char* e = std::getenv("DVMAT_DOSE_B")) opts->dose_block_rows = std::atoi(e);
     if (const char* e = std::getenv("DVMAT_PRICE_B")) opts->price_block_rows = std::atoi(e);
     if (const char* e = std::getenv("DVMAT_INTERLEAVE")) opts->interleave = std::atoi(e);
@@ -348,7 +364,8 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
     if (opts) o = *opts;
     auto okB = [](int b) { return b == 1 || b == 2 || b == 4; };
     if (!okB(o.dose_block_rows) || !okB(o.price_block_rows) || (o.interleave != 0 && o.interleave != 1) ||
-        o.unit_entries < 4 || o.unit_entries > (1 << 24))
+        o.unit_entries < 4 || o.unit_entries > (1 << 24) || (o.dose_row_order != 0 && o.dose_row_order != 1) ||
+        (o.price_row_order != 0 && o.price_row_order != 1))
         return set_error(DVMAT_E_ARG, "dvmat_ddc_create: bad build options (block rows %d/%d, interleave %d, unit %d)",
                          o.dose_block_rows, o.price_block_rows, o.interleave, o.unit_entries);
     *out = nullptr;
@@ -421,7 +438,8 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
             for (auto& s : d->host_scale)
                 if (!(s > 0.0f)) s = 1.0f;
         }
-        if ((st = build_blocked(sr, n_vox, o.dose_block_rows, o.interleave != 0, o.unit_entries, d->host_dose, fvalb))) {
+        if ((st = build_blocked(sr, n_vox, o.dose_block_rows, o.interleave != 0, o.unit_entries, o.dose_row_order == 1,
+                                d->host_dose, fvalb))) {
             delete d;
             return st;
         }
@@ -436,7 +454,8 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
         SortedRows sr;
         std::vector<float> fvalb;
         if ((st = sort_rows(n_bl, nnz, col_bl, row_vox, val, sr))) { delete d; return st; }
-        if ((st = build_blocked(sr, n_bl, o.price_block_rows, o.interleave != 0, o.unit_entries, d->host_price, fvalb))) {
+        if ((st = build_blocked(sr, n_bl, o.price_block_rows, o.interleave != 0, o.unit_entries, o.price_row_order == 1,
+                                d->host_price, fvalb))) {
             delete d;
             return st;
         }
@@ -454,10 +473,12 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
     d->off_dose_col = take(hd.col.size() * 4);
     d->off_dose_val = take(hd.val.size());
     d->off_dose_blocks = take(hd.blocks.size() * 4);
+    d->off_dose_perm = take(hd.perm.size() * 4);
     d->off_price_rowptr = take(hp.rowptr.size() * 8);
     d->off_price_col = take(hp.col.size() * 4);
     d->off_price_val = take(hp.val.size());
     d->off_price_blocks = take(hp.blocks.size() * 4);
+    d->off_price_perm = take(hp.perm.size() * 4);
     if (storage != DVMAT_F32) {
         d->off_scale = take(n_bl * 4);
         d->off_xs = take(n_bl * 4 * kMaxRhs);
@@ -499,6 +520,8 @@ dvmat_status dvmat_ddc_info(dvmat_ddc d, dvmat_ddc_info_t* info) {
     info->price_tuned_ms = d->price_tuned_ms;
     info->dose_block_rows = d->dose.B;
     info->price_block_rows = d->price.B;
+    info->dose_row_order = d->opts.dose_row_order;
+    info->price_row_order = d->opts.price_row_order;
     return DVMAT_OK;
 }
 
@@ -522,10 +545,12 @@ dvmat_status dvmat_ddc_bind(dvmat_ddc d, void* ws, size_t bytes, dvmat_stream st
     if ((st = up(d->off_dose_col, hd.col.data(), hd.col.size() * 4))) return st;
     if ((st = up(d->off_dose_val, hd.val.data(), hd.val.size()))) return st;
     if ((st = up(d->off_dose_blocks, hd.blocks.data(), hd.blocks.size() * 4))) return st;
+    if ((st = up(d->off_dose_perm, hd.perm.data(), hd.perm.size() * 4))) return st;
     if ((st = up(d->off_price_rowptr, hp.rowptr.data(), hp.rowptr.size() * 8))) return st;
     if ((st = up(d->off_price_col, hp.col.data(), hp.col.size() * 4))) return st;
     if ((st = up(d->off_price_val, hp.val.data(), hp.val.size()))) return st;
     if ((st = up(d->off_price_blocks, hp.blocks.data(), hp.blocks.size() * 4))) return st;
+    if ((st = up(d->off_price_perm, hp.perm.data(), hp.perm.size() * 4))) return st;
     if (d->storage != DVMAT_F32)
         if ((st = up(d->off_scale, d->host_scale.data(), d->host_scale.size() * 4))) return st;
     if ((st = check_hip(hipStreamSynchronize(s), "dvmat_ddc_bind: synchronize"))) return st;
@@ -533,10 +558,12 @@ dvmat_status dvmat_ddc_bind(dvmat_ddc d, void* ws, size_t bytes, dvmat_stream st
     d->dose.col = reinterpret_cast<const int32_t*>(base + d->off_dose_col);
     d->dose.val = base + d->off_dose_val;
     d->dose.blocks = reinterpret_cast<const int32_t*>(base + d->off_dose_blocks);
+    d->dose.perm = hd.perm.empty() ? nullptr : reinterpret_cast<const int32_t*>(base + d->off_dose_perm);
     d->price.rowptr = reinterpret_cast<const int64_t*>(base + d->off_price_rowptr);
     d->price.col = reinterpret_cast<const int32_t*>(base + d->off_price_col);
     d->price.val = base + d->off_price_val;
     d->price.blocks = reinterpret_cast<const int32_t*>(base + d->off_price_blocks);
+    d->price.perm = hp.perm.empty() ? nullptr : reinterpret_cast<const int32_t*>(base + d->off_price_perm);
     if (d->storage != DVMAT_F32) {
         d->scale = reinterpret_cast<const float*>(base + d->off_scale);
         d->xs = reinterpret_cast<float*>(base + d->off_xs);

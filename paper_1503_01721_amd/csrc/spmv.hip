@@ -45,6 +45,7 @@ struct SpmvParams {
     const void* val;
     const int32_t* blocks;
     int64_t n_blocks;
+    const int32_t* perm;     // stored position -> row, or nullptr
     const float* x;
     float* y;                // output rows (nullable for EPI_CURV)
     const uint8_t* sid;      // objective epilogue
@@ -259,7 +260,7 @@ __device__ __forceinline__ void block_rows(const SpmvParams& P, int64_t b, int l
 #pragma unroll
             for (int q = 0; q < B; ++q) {
                 const int64_t r = (int64_t)br * B + q;
-                if (r < P.n_rows) row_epilogue<NRHS, EPI>(P, (int)r, acc[q], fpart, cpart);
+                if (r < P.n_rows) row_epilogue<NRHS, EPI>(P, P.perm ? P.perm[r] : (int)r, acc[q], fpart, cpart);
             }
         }
     }
@@ -322,7 +323,7 @@ __device__ __forceinline__ void block_stream(const SpmvParams& P, int64_t b, int
         float a[NRHS];
 #pragma unroll
         for (int h = 0; h < NRHS; ++h) a[h] = acc_l[i * NRHS + h];
-        row_epilogue<NRHS, EPI>(P, r0 + i, a, fpart, cpart);
+        row_epilogue<NRHS, EPI>(P, P.perm ? P.perm[r0 + i] : r0 + i, a, fpart, cpart);
     }
     wave_sync_lds();
 }
@@ -412,6 +413,7 @@ struct PlanDev {
     const void* val;
     const int32_t* blocks;
     const float* scale;   // per-beamlet scale (16-bit storage) or nullptr
+    const int32_t* perm;  // stored position -> row, or nullptr
     int64_t n_rows;       // rows of the orientation
     int64_t block_base;   // first global block of this plan
     int64_t n_blocks;
@@ -443,6 +445,7 @@ __global__ __launch_bounds__(kSpmvThreads) void spmv_batch_kernel(BatchParams B)
         const PlanDev& pd = B.plans[p];
         SpmvParams P{};
         P.n_rows = pd.n_rows;
+        P.perm = pd.perm;
         P.rowptr = pd.rowptr;
         P.col = pd.col;
         P.val = pd.val;
@@ -605,6 +608,7 @@ static dvmat_status check_ddc(const dvmat_ddc_s* d, const char* fn) {
 static SpmvParams orientation_params(const CsrDev& c) {
     SpmvParams P{};
     P.n_rows = c.n_rows;
+    P.perm = c.perm;
     P.rowptr = c.rowptr;
     P.col = c.col;
     P.val = c.val;
@@ -942,10 +946,10 @@ dvmat_status dvmat_batch_create(const dvmat_ddc* ddcs, int32_t n, void* ws, size
             return set_error(DVMAT_E_ARG, "dvmat_batch_create: plan %d has a different storage type", i);
         if (d->dose.B != ddcs[0]->dose.B || d->price.B != ddcs[0]->price.B)
             return set_error(DVMAT_E_ARG, "dvmat_batch_create: plan %d has a different block-row layout", i);
-        dp[i] = PlanDev{d->dose.rowptr, d->dose.col, d->dose.val, d->dose.blocks, d->scale, d->dose.n_rows, bd,
-                        d->dose.n_blocks};
-        pp[i] = PlanDev{d->price.rowptr, d->price.col, d->price.val, d->price.blocks, d->scale, d->price.n_rows, bp,
-                        d->price.n_blocks};
+        dp[i] = PlanDev{d->dose.rowptr, d->dose.col, d->dose.val, d->dose.blocks, d->scale, d->dose.perm,
+                        d->dose.n_rows, bd, d->dose.n_blocks};
+        pp[i] = PlanDev{d->price.rowptr, d->price.col, d->price.val, d->price.blocks, d->scale, d->price.perm,
+                        d->price.n_rows, bp, d->price.n_blocks};
         bd += d->dose.n_blocks;
         bp += d->price.n_blocks;
     }

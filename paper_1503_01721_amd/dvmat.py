@@ -43,12 +43,14 @@ class DdcInfo(ctypes.Structure):
                 ("dose_kernel", ctypes.c_int32), ("dose_workgroups", ctypes.c_int32),
                 ("price_kernel", ctypes.c_int32), ("price_workgroups", ctypes.c_int32),
                 ("dose_tuned_ms", ctypes.c_float), ("price_tuned_ms", ctypes.c_float),
-                ("dose_block_rows", ctypes.c_int32), ("price_block_rows", ctypes.c_int32)]
+                ("dose_block_rows", ctypes.c_int32), ("price_block_rows", ctypes.c_int32),
+                ("dose_row_order", ctypes.c_int32), ("price_row_order", ctypes.c_int32)]
 
 
 class BuildOpts(ctypes.Structure):
     _fields_ = [("dose_block_rows", ctypes.c_int32), ("price_block_rows", ctypes.c_int32),
-                ("interleave", ctypes.c_int32), ("unit_entries", ctypes.c_int32)]
+                ("interleave", ctypes.c_int32), ("unit_entries", ctypes.c_int32),
+                ("dose_row_order", ctypes.c_int32), ("price_row_order", ctypes.c_int32)]
 
 
 class Geom(ctypes.Structure):
@@ -181,7 +183,8 @@ class DDC:
     """DDC matrix in both CSR orientations, resident in one GPU's memory."""
 
     def __init__(self, row, col, val, n_vox: int, n_bl: int, storage: str = "f32", device="cuda",
-                 dose_block_rows=None, price_block_rows=None, interleave=None, unit_entries=None):
+                 dose_block_rows=None, price_block_rows=None, interleave=None, unit_entries=None,
+                 dose_row_order=None, price_row_order=None):
         row = np.ascontiguousarray(row, dtype=np.int32)
         col = np.ascontiguousarray(col, dtype=np.int32)
         val = np.ascontiguousarray(val, dtype=np.float32)
@@ -192,7 +195,8 @@ class DDC:
         opts = BuildOpts()
         _check(lib.dvmat_ddc_default_opts(ctypes.byref(opts)))
         for name, v in (("dose_block_rows", dose_block_rows), ("price_block_rows", price_block_rows),
-                        ("interleave", interleave), ("unit_entries", unit_entries)):
+                        ("interleave", interleave), ("unit_entries", unit_entries),
+                        ("dose_row_order", dose_row_order), ("price_row_order", price_row_order)):
             if v is not None:
                 setattr(opts, name, int(v))
         h = _P()

@@ -474,12 +474,14 @@ def test_autotune_keeps_results_within_tolerance(dv, plan1):
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("B", [1, 2, 4])
-def test_block_rows_plain_method_workload(dv, plan1, storage, B):
+@pytest.mark.parametrize("order", [0, 1])
+def test_block_rows_plain_method_workload(dv, plan1, storage, B, order):
     """Every block-row layout and storage type on the 20-angle workload, with
     the objective epilogue, the curvature pass and 8 right-hand sides."""
     d, sid, table, _, obj = plan1
     ddc = dv.DDC(d["row"], d["col"], d["val"], PLAN1.n_vox, PLAN1.n_bl, storage=storage,
-                 dose_block_rows=B, price_block_rows=B)
+                 dose_block_rows=B, price_block_rows=B, dose_row_order=order, price_row_order=order)
+    assert ddc.info.price_row_order == order
     val = d["val"].astype(np.float64)
     if storage != "f32":
         s = np.zeros(PLAN1.n_bl, np.float32)
