@@ -101,3 +101,88 @@ def aperture_members(cp, L, R, n_cp, n_rows, n_cols):
     for r in range(n_rows):
         m[cp, r, int(L[r]):int(R[r])] = True
     return m.ravel()
+
+
+# ---------------------------------------------------------------- interdigitation
+#
+# Sec. 2.2.2: with the interdigitation constraint L_r <= min(R_{r-1}, R_{r+1})
+# the leaf rows are coupled; the paper enumerates the combinations of row
+# openings per control point.  Readings: for adjacent rows the constraint is
+# L_r <= R_{r+1} and L_{r+1} <= R_r; a closed row may park its leaves at any
+# position p (L = R = p, sum 0), and where it parks matters for its
+# neighbours.  The best aperture minimises the sum of p over its openings.
+
+def states(n):
+    """All openings (L, R), 0 <= L <= R <= n, closed rows included."""
+    return [(L, R) for L in range(n + 1) for R in range(L, n + 1)]
+
+
+def compatible(a, b):
+    """Interdigitation between adjacent rows with openings a and b."""
+    return a[0] <= b[1] and b[0] <= a[1]
+
+
+def best_aperture_interdigitated_bruteforce(p_cp):
+    """Exhaustive search over the Cartesian product of row openings (tiny grids)."""
+    p_cp = np.asarray(p_cp, np.float64)
+    n_rows, n = p_cp.shape
+    st = states(n)
+    sums = [[p_cp[r, a:b].sum() for (a, b) in st] for r in range(n_rows)]
+    best, arg = np.inf, None
+    for combo in itertools.product(range(len(st)), repeat=n_rows):
+        if any(not compatible(st[combo[r]], st[combo[r + 1]]) for r in range(n_rows - 1)):
+            continue
+        s = sum(sums[r][combo[r]] for r in range(n_rows))
+        if s < best:
+            best, arg = s, tuple(st[c] for c in combo)
+    return best, arg
+
+
+def best_aperture_interdigitated(p_cp):
+    """Best aperture of one control point under interdigitation, by dynamic
+    programming over the leaf rows: value[r][s] = rowsum_r(s) + min over
+    states s' of row r-1 compatible with s of value[r-1][s'].
+    Returns (price, openings [(L, R)] per row)."""
+    p_cp = np.asarray(p_cp, np.float64)
+    n_rows, n = p_cp.shape
+    st = states(n)
+    cs = np.concatenate([np.zeros((n_rows, 1)), np.cumsum(p_cp, axis=1)], axis=1)
+    rowsum = np.array([[cs[r, b] - cs[r, a] for (a, b) in st] for r in range(n_rows)])
+    value = [rowsum[0].copy()]
+    choice = []
+    comp = np.array([[compatible(s1, s2) for s2 in st] for s1 in st])   # [prev, cur]
+    for r in range(1, n_rows):
+        prev = value[-1]
+        cand = np.where(comp, prev[:, None], np.inf)                     # [prev, cur]
+        arg = np.argmin(cand, axis=0)
+        value.append(rowsum[r] + cand[arg, np.arange(len(st))])
+        choice.append(arg)
+    last = int(np.argmin(value[-1]))
+    path = [last]
+    for r in range(n_rows - 1, 0, -1):
+        path.append(int(choice[r - 1][path[-1]]))
+    path.reverse()
+    return float(value[-1][last]), [st[i] for i in path]
+
+
+def select_interdigitated(p, n_cp, n_rows, n_cols, occupied):
+    """Aperture selection under interdigitation over the unoccupied control points."""
+    P = np.asarray(p, np.float64).reshape(n_cp, n_rows, n_cols)
+    occ = np.asarray(occupied, bool)
+    L = np.zeros((n_cp, n_rows), np.int32)
+    R = np.zeros((n_cp, n_rows), np.int32)
+    cp_price = np.full(n_cp, np.inf)
+    for k in range(n_cp):
+        if occ[k]:
+            continue
+        v, path = best_aperture_interdigitated(P[k])
+        cp_price[k] = v
+        L[k] = [a for a, _ in path]
+        R[k] = [b for _, b in path]
+    best, best_price = -1, np.inf
+    for k in range(n_cp):
+        if not occ[k] and cp_price[k] < best_price:
+            best, best_price = k, cp_price[k]
+    if best >= 0 and not best_price < 0.0:
+        best = -1
+    return dict(L=L, R=R, cp_price=cp_price, best=best, best_price=best_price)

@@ -467,3 +467,33 @@ def test_table2_sizes_pin_fp32_int32_and_gib(golden_dir):
     # CSR is about 2/3 of COO in every case (8 vs 12 bytes per non-zero)
     for coo, csr in g["table3_coo_csr_gb"]:
         assert abs(csr / coo - 2.0 / 3.0) < 0.005
+
+
+# ---------------------------------------------------------------- interdigitation
+
+def test_interdigitated_dp_matches_exhaustive_search():
+    rng = np.random.default_rng(31)
+    for trial in range(25):
+        n_rows, n = (3, 4) if trial % 2 else (4, 3)
+        p_cp = rng.integers(-5, 6, size=(n_rows, n)).astype(np.float64)
+        v_dp, path = ap.best_aperture_interdigitated(p_cp)
+        v_bf, _ = ap.best_aperture_interdigitated_bruteforce(p_cp)
+        assert v_dp == v_bf
+        # the returned openings are feasible and achieve the value
+        assert all(ap.compatible(path[r], path[r + 1]) for r in range(n_rows - 1))
+        assert sum(p_cp[r, a:b].sum() for r, (a, b) in enumerate(path)) == v_dp
+        # the constraint can only cost: never better than the free rows
+        _, _, S = ap.best_intervals(p_cp)
+        assert v_dp >= S.sum()
+
+
+def test_interdigitation_binds_on_hand_built_case():
+    # row 0 wants beamlets 0..1, row 1 wants 3..4: [0,2) and [3,5) interdigitate
+    # (L_1 = 3 > R_0 = 2), so the best feasible aperture must give something up
+    p_cp = np.array([[-5.0, -5.0, 1.0, 1.0, 1.0],
+                     [1.0, 1.0, 1.0, -5.0, -5.0]])
+    free = ap.best_intervals(p_cp)[2].sum()
+    assert free == -20.0
+    v, path = ap.best_aperture_interdigitated(p_cp)
+    assert v == -19.0            # e.g. row 0 takes [0, 3): -9, row 1 takes [3, 5): -10
+    assert ap.compatible(path[0], path[1])
