@@ -225,6 +225,20 @@ dvmat_status dvmat_aperture_select(dvmat_geom geom, const float* p, const uint8_
                                    int32_t* L, int32_t* R, float* cp_price,
                                    int32_t* best, float* best_price, dvmat_stream stream);
 
+/* Aperture selection under the interdigitation constraint of Sec. 2.2.2,
+ * L_r <= min(R_{r-1}, R_{r+1}): adjacent rows need L_r <= R_{r+1} and
+ * L_{r+1} <= R_r, so the rows are coupled; a closed row may park at any
+ * position p (L = R = p, sum 0).  Exact minimum over all feasible apertures
+ * by dynamic programming over the rows (state = one row's opening); ties go to
+ * the smallest state index, states ordered by L then R.  Outputs as
+ * dvmat_aperture_select.  n_cols <= 96 (the row DP works in LDS); d_workspace: device memory of
+ * dvmat_aperture_select_ws_size bytes (per-row state values for backtracking). */
+dvmat_status dvmat_aperture_select_ws_size(dvmat_geom geom, size_t* bytes);
+dvmat_status dvmat_aperture_select_interdigitated(dvmat_geom geom, const float* p, const uint8_t* occupied,
+                                                  int32_t* L, int32_t* R, float* cp_price,
+                                                  int32_t* best, float* best_price,
+                                                  void* d_workspace, size_t bytes, dvmat_stream stream);
+
 /* ------------------------------------------------------------------------
  * Master problem (Eq. 6) by Barzilai-Borwein steps (Eqs. 7-8, alternating)
  * with the subspace bound rules (Eqs. 9-10), state kept on the device.

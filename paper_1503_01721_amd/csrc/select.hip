@@ -107,6 +107,146 @@ __global__ __launch_bounds__(256) void select_best_kernel(int n_cp, const float*
     }
 }
 
+// ---- interdigitation -------------------------------------------------------
+//
+// With the constraint L_r <= min(R_{r-1}, R_{r+1}) (Sec. 2.2.2) adjacent rows
+// must satisfy L_r <= R_{r+1} and L_{r+1} <= R_r; a closed row may park at any
+// position p (L = R = p).  Dynamic programming over the rows, state = opening
+// (L, R), 0 <= L <= R <= n, triangular index L*(n+1) - L*(L-1)/2 + (R - L):
+//   V_r(L, R) = rowsum_r(L, R) + min { V_{r-1}(L', R') : L' <= R, R' >= L }.
+// The inner minimum is M(R, L) with M(a, b) = min_{L' <= a} min_{R' >= max(b, L')}
+// V_{r-1}(L', R'): a suffix minimum over R' per L', then a prefix minimum
+// over L'.  Each row's V goes to the workspace; backtracking picks, per row,
+// the smallest-index compatible state attaining the minimum.
+
+__device__ __forceinline__ int tri_index(int L, int R, int n) { return L * (n + 1) - L * (L - 1) / 2 + (R - L); }
+
+__global__ __launch_bounds__(256) void select_interdig_kernel(int n_rows, int n, const float* __restrict__ p,
+                                                              const uint8_t* __restrict__ occ,
+                                                              int32_t* __restrict__ L, int32_t* __restrict__ R,
+                                                              float* __restrict__ cp_price,
+                                                              float* __restrict__ hist) {
+    extern __shared__ float sm[];
+    const int S = (n + 1) * (n + 2) / 2;
+    const int W = n + 1;
+    float* grid = sm;                 // [W][W]: suffix minima, then M
+    float* cur = grid + W * W;        // [S]
+    float* pre = cur + S;             // [W] prefix sums of the current row
+    __shared__ float rv[256];
+    __shared__ int ri[256];
+    const int k = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (occ != nullptr && occ[k] != 0) {
+        for (int r = tid; r < n_rows; r += blockDim.x) {
+            L[(int64_t)k * n_rows + r] = 0;
+            R[(int64_t)k * n_rows + r] = 0;
+        }
+        if (tid == 0) cp_price[k] = INFINITY;
+        return;
+    }
+    const float* pk = p + (int64_t)k * n_rows * n;
+    float* hk = hist + (int64_t)k * n_rows * S;
+    for (int r = 0; r < n_rows; ++r) {
+        if (tid == 0) {
+            float a = 0.0f;
+            pre[0] = 0.0f;
+            for (int c = 0; c < n; ++c) {
+                a += pk[(int64_t)r * n + c];
+                pre[c + 1] = a;
+            }
+        }
+        if (r > 0) {
+            // suffix minima over R' >= b for each L' (thread per L')
+            for (int l = tid; l < W; l += blockDim.x) {
+                float m = INFINITY;
+                for (int b = n; b >= 0; --b) {
+                    if (b >= l) m = fminf(m, cur[tri_index(l, b, n)]);
+                    grid[l * W + b] = m;
+                }
+            }
+            __syncthreads();
+            // prefix minima over L' <= a (thread per b)
+            for (int b = tid; b < W; b += blockDim.x) {
+                float m = INFINITY;
+                for (int a = 0; a < W; ++a) {
+                    m = fminf(m, grid[a * W + b]);
+                    grid[a * W + b] = m;
+                }
+            }
+        }
+        __syncthreads();
+        for (int s = tid; s < S; s += blockDim.x) {
+            // decode s -> (Lo, Ro)
+            int Lo = 0, off = 0;
+            while (off + (n + 1 - Lo) <= s) { off += n + 1 - Lo; ++Lo; }
+            const int Ro = Lo + (s - off);
+            float v = pre[Ro] - pre[Lo];
+            if (r > 0) v += grid[Ro * W + Lo];
+            cur[s] = v;
+            hk[(int64_t)r * S + s] = v;
+        }
+        __syncthreads();
+    }
+    // best final state: smallest value, then smallest index
+    float bv = INFINITY;
+    int bi = S;
+    for (int s = tid; s < S; s += blockDim.x)
+        if (cur[s] < bv) { bv = cur[s]; bi = s; }
+    rv[tid] = bv;
+    ri[tid] = bi;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+        if (tid < o) {
+            const float v2 = rv[tid + o];
+            const int i2 = ri[tid + o];
+            if (v2 < rv[tid] || (v2 == rv[tid] && i2 < ri[tid])) { rv[tid] = v2; ri[tid] = i2; }
+        }
+        __syncthreads();
+    }
+    __shared__ int state;
+    if (tid == 0) {
+        cp_price[k] = rv[0];
+        state = ri[0];
+    }
+    __syncthreads();
+    for (int r = n_rows - 1; r >= 0; --r) {
+        const int s = state;
+        int Ls = 0, off = 0;
+        while (off + (n + 1 - Ls) <= s) { off += n + 1 - Ls; ++Ls; }
+        const int Rs = Ls + (s - off);
+        if (tid == 0) {
+            L[(int64_t)k * n_rows + r] = Ls;
+            R[(int64_t)k * n_rows + r] = Rs;
+        }
+        if (r == 0) break;
+        // smallest-index compatible state of row r-1 with the minimal value
+        float v = INFINITY;
+        int vi = S;
+        for (int q = tid; q < S; q += blockDim.x) {
+            int Lq = 0, oq = 0;
+            while (oq + (n + 1 - Lq) <= q) { oq += n + 1 - Lq; ++Lq; }
+            const int Rq = Lq + (q - oq);
+            if (Lq <= Rs && Ls <= Rq) {
+                const float hv = hk[(int64_t)(r - 1) * S + q];
+                if (hv < v) { v = hv; vi = q; }
+            }
+        }
+        rv[tid] = v;
+        ri[tid] = vi;
+        __syncthreads();
+        for (int o = 128; o >= 1; o >>= 1) {
+            if (tid < o) {
+                const float v2 = rv[tid + o];
+                const int i2 = ri[tid + o];
+                if (v2 < rv[tid] || (v2 == rv[tid] && i2 < ri[tid])) { rv[tid] = v2; ri[tid] = i2; }
+            }
+            __syncthreads();
+        }
+        if (tid == 0) state = ri[0];
+        __syncthreads();
+    }
+}
+
 }  // namespace dvmat
 
 using namespace dvmat;
@@ -128,4 +268,35 @@ extern "C" dvmat_status dvmat_aperture_select(dvmat_geom geom, const float* p, c
                        L, R, cp_price);
     hipLaunchKernelGGL(select_best_kernel, dim3(1), dim3(256), 0, s, geom.n_cp, cp_price, best, best_price);
     return check_hip(hipGetLastError(), "dvmat_aperture_select launch");
+}
+
+extern "C" dvmat_status dvmat_aperture_select_ws_size(dvmat_geom geom, size_t* bytes) {
+    if (!bytes) return set_error(DVMAT_E_ARG, "dvmat_aperture_select_ws_size: bytes is NULL");
+    if (geom.n_cp < 1 || geom.n_rows < 1 || geom.n_cols < 1 || geom.n_cols > 96)
+        return set_error(DVMAT_E_SHAPE, "dvmat_aperture_select_ws_size: geometry %d x %d x %d (n_cols <= 96)",
+                         geom.n_cp, geom.n_rows, geom.n_cols);
+    const int64_t S = (int64_t)(geom.n_cols + 1) * (geom.n_cols + 2) / 2;
+    *bytes = (size_t)geom.n_cp * geom.n_rows * S * sizeof(float);
+    return DVMAT_OK;
+}
+
+extern "C" dvmat_status dvmat_aperture_select_interdigitated(dvmat_geom geom, const float* p, const uint8_t* occupied,
+                                                             int32_t* L, int32_t* R, float* cp_price, int32_t* best,
+                                                             float* best_price, void* d_workspace, size_t bytes,
+                                                             dvmat_stream stream) {
+    size_t need = 0;
+    dvmat_status st = dvmat_aperture_select_ws_size(geom, &need);
+    if (st) return st;
+    if (!p || !L || !R || !cp_price || !best || !best_price || !d_workspace)
+        return set_error(DVMAT_E_ARG, "dvmat_aperture_select_interdigitated: NULL argument");
+    if (bytes < need)
+        return set_error(DVMAT_E_NOMEM, "dvmat_aperture_select_interdigitated: workspace %zu < %zu bytes", bytes, need);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int W = geom.n_cols + 1;
+    const int S = W * (W + 1) / 2;
+    const size_t lds = ((size_t)W * W + S + W) * sizeof(float);
+    hipLaunchKernelGGL(select_interdig_kernel, dim3(geom.n_cp), dim3(256), lds, s, geom.n_rows, geom.n_cols, p,
+                       occupied, L, R, cp_price, static_cast<float*>(d_workspace));
+    hipLaunchKernelGGL(select_best_kernel, dim3(1), dim3(256), 0, s, geom.n_cp, cp_price, best, best_price);
+    return check_hip(hipGetLastError(), "dvmat_aperture_select_interdigitated launch");
 }

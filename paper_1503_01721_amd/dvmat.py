@@ -94,6 +94,8 @@ _SIGNATURES = {
     "dvmat_batch_set_kernel": (_I32, [_P, _I32, _I32, _I32]),
     "dvmat_batch_info": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I32)]),
     "dvmat_aperture_select": (_I32, [Geom, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "dvmat_aperture_select_ws_size": (_I32, [Geom, ctypes.POINTER(_SZ)]),
+    "dvmat_aperture_select_interdigitated": (_I32, [Geom, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "dvmat_bb_workspace_size": (_I32, [Geom, _I32, ctypes.POINTER(_SZ)]),
     "dvmat_bb_create": (_I32, [Geom, _I32, BBParams, _P, _SZ, _P, ctypes.POINTER(_P)]),
     "dvmat_bb_destroy": (None, [_P]),
@@ -337,11 +339,18 @@ class Objective:
 
 
 class ApertureSelector:
-    """Row-wise aperture selection over control points (preallocated outputs)."""
+    """Aperture selection over control points (preallocated outputs); with
+    interdigitated=True the leaf rows obey the interdigitation constraint."""
 
-    def __init__(self, n_cp, n_rows, n_cols, device="cuda"):
+    def __init__(self, n_cp, n_rows, n_cols, device="cuda", interdigitated=False):
         self.geom = Geom(n_cp, n_rows, n_cols)
         dev = torch.device(device)
+        self.interdigitated = interdigitated
+        self.ws = None
+        if interdigitated:
+            nbytes = _SZ()
+            _check(lib.dvmat_aperture_select_ws_size(self.geom, ctypes.byref(nbytes)))
+            self.ws = _workspace(nbytes.value, dev)
         self.L = torch.empty((n_cp, n_rows), dtype=torch.int32, device=dev)
         self.R = torch.empty((n_cp, n_rows), dtype=torch.int32, device=dev)
         self.cp_price = torch.empty(n_cp, dtype=torch.float32, device=dev)
@@ -354,14 +363,19 @@ class ApertureSelector:
         if not isinstance(occupied, ctypes.c_void_p):
             _need(occupied, g.n_cp, torch.uint8, name="occupied")
         occ = occupied if isinstance(occupied, ctypes.c_void_p) else _ptr(occupied)
+        if self.interdigitated:
+            _check(lib.dvmat_aperture_select_interdigitated(
+                self.geom, _ptr(p), occ, _ptr(self.L), _ptr(self.R), _ptr(self.cp_price), _ptr(self.best),
+                _ptr(self.best_price), _ptr(self.ws), self.ws.numel(), _stream(stream)))
+            return self
         _check(lib.dvmat_aperture_select(self.geom, _ptr(p), occ, _ptr(self.L), _ptr(self.R),
                                          _ptr(self.cp_price), _ptr(self.best), _ptr(self.best_price),
                                          _stream(stream)))
         return self
 
 
-def aperture_select(p, n_cp, n_rows, n_cols, occupied=None):
-    sel = ApertureSelector(n_cp, n_rows, n_cols, device=p.device)
+def aperture_select(p, n_cp, n_rows, n_cols, occupied=None, interdigitated=False):
+    sel = ApertureSelector(n_cp, n_rows, n_cols, device=p.device, interdigitated=interdigitated)
     sel(p, occupied)
     return dict(L=sel.L, R=sel.R, cp_price=sel.cp_price, best=sel.best, best_price=sel.best_price)
 

@@ -245,6 +245,75 @@ def test_aperture_select_real_prices(dv, plan1):
     assert abs(ref["cp_price"][best] - ref["best_price"]) <= bound.sum(axis=1).max()
 
 
+def _interdig_feasible(L, R):
+    ok = (L <= R).all()
+    ok &= (L[:, :-1] <= R[:, 1:]).all() and (L[:, 1:] <= R[:, :-1]).all()
+    return bool(ok)
+
+
+def test_aperture_select_interdigitated_exact_integer_prices(dv):
+    # integer prices are exact in FP32, so values and tie-breaks must agree exactly
+    n_cp, n_rows, n_cols = 13, 7, 9
+    rng = np.random.default_rng(31)
+    p = rng.integers(-5, 6, size=(n_cp, n_rows, n_cols)).astype(np.float32)
+    p[rng.random(p.shape) < 0.3] = 0.0
+    occ = (rng.random(n_cp) < 0.25).astype(np.uint8)
+    ref = oap.select_interdigitated(p.ravel(), n_cp, n_rows, n_cols, occ.astype(bool))
+    out = dv.aperture_select(cuda(p.ravel()), n_cp, n_rows, n_cols, cuda(occ), interdigitated=True)
+    assert np.array_equal(out["cp_price"].cpu().numpy().astype(np.float64), ref["cp_price"])
+    assert np.array_equal(out["L"].cpu().numpy(), ref["L"])
+    assert np.array_equal(out["R"].cpu().numpy(), ref["R"])
+    assert int(out["best"].cpu()[0]) == ref["best"]
+    # the constraint only removes apertures: never better than the free optimum
+    free = oap.select(p.ravel(), n_cp, n_rows, n_cols, occ.astype(bool))
+    keep = ~occ.astype(bool)
+    assert (ref["cp_price"][keep] >= free["cp_price"][keep]).all()
+    # a single row has no neighbour: the constrained and free prices coincide
+    out1 = dv.aperture_select(cuda(p[:, :1].ravel()), n_cp, 1, n_cols, None, interdigitated=True)
+    free1 = oap.select(p[:, :1].ravel(), n_cp, 1, n_cols, np.zeros(n_cp, bool))
+    assert np.array_equal(out1["cp_price"].cpu().numpy().astype(np.float64), free1["cp_price"])
+    # all occupied -> -1; all non-negative -> -1
+    out = dv.aperture_select(cuda(p.ravel()), n_cp, n_rows, n_cols,
+                             torch.ones(n_cp, dtype=torch.uint8, device="cuda"), interdigitated=True)
+    assert int(out["best"].cpu()[0]) == -1 and torch.isinf(out["cp_price"]).all()
+    out = dv.aperture_select(cuda(np.abs(p).ravel()), n_cp, n_rows, n_cols, None, interdigitated=True)
+    assert int(out["best"].cpu()[0]) == -1
+
+
+def test_aperture_select_interdigitated_real_prices(dv, plan1):
+    d, sid, table, ddc, obj = plan1
+    z, g, F = ddc.dose(torch.zeros(PLAN1.n_bl, device="cuda"), obj, with_grad=True)
+    p = ddc.price(g)
+    p64 = p.cpu().numpy().astype(np.float64)
+    n_cp, n_rows, n_cols = PLAN1.n_cp, PLAN1.n_rows, PLAN1.n_cols
+    ref = oap.select_interdigitated(p64, n_cp, n_rows, n_cols, np.zeros(n_cp, bool))
+    sel = dv.ApertureSelector(n_cp, n_rows, n_cols, interdigitated=True)
+    for _ in range(2):                                   # reuse of the preallocated workspace
+        out = sel(p)
+        L, R = sel.L.cpu().numpy(), sel.R.cpu().numpy()
+        P = p64.reshape(n_cp, n_rows, n_cols)
+        bound = 64 * 2.0 ** -24 * np.abs(P).sum(axis=(1, 2))
+        for k in range(n_cp):
+            assert _interdig_feasible(L[k][None], R[k][None])
+            chosen = sum(P[k, r, L[k, r]:R[k, r]].sum() for r in range(n_rows))
+            assert abs(chosen - ref["cp_price"][k]) <= bound[k]
+            assert abs(float(sel.cp_price[k].cpu()) - ref["cp_price"][k]) <= bound[k]
+        b = int(sel.best.cpu()[0])
+        assert b >= 0 and abs(ref["cp_price"][b] - ref["best_price"]) <= bound.max()
+
+
+def test_aperture_select_interdigitated_widest_rows(dv):
+    # the widest geometry the LDS row DP takes, with the tail of the oracle
+    n_cp, n_rows, n_cols = 2, 4, 96
+    rng = np.random.default_rng(33)
+    p = rng.integers(-3, 4, size=(n_cp, n_rows, n_cols)).astype(np.float32)
+    ref = oap.select_interdigitated(p.ravel(), n_cp, n_rows, n_cols, np.zeros(n_cp, bool))
+    out = dv.aperture_select(cuda(p.ravel()), n_cp, n_rows, n_cols, None, interdigitated=True)
+    assert np.array_equal(out["cp_price"].cpu().numpy().astype(np.float64), ref["cp_price"])
+    assert np.array_equal(out["L"].cpu().numpy(), ref["L"])
+    assert np.array_equal(out["R"].cpu().numpy(), ref["R"])
+
+
 # ---------------------------------------------------------------- master problem
 
 def _device_apertures(dv, plan, m, seed, lo, hi, max_iter, eps_f=0.0, eps_step=0.0):
