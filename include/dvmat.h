@@ -91,8 +91,8 @@ typedef struct {
  * consecutive rows form a block row that stores the union of their columns
  * once, with B values per column (zeros where a row lacks it), so one index
  * load and one gather of the input vector serve B rows.  Neighbouring voxels
- * see almost the same beamlets (the dose matrix gains; default B = 4 there);
- * neighbouring beamlets overlap less (default B = 1 for the price matrix).
+ * see almost the same beamlets (the dose matrix gains most); neighbouring
+ * beamlets overlap less.  Defaults depend on the storage type (below).
  * interleave (0/1, default 1): store the entries of each 256-entry chunk of a
  * block row interleaved so that each gather instruction of a wave covers
  * consecutive columns.  unit_entries: stored values per work unit (default 2048).
@@ -109,8 +109,13 @@ typedef struct {
     int32_t price_row_order;
 } dvmat_build_opts;
 
-/* Fill opts with the defaults. */
-dvmat_status dvmat_ddc_default_opts(dvmat_build_opts* opts);
+/* Fill opts with the defaults for a storage type (DVMAT_F32/F16/BF16): the
+ * fastest measured layout, dose B = 2 at 4-byte values and 4 at 2-byte values,
+ * price B = 1 at 4-byte and 2 at 2-byte values, price rows in first-column
+ * order.  Environment variables DVMAT_DOSE_B, DVMAT_PRICE_B,
+ * DVMAT_INTERLEAVE, DVMAT_BLOCK_NNZ, DVMAT_DOSE_ORDER, DVMAT_PRICE_ORDER
+ * override single fields.  DVMAT_E_ARG for an unknown storage. */
+dvmat_status dvmat_ddc_default_opts(int32_t storage, dvmat_build_opts* opts);
 
 /* Validate host COO (row = voxel, col = beamlet, val; length nnz; read during
  * the call only), sum duplicate pairs, build both CSR orientations, row blocks

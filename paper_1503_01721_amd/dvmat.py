@@ -71,7 +71,7 @@ _SIGNATURES = {
     "dvmat_ddc_create": (_I32, [_I64, _I64, _I64, _P, _P, _P, _I32, ctypes.POINTER(_P)]),
     "dvmat_ddc_create_ex": (_I32, [_I64, _I64, _I64, _P, _P, _P, _I32, ctypes.POINTER(BuildOpts),
                                    ctypes.POINTER(_P)]),
-    "dvmat_ddc_default_opts": (_I32, [ctypes.POINTER(BuildOpts)]),
+    "dvmat_ddc_default_opts": (_I32, [_I32, ctypes.POINTER(BuildOpts)]),
     "dvmat_ddc_info": (_I32, [_P, ctypes.POINTER(DdcInfo)]),
     "dvmat_ddc_bind": (_I32, [_P, _P, _SZ, _P]),
     "dvmat_ddc_destroy": (None, [_P]),
@@ -195,7 +195,7 @@ class DDC:
         self.n_vox, self.n_bl = int(n_vox), int(n_bl)
         self.storage = storage
         opts = BuildOpts()
-        _check(lib.dvmat_ddc_default_opts(ctypes.byref(opts)))
+        _check(lib.dvmat_ddc_default_opts(STORAGE[storage], ctypes.byref(opts)))
         for name, v in (("dose_block_rows", dose_block_rows), ("price_block_rows", price_block_rows),
                         ("interleave", interleave), ("unit_entries", unit_entries),
                         ("dose_row_order", dose_row_order), ("price_row_order", price_row_order)):

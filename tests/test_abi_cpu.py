@@ -131,8 +131,10 @@ def test_bb_and_select_argument_checks(dv):
 def test_build_options(dv):
     from paper_1503_01721_amd import synth
     opts = dv.BuildOpts()
-    assert dv.lib.dvmat_ddc_default_opts(ctypes.byref(opts)) == 0
-    assert opts.dose_block_rows in (1, 2, 4) and opts.price_block_rows in (1, 2, 4) and opts.interleave in (0, 1)
+    for storage in (0, 1, 2):
+        assert dv.lib.dvmat_ddc_default_opts(storage, ctypes.byref(opts)) == 0
+        assert opts.dose_block_rows in (1, 2, 4) and opts.price_block_rows in (1, 2, 4) and opts.interleave in (0, 1)
+    assert dv.lib.dvmat_ddc_default_opts(7, ctypes.byref(opts)) == -1
     plan = synth.PLANS["small_cp8_bl6x6_vox16"]
     d = synth.generate_ddc(plan)
     row = np.ascontiguousarray(d["row"]); col = np.ascontiguousarray(d["col"]); val = np.ascontiguousarray(d["val"])

@@ -513,7 +513,8 @@ def test_launch_shapes_match_oracle(dv, kind, B, wg, interleave):
 
 def test_stream_kernel_objective_and_curvature(dv, plan1):
     d, sid, table, _, obj = plan1
-    ddc = dv.DDC(d["row"], d["col"], d["val"], PLAN1.n_vox, PLAN1.n_bl)
+    # the stream kernel takes one row per block row
+    ddc = dv.DDC(d["row"], d["col"], d["val"], PLAN1.n_vox, PLAN1.n_bl, dose_block_rows=1)
     ddc.set_kernel("dose", "stream", 2048)
     x = synth.bench_vectors(PLAN1.n_bl, PLAN1.n_vox, 91)[0] * 4.0
     z_ref = oprod.dose(d["row"], d["col"], d["val"], x, PLAN1.n_vox)
