@@ -264,6 +264,10 @@ def main():
     ap.add_argument("--bb-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--dose-kernel", default=None, metavar="KIND:WG",
+                    help="fix the dose launch (e.g. row:1024) instead of autotuning it")
+    ap.add_argument("--price-kernel", default=None, metavar="KIND:WG",
+                    help="fix the price launch (e.g. row:8192) instead of autotuning it")
     ap.add_argument("--mode", default="colgen", choices=["colgen", "batched", "autograd"],
                     help="colgen: column-generation iterations (default); batched: many plans x 8 "
                          "right-hand sides in one launch vs one plan at a time; autograd: F(D B y) "
@@ -310,12 +314,19 @@ def main():
     t_build = time.perf_counter() - t
     info = ddc.info
     log(f"built CSR(D) + CSR(D^T) and uploaded {info.workspace_bytes / 2**30:.2f} GiB in {t_build:.1f} s")
-    if not args.no_autotune:
+    fixed = {"dose": args.dose_kernel, "price": args.price_kernel}
+    if not args.no_autotune and not any(fixed.values()):
         t = time.perf_counter()
         info = ddc.autotune(reps=5)
         log(f"autotuned in {time.perf_counter() - t:.1f} s: dose kernel {('row', 'stream')[info.dose_kernel]} "
             f"x {info.dose_workgroups} wg ({info.dose_tuned_ms:.3f} ms), price kernel "
             f"{('row', 'stream')[info.price_kernel]} x {info.price_workgroups} wg ({info.price_tuned_ms:.3f} ms)")
+    for orient, spec in fixed.items():
+        if spec:
+            kind, wg = spec.split(":")
+            ddc.set_kernel(orient, kind, int(wg))
+            info = ddc.refresh_info()
+            log(f"{orient} launch fixed at {kind} x {wg} workgroups")
 
     cg = ColumnGeneration(ddc, obj, plan.n_cp, plan.n_rows, plan.n_cols,
                           max_apertures=args.warmup + args.steps, bb_steps=args.bb_steps, form=args.form)
