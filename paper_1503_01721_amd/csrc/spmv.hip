@@ -128,38 +128,61 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Inputs of one row's epilogue that sit in memory: they are loaded before
+// the row's products are formed, so their latency overlaps the matrix stream.
+// The natural row index (rows may be stored in another order) is looked up at
+// the epilogue: only the beamlet rows are reordered, and those are long.
+struct EpiRow {
+    int sid;     // structure id (objective, curvature)
+    float zr;    // reference dose (curvature)
+    float rs;    // row scale (16-bit price)
+};
+
+__device__ __forceinline__ int64_t natural_row(const SpmvParams& P, int64_t r) { return P.perm ? P.perm[r] : r; }
+
+template <int EPI>
+__device__ __forceinline__ EpiRow epi_load(const SpmvParams& P, int64_t r) {
+    EpiRow e{0, 0.0f, 1.0f};
+    if constexpr (EPI != EPI_PLAIN) {
+        if (r < P.n_rows) {
+            const int64_t n = natural_row(P, r);
+            if constexpr (EPI == EPI_OBJ || EPI == EPI_CURV) e.sid = P.sid[n];
+            if constexpr (EPI == EPI_CURV) e.zr = P.zref[n];
+            if constexpr (EPI == EPI_SCALE) e.rs = P.row_scale[n];
+        }
+    }
+    return e;
+}
+
 // Row epilogue (one lane per row): plain, per-row scale, objective, curvature.
+// tab: the objective table (T, w+, w-, 0) per structure, staged in LDS.
 template <int NRHS, int EPI>
-__device__ __forceinline__ void row_epilogue(const SpmvParams& P, int r, const float (&acc)[NRHS],
-                                             float (&fpart)[NRHS], double& cpart) {
+__device__ __forceinline__ void row_epilogue(const SpmvParams& P, int64_t r, const EpiRow& e, const f32x4* tab,
+                                             const float (&acc)[NRHS], float (&fpart)[NRHS], double& cpart) {
     if constexpr (EPI == EPI_PLAIN) {
 #pragma unroll
-        for (int h = 0; h < NRHS; ++h) P.y[(int64_t)r * NRHS + h] = acc[h];
+        for (int h = 0; h < NRHS; ++h) P.y[r * NRHS + h] = acc[h];
     } else if constexpr (EPI == EPI_SCALE) {
-        const float s = P.row_scale[r];
 #pragma unroll
-        for (int h = 0; h < NRHS; ++h) P.y[(int64_t)r * NRHS + h] = acc[h] * s;
+        for (int h = 0; h < NRHS; ++h) P.y[r * NRHS + h] = acc[h] * e.rs;
     } else if constexpr (EPI == EPI_OBJ) {
-        const int s = P.sid[r];
-        const float T = P.table[s * 4 + 0];
-        const float wo = P.table[s * 4 + 1];
-        const float wu = P.table[s * 4 + 2];
+        const f32x4 t = tab[e.sid];
+        const float T = t.x, wo = t.y, wu = t.z;
 #pragma unroll
         for (int h = 0; h < NRHS; ++h) {
             const float z = acc[h];
-            P.y[(int64_t)r * NRHS + h] = z;
+            P.y[r * NRHS + h] = z;
             const float over = fmaxf(z - T, 0.0f);
             const float under = fmaxf(T - z, 0.0f);
-            if (P.g) P.g[(int64_t)r * NRHS + h] = 2.0f * wo * over - 2.0f * wu * under;
+            if (P.g) P.g[r * NRHS + h] = 2.0f * wo * over - 2.0f * wu * under;
             fpart[h] += wo * over * over + wu * under * under;
         }
     } else {  // EPI_CURV
         const float d = acc[0];
         if (P.y) P.y[r] = d;
-        const int s = P.sid[r];
-        const float T = P.table[s * 4 + 0];
-        const float zr = P.zref[r];
-        const float w = zr > T ? P.table[s * 4 + 1] : (zr < T ? P.table[s * 4 + 2] : 0.0f);
+        const f32x4 t = tab[e.sid];
+        const float T = t.x;
+        const float w = e.zr > T ? t.y : (e.zr < T ? t.z : 0.0f);
         cpart += (double)w * (double)d * (double)d;
     }
 }
@@ -210,15 +233,31 @@ __device__ __forceinline__ void fma4_blocked(float (&acc)[B][NRHS], const SpmvPa
 // Kernel body "row": block rows in order; per block row each lane streams 4
 // consecutive block entries per step (16-byte column load, B 16-byte value
 // loads at FP32), two steps in flight; the wave's butterfly reduces each of
-// the B rows, lane 0 finishes them.
+// the B rows, lane 0 finishes them.  The row pointers and epilogue inputs of
+// every block row of the unit are loaded up front, lane i for block row i, so
+// the short block rows of the dose do not each wait for them in turn.
 template <int ST, int NRHS, int EPI, bool SCALE_X, int B>
-__device__ __forceinline__ void block_rows(const SpmvParams& P, int64_t b, int lane, float (&fpart)[NRHS],
-                                           double& cpart) {
-    const int r0 = P.blocks[b];
-    const int r1 = P.blocks[b + 1];
-    for (int br = r0; br < r1; ++br) {
-        const int64_t e0 = P.rowptr[br];
-        const int64_t e1 = P.rowptr[br + 1];
+__device__ __forceinline__ void block_rows(const SpmvParams& P, int r0, int r1, int lane, const f32x4* tab,
+                                           float (&fpart)[NRHS], double& cpart) {
+    const int nbr = r1 - r0;                              // 1 .. kBlockRowsMax
+    const int li = lane < nbr ? lane : nbr - 1;
+    // block row starts relative to the unit's first entry (a unit holds fewer
+    // than 2^31 stored positions)
+    const int64_t base = P.rowptr[r0];
+    const int64_t last = P.rowptr[r1];
+    const int rel = (int)(P.rowptr[r0 + li] - base);
+    // epilogue inputs: structure ids packed one byte per row, or floats
+    int sid4 = 0;
+    float ef[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+        const EpiRow e = epi_load<EPI>(P, (int64_t)(r0 + li) * B + q);
+        sid4 |= e.sid << (8 * q);
+        ef[q] = EPI == EPI_CURV ? e.zr : e.rs;
+    }
+    for (int i = 0; i < nbr; ++i) {
+        const int64_t e0 = base + __builtin_amdgcn_readlane(rel, i);
+        const int64_t e1 = i + 1 < nbr ? base + __builtin_amdgcn_readlane(rel, i + 1) : last;
         float acc[B][NRHS];
 #pragma unroll
         for (int q = 0; q < B; ++q)
@@ -256,11 +295,18 @@ __device__ __forceinline__ void block_rows(const SpmvParams& P, int64_t b, int l
         for (int q = 0; q < B; ++q)
 #pragma unroll
             for (int h = 0; h < NRHS; ++h) acc[q][h] = wave_sum(acc[q][h]);
+        const int sids = __builtin_amdgcn_readlane(sid4, i);
+        float efs[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) efs[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ef[q]), i));
         if (lane == 0) {
 #pragma unroll
             for (int q = 0; q < B; ++q) {
-                const int64_t r = (int64_t)br * B + q;
-                if (r < P.n_rows) row_epilogue<NRHS, EPI>(P, P.perm ? P.perm[r] : (int)r, acc[q], fpart, cpart);
+                const int64_t r = (int64_t)(r0 + i) * B + q;
+                if (r < P.n_rows) {
+                    const EpiRow e{(sids >> (8 * q)) & 0xff, efs[q], efs[q]};
+                    row_epilogue<NRHS, EPI>(P, natural_row(P, r), e, tab, acc[q], fpart, cpart);
+                }
             }
         }
     }
@@ -268,10 +314,11 @@ __device__ __forceinline__ void block_rows(const SpmvParams& P, int64_t b, int l
 
 // acc_l: this wave's LDS row accumulators [kBlockRowsMax * NRHS]; rel: [kBlockRowsMax + 1].
 template <int ST, int NRHS, int EPI, bool SCALE_X>
-__device__ __forceinline__ void block_stream(const SpmvParams& P, int64_t b, int lane, float* acc_l, int* rel,
-                                             float (&fpart)[NRHS], double& cpart) {
-    const int r0 = P.blocks[b];
-    const int nr = P.blocks[b + 1] - r0;               // 1 .. kBlockRowsMax
+__device__ __forceinline__ void block_stream(const SpmvParams& P, int r0, int r1, int lane, float* acc_l, int* rel,
+                                             const f32x4* tab, float (&fpart)[NRHS], double& cpart) {
+    const int nr = r1 - r0;                            // 1 .. kBlockRowsMax
+    const EpiRow ein = epi_load<EPI>(P, lane < nr ? (int64_t)r0 + lane : P.n_rows);
+    const int64_t nat = lane < nr ? natural_row(P, (int64_t)r0 + lane) : 0;
     const int64_t e0 = P.rowptr[r0];
     const int ne = (int)(P.rowptr[r0 + nr] - e0);
     for (int i = lane; i <= nr; i += kWaveSize) rel[i] = (int)(P.rowptr[r0 + i] - e0);
@@ -319,11 +366,11 @@ __device__ __forceinline__ void block_stream(const SpmvParams& P, int64_t b, int
         }
     }
     wave_sync_lds();
-    for (int i = lane; i < nr; i += kWaveSize) {
+    if (lane < nr) {
         float a[NRHS];
 #pragma unroll
-        for (int h = 0; h < NRHS; ++h) a[h] = acc_l[i * NRHS + h];
-        row_epilogue<NRHS, EPI>(P, P.perm ? P.perm[r0 + i] : r0 + i, a, fpart, cpart);
+        for (int h = 0; h < NRHS; ++h) a[h] = acc_l[lane * NRHS + h];
+        row_epilogue<NRHS, EPI>(P, nat, ein, tab, a, fpart, cpart);
     }
     wave_sync_lds();
 }
@@ -383,8 +430,10 @@ __device__ __forceinline__ WaveSlot wave_slot() {
     return s;
 }
 
+// Eight waves per SIMD (at most 64 VGPRs): the loads in flight, not the
+// registers per wave, set the throughput of these kernels.
 template <int KIND, int ST, int NRHS, int EPI, int B>
-__global__ __launch_bounds__(kSpmvThreads) void spmv_kernel(SpmvParams P) {
+__global__ __launch_bounds__(kSpmvThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void spmv_kernel(SpmvParams P) {
     constexpr int kWaves = kSpmvThreads / kWaveSize;
     const WaveSlot w = wave_slot();
     const int64_t b0 = P.n_blocks * w.xcd / kNumXcd;
@@ -393,14 +442,27 @@ __global__ __launch_bounds__(kSpmvThreads) void spmv_kernel(SpmvParams P) {
 #pragma unroll
     for (int h = 0; h < NRHS; ++h) fpart[h] = 0.0f;
     double cpart = 0.0;
-    if constexpr (KIND == KIND_ROW || B != 1) {
-        for (int64_t b = b0 + w.lw; b < b1; b += w.waves_per_xcd)
-            block_rows<ST, NRHS, EPI, false, B>(P, b, w.lane, fpart, cpart);
-    } else {
-        __shared__ float s_acc[kWaves][kBlockRowsMax * NRHS];
-        __shared__ int s_rel[kWaves][kBlockRowsMax + 1];
-        for (int64_t b = b0 + w.lw; b < b1; b += w.waves_per_xcd)
-            block_stream<ST, NRHS, EPI, false>(P, b, w.lane, s_acc[w.wid], s_rel[w.wid], fpart, cpart);
+    __shared__ f32x4 s_tab[(EPI == EPI_OBJ || EPI == EPI_CURV) ? 256 : 1];
+    if constexpr (EPI == EPI_OBJ || EPI == EPI_CURV) {
+        static_assert(kSpmvThreads == 256, "one table row per thread");
+        s_tab[threadIdx.x] = reinterpret_cast<const f32x4*>(P.table)[threadIdx.x];
+        __syncthreads();
+    }
+    // the unit's first and last block row; the next unit's are loaded while
+    // this one runs (lanes 0 and 1)
+    int64_t b = b0 + w.lw;
+    int bnd = b < b1 ? P.blocks[b + (w.lane & 1)] : 0;
+    __shared__ float s_acc[(KIND == KIND_STREAM && B == 1) ? kWaves : 1][kBlockRowsMax * NRHS];
+    __shared__ int s_rel[(KIND == KIND_STREAM && B == 1) ? kWaves : 1][kBlockRowsMax + 1];
+    for (; b < b1; b += w.waves_per_xcd) {
+        const int r0 = __builtin_amdgcn_readlane(bnd, 0);
+        const int r1 = __builtin_amdgcn_readlane(bnd, 1);
+        const int64_t bn = b + w.waves_per_xcd;
+        if (bn < b1) bnd = P.blocks[bn + (w.lane & 1)];
+        if constexpr (KIND == KIND_ROW || B != 1)
+            block_rows<ST, NRHS, EPI, false, B>(P, r0, r1, w.lane, s_tab, fpart, cpart);
+        else
+            block_stream<ST, NRHS, EPI, false>(P, r0, r1, w.lane, s_acc[w.wid], s_rel[w.wid], s_tab, fpart, cpart);
     }
     workgroup_partials<NRHS, EPI>(P, w.lane, w.wid, fpart, cpart);
 }
@@ -439,10 +501,13 @@ __global__ __launch_bounds__(kSpmvThreads) void spmv_batch_kernel(BatchParams B)
     double cpart = 0.0;
     __shared__ float s_acc[kWaves][(KIND == KIND_STREAM ? kBlockRowsMax : 1) * NRHS];
     __shared__ int s_rel[kWaves][(KIND == KIND_STREAM ? kBlockRowsMax + 1 : 1)];
+    static_assert(EPI == EPI_PLAIN || EPI == EPI_SCALE, "the batched launch has no objective epilogue");
     int p = 0;
     for (int64_t b = b0 + w.lw; b < b1; b += w.waves_per_xcd) {
         while (p + 1 < B.n_plans && B.plans[p + 1].block_base <= b) ++p;   // b only grows
         const PlanDev& pd = B.plans[p];
+        const int r0 = pd.blocks[b - pd.block_base];
+        const int r1 = pd.blocks[b - pd.block_base + 1];
         SpmvParams P{};
         P.n_rows = pd.n_rows;
         P.perm = pd.perm;
@@ -456,9 +521,9 @@ __global__ __launch_bounds__(kSpmvThreads) void spmv_batch_kernel(BatchParams B)
         P.row_scale = pd.scale;
         P.x_scale = pd.scale;
         if constexpr (KIND == KIND_ROW || BR != 1)
-            block_rows<ST, NRHS, EPI, SCALE_X, BR>(P, b - pd.block_base, w.lane, fpart, cpart);
+            block_rows<ST, NRHS, EPI, SCALE_X, BR>(P, r0, r1, w.lane, nullptr, fpart, cpart);
         else
-            block_stream<ST, NRHS, EPI, SCALE_X>(P, b - pd.block_base, w.lane, s_acc[w.wid], s_rel[w.wid], fpart,
+            block_stream<ST, NRHS, EPI, SCALE_X>(P, r0, r1, w.lane, s_acc[w.wid], s_rel[w.wid], nullptr, fpart,
                                                  cpart);
     }
 }
