@@ -318,9 +318,9 @@ def main():
     if not args.no_autotune and not any(fixed.values()):
         t = time.perf_counter()
         info = ddc.autotune(reps=5)
-        log(f"autotuned in {time.perf_counter() - t:.1f} s: dose kernel {('row', 'stream')[info.dose_kernel]} "
+        log(f"autotuned in {time.perf_counter() - t:.1f} s: dose kernel {('row', 'stream', 'pipe')[info.dose_kernel]} "
             f"x {info.dose_workgroups} wg ({info.dose_tuned_ms:.3f} ms), price kernel "
-            f"{('row', 'stream')[info.price_kernel]} x {info.price_workgroups} wg ({info.price_tuned_ms:.3f} ms)")
+            f"{('row', 'stream', 'pipe')[info.price_kernel]} x {info.price_workgroups} wg ({info.price_tuned_ms:.3f} ms)")
     for orient, spec in fixed.items():
         if spec:
             kind, wg = spec.split(":")
@@ -409,8 +409,8 @@ def main():
             "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
             "mean_dose_call_ms": round(mean_dose, 4), "mean_price_call_ms": round(mean_price, 4),
             "generate_s": round(t_gen, 2), "build_upload_s": round(t_build, 2),
-            "dose_launch": {"kernel": ("row", "stream")[info.dose_kernel], "workgroups": info.dose_workgroups},
-            "price_launch": {"kernel": ("row", "stream")[info.price_kernel], "workgroups": info.price_workgroups},
+            "dose_launch": {"kernel": ("row", "stream", "pipe")[info.dose_kernel], "workgroups": info.dose_workgroups},
+            "price_launch": {"kernel": ("row", "stream", "pipe")[info.price_kernel], "workgroups": info.price_workgroups},
         },
         "roofline": {
             "bound": "hbm", "kernel": kname,

@@ -80,7 +80,7 @@ typedef struct {
     int32_t storage;                     /* DVMAT_F32 / F16 / BF16               */
     int32_t value_bytes;                 /* 4 or 2                               */
     size_t workspace_bytes;              /* device bytes needed by dvmat_ddc_bind */
-    int32_t dose_kernel, dose_workgroups;   /* launch shape in use: kernel 0 = row, 1 = stream */
+    int32_t dose_kernel, dose_workgroups;   /* launch shape in use: kernel 0 = row, 1 = stream, 2 = pipe */
     int32_t price_kernel, price_workgroups;
     float dose_tuned_ms, price_tuned_ms;    /* autotuner's best times (0 before tuning) */
     int32_t dose_block_rows, price_block_rows;  /* rows sharing one column index (build option) */
@@ -185,8 +185,8 @@ dvmat_status dvmat_dose(dvmat_ddc ddc, const float* x, int32_t nrhs, float* z,
 dvmat_status dvmat_price(dvmat_ddc ddc, const float* g, int32_t nrhs, float* p,
                          dvmat_stream stream);
 
-/* Autotuner: times every candidate launch shape (block kernel "row" or
- * "stream" x workgroup count) of the plain dose and of the price on the
+/* Autotuner: times every candidate launch shape (block kernel "row",
+ * "stream" or "pipe" x workgroup count) of the plain dose and of the price on the
  * caller's vectors (x: device float[n_bl], z: float[n_vox], g: float[n_vox],
  * p: float[n_bl], contents of z and p are overwritten), reps timed launches
  * each after one warm-up, and keeps the fastest per orientation for all later
@@ -195,7 +195,10 @@ dvmat_status dvmat_price(dvmat_ddc ddc, const float* g, int32_t nrhs, float* p,
 dvmat_status dvmat_ddc_autotune(dvmat_ddc ddc, const float* x, float* z, const float* g, float* p,
                                 int32_t reps, dvmat_stream stream);
 /* Set the launch shape by hand: orientation 0 = dose, 1 = price; kind 0 =
- * row, 1 = stream; workgroups in [8, 8192] (rounded to a multiple of 8). */
+ * row (one block row at a time), 1 = stream (a unit's entries as one range;
+ * one row per block row only), 2 = pipe (row, with the next step's loads
+ * issued before the current step's gathers, across block rows); workgroups
+ * in [8, 8192] (rounded to a multiple of 8). */
 dvmat_status dvmat_ddc_set_kernel(dvmat_ddc ddc, int32_t orientation, int32_t kind, int32_t workgroups);
 
 /* Curvature of F along a fluence direction, for the first step length of a

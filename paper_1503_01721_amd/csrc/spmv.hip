@@ -312,6 +312,123 @@ __device__ __forceinline__ void block_rows(const SpmvParams& P, int r0, int r1, 
     }
 }
 
+// One step of the pipelined kernel: the 4 block entries of this lane at
+// position k (relative to base), or zeros past the block row's end e.
+template <int ST, int B>
+__device__ __forceinline__ void load_step(const SpmvParams& P, int64_t base, int k, int e, int lane, f32x4 (&V)[B],
+                                          i32x4& c) {
+    const int kl = k + 4 * lane;
+    if (kl < e) {
+        load_block_vals<ST, B>(P.val, base + kl, V);
+        c = load_cols(P.col, base + kl);
+    } else {
+#pragma unroll
+        for (int t = 0; t < B; ++t) V[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        c = i32x4{0, 0, 0, 0};
+    }
+}
+
+// Kernel body "pipe": the row kernel's arithmetic, software-pipelined over the
+// steps of the whole unit: the loads of the next step (which may be the first
+// step of a later block row) are issued before the gathers of the current
+// step, so the matrix stream of one step overlaps the gathers of the other.
+// Empty block rows take no step; their outputs are written when the wave
+// passes them.
+template <int ST, int NRHS, int EPI, bool SCALE_X, int B>
+__device__ __forceinline__ void block_pipe(const SpmvParams& P, int r0, int r1, int lane, const f32x4* tab,
+                                           float (&fpart)[NRHS], double& cpart) {
+    const int nbr = r1 - r0;                              // 1 .. kBlockRowsMax
+    const int li = lane < nbr ? lane : nbr - 1;
+    const int64_t base = P.rowptr[r0];
+    const int total = (int)(P.rowptr[r1] - base);
+    const int rel = (int)(P.rowptr[r0 + li] - base);
+    int sid4 = 0;
+    float ef[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+        const EpiRow e = epi_load<EPI>(P, (int64_t)(r0 + li) * B + q);
+        sid4 |= e.sid << (8 * q);
+        ef[q] = EPI == EPI_CURV ? e.zr : e.rs;
+    }
+    // end of block row j, relative to base
+    auto row_end = [&](int j) -> int { return j + 1 < nbr ? __builtin_amdgcn_readlane(rel, j + 1) : total; };
+    // outputs of block row j from its (already reduced) sums
+    auto finish = [&](int j, const float (&sum)[B][NRHS]) {
+        const int sids = __builtin_amdgcn_readlane(sid4, j);
+        float efs[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) efs[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ef[q]), j));
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < B; ++q) {
+                const int64_t r = (int64_t)(r0 + j) * B + q;
+                if (r < P.n_rows) {
+                    const EpiRow e{(sids >> (8 * q)) & 0xff, efs[q], efs[q]};
+                    row_epilogue<NRHS, EPI>(P, natural_row(P, r), e, tab, sum[q], fpart, cpart);
+                }
+            }
+        }
+    };
+    float zero[B][NRHS];
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+#pragma unroll
+        for (int h = 0; h < NRHS; ++h) zero[q][h] = 0.0f;
+    // leading empty block rows
+    int i = 0, k = 0, e1 = row_end(0);
+    while (k >= e1) {
+        finish(i, zero);
+        if (++i == nbr) return;
+        e1 = row_end(i);
+    }
+    float acc[B][NRHS];
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+#pragma unroll
+        for (int h = 0; h < NRHS; ++h) acc[q][h] = 0.0f;
+    f32x4 V[B];
+    i32x4 c;
+    load_step<ST, B>(P, base, k, e1, lane, V, c);
+    while (true) {
+        // the step after (i, k): the next 256 entries of row i, else the first
+        // step of the next non-empty block row
+        int kn = k + 256, in = i, e1n = e1;
+        if (kn >= e1) {
+            kn = e1;
+            in = i + 1;
+            e1n = in < nbr ? row_end(in) : kn;
+            while (in < nbr && kn >= e1n) {
+                ++in;
+                e1n = in < nbr ? row_end(in) : kn;
+            }
+        }
+        const bool more = in < nbr;
+        f32x4 Vn[B];
+        i32x4 cn;
+        if (more) load_step<ST, B>(P, base, kn, e1n, lane, Vn, cn);
+        if (k + 4 * lane < e1) fma4_blocked<NRHS, B, SCALE_X>(acc, P, V, c);
+        if (in != i) {
+#pragma unroll
+            for (int q = 0; q < B; ++q)
+#pragma unroll
+                for (int h = 0; h < NRHS; ++h) acc[q][h] = wave_sum(acc[q][h]);
+            finish(i, acc);
+#pragma unroll
+            for (int q = 0; q < B; ++q)
+#pragma unroll
+                for (int h = 0; h < NRHS; ++h) acc[q][h] = 0.0f;
+            for (int j = i + 1; j < in; ++j) finish(j, zero);
+        }
+        if (!more) break;
+        i = in;
+        k = kn;
+        e1 = e1n;
+#pragma unroll
+        for (int t = 0; t < B; ++t) V[t] = Vn[t];
+        c = cn;
+    }
+}
+
 // acc_l: this wave's LDS row accumulators [kBlockRowsMax * NRHS]; rel: [kBlockRowsMax + 1].
 template <int ST, int NRHS, int EPI, bool SCALE_X>
 __device__ __forceinline__ void block_stream(const SpmvParams& P, int r0, int r1, int lane, float* acc_l, int* rel,
@@ -412,7 +529,7 @@ __device__ __forceinline__ void workgroup_partials(const SpmvParams& P, int lane
     }
 }
 
-enum Kind { KIND_ROW = 0, KIND_STREAM = 1 };
+enum Kind { KIND_ROW = 0, KIND_STREAM = 1, KIND_PIPE = 2 };
 
 // Wave position: workgroup w on XCD w % 8; the XCD's waves share its block range.
 struct WaveSlot {
@@ -459,7 +576,9 @@ __global__ __launch_bounds__(kSpmvThreads) __attribute__((amdgpu_waves_per_eu(8,
         const int r1 = __builtin_amdgcn_readlane(bnd, 1);
         const int64_t bn = b + w.waves_per_xcd;
         if (bn < b1) bnd = P.blocks[bn + (w.lane & 1)];
-        if constexpr (KIND == KIND_ROW || B != 1)
+        if constexpr (KIND == KIND_PIPE)
+            block_pipe<ST, NRHS, EPI, false, B>(P, r0, r1, w.lane, s_tab, fpart, cpart);
+        else if constexpr (KIND == KIND_ROW || B != 1)
             block_rows<ST, NRHS, EPI, false, B>(P, r0, r1, w.lane, s_tab, fpart, cpart);
         else
             block_stream<ST, NRHS, EPI, false>(P, r0, r1, w.lane, s_acc[w.wid], s_rel[w.wid], s_tab, fpart, cpart);
@@ -608,7 +727,7 @@ static int clamp_workgroups(int want, int64_t n_blocks) {
 // Default launch shape; the autotuner overrides it per matrix orientation.
 static KernelCfg default_cfg() {
     KernelCfg c{KIND_ROW, 2048};
-    if (const char* s = std::getenv("DVMAT_SPMV_KIND")) c.kind = s[0] == 's' ? KIND_STREAM : KIND_ROW;
+    if (const char* s = std::getenv("DVMAT_SPMV_KIND")) c.kind = s[0] == 's' ? KIND_STREAM : s[0] == 'p' ? KIND_PIPE : KIND_ROW;
     if (const char* s = std::getenv("DVMAT_SPMV_WG")) c.workgroups = std::max(8, std::atoi(s));
     return c;
 }
@@ -628,7 +747,11 @@ static void launch_nrhs(const SpmvParams& P, int nrhs, int nwg, hipStream_t s) {
 
 template <int ST, int EPI>
 static void launch_st(const KernelCfg& cfg, int B, const SpmvParams& P, int nrhs, int nwg, hipStream_t s) {
-    if (B == 4) launch_nrhs<KIND_ROW, ST, EPI, 4>(P, nrhs, nwg, s);
+    if (cfg.kind == KIND_PIPE) {
+        if (B == 4) launch_nrhs<KIND_PIPE, ST, EPI, 4>(P, nrhs, nwg, s);
+        else if (B == 2) launch_nrhs<KIND_PIPE, ST, EPI, 2>(P, nrhs, nwg, s);
+        else launch_nrhs<KIND_PIPE, ST, EPI, 1>(P, nrhs, nwg, s);
+    } else if (B == 4) launch_nrhs<KIND_ROW, ST, EPI, 4>(P, nrhs, nwg, s);
     else if (B == 2) launch_nrhs<KIND_ROW, ST, EPI, 2>(P, nrhs, nwg, s);
     else if (cfg.kind == KIND_STREAM) launch_nrhs<KIND_STREAM, ST, EPI, 1>(P, nrhs, nwg, s);
     else launch_nrhs<KIND_ROW, ST, EPI, 1>(P, nrhs, nwg, s);
@@ -646,7 +769,11 @@ static void launch_spmv(const KernelCfg& cfg, int storage, int B, const SpmvPara
 template <int ST>
 static void launch_curv_st(const KernelCfg& cfg, int B, const SpmvParams& P, int nwg, hipStream_t s) {
     dim3 grid(nwg), block(kSpmvThreads);
-    if (B == 4) hipLaunchKernelGGL((spmv_kernel<KIND_ROW, ST, 1, EPI_CURV, 4>), grid, block, 0, s, P);
+    if (cfg.kind == KIND_PIPE) {
+        if (B == 4) hipLaunchKernelGGL((spmv_kernel<KIND_PIPE, ST, 1, EPI_CURV, 4>), grid, block, 0, s, P);
+        else if (B == 2) hipLaunchKernelGGL((spmv_kernel<KIND_PIPE, ST, 1, EPI_CURV, 2>), grid, block, 0, s, P);
+        else hipLaunchKernelGGL((spmv_kernel<KIND_PIPE, ST, 1, EPI_CURV, 1>), grid, block, 0, s, P);
+    } else if (B == 4) hipLaunchKernelGGL((spmv_kernel<KIND_ROW, ST, 1, EPI_CURV, 4>), grid, block, 0, s, P);
     else if (B == 2) hipLaunchKernelGGL((spmv_kernel<KIND_ROW, ST, 1, EPI_CURV, 2>), grid, block, 0, s, P);
     else if (cfg.kind == KIND_STREAM) hipLaunchKernelGGL((spmv_kernel<KIND_STREAM, ST, 1, EPI_CURV, 1>), grid, block, 0, s, P);
     else hipLaunchKernelGGL((spmv_kernel<KIND_ROW, ST, 1, EPI_CURV, 1>), grid, block, 0, s, P);
@@ -803,16 +930,19 @@ static dvmat_status time_config(Run&& run, int reps, hipStream_t s, float* ms_ou
 }
 
 template <class RunCfg>
-static dvmat_status tune(RunCfg&& run_cfg, int reps, hipStream_t s, KernelCfg* best, float* best_ms, int B) {
+static dvmat_status tune(RunCfg&& run_cfg, int reps, hipStream_t s, KernelCfg* best, float* best_ms, int B,
+                         bool with_pipe = true) {
     *best_ms = INFINITY;
-    for (int kind = 0; kind < (B == 1 ? 2 : 1); ++kind)
+    for (int kind : {KIND_ROW, KIND_STREAM, KIND_PIPE})
         for (int wg : kTuneWorkgroups) {
+            if ((kind == KIND_STREAM && B != 1) || (kind == KIND_PIPE && !with_pipe)) continue;
             KernelCfg c{kind, wg};
             float ms = 0.0f;
             dvmat_status st = time_config([&] { return run_cfg(c); }, reps, s, &ms);
             if (st) return st;
             if (std::getenv("DVMAT_AUTOTUNE_VERBOSE"))
-                fprintf(stderr, "[dvmat autotune] kernel=%s workgroups=%d %.4f ms\n", kind ? "stream" : "row", wg, ms);
+                fprintf(stderr, "[dvmat autotune] kernel=%s workgroups=%d %.4f ms\n",
+                        kind == KIND_ROW ? "row" : kind == KIND_STREAM ? "stream" : "pipe", wg, ms);
             if (ms < *best_ms) { *best_ms = ms; *best = c; }
         }
     return DVMAT_OK;
@@ -970,7 +1100,8 @@ dvmat_status dvmat_ddc_autotune(dvmat_ddc d, const float* x, float* z, const flo
 
 dvmat_status dvmat_ddc_set_kernel(dvmat_ddc d, int32_t orientation, int32_t kind, int32_t workgroups) {
     if (!d) return set_error(DVMAT_E_ARG, "dvmat_ddc_set_kernel: NULL handle");
-    if (kind != 0 && kind != 1) return set_error(DVMAT_E_ARG, "dvmat_ddc_set_kernel: kind %d", kind);
+    if (kind != KIND_ROW && kind != KIND_STREAM && kind != KIND_PIPE)
+        return set_error(DVMAT_E_ARG, "dvmat_ddc_set_kernel: kind %d", kind);
     if (workgroups < kNumXcd || workgroups > kMaxSpmvWorkgroups)
         return set_error(DVMAT_E_ARG, "dvmat_ddc_set_kernel: workgroups %d not in [8, 8192]", workgroups);
     KernelCfg c{kind, workgroups};
@@ -1068,11 +1199,11 @@ dvmat_status dvmat_batch_autotune(dvmat_batch b, const float* const* xs, float* 
     KernelCfg best{};
     float ms = 0.0f;
     dvmat_status st = tune([&](const KernelCfg& c) { return batch_call(b, true, c, xs, nrhs, zs, s, "dvmat_batch_autotune"); },
-                           reps, s, &best, &ms, b->dose_B);
+                           reps, s, &best, &ms, b->dose_B, false);
     if (st) return st;
     b->dose_cfg = best;
     st = tune([&](const KernelCfg& c) { return batch_call(b, false, c, gs, nrhs, ps, s, "dvmat_batch_autotune"); },
-              reps, s, &best, &ms, b->price_B);
+              reps, s, &best, &ms, b->price_B, false);
     if (st) return st;
     b->price_cfg = best;
     return DVMAT_OK;

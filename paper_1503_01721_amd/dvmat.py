@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "lib", "libdvmat.so")
 
 F32, F16, BF16 = 0, 1, 2
 STORAGE = {"f32": F32, "f16": F16, "bf16": BF16}
+KERNEL_KINDS = ("row", "stream", "pipe")
 
 BB_REL_F, BB_SMALL_STEP, BB_MAX_ITER, BB_FALLBACK, BB_CONVERGED, BB_NONFINITE = 1, 2, 4, 8, 16, 32
 BB_STOP_MASK = BB_REL_F | BB_SMALL_STEP | BB_MAX_ITER | BB_CONVERGED | BB_NONFINITE
@@ -281,7 +282,7 @@ class DDC:
 
     def set_kernel(self, orientation: str, kind: str, workgroups: int):
         _check(lib.dvmat_ddc_set_kernel(self._h, {"dose": 0, "price": 1}[orientation],
-                                        {"row": 0, "stream": 1}[kind], int(workgroups)))
+                                        KERNEL_KINDS.index(kind), int(workgroups)))
         return self.refresh_info()
 
     def curvature_(self, x_dir, obj, z_ref, curv, d_out=None, stream=None):
