@@ -207,7 +207,8 @@ def bench_autograd(args):
     t_gen = time.perf_counter() - t
     log(f"generated {plan.name}: nnz={len(d['val'])} in {t_gen:.1f} s")
     t = time.perf_counter()
-    ddc = dvmat.DDC(d["row"], d["col"], d["val"], plan.n_vox, plan.n_bl, storage=storage)
+    layout = {} if args.layout == "csr" else plan.grids
+    ddc = dvmat.DDC(d["row"], d["col"], d["val"], plan.n_vox, plan.n_bl, storage=storage, **layout)
     del d
     obj = dvmat.Objective(sid, table)
     t_build = time.perf_counter() - t
@@ -276,6 +277,9 @@ def main():
     ap.add_argument("--form", default="D", choices=["D", "DA"],
                     help="master problem over the whole matrix (D, default: every BB iteration runs "
                          "a dose and a price product) or over the aperture dose vectors (DA)")
+    ap.add_argument("--layout", default="panel", choices=["panel", "csr"],
+                    help="device layout of both orientations: panels (vector slices staged in LDS, "
+                         "default) or CSR (gathers from global memory)")
     ap.add_argument("--copy-calibration", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
 
@@ -308,7 +312,8 @@ def main():
     log(f"generated nnz={len(d['val'])} in {t_gen:.1f} s")
 
     t = time.perf_counter()
-    ddc = dvmat.DDC(d["row"], d["col"], d["val"], plan.n_vox, plan.n_bl, storage=args.storage)
+    layout = {} if args.layout == "csr" else plan.grids
+    ddc = dvmat.DDC(d["row"], d["col"], d["val"], plan.n_vox, plan.n_bl, storage=args.storage, **layout)
     obj = dvmat.Objective(sid, table)
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t
@@ -318,9 +323,9 @@ def main():
     if not args.no_autotune and not any(fixed.values()):
         t = time.perf_counter()
         info = ddc.autotune(reps=5)
-        log(f"autotuned in {time.perf_counter() - t:.1f} s: dose kernel {('row', 'stream', 'pipe')[info.dose_kernel]} "
+        log(f"autotuned in {time.perf_counter() - t:.1f} s: dose kernel {('row', 'stream', 'pipe', 'panel')[info.dose_kernel]} "
             f"x {info.dose_workgroups} wg ({info.dose_tuned_ms:.3f} ms), price kernel "
-            f"{('row', 'stream', 'pipe')[info.price_kernel]} x {info.price_workgroups} wg ({info.price_tuned_ms:.3f} ms)")
+            f"{('row', 'stream', 'pipe', 'panel')[info.price_kernel]} x {info.price_workgroups} wg ({info.price_tuned_ms:.3f} ms)")
     for orient, spec in fixed.items():
         if spec:
             kind, wg = spec.split(":")
@@ -409,8 +414,10 @@ def main():
             "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
             "mean_dose_call_ms": round(mean_dose, 4), "mean_price_call_ms": round(mean_price, 4),
             "generate_s": round(t_gen, 2), "build_upload_s": round(t_build, 2),
-            "dose_launch": {"kernel": ("row", "stream", "pipe")[info.dose_kernel], "workgroups": info.dose_workgroups},
-            "price_launch": {"kernel": ("row", "stream", "pipe")[info.price_kernel], "workgroups": info.price_workgroups},
+            "layout": args.layout,
+            "dose_panels": int(info.dose_panels), "price_panels": int(info.price_panels),
+            "dose_launch": {"kernel": ("row", "stream", "pipe", "panel")[info.dose_kernel], "workgroups": info.dose_workgroups},
+            "price_launch": {"kernel": ("row", "stream", "pipe", "panel")[info.price_kernel], "workgroups": info.price_workgroups},
         },
         "roofline": {
             "bound": "hbm", "kernel": kname,

@@ -85,6 +85,10 @@ typedef struct {
     float dose_tuned_ms, price_tuned_ms;    /* autotuner's best times (0 before tuning) */
     int32_t dose_block_rows, price_block_rows;  /* rows sharing one column index (build option) */
     int32_t dose_row_order, price_row_order;    /* row order of the layout (build option) */
+    int32_t dose_layout, price_layout;          /* 0 = CSR, 1 = panels (as built)           */
+    int64_t dose_panels, price_panels;          /* panels (layout 1), else 0                */
+    int64_t dose_panel_cols, price_panel_cols;  /* largest column list of a panel           */
+    int64_t dose_panel_cols_total, price_panel_cols_total; /* sum of the panels' column lists */
 } dvmat_ddc_info_t;
 
 /* Build options of the device layout.  block_rows B in {1, 2, 4}: B
@@ -99,7 +103,23 @@ typedef struct {
  * row_order: 0 = natural; 1 = rows stored in order of their first column
  * (empty rows last), so rows that read the same part of the input vector run
  * together (for the price matrix: beamlets covering the same slab of voxels,
- * from every angle); outputs are still written in natural order. */
+ * from every angle); outputs are still written in natural order.
+ *
+ * layout: 0 = CSR, every product gathers the input vector from global memory;
+ * 1 = panels: rows are grouped into panels, each with the sorted list of the
+ * distinct columns its rows touch (at most panel_cols of them); the stored
+ * column index is the position in that list (16 bits), and a product first
+ * copies the panel's slice of the input vector into the compute unit's local
+ * memory (LDS), then gathers from there.  Rows of neighbouring voxels (or of
+ * neighbouring beamlets at neighbouring angles) touch few distinct columns, so
+ * each staged value serves many products.  grid: the rows as a 3-D grid,
+ * fastest axis first (voxels: nx, ny, nz; beamlets: columns, MLC rows,
+ * control points), product equal to the row count; tile: the sub-grid of rows
+ * that forms one panel (a tile with more distinct columns than panel_cols is
+ * split along the row order).  A zero grid keeps the natural row order and
+ * cuts panels greedily.  With block rows, tile[0] must be a multiple of B.
+ * If a single block row has more than panel_cols distinct columns the
+ * orientation is built as CSR (dvmat_ddc_info reports the layout built). */
 typedef struct {
     int32_t dose_block_rows;
     int32_t price_block_rows;
@@ -107,13 +127,19 @@ typedef struct {
     int32_t unit_entries;
     int32_t dose_row_order;
     int32_t price_row_order;
+    int32_t dose_layout, price_layout;
+    int32_t dose_grid[3], price_grid[3];
+    int32_t dose_tile[3], price_tile[3];
+    int32_t panel_cols;
 } dvmat_build_opts;
 
 /* Fill opts with the defaults for a storage type (DVMAT_F32/F16/BF16): the
- * fastest measured layout, dose B = 2 at 4-byte values and 4 at 2-byte values,
- * price B = 1 at 4-byte and 2 at 2-byte values, price rows in first-column
- * order.  Environment variables DVMAT_DOSE_B, DVMAT_PRICE_B,
- * DVMAT_INTERLEAVE, DVMAT_BLOCK_NNZ, DVMAT_DOSE_ORDER, DVMAT_PRICE_ORDER
+ * fastest measured CSR layout, dose B = 2 at 4-byte values and 4 at 2-byte
+ * values, price B = 1 at 4-byte and 2 at 2-byte values, price rows in
+ * first-column order; layout CSR with zero grids (a caller that knows the
+ * voxel and beamlet grids sets layout 1, the grids and tiles), panel_cols
+ * 8192.  Environment variables DVMAT_DOSE_B, DVMAT_PRICE_B, DVMAT_INTERLEAVE,
+ * DVMAT_BLOCK_NNZ, DVMAT_DOSE_ORDER, DVMAT_PRICE_ORDER, DVMAT_PANEL_COLS
  * override single fields.  DVMAT_E_ARG for an unknown storage. */
 dvmat_status dvmat_ddc_default_opts(int32_t storage, dvmat_build_opts* opts);
 
@@ -134,6 +160,18 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz,
                                  const dvmat_build_opts* opts, dvmat_ddc* out);
 /* Sizes and counts; valid right after create. */
 dvmat_status dvmat_ddc_info(dvmat_ddc ddc, dvmat_ddc_info_t* info);
+
+/* Copy one array of an orientation's device layout as built on the host
+ * (between create and bind; DVMAT_E_STATE after bind), for inspection.
+ * orientation 0 = dose, 1 = price; which: 0 = block-row pointers (int64),
+ * 1 = column indices (int32 for CSR, uint16 panel-local for panels), 2 =
+ * values (storage type, B per position), 3 = work units (int32 first block
+ * rows), 4 = row at each stored position (int32; empty for natural order),
+ * 5 = panel column lists (int32), 6 = panel offsets into them (int64), 7 =
+ * first work unit of each panel (int32).  *size receives the array's byte
+ * size; dst (host, may be NULL to query) must hold cap >= *size bytes. */
+dvmat_status dvmat_ddc_layout_array(dvmat_ddc ddc, int32_t orientation, int32_t which, void* dst, size_t cap,
+                                    size_t* size);
 /* Copy the staged matrices into the caller's device workspace (>= info.
  * workspace_bytes, 256-byte aligned), synchronise the stream and release the
  * host staging.  Binding once is allowed; DVMAT_E_STATE on a second bind,

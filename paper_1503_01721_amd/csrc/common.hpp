@@ -37,6 +37,9 @@ struct KernelCfg {
 };
 KernelCfg initial_kernel_cfg();
 
+// Block kernels: row, stream and pipe read the CSR layout, panel the panel layout.
+enum Kind { KIND_ROW = 0, KIND_STREAM = 1, KIND_PIPE = 2, KIND_PANEL = 3 };
+
 dvmat_status set_error(dvmat_status code, const char* fmt, ...);
 dvmat_status check_hip(hipError_t e, const char* what);
 
@@ -54,6 +57,14 @@ struct CsrDev {
     const void* val = nullptr;         // [block entries * B] of value_bytes
     const int32_t* blocks = nullptr;   // [n_blocks + 1] first block row of each work unit
     const int32_t* perm = nullptr;     // [n_rows] row stored at each position, or nullptr (natural order)
+    // panel layout (layout 1): col is unused, col16 holds panel-local columns
+    int layout = 0;
+    int64_t n_panels = 0;
+    int64_t max_panel_cols = 0;
+    const uint16_t* col16 = nullptr;   // [block entries] position in the panel's column list
+    const int32_t* ulist = nullptr;    // concatenated sorted column lists of the panels
+    const int64_t* panel_u = nullptr;  // [n_panels + 1] offsets into ulist
+    const int32_t* panel_units = nullptr;  // [n_panels + 1] first work unit of each panel
 };
 
 // Host staging of one orientation before bind.
@@ -67,6 +78,12 @@ struct CsrHost {
     std::vector<int32_t> blocks;
     std::vector<int32_t> perm;         // empty: natural row order
     int64_t nonempty = 0;
+    int layout = 0;
+    std::vector<uint16_t> col16;
+    std::vector<int32_t> ulist;
+    std::vector<int64_t> panel_u;
+    std::vector<int32_t> panel_units;
+    int64_t max_panel_cols = 0;
 };
 
 }  // namespace dvmat
@@ -88,7 +105,10 @@ struct dvmat_ddc_s {
     // workspace layout offsets
     size_t off_dose_rowptr = 0, off_dose_col = 0, off_dose_val = 0, off_dose_blocks = 0, off_dose_perm = 0;
     size_t off_price_rowptr = 0, off_price_col = 0, off_price_val = 0, off_price_blocks = 0, off_price_perm = 0;
+    size_t off_dose_ulist = 0, off_dose_panel_u = 0, off_dose_panel_units = 0;
+    size_t off_price_ulist = 0, off_price_panel_u = 0, off_price_panel_units = 0;
     size_t off_scale = 0, off_xs = 0;
+    int64_t dose_panel_cols_total = 0, price_panel_cols_total = 0;
 };
 
 struct dvmat_obj_s {

@@ -76,6 +76,14 @@ static uint16_t float_to_bf16_bits(float f) {
     return (uint16_t)(u >> 16);
 }
 
+// Layout options of one orientation (from dvmat_build_opts).
+struct OrientOpts {
+    int layout = 0;
+    int row_order = 0;
+    int32_t grid[3] = {0, 0, 0};
+    int32_t tile[3] = {0, 0, 0};
+};
+
 // Rows of one orientation, sorted by column with duplicates summed: row r's
 // entries sit at [start[r], start[r] + len[r]) of col/val.
 struct SortedRows {
@@ -183,23 +191,194 @@ static dvmat_status sort_rows(int64_t n_rows, int64_t nnz, const int32_t* rk, co
 // chunk: n entries) sorted entry l + q*(n/4) is stored at position 4*l + q: a
 // lane's 16-byte column load then holds entries l, l+n/4, l+2n/4, l+3n/4 and
 // each gather instruction of a wave covers n/4 consecutive sorted columns.
-static dvmat_status build_blocked(const SortedRows& sr, int64_t n_rows, int B, bool interleave, int64_t unit_cap,
-                                  bool order_by_first_col, CsrHost& out, std::vector<float>& fvalb) {
+// Row order of one orientation: position p holds row perm[p] (empty: natural
+// order).  Tiles of a row grid (panel layout) keep each tile's rows together
+// in natural order; otherwise rows may be sorted by their first column (empty
+// rows last) so rows touching the same part of the input vector run together.
+// tile_of_pos: the tile of the row at each position (empty without a grid).
+static dvmat_status order_rows(const SortedRows& sr, int64_t n_rows, int B, const OrientOpts& oo,
+                               std::vector<int32_t>& perm, std::vector<int32_t>& tile_of_pos) {
+    perm.clear();
+    tile_of_pos.clear();
+    const int64_t g0 = oo.grid[0], g1 = oo.grid[1], g2 = oo.grid[2];
+    try {
+        if (oo.layout == 1 && (g0 | g1 | g2) != 0) {
+            if (g0 < 1 || g1 < 1 || g2 < 1 || g0 * g1 * g2 != n_rows)
+                return set_error(DVMAT_E_ARG, "row grid %lld x %lld x %lld does not match %lld rows", (long long)g0,
+                                 (long long)g1, (long long)g2, (long long)n_rows);
+            const int64_t t0 = oo.tile[0], t1 = oo.tile[1], t2 = oo.tile[2];
+            if (t0 < 1 || t1 < 1 || t2 < 1 || t0 % B != 0)
+                return set_error(DVMAT_E_ARG, "tile %lld x %lld x %lld: positive, first extent a multiple of %d",
+                                 (long long)t0, (long long)t1, (long long)t2, B);
+            const int64_t T0 = (g0 + t0 - 1) / t0, T1 = (g1 + t1 - 1) / t1, T2 = (g2 + t2 - 1) / t2;
+            if (T0 * T1 * T2 >= (int64_t(1) << 31)) return set_error(DVMAT_E_ARG, "too many tiles");
+            std::vector<int32_t> tile(n_rows);
+            parallel_for(n_rows, [&](int64_t a, int64_t b, int) {
+                for (int64_t r = a; r < b; ++r) {
+                    const int64_t i = r % g0, j = (r / g0) % g1, k = r / (g0 * g1);
+                    tile[r] = (int32_t)(((k / t2) * T1 + j / t1) * T0 + i / t0);
+                }
+            });
+            perm.resize(n_rows);
+            std::iota(perm.begin(), perm.end(), 0);
+            std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return tile[a] < tile[b]; });
+            tile_of_pos.resize(n_rows);
+            for (int64_t p = 0; p < n_rows; ++p) tile_of_pos[p] = tile[perm[p]];
+        } else if (oo.row_order == 1) {
+            perm.resize(n_rows);
+            std::iota(perm.begin(), perm.end(), 0);
+            auto key = [&](int32_t r) -> int64_t { return sr.len[r] > 0 ? sr.col[sr.start[r]] : INT64_MAX; };
+            std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return key(a) < key(b); });
+        }
+    } catch (const std::bad_alloc&) {
+        return set_error(DVMAT_E_NOMEM, "host allocation failed while ordering %lld rows", (long long)n_rows);
+    }
+    return DVMAT_OK;
+}
+
+// Work units: consecutive block rows [b0, b1) up to a stored-value budget and
+// kBlockRowsMax block rows; a longer block row is a unit of its own.
+static void cut_units(const CsrHost& out, int64_t b0, int64_t b1, int64_t unit_cap, std::vector<int32_t>& blocks) {
+    int64_t acc = 0;
+    int32_t rows_in = 0;
+    for (int64_t br = b0; br < b1; ++br) {
+        const int64_t lp = (out.rowptr[br + 1] - out.rowptr[br]) * out.B;
+        if (rows_in > 0 && (acc + lp > unit_cap || rows_in >= kBlockRowsMax)) {
+            blocks.push_back((int32_t)br);
+            acc = 0;
+            rows_in = 0;
+        }
+        acc += lp;
+        rows_in++;
+    }
+    blocks.push_back((int32_t)b1);
+}
+
+// Panels over the block rows (panel layout): a panel is a run of block rows of
+// one tile whose columns number at most cap; each gets its sorted column list
+// and every stored column index becomes the position in that list.  Returns
+// DVMAT_E_SHAPE (no error text) when a single block row has more than cap
+// columns: the caller then keeps the CSR layout.
+static dvmat_status build_panels(CsrHost& out, int64_t n_cols, const std::vector<int32_t>& tile_of_pos, int64_t cap,
+                                 int64_t unit_cap) {
+    const int64_t n_br = out.n_brows;
+    const int B = out.B;
+    auto tile_of_br = [&](int64_t br) -> int64_t { return tile_of_pos.empty() ? 0 : tile_of_pos[br * B]; };
+    // tiles: runs of block rows with the same tile id
+    std::vector<int64_t> tstart;
+    for (int64_t br = 0; br < n_br; ++br)
+        if (br == 0 || tile_of_br(br) != tile_of_br(br - 1)) tstart.push_back(br);
+    tstart.push_back(n_br);
+    const int64_t n_tiles = (int64_t)tstart.size() - 1;
+    // greedy cut of each tile (parallel over tiles).  Per thread, mark[c] holds
+    // the id of the last panel that took column c and seen[c] the last block
+    // row that looked at it; ids are global block row indices, so no clearing.
+    std::vector<std::vector<int64_t>> cuts(n_tiles);
+    std::atomic<int> too_wide(0);
+    const int T = host_threads();
+    std::vector<std::vector<int64_t>> marks(T), seens(T);
+    parallel_for(n_tiles, [&](int64_t a, int64_t b, int t) {
+        std::vector<int64_t>& mark = marks[t];
+        std::vector<int64_t>& seen = seens[t];
+        if (mark.empty()) {
+            mark.assign(n_cols, -1);
+            seen.assign(n_cols, -1);
+        }
+        for (int64_t ti = a; ti < b; ++ti) {
+            int64_t pid = tstart[ti];         // panel id: its first block row
+            int64_t count = 0;
+            cuts[ti].push_back(tstart[ti]);
+            for (int64_t br = tstart[ti]; br < tstart[ti + 1]; ++br) {
+                const int32_t* c = out.col.data() + out.rowptr[br];
+                const int64_t n = out.rowptr[br + 1] - out.rowptr[br];
+                int64_t fresh = 0;                // distinct columns of this block row new to the panel
+                for (int64_t k = 0; k < n; ++k)
+                    if (mark[c[k]] != pid && seen[c[k]] != br) {
+                        seen[c[k]] = br;
+                        ++fresh;
+                    }
+                if (count + fresh > cap && br > pid) {
+                    // close the panel before this block row; the row starts the next one
+                    cuts[ti].push_back(br);
+                    pid = br;
+                    count = 0;
+                    fresh = 0;
+                    for (int64_t k = 0; k < n; ++k)
+                        if (mark[c[k]] != pid) {
+                            mark[c[k]] = pid;
+                            ++fresh;
+                        }
+                } else {
+                    for (int64_t k = 0; k < n; ++k) mark[c[k]] = pid;
+                }
+                count += fresh;
+                if (count > cap) {                // a single block row wider than the budget
+                    too_wide.store(1);
+                    return;
+                }
+            }
+        }
+    });
+    marks.clear();
+    seens.clear();
+    if (too_wide.load()) return DVMAT_E_SHAPE;
+    std::vector<int64_t> pstart;
+    for (auto& v : cuts)
+        for (int64_t x : v) pstart.push_back(x);
+    pstart.push_back(n_br);
+    const int64_t n_pan = (int64_t)pstart.size() - 1;
+    // column lists and local indices (parallel over panels)
+    std::vector<std::vector<int32_t>> ul(n_pan);
+    out.col16.assign(out.col.size(), 0);
+    std::vector<std::vector<int32_t>> loc(T);
+    parallel_for(n_pan, [&](int64_t a, int64_t b, int t) {
+        std::vector<int32_t>& lo = loc[t];
+        if (lo.empty()) lo.assign(n_cols, 0);
+        for (int64_t p = a; p < b; ++p) {
+            const int64_t e0 = out.rowptr[pstart[p]], e1 = out.rowptr[pstart[p + 1]];
+            std::vector<int32_t>& u = ul[p];
+            u.assign(out.col.begin() + e0, out.col.begin() + e1);
+            std::sort(u.begin(), u.end());
+            u.erase(std::unique(u.begin(), u.end()), u.end());
+            for (size_t i = 0; i < u.size(); ++i) lo[u[i]] = (int32_t)i;
+            for (int64_t k = e0; k < e1; ++k) out.col16[k] = (uint16_t)lo[out.col[k]];
+        }
+    });
+    loc.clear();
+    out.panel_u.assign(n_pan + 1, 0);
+    out.max_panel_cols = 0;
+    for (int64_t p = 0; p < n_pan; ++p) {
+        out.panel_u[p + 1] = out.panel_u[p] + (int64_t)ul[p].size();
+        out.max_panel_cols = std::max<int64_t>(out.max_panel_cols, (int64_t)ul[p].size());
+    }
+    out.ulist.resize(out.panel_u[n_pan]);
+    parallel_for(n_pan, [&](int64_t a, int64_t b, int) {
+        for (int64_t p = a; p < b; ++p) std::copy(ul[p].begin(), ul[p].end(), out.ulist.begin() + out.panel_u[p]);
+    });
+    // work units inside each panel
+    out.blocks.clear();
+    out.blocks.push_back(0);
+    out.panel_units.assign(1, 0);
+    for (int64_t p = 0; p < n_pan; ++p) {
+        if (pstart[p + 1] > pstart[p]) cut_units(out, pstart[p], pstart[p + 1], unit_cap, out.blocks);
+        out.panel_units.push_back((int32_t)out.blocks.size() - 1);
+    }
+    out.layout = 1;
+    return DVMAT_OK;
+}
+
+static dvmat_status build_blocked(const SortedRows& sr, int64_t n_rows, int64_t n_cols, int B, bool interleave,
+                                  int64_t unit_cap, const OrientOpts& oo, int64_t panel_cols, CsrHost& out,
+                                  std::vector<float>& fvalb) {
+    std::vector<int32_t> tile_of_pos;
+    dvmat_status st0 = order_rows(sr, n_rows, B, oo, out.perm, tile_of_pos);
+    if (st0) return st0;
     try {
         const int64_t n_br = (n_rows + B - 1) / B;
         out.n_rows = n_rows;
         out.B = B;
         out.n_brows = n_br;
-        // optional row order: position p holds row perm[p]; rows sorted by their
-        // first column (empty rows last), so rows touching the same part of the
-        // input vector are processed together
-        out.perm.clear();
-        if (order_by_first_col) {
-            out.perm.resize(n_rows);
-            std::iota(out.perm.begin(), out.perm.end(), 0);
-            auto key = [&](int32_t r) -> int64_t { return sr.len[r] > 0 ? sr.col[sr.start[r]] : INT64_MAX; };
-            std::stable_sort(out.perm.begin(), out.perm.end(), [&](int32_t a, int32_t b) { return key(a) < key(b); });
-        }
+        out.layout = 0;
         auto row_at = [&](int64_t pos) -> int64_t { return out.perm.empty() ? pos : out.perm[pos]; };
         std::vector<int64_t> uni(n_br, 0);
         // union size of each block row (B-way merge of sorted column lists)
@@ -270,23 +449,19 @@ static dvmat_status build_blocked(const SortedRows& sr, int64_t n_rows, int B, b
                 }
             }
         });
-        // work units: consecutive block rows up to a stored-value budget and
-        // kBlockRowsMax block rows; a longer block row is a unit of its own
         out.blocks.clear();
         out.blocks.push_back(0);
-        int64_t acc = 0;
-        int32_t rows_in = 0;
-        for (int64_t br = 0; br < n_br; ++br) {
-            const int64_t lp = (out.rowptr[br + 1] - out.rowptr[br]) * B;
-            if (rows_in > 0 && (acc + lp > unit_cap || rows_in >= kBlockRowsMax)) {
-                out.blocks.push_back((int32_t)br);
-                acc = 0;
-                rows_in = 0;
-            }
-            acc += lp;
-            rows_in++;
+        bool csr = oo.layout != 1;
+        if (!csr) {
+            const dvmat_status sp = build_panels(out, n_cols, tile_of_pos, panel_cols, unit_cap);
+            if (sp == DVMAT_E_SHAPE) csr = true;             // a block row wider than the panel budget
+            else if (sp) return sp;
         }
-        out.blocks.push_back((int32_t)n_br);
+        if (csr) {
+            out.layout = 0;
+            out.blocks.assign(1, 0);
+            if (n_br > 0) cut_units(out, 0, n_br, unit_cap, out.blocks);
+        }
         out.nonempty = 0;
         for (int64_t r = 0; r < n_rows; ++r) out.nonempty += sr.len[r] > 0;
     } catch (const std::bad_alloc&) {
@@ -299,9 +474,11 @@ static dvmat_status build_blocked(const SortedRows& sr, int64_t n_rows, int B, b
 // Store the values in the requested type.  16-bit storage keeps v / s_j with
 // s_j the scale of the value's beamlet: the column for the dose orientation,
 // the row for the price orientation.
+// The global column indices (h.col) are still present here in both layouts;
+// the panel layout drops them afterwards.
 static void encode_values(CsrHost& h, const std::vector<float>& fvalb, int32_t storage,
                           const std::vector<float>& scale, bool beamlet_is_row) {
-    const int64_t ne = (int64_t)h.col.size();
+    const int64_t ne = h.rowptr.empty() ? 0 : h.rowptr[h.n_brows];
     const int B = h.B;
     if (storage == DVMAT_F32) {
         h.val.resize(ne * B * 4);
@@ -348,6 +525,14 @@ dvmat_status dvmat_ddc_default_opts(int32_t storage, dvmat_build_opts* opts) {
     opts->unit_entries = 2048;
     opts->dose_row_order = 0;
     opts->price_row_order = 1;
+    opts->dose_layout = 0;
+    opts->price_layout = 0;
+    for (int i = 0; i < 3; ++i) {
+        opts->dose_grid[i] = opts->price_grid[i] = 0;
+        opts->dose_tile[i] = opts->price_tile[i] = 0;
+    }
+    opts->panel_cols = 8192;
+    if (const char* e = std::getenv("DVMAT_PANEL_COLS")) opts->panel_cols = std::atoi(e);
     if (const char* e = std::getenv("DVMAT_DOSE_ORDER")) opts->dose_row_order = std::atoi(e);
     if (const char* e = std::getenv("DVMAT_PRICE_ORDER")) opts->price_row_order = std::atoi(e);
     if (const char* e = std::getenv("DVMAT_DOSE_B")) opts->dose_block_rows = std::atoi(e);
@@ -375,7 +560,8 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
     auto okB = [](int b) { return b == 1 || b == 2 || b == 4; };
     if (!okB(o.dose_block_rows) || !okB(o.price_block_rows) || (o.interleave != 0 && o.interleave != 1) ||
         o.unit_entries < 4 || o.unit_entries > (1 << 24) || (o.dose_row_order != 0 && o.dose_row_order != 1) ||
-        (o.price_row_order != 0 && o.price_row_order != 1))
+        (o.price_row_order != 0 && o.price_row_order != 1) || (o.dose_layout != 0 && o.dose_layout != 1) ||
+        (o.price_layout != 0 && o.price_layout != 1) || o.panel_cols < 1 || o.panel_cols > 65536)
         return set_error(DVMAT_E_ARG, "dvmat_ddc_create: bad build options (block rows %d/%d, interleave %d, unit %d)",
                          o.dose_block_rows, o.price_block_rows, o.interleave, o.unit_entries);
     *out = nullptr;
@@ -422,6 +608,17 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
     d->value_bytes = storage == DVMAT_F32 ? 4 : 2;
     d->opts = o;
     dvmat_status st = DVMAT_OK;
+    OrientOpts dose_oo, price_oo;
+    dose_oo.layout = o.dose_layout;
+    dose_oo.row_order = o.dose_row_order;
+    price_oo.layout = o.price_layout;
+    price_oo.row_order = o.price_row_order;
+    for (int i = 0; i < 3; ++i) {
+        dose_oo.grid[i] = o.dose_grid[i];
+        dose_oo.tile[i] = o.dose_tile[i];
+        price_oo.grid[i] = o.price_grid[i];
+        price_oo.tile[i] = o.price_tile[i];
+    }
     {
         // dose orientation: rows = voxels, columns = beamlets
         SortedRows sr;
@@ -448,7 +645,7 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
             for (auto& s : d->host_scale)
                 if (!(s > 0.0f)) s = 1.0f;
         }
-        if ((st = build_blocked(sr, n_vox, o.dose_block_rows, o.interleave != 0, o.unit_entries, o.dose_row_order == 1,
+        if ((st = build_blocked(sr, n_vox, n_bl, o.dose_block_rows, o.interleave != 0, o.unit_entries, dose_oo, o.panel_cols,
                                 d->host_dose, fvalb))) {
             delete d;
             return st;
@@ -458,13 +655,14 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
         std::vector<int32_t>().swap(sr.col);
         std::vector<float>().swap(sr.val);
         encode_values(d->host_dose, fvalb, storage, d->host_scale, false);
+        if (d->host_dose.layout == 1) std::vector<int32_t>().swap(d->host_dose.col);
     }
     {
         // price orientation: rows = beamlets, columns = voxels
         SortedRows sr;
         std::vector<float> fvalb;
         if ((st = sort_rows(n_bl, nnz, col_bl, row_vox, val, sr))) { delete d; return st; }
-        if ((st = build_blocked(sr, n_bl, o.price_block_rows, o.interleave != 0, o.unit_entries, o.price_row_order == 1,
+        if ((st = build_blocked(sr, n_bl, n_vox, o.price_block_rows, o.interleave != 0, o.unit_entries, price_oo, o.panel_cols,
                                 d->host_price, fvalb))) {
             delete d;
             return st;
@@ -472,6 +670,7 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
         std::vector<int32_t>().swap(sr.col);
         std::vector<float>().swap(sr.val);
         encode_values(d->host_price, fvalb, storage, d->host_scale, true);
+        if (d->host_price.layout == 1) std::vector<int32_t>().swap(d->host_price.col);
     }
 
     // device workspace layout
@@ -480,15 +679,21 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
     const CsrHost& hd = d->host_dose;
     const CsrHost& hp = d->host_price;
     d->off_dose_rowptr = take(hd.rowptr.size() * 8);
-    d->off_dose_col = take(hd.col.size() * 4);
+    d->off_dose_col = take(hd.layout == 1 ? hd.col16.size() * 2 : hd.col.size() * 4);
     d->off_dose_val = take(hd.val.size());
     d->off_dose_blocks = take(hd.blocks.size() * 4);
     d->off_dose_perm = take(hd.perm.size() * 4);
+    d->off_dose_ulist = take(hd.ulist.size() * 4);
+    d->off_dose_panel_u = take(hd.panel_u.size() * 8);
+    d->off_dose_panel_units = take(hd.panel_units.size() * 4);
     d->off_price_rowptr = take(hp.rowptr.size() * 8);
-    d->off_price_col = take(hp.col.size() * 4);
+    d->off_price_col = take(hp.layout == 1 ? hp.col16.size() * 2 : hp.col.size() * 4);
     d->off_price_val = take(hp.val.size());
     d->off_price_blocks = take(hp.blocks.size() * 4);
     d->off_price_perm = take(hp.perm.size() * 4);
+    d->off_price_ulist = take(hp.ulist.size() * 4);
+    d->off_price_panel_u = take(hp.panel_u.size() * 8);
+    d->off_price_panel_units = take(hp.panel_units.size() * 4);
     if (storage != DVMAT_F32) {
         d->off_scale = take(n_bl * 4);
         d->off_xs = take(n_bl * 4 * kMaxRhs);
@@ -496,12 +701,22 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
     d->ws_bytes = std::max<size_t>(off, kAlign);
     d->dose.n_rows = n_vox;
     d->dose.B = hd.B;
-    d->dose.nnz_pad = (int64_t)hd.col.size() * hd.B;
+    d->dose.nnz_pad = (int64_t)(hd.layout == 1 ? hd.col16.size() : hd.col.size()) * hd.B;
+    d->dose.layout = hd.layout;
+    d->dose.n_panels = hd.layout == 1 ? (int64_t)hd.panel_u.size() - 1 : 0;
+    d->dose.max_panel_cols = hd.max_panel_cols;
+    d->dose_panel_cols_total = hd.ulist.size();
     d->dose.n_blocks = (int64_t)hd.blocks.size() - 1;
     d->dose.nonempty = hd.nonempty;
     d->price.n_rows = n_bl;
     d->price.B = hp.B;
-    d->price.nnz_pad = (int64_t)hp.col.size() * hp.B;
+    d->price.nnz_pad = (int64_t)(hp.layout == 1 ? hp.col16.size() : hp.col.size()) * hp.B;
+    d->price.layout = hp.layout;
+    d->price.n_panels = hp.layout == 1 ? (int64_t)hp.panel_u.size() - 1 : 0;
+    if (hd.layout == 1) d->dose_cfg.kind = KIND_PANEL;
+    if (hp.layout == 1) d->price_cfg.kind = KIND_PANEL;
+    d->price.max_panel_cols = hp.max_panel_cols;
+    d->price_panel_cols_total = hp.ulist.size();
     d->price.n_blocks = (int64_t)hp.blocks.size() - 1;
     d->price.nonempty = hp.nonempty;
     *out = d;
@@ -532,6 +747,14 @@ dvmat_status dvmat_ddc_info(dvmat_ddc d, dvmat_ddc_info_t* info) {
     info->price_block_rows = d->price.B;
     info->dose_row_order = d->opts.dose_row_order;
     info->price_row_order = d->opts.price_row_order;
+    info->dose_layout = d->dose.layout;
+    info->price_layout = d->price.layout;
+    info->dose_panels = d->dose.n_panels;
+    info->price_panels = d->price.n_panels;
+    info->dose_panel_cols = d->dose.max_panel_cols;
+    info->price_panel_cols = d->price.max_panel_cols;
+    info->dose_panel_cols_total = d->dose_panel_cols_total;
+    info->price_panel_cols_total = d->price_panel_cols_total;
     return DVMAT_OK;
 }
 
@@ -552,12 +775,26 @@ dvmat_status dvmat_ddc_bind(dvmat_ddc d, void* ws, size_t bytes, dvmat_stream st
     const CsrHost& hp = d->host_price;
     dvmat_status st = DVMAT_OK;
     if ((st = up(d->off_dose_rowptr, hd.rowptr.data(), hd.rowptr.size() * 8))) return st;
-    if ((st = up(d->off_dose_col, hd.col.data(), hd.col.size() * 4))) return st;
+    if (hd.layout == 1) {
+        if ((st = up(d->off_dose_col, hd.col16.data(), hd.col16.size() * 2))) return st;
+        if ((st = up(d->off_dose_ulist, hd.ulist.data(), hd.ulist.size() * 4))) return st;
+        if ((st = up(d->off_dose_panel_u, hd.panel_u.data(), hd.panel_u.size() * 8))) return st;
+        if ((st = up(d->off_dose_panel_units, hd.panel_units.data(), hd.panel_units.size() * 4))) return st;
+    } else if ((st = up(d->off_dose_col, hd.col.data(), hd.col.size() * 4))) {
+        return st;
+    }
     if ((st = up(d->off_dose_val, hd.val.data(), hd.val.size()))) return st;
     if ((st = up(d->off_dose_blocks, hd.blocks.data(), hd.blocks.size() * 4))) return st;
     if ((st = up(d->off_dose_perm, hd.perm.data(), hd.perm.size() * 4))) return st;
     if ((st = up(d->off_price_rowptr, hp.rowptr.data(), hp.rowptr.size() * 8))) return st;
-    if ((st = up(d->off_price_col, hp.col.data(), hp.col.size() * 4))) return st;
+    if (hp.layout == 1) {
+        if ((st = up(d->off_price_col, hp.col16.data(), hp.col16.size() * 2))) return st;
+        if ((st = up(d->off_price_ulist, hp.ulist.data(), hp.ulist.size() * 4))) return st;
+        if ((st = up(d->off_price_panel_u, hp.panel_u.data(), hp.panel_u.size() * 8))) return st;
+        if ((st = up(d->off_price_panel_units, hp.panel_units.data(), hp.panel_units.size() * 4))) return st;
+    } else if ((st = up(d->off_price_col, hp.col.data(), hp.col.size() * 4))) {
+        return st;
+    }
     if ((st = up(d->off_price_val, hp.val.data(), hp.val.size()))) return st;
     if ((st = up(d->off_price_blocks, hp.blocks.data(), hp.blocks.size() * 4))) return st;
     if ((st = up(d->off_price_perm, hp.perm.data(), hp.perm.size() * 4))) return st;
@@ -565,12 +802,24 @@ dvmat_status dvmat_ddc_bind(dvmat_ddc d, void* ws, size_t bytes, dvmat_stream st
         if ((st = up(d->off_scale, d->host_scale.data(), d->host_scale.size() * 4))) return st;
     if ((st = check_hip(hipStreamSynchronize(s), "dvmat_ddc_bind: synchronize"))) return st;
     d->dose.rowptr = reinterpret_cast<const int64_t*>(base + d->off_dose_rowptr);
-    d->dose.col = reinterpret_cast<const int32_t*>(base + d->off_dose_col);
+    d->dose.col = hd.layout == 1 ? nullptr : reinterpret_cast<const int32_t*>(base + d->off_dose_col);
+    if (hd.layout == 1) {
+        d->dose.col16 = reinterpret_cast<const uint16_t*>(base + d->off_dose_col);
+        d->dose.ulist = reinterpret_cast<const int32_t*>(base + d->off_dose_ulist);
+        d->dose.panel_u = reinterpret_cast<const int64_t*>(base + d->off_dose_panel_u);
+        d->dose.panel_units = reinterpret_cast<const int32_t*>(base + d->off_dose_panel_units);
+    }
     d->dose.val = base + d->off_dose_val;
     d->dose.blocks = reinterpret_cast<const int32_t*>(base + d->off_dose_blocks);
     d->dose.perm = hd.perm.empty() ? nullptr : reinterpret_cast<const int32_t*>(base + d->off_dose_perm);
     d->price.rowptr = reinterpret_cast<const int64_t*>(base + d->off_price_rowptr);
-    d->price.col = reinterpret_cast<const int32_t*>(base + d->off_price_col);
+    d->price.col = hp.layout == 1 ? nullptr : reinterpret_cast<const int32_t*>(base + d->off_price_col);
+    if (hp.layout == 1) {
+        d->price.col16 = reinterpret_cast<const uint16_t*>(base + d->off_price_col);
+        d->price.ulist = reinterpret_cast<const int32_t*>(base + d->off_price_ulist);
+        d->price.panel_u = reinterpret_cast<const int64_t*>(base + d->off_price_panel_u);
+        d->price.panel_units = reinterpret_cast<const int32_t*>(base + d->off_price_panel_units);
+    }
     d->price.val = base + d->off_price_val;
     d->price.blocks = reinterpret_cast<const int32_t*>(base + d->off_price_blocks);
     d->price.perm = hp.perm.empty() ? nullptr : reinterpret_cast<const int32_t*>(base + d->off_price_perm);
@@ -582,6 +831,36 @@ dvmat_status dvmat_ddc_bind(dvmat_ddc d, void* ws, size_t bytes, dvmat_stream st
     d->host_dose = CsrHost();
     d->host_price = CsrHost();
     d->bound = true;
+    return DVMAT_OK;
+}
+
+dvmat_status dvmat_ddc_layout_array(dvmat_ddc d, int32_t orientation, int32_t which, void* dst, size_t cap,
+                                    size_t* size) {
+    if (!d || !size) return set_error(DVMAT_E_ARG, "dvmat_ddc_layout_array: NULL argument");
+    if (d->bound) return set_error(DVMAT_E_STATE, "dvmat_ddc_layout_array: the host layout is released at bind");
+    if (orientation != 0 && orientation != 1)
+        return set_error(DVMAT_E_ARG, "dvmat_ddc_layout_array: orientation %d", orientation);
+    const CsrHost& h = orientation == 0 ? d->host_dose : d->host_price;
+    const void* src = nullptr;
+    size_t n = 0;
+    switch (which) {
+        case 0: src = h.rowptr.data(); n = h.rowptr.size() * 8; break;
+        case 1:
+            if (h.layout == 1) { src = h.col16.data(); n = h.col16.size() * 2; }
+            else { src = h.col.data(); n = h.col.size() * 4; }
+            break;
+        case 2: src = h.val.data(); n = h.val.size(); break;
+        case 3: src = h.blocks.data(); n = h.blocks.size() * 4; break;
+        case 4: src = h.perm.data(); n = h.perm.size() * 4; break;
+        case 5: src = h.ulist.data(); n = h.ulist.size() * 4; break;
+        case 6: src = h.panel_u.data(); n = h.panel_u.size() * 8; break;
+        case 7: src = h.panel_units.data(); n = h.panel_units.size() * 4; break;
+        default: return set_error(DVMAT_E_ARG, "dvmat_ddc_layout_array: which %d", which);
+    }
+    *size = n;
+    if (!dst) return DVMAT_OK;
+    if (cap < n) return set_error(DVMAT_E_ARG, "dvmat_ddc_layout_array: %zu bytes < %zu", cap, n);
+    if (n) std::memcpy(dst, src, n);
     return DVMAT_OK;
 }
 

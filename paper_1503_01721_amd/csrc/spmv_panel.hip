@@ -1,0 +1,135 @@
+// Sparse products on the panel layout.
+//
+// The rows of one orientation are grouped into panels (a tile of the voxel
+// grid for the dose; neighbouring beamlets at neighbouring gantry angles for
+// the price).  Each panel lists the distinct columns its rows touch, and the
+// stored column indices are positions in that list (16 bits).  A workgroup
+// takes one panel at a time: it copies the panel's slice of the input vector
+// into LDS (one coalesced pass over the sorted list), then its four waves run
+// the block-row arithmetic of the CSR row kernel with gathers served by LDS.
+// The gathers thus leave the L1/L2 request path, which bounds the CSR kernels:
+// there a gathered value costs a cache-line request of its own, here a staged
+// value serves tens of products (Sec. 2.2.2 gives the products; this layout is
+// the GPU mapping of them).
+//
+// Right-hand sides beyond what LDS holds are processed in chunks, each chunk
+// one launch over the matrix.
+#include "spmv_device.hpp"
+
+#include <algorithm>
+
+namespace dvmat {
+
+struct PanelParams {
+    const float* x;             // input vector, ldx values per column (chunk offset applied)
+    int64_t ldx;
+    const uint16_t* col16;
+    const int32_t* ulist;
+    const int64_t* panel_u;
+    const int32_t* panel_units;
+    int64_t n_panels;
+};
+
+template <int ST, int R, int EPI, int B>
+__global__ __launch_bounds__(kSpmvThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void spmv_panel_kernel(
+    SpmvParams P, PanelParams Q) {
+    constexpr int kWaves = kSpmvThreads / kWaveSize;
+    extern __shared__ float xs[];
+    __shared__ f32x4 s_tab[(EPI == EPI_OBJ || EPI == EPI_CURV) ? 256 : 1];
+    if constexpr (EPI == EPI_OBJ || EPI == EPI_CURV) {
+        static_assert(kSpmvThreads == 256, "one table row per thread");
+        s_tab[threadIdx.x] = reinterpret_cast<const f32x4*>(P.table)[threadIdx.x];
+    }
+    const int lane = threadIdx.x & (kWaveSize - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWaveSize);
+    float fpart[R];
+#pragma unroll
+    for (int h = 0; h < R; ++h) fpart[h] = 0.0f;
+    double cpart = 0.0;
+    for (int64_t p = blockIdx.x; p < Q.n_panels; p += gridDim.x) {
+        const int64_t u0 = Q.panel_u[p];
+        const int nu = (int)(Q.panel_u[p + 1] - u0);
+        __syncthreads();                              // the previous panel's gathers are done
+        for (int i = threadIdx.x; i < nu; i += kSpmvThreads) {
+            const int64_t j = Q.ulist[u0 + i];
+#pragma unroll
+            for (int h = 0; h < R; ++h) xs[i * R + h] = Q.x[j * Q.ldx + h];
+        }
+        __syncthreads();
+        const int q0 = Q.panel_units[p], q1 = Q.panel_units[p + 1];
+        for (int q = q0 + wid; q < q1; q += kWaves)
+            block_rows<ST, R, EPI, false, B, true>(P, P.blocks[q], P.blocks[q + 1], lane, s_tab, fpart, cpart, xs,
+                                                   Q.col16);
+    }
+    workgroup_partials<R, EPI>(P, lane, wid, fpart, cpart);
+}
+
+// Largest LDS slice a launch uses (the objective table and partials take the rest).
+constexpr size_t kPanelLdsBytes = 60 * 1024;
+
+template <int ST, int R, int EPI>
+static void launch_chunk(int B, int nwg, size_t lds, const SpmvParams& P, const PanelParams& Q, hipStream_t s) {
+    dim3 grid(nwg), block(kSpmvThreads);
+    if (B == 4) hipLaunchKernelGGL((spmv_panel_kernel<ST, R, EPI, 4>), grid, block, lds, s, P, Q);
+    else if (B == 2) hipLaunchKernelGGL((spmv_panel_kernel<ST, R, EPI, 2>), grid, block, lds, s, P, Q);
+    else hipLaunchKernelGGL((spmv_panel_kernel<ST, R, EPI, 1>), grid, block, lds, s, P, Q);
+}
+
+template <int ST, int EPI>
+static void launch_chunk_r(int R, int B, int nwg, size_t lds, const SpmvParams& P, const PanelParams& Q,
+                           hipStream_t s) {
+    if constexpr (EPI == EPI_CURV) {
+        launch_chunk<ST, 1, EPI>(B, nwg, lds, P, Q, s);
+    } else {
+        if (R == 8) launch_chunk<ST, 8, EPI>(B, nwg, lds, P, Q, s);
+        else if (R == 4) launch_chunk<ST, 4, EPI>(B, nwg, lds, P, Q, s);
+        else if (R == 2) launch_chunk<ST, 2, EPI>(B, nwg, lds, P, Q, s);
+        else launch_chunk<ST, 1, EPI>(B, nwg, lds, P, Q, s);
+    }
+}
+
+template <int EPI>
+dvmat_status launch_panel(const KernelCfg& cfg, int storage, const CsrDev& c, const SpmvParams& P0, const float* x,
+                          int nrhs, hipStream_t s, int* nwg_out) {
+    const int64_t want = std::max(1, cfg.workgroups);
+    const int nwg = (int)std::max<int64_t>(1, std::min<int64_t>(want, c.n_panels));
+    *nwg_out = nwg;
+    if (c.n_panels == 0) return DVMAT_OK;
+    const size_t per_rhs = (size_t)std::max<int64_t>(c.max_panel_cols, 1) * sizeof(float);
+    if (per_rhs > kPanelLdsBytes)
+        return set_error(DVMAT_E_SHAPE, "panel of %lld columns exceeds the LDS slice", (long long)c.max_panel_cols);
+    PanelParams Q{};
+    Q.ldx = nrhs;
+    Q.col16 = c.col16;
+    Q.ulist = c.ulist;
+    Q.panel_u = c.panel_u;
+    Q.panel_units = c.panel_units;
+    Q.n_panels = c.n_panels;
+    for (int h0 = 0; h0 < nrhs;) {
+        int R = 8;
+        while (R > 1 && (R > nrhs - h0 || per_rhs * R > kPanelLdsBytes)) R >>= 1;
+        SpmvParams P = P0;
+        P.ld = nrhs;
+        if (P.y) P.y += h0;
+        if (P.g) P.g += h0;
+        if (P.partial) P.partial += h0;
+        Q.x = x + h0;
+        const size_t lds = per_rhs * R;
+        if (storage == DVMAT_F32) launch_chunk_r<DVMAT_F32, EPI>(R, c.B, nwg, lds, P, Q, s);
+        else if (storage == DVMAT_F16) launch_chunk_r<DVMAT_F16, EPI>(R, c.B, nwg, lds, P, Q, s);
+        else launch_chunk_r<DVMAT_BF16, EPI>(R, c.B, nwg, lds, P, Q, s);
+        h0 += R;
+    }
+    return check_hip(hipGetLastError(), "panel launch");
+}
+
+template dvmat_status launch_panel<EPI_PLAIN>(const KernelCfg&, int, const CsrDev&, const SpmvParams&, const float*,
+                                              int, hipStream_t, int*);
+template dvmat_status launch_panel<EPI_OBJ>(const KernelCfg&, int, const CsrDev&, const SpmvParams&, const float*, int,
+                                            hipStream_t, int*);
+template dvmat_status launch_panel<EPI_CURV>(const KernelCfg&, int, const CsrDev&, const SpmvParams&, const float*,
+                                             int, hipStream_t, int*);
+template dvmat_status launch_panel<EPI_SCALE>(const KernelCfg&, int, const CsrDev&, const SpmvParams&, const float*,
+                                              int, hipStream_t, int*);
+
+}  // namespace dvmat

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "lib", "libdvmat.so")
 
 F32, F16, BF16 = 0, 1, 2
 STORAGE = {"f32": F32, "f16": F16, "bf16": BF16}
-KERNEL_KINDS = ("row", "stream", "pipe")
+KERNEL_KINDS = ("row", "stream", "pipe", "panel")
 
 BB_REL_F, BB_SMALL_STEP, BB_MAX_ITER, BB_FALLBACK, BB_CONVERGED, BB_NONFINITE = 1, 2, 4, 8, 16, 32
 BB_STOP_MASK = BB_REL_F | BB_SMALL_STEP | BB_MAX_ITER | BB_CONVERGED | BB_NONFINITE
@@ -45,13 +45,28 @@ class DdcInfo(ctypes.Structure):
                 ("price_kernel", ctypes.c_int32), ("price_workgroups", ctypes.c_int32),
                 ("dose_tuned_ms", ctypes.c_float), ("price_tuned_ms", ctypes.c_float),
                 ("dose_block_rows", ctypes.c_int32), ("price_block_rows", ctypes.c_int32),
-                ("dose_row_order", ctypes.c_int32), ("price_row_order", ctypes.c_int32)]
+                ("dose_row_order", ctypes.c_int32), ("price_row_order", ctypes.c_int32),
+                ("dose_layout", ctypes.c_int32), ("price_layout", ctypes.c_int32),
+                ("dose_panels", ctypes.c_int64), ("price_panels", ctypes.c_int64),
+                ("dose_panel_cols", ctypes.c_int64), ("price_panel_cols", ctypes.c_int64),
+                ("dose_panel_cols_total", ctypes.c_int64), ("price_panel_cols_total", ctypes.c_int64)]
 
 
 class BuildOpts(ctypes.Structure):
     _fields_ = [("dose_block_rows", ctypes.c_int32), ("price_block_rows", ctypes.c_int32),
                 ("interleave", ctypes.c_int32), ("unit_entries", ctypes.c_int32),
-                ("dose_row_order", ctypes.c_int32), ("price_row_order", ctypes.c_int32)]
+                ("dose_row_order", ctypes.c_int32), ("price_row_order", ctypes.c_int32),
+                ("dose_layout", ctypes.c_int32), ("price_layout", ctypes.c_int32),
+                ("dose_grid", ctypes.c_int32 * 3), ("price_grid", ctypes.c_int32 * 3),
+                ("dose_tile", ctypes.c_int32 * 3), ("price_tile", ctypes.c_int32 * 3),
+                ("panel_cols", ctypes.c_int32)]
+
+
+# Panel tiles used when the grids are known: 8x8x8 voxels (dose); 4 beamlet
+# columns x 2 MLC rows x 8 control points (price).
+DOSE_TILE = (8, 8, 8)
+PRICE_TILE = (4, 2, 8)
+LAYOUTS = {"csr": 0, "panel": 1}
 
 
 class Geom(ctypes.Structure):
@@ -72,6 +87,7 @@ _SIGNATURES = {
     "dvmat_ddc_create": (_I32, [_I64, _I64, _I64, _P, _P, _P, _I32, ctypes.POINTER(_P)]),
     "dvmat_ddc_create_ex": (_I32, [_I64, _I64, _I64, _P, _P, _P, _I32, ctypes.POINTER(BuildOpts),
                                    ctypes.POINTER(_P)]),
+    "dvmat_ddc_layout_array": (_I32, [_P, _I32, _I32, _P, _SZ, ctypes.POINTER(_SZ)]),
     "dvmat_ddc_default_opts": (_I32, [_I32, ctypes.POINTER(BuildOpts)]),
     "dvmat_ddc_info": (_I32, [_P, ctypes.POINTER(DdcInfo)]),
     "dvmat_ddc_bind": (_I32, [_P, _P, _SZ, _P]),
@@ -187,7 +203,14 @@ class DDC:
 
     def __init__(self, row, col, val, n_vox: int, n_bl: int, storage: str = "f32", device="cuda",
                  dose_block_rows=None, price_block_rows=None, interleave=None, unit_entries=None,
-                 dose_row_order=None, price_row_order=None):
+                 dose_row_order=None, price_row_order=None, dose_grid=None, price_grid=None,
+                 dose_layout=None, price_layout=None, dose_tile=None, price_tile=None, panel_cols=None):
+        """COO (row = voxel, col = beamlet) to the device layouts.
+
+        dose_grid / price_grid: the voxel grid (nx, ny, nz) and the beamlet grid
+        (columns, MLC rows, control points), fastest axis first.  With a grid
+        the orientation defaults to the panel layout (tiles DOSE_TILE /
+        PRICE_TILE); without one, to CSR.  *_layout: "csr" or "panel"."""
         row = np.ascontiguousarray(row, dtype=np.int32)
         col = np.ascontiguousarray(col, dtype=np.int32)
         val = np.ascontiguousarray(val, dtype=np.float32)
@@ -199,9 +222,18 @@ class DDC:
         _check(lib.dvmat_ddc_default_opts(STORAGE[storage], ctypes.byref(opts)))
         for name, v in (("dose_block_rows", dose_block_rows), ("price_block_rows", price_block_rows),
                         ("interleave", interleave), ("unit_entries", unit_entries),
-                        ("dose_row_order", dose_row_order), ("price_row_order", price_row_order)):
+                        ("dose_row_order", dose_row_order), ("price_row_order", price_row_order),
+                        ("panel_cols", panel_cols)):
             if v is not None:
                 setattr(opts, name, int(v))
+        for side, grid, lay, tile, dflt in (("dose", dose_grid, dose_layout, dose_tile, DOSE_TILE),
+                                            ("price", price_grid, price_layout, price_tile, PRICE_TILE)):
+            if lay is None:
+                lay = "panel" if grid is not None else "csr"
+            setattr(opts, side + "_layout", LAYOUTS[lay])
+            if grid is not None:
+                getattr(opts, side + "_grid")[:] = [int(v) for v in grid]
+                getattr(opts, side + "_tile")[:] = [int(v) for v in (tile if tile is not None else dflt)]
         h = _P()
         _check(lib.dvmat_ddc_create_ex(self.n_vox, self.n_bl, len(val),
                                        row.ctypes.data_as(_P) if len(val) else None,

@@ -76,6 +76,13 @@ class Plan:
         return self.n_cp * self.n_rows * self.n_cols
 
     @property
+    def grids(self) -> dict:
+        """Row grids of the two orientations, fastest axis first: voxels
+        (x, y, z) and beamlets (column, MLC row, control point)."""
+        return {"dose_grid": (self.n_grid, self.n_grid, self.n_grid),
+                "price_grid": (self.n_cols, self.n_rows, self.n_cp)}
+
+    @property
     def body_radius(self) -> float:
         return min(0.45 * self.n_grid * self.vox_mm, 115.0)
 

@@ -140,7 +140,9 @@ def test_build_options(dv):
     row = np.ascontiguousarray(d["row"]); col = np.ascontiguousarray(d["col"]); val = np.ascontiguousarray(d["val"])
     P = ctypes.c_void_p
     for bd, bp in ((1, 1), (2, 4), (4, 2), (3, 1), (1, 0)):
-        o = dv.BuildOpts(bd, bp, 1, 2048, 0, 1)
+        o = dv.BuildOpts()
+        assert dv.lib.dvmat_ddc_default_opts(0, ctypes.byref(o)) == 0
+        o.dose_block_rows, o.price_block_rows, o.price_row_order = bd, bp, 1
         h = ctypes.c_void_p()
         code = dv.lib.dvmat_ddc_create_ex(plan.n_vox, plan.n_bl, len(val), row.ctypes.data_as(P), col.ctypes.data_as(P),
                                           val.ctypes.data_as(P), 0, ctypes.byref(o), ctypes.byref(h))

@@ -1,8 +1,8 @@
 """Parity at full size, in the launch configuration the benchmark times.
 
 The full-scale single-arc workload (180 control points x 40x40 beamlets,
-128^3 voxels, ~5e8 non-zeros) is built with the default layout and
-autotuned exactly as bench.py does.  The FP64 oracle cannot run the whole
+128^3 voxels, ~5e8 non-zeros) is built in the panel layout the benchmark
+uses (and in the CSR layout) and autotuned exactly as bench.py does.  The FP64 oracle cannot run the whole
 products quickly, so it checks sampled outputs one by one: each sampled
 dose row and price row is formed from the generator's pointwise definition of
 D_ij (independent of the COO arrays and of the library), plus properties that
@@ -22,13 +22,15 @@ PLAN = synth.PLANS["cp180_bl40x40_vox128"]
 TOL = 1e-5
 
 
-@pytest.fixture(scope="module")
+@pytest.fixture(scope="module", params=["panel", "csr"])
 def full(request):
     assert torch.cuda.is_available()
     from paper_1503_01721_amd import dvmat
     d = synth.generate_ddc(PLAN)
     sid, table = synth.structures(PLAN)
-    ddc = dvmat.DDC(d["row"], d["col"], d["val"], PLAN.n_vox, PLAN.n_bl)
+    layout = PLAN.grids if request.param == "panel" else {}
+    ddc = dvmat.DDC(d["row"], d["col"], d["val"], PLAN.n_vox, PLAN.n_bl, **layout)
+    assert ddc.info.dose_layout == (request.param == "panel")
     nnz = len(d["val"])
     del d
     ddc.autotune(reps=3)

@@ -581,6 +581,108 @@ def test_block_rows_plain_method_workload(dv, plan1, storage, B, order):
     assert np.abs(ddc.dose(cuda(X)).cpu().numpy() - Z_ref).max() <= TOL * Z_ref.max()
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("B", [(1, 1), (2, 1), (4, 2)])
+@pytest.mark.parametrize("panel_cols", [8192, 700])
+def test_panel_layout_plain_method_workload(dv, plan1, storage, B, panel_cols):
+    """The panel layout (vector slices staged in LDS) on the 20-angle workload:
+    dose with the objective epilogue, price, curvature, and 1, 3 and 8
+    right-hand sides (the last two in chunks that fit LDS)."""
+    d, sid, table, _, obj = plan1
+    ddc = dv.DDC(d["row"], d["col"], d["val"], PLAN1.n_vox, PLAN1.n_bl, storage=storage,
+                 dose_block_rows=B[0], price_block_rows=B[1], panel_cols=panel_cols, **PLAN1.grids)
+    info = ddc.info
+    assert (info.dose_layout, info.price_layout) == (1, 1)
+    assert (info.dose_kernel, info.price_kernel) == (3, 3)
+    assert info.dose_panel_cols <= panel_cols and info.price_panel_cols <= panel_cols
+    val = d["val"].astype(np.float64)
+    if storage != "f32":
+        s = np.zeros(PLAN1.n_bl, np.float32)
+        np.maximum.at(s, d["col"], np.abs(d["val"]))
+        s[s == 0] = 1.0
+        q = d["val"] / s[d["col"]]
+        q = q.astype(np.float16).astype(np.float32) if storage == "f16" else _bf16_round(q)
+        val = q.astype(np.float64) * s[d["col"]]
+    x = synth.bench_vectors(PLAN1.n_bl, PLAN1.n_vox, 310 + B[0])[0] * 4.0
+    z_ref = oprod.dose(d["row"], d["col"], val, x, PLAN1.n_vox)
+    z, g, F = ddc.dose(cuda(x), obj, with_grad=True)
+    assert np.abs(z.cpu().numpy() - z_ref).max() <= TOL * z_ref.max()
+    F_ref = oobj.objective(z_ref, sid, table)
+    assert abs(float(F.cpu()[0]) - F_ref) <= 1e-5 * F_ref
+    assert np.allclose(g.cpu().numpy(), oobj.gradient(z.cpu().numpy().astype(np.float64), sid, table),
+                       rtol=1e-5, atol=1e-4)
+    gz = g.cpu().numpy().astype(np.float64)
+    p_ref = oprod.price(d["row"], d["col"], val, gz, PLAN1.n_bl)
+    p = ddc.price(g).cpu().numpy()
+    assert np.abs(p - p_ref).max() <= TOL * oprod.price(d["row"], d["col"], np.abs(val), np.abs(gz), PLAN1.n_bl).max()
+    curv = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ddc.curvature_(cuda(x), obj, z, curv)
+    c_ref = oobj.curvature(z_ref, z.cpu().numpy().astype(np.float64), sid, table)
+    assert abs(float(curv.cpu()[0]) - c_ref) <= 3e-5 * c_ref
+    rng = np.random.default_rng(B[0] + panel_cols)
+    for nrhs in (3, 8):
+        X = rng.random((PLAN1.n_bl, nrhs)).astype(np.float32)
+        Z_ref = oprod.dose(d["row"], d["col"], val, X, PLAN1.n_vox)
+        assert np.abs(ddc.dose(cuda(X)).cpu().numpy() - Z_ref).max() <= TOL * Z_ref.max()
+        G = rng.standard_normal((PLAN1.n_vox, nrhs)).astype(np.float32)
+        P_ref = oprod.price(d["row"], d["col"], val, G, PLAN1.n_bl)
+        scale = oprod.price(d["row"], d["col"], np.abs(val), np.abs(G), PLAN1.n_bl).max()
+        assert np.abs(ddc.price(cuda(G)).cpu().numpy() - P_ref).max() <= TOL * scale
+        Zo, Go, Fo = ddc.dose(cuda(X), obj, with_grad=True)
+        Fo_ref = np.array([oobj.objective(Z_ref[:, h], sid, table) for h in range(nrhs)])
+        assert np.all(np.abs(Fo.cpu().numpy() - Fo_ref) <= 1e-5 * Fo_ref)
+    # the same call twice gives the same bits (fixed reduction order)
+    a = ddc.dose(cuda(x), obj, with_grad=True)
+    assert torch.equal(a[0], z) and torch.equal(a[2], F)
+
+
+@pytest.mark.parametrize("wg", [8, 100, 8192])
+def test_panel_layout_unstructured(dv, wg):
+    """Greedy panels over a ragged matrix in natural row order (no grid): empty
+    rows, a band of long rows, duplicates; and the CSR fallback when a row is
+    wider than the panel budget."""
+    rng = np.random.default_rng(93)
+    n_vox, n_bl = 2500, 3100
+    mask = rng.random((n_vox, n_bl)) < 0.01
+    mask[100:140] = rng.random((40, n_bl)) < 0.3          # rows of ~930 entries, pairs of ~1580
+    mask[2000:2300] = False
+    mask[:, 50:80] = False
+    r, c = np.nonzero(mask)
+    r = np.concatenate([r, r[:100]])
+    c = np.concatenate([c, c[:100]])
+    v = rng.uniform(0.001, 1, len(r)).astype(np.float32)
+    for cap, want in ((2048, (1, 1)), (1000, (0, 1))):
+        ddc = dv.DDC(r, c, v, n_vox, n_bl, dose_block_rows=2, dose_layout="panel", price_layout="panel",
+                     panel_cols=cap)
+        assert (ddc.info.dose_layout, ddc.info.price_layout) == want
+        if want[0] == 1:
+            ddc.set_kernel("dose", "panel", wg)
+        ddc.set_kernel("price", "panel", wg)
+        for nrhs in (1, 2, 5):
+            X = rng.random((n_bl, nrhs)).astype(np.float32)
+            G = rng.standard_normal((n_vox, nrhs)).astype(np.float32)
+            x, g = (X[:, 0].copy(), G[:, 0].copy()) if nrhs == 1 else (X, G)
+            z_ref = oprod.dose(r, c, v, x, n_vox)
+            p_ref = oprod.price(r, c, v, g, n_bl)
+            assert np.abs(ddc.dose(cuda(x)).cpu().numpy() - z_ref).max() <= TOL * np.abs(z_ref).max()
+            p = ddc.price(cuda(g)).cpu().numpy()
+            assert np.abs(p - p_ref).max() <= TOL * oprod.price(r, c, v, np.abs(g), n_bl).max()
+
+
+def test_panel_layout_kind_checks_and_batch(dv, plan1):
+    d, _, _, _, _ = plan1
+    ddc = dv.DDC(d["row"], d["col"], d["val"], PLAN1.n_vox, PLAN1.n_bl, **PLAN1.grids)
+    with pytest.raises(dv.DvmatError):
+        ddc.set_kernel("dose", "row", 1024)
+    csr = dv.DDC(d["row"], d["col"], d["val"], PLAN1.n_vox, PLAN1.n_bl)
+    with pytest.raises(dv.DvmatError):
+        csr.set_kernel("dose", "panel", 1024)
+    with pytest.raises(dv.DvmatError):
+        dv.Batch([ddc])
+    info = ddc.autotune(reps=2)
+    assert info.dose_kernel == 3 and info.price_kernel == 3 and info.dose_tuned_ms > 0
+
+
 def test_da_columns_and_eval(dv, plan1):
     """DA-form pieces: the columns equal Eq. (5) and one evaluation gives the
     oracle's z = sum_k DA_k y_k, F and G_k = <DA_k, dF/dz>."""
