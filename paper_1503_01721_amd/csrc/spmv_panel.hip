@@ -64,8 +64,9 @@ __global__ __launch_bounds__(kSpmvThreads) __attribute__((amdgpu_waves_per_eu(8,
     workgroup_partials<R, EPI>(P, lane, wid, fpart, cpart);
 }
 
-// Largest LDS slice a launch uses (the objective table and partials take the rest).
-constexpr size_t kPanelLdsBytes = 60 * 1024;
+// Largest LDS slice a launch uses; with the objective table (4 KB) and the
+// partial sums the workgroup stays within 64 KB.
+constexpr size_t kPanelLdsBytes = 56 * 1024;
 
 template <int ST, int R, int EPI>
 static void launch_chunk(int B, int nwg, size_t lds, const SpmvParams& P, const PanelParams& Q, hipStream_t s) {
