@@ -57,6 +57,7 @@ struct CsrDev {
     const void* val = nullptr;         // [block entries * B] of value_bytes
     const int32_t* blocks = nullptr;   // [n_blocks + 1] first block row of each work unit
     const int32_t* perm = nullptr;     // [n_rows] row stored at each position, or nullptr (natural order)
+    int perm_runs = 0;                 // every block row's rows are consecutive natural rows
     // panel layout (layout 1): col is unused, col16 holds panel-local columns
     int layout = 0;
     int64_t n_panels = 0;
@@ -77,6 +78,7 @@ struct CsrHost {
     std::vector<uint8_t> val;          // value_bytes per value, B values per block entry
     std::vector<int32_t> blocks;
     std::vector<int32_t> perm;         // empty: natural row order
+    int perm_runs = 0;
     int64_t nonempty = 0;
     int layout = 0;
     std::vector<uint16_t> col16;

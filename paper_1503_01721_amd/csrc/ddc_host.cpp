@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
@@ -37,6 +39,16 @@ dvmat_status set_error(dvmat_status code, const char* fmt, ...) {
 dvmat_status check_hip(hipError_t e, const char* what) {
     if (e == hipSuccess) return DVMAT_OK;
     return set_error(DVMAT_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Build phase timing on stderr when DVMAT_BUILD_VERBOSE is set.
+static void phase(const char* what) {
+    static const bool on = std::getenv("DVMAT_BUILD_VERBOSE") != nullptr;
+    static auto t0 = std::chrono::steady_clock::now();
+    if (!on) return;
+    const auto t = std::chrono::steady_clock::now();
+    fprintf(stderr, "[dvmat build] %-28s %8.3f s\n", what, std::chrono::duration<double>(t - t0).count());
+    t0 = t;
 }
 
 static int host_threads() {
@@ -321,6 +333,7 @@ static dvmat_status build_panels(CsrHost& out, int64_t n_cols, const std::vector
     });
     marks.clear();
     seens.clear();
+    phase("panel cuts");
     if (too_wide.load()) return DVMAT_E_SHAPE;
     std::vector<int64_t> pstart;
     for (auto& v : cuts)
@@ -330,21 +343,35 @@ static dvmat_status build_panels(CsrHost& out, int64_t n_cols, const std::vector
     // column lists and local indices (parallel over panels)
     std::vector<std::vector<int32_t>> ul(n_pan);
     out.col16.assign(out.col.size(), 0);
+    // per thread: stamp[c] = last panel that listed column c, lo[c] = its local index
+    std::vector<std::vector<int64_t>> stamps(T);
     std::vector<std::vector<int32_t>> loc(T);
     parallel_for(n_pan, [&](int64_t a, int64_t b, int t) {
+        std::vector<int64_t>& stamp = stamps[t];
         std::vector<int32_t>& lo = loc[t];
-        if (lo.empty()) lo.assign(n_cols, 0);
+        if (lo.empty()) {
+            lo.assign(n_cols, 0);
+            stamp.assign(n_cols, -1);
+        }
         for (int64_t p = a; p < b; ++p) {
             const int64_t e0 = out.rowptr[pstart[p]], e1 = out.rowptr[pstart[p + 1]];
             std::vector<int32_t>& u = ul[p];
-            u.assign(out.col.begin() + e0, out.col.begin() + e1);
+            u.clear();
+            for (int64_t k = e0; k < e1; ++k) {
+                const int32_t c = out.col[k];
+                if (stamp[c] != p) {
+                    stamp[c] = p;
+                    u.push_back(c);
+                }
+            }
             std::sort(u.begin(), u.end());
-            u.erase(std::unique(u.begin(), u.end()), u.end());
             for (size_t i = 0; i < u.size(); ++i) lo[u[i]] = (int32_t)i;
             for (int64_t k = e0; k < e1; ++k) out.col16[k] = (uint16_t)lo[out.col[k]];
         }
     });
+    stamps.clear();
     loc.clear();
+    phase("panel column lists");
     out.panel_u.assign(n_pan + 1, 0);
     out.max_panel_cols = 0;
     for (int64_t p = 0; p < n_pan; ++p) {
@@ -364,6 +391,7 @@ static dvmat_status build_panels(CsrHost& out, int64_t n_cols, const std::vector
         out.panel_units.push_back((int32_t)out.blocks.size() - 1);
     }
     out.layout = 1;
+    phase("panel units");
     return DVMAT_OK;
 }
 
@@ -371,8 +399,17 @@ static dvmat_status build_blocked(const SortedRows& sr, int64_t n_rows, int64_t 
                                   int64_t unit_cap, const OrientOpts& oo, int64_t panel_cols, CsrHost& out,
                                   std::vector<float>& fvalb) {
     std::vector<int32_t> tile_of_pos;
+    phase("start orientation");
     dvmat_status st0 = order_rows(sr, n_rows, B, oo, out.perm, tile_of_pos);
     if (st0) return st0;
+    out.perm_runs = 0;
+    if (!out.perm.empty()) {
+        bool runs = true;
+        for (int64_t p = 0; p < n_rows && runs; ++p)
+            if (p % B != 0 && out.perm[p] != out.perm[p - 1] + 1) runs = false;
+        out.perm_runs = runs ? 1 : 0;
+    }
+    phase("row order");
     try {
         const int64_t n_br = (n_rows + B - 1) / B;
         out.n_rows = n_rows;
@@ -449,6 +486,7 @@ static dvmat_status build_blocked(const SortedRows& sr, int64_t n_rows, int64_t 
                 }
             }
         });
+        phase("block rows");
         out.blocks.clear();
         out.blocks.push_back(0);
         bool csr = oo.layout != 1;
@@ -623,7 +661,9 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
         // dose orientation: rows = voxels, columns = beamlets
         SortedRows sr;
         std::vector<float> fvalb;
+        phase("validate");
         if ((st = sort_rows(n_vox, nnz, row_vox, col_bl, val, sr))) { delete d; return st; }
+        phase("sort dose rows");
         int64_t nnz_u = 0;
         for (int64_t x : sr.len) nnz_u += x;
         d->nnz = nnz_u;
@@ -655,6 +695,7 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
         std::vector<int32_t>().swap(sr.col);
         std::vector<float>().swap(sr.val);
         encode_values(d->host_dose, fvalb, storage, d->host_scale, false);
+        phase("encode dose values");
         if (d->host_dose.layout == 1) std::vector<int32_t>().swap(d->host_dose.col);
     }
     {
@@ -662,6 +703,7 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
         SortedRows sr;
         std::vector<float> fvalb;
         if ((st = sort_rows(n_bl, nnz, col_bl, row_vox, val, sr))) { delete d; return st; }
+        phase("sort price rows");
         if ((st = build_blocked(sr, n_bl, n_vox, o.price_block_rows, o.interleave != 0, o.unit_entries, price_oo, o.panel_cols,
                                 d->host_price, fvalb))) {
             delete d;
@@ -670,6 +712,7 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
         std::vector<int32_t>().swap(sr.col);
         std::vector<float>().swap(sr.val);
         encode_values(d->host_price, fvalb, storage, d->host_scale, true);
+        phase("encode price values");
         if (d->host_price.layout == 1) std::vector<int32_t>().swap(d->host_price.col);
     }
 
@@ -812,6 +855,7 @@ dvmat_status dvmat_ddc_bind(dvmat_ddc d, void* ws, size_t bytes, dvmat_stream st
     d->dose.val = base + d->off_dose_val;
     d->dose.blocks = reinterpret_cast<const int32_t*>(base + d->off_dose_blocks);
     d->dose.perm = hd.perm.empty() ? nullptr : reinterpret_cast<const int32_t*>(base + d->off_dose_perm);
+    d->dose.perm_runs = hd.perm_runs;
     d->price.rowptr = reinterpret_cast<const int64_t*>(base + d->off_price_rowptr);
     d->price.col = hp.layout == 1 ? nullptr : reinterpret_cast<const int32_t*>(base + d->off_price_col);
     if (hp.layout == 1) {
@@ -823,6 +867,7 @@ dvmat_status dvmat_ddc_bind(dvmat_ddc d, void* ws, size_t bytes, dvmat_stream st
     d->price.val = base + d->off_price_val;
     d->price.blocks = reinterpret_cast<const int32_t*>(base + d->off_price_blocks);
     d->price.perm = hp.perm.empty() ? nullptr : reinterpret_cast<const int32_t*>(base + d->off_price_perm);
+    d->price.perm_runs = hp.perm_runs;
     if (d->storage != DVMAT_F32) {
         d->scale = reinterpret_cast<const float*>(base + d->off_scale);
         d->xs = reinterpret_cast<float*>(base + d->off_xs);

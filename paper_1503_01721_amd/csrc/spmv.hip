@@ -290,6 +290,7 @@ static SpmvParams orientation_params(const CsrDev& c) {
     SpmvParams P{};
     P.n_rows = c.n_rows;
     P.perm = c.perm;
+    P.perm_runs = c.perm_runs;
     P.rowptr = c.rowptr;
     P.col = c.col;
     P.val = c.val;

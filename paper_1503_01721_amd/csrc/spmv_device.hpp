@@ -23,6 +23,7 @@ struct SpmvParams {
     const int32_t* blocks;
     int64_t n_blocks;
     const int32_t* perm;     // stored position -> row, or nullptr
+    int perm_runs;           // 1: the B rows of every block row are consecutive natural rows
     const float* x;
     float* y;                // output rows (nullable for EPI_CURV)
     const uint8_t* sid;      // objective epilogue
@@ -242,7 +243,8 @@ __device__ __forceinline__ void block_rows(const SpmvParams& P, int r0, int r1, 
     const int64_t base = P.rowptr[r0];
     const int64_t last = P.rowptr[r1];
     const int rel = (int)(P.rowptr[r0 + li] - base);
-    // epilogue inputs: structure ids packed one byte per row, or floats
+    // epilogue inputs: structure ids packed one byte per row, or floats; the
+    // natural index of the block row's first row when its rows run consecutively
     int sid4 = 0;
     float ef[B];
 #pragma unroll
@@ -251,6 +253,7 @@ __device__ __forceinline__ void block_rows(const SpmvParams& P, int r0, int r1, 
         sid4 |= e.sid << (8 * q);
         ef[q] = EPI == EPI_CURV ? e.zr : e.rs;
     }
+    const int nat0 = P.perm && P.perm_runs ? P.perm[(int64_t)(r0 + li) * B] : 0;
     for (int i = 0; i < nbr; ++i) {
         const int64_t e0 = base + __builtin_amdgcn_readlane(rel, i);
         const int64_t e1 = i + 1 < nbr ? base + __builtin_amdgcn_readlane(rel, i + 1) : last;
@@ -292,6 +295,7 @@ __device__ __forceinline__ void block_rows(const SpmvParams& P, int r0, int r1, 
 #pragma unroll
             for (int h = 0; h < NRHS; ++h) acc[q][h] = wave_sum(acc[q][h]);
         const int sids = __builtin_amdgcn_readlane(sid4, i);
+        const int n0 = __builtin_amdgcn_readlane(nat0, i);
         float efs[B];
 #pragma unroll
         for (int q = 0; q < B; ++q) efs[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ef[q]), i));
@@ -301,7 +305,8 @@ __device__ __forceinline__ void block_rows(const SpmvParams& P, int r0, int r1, 
                 const int64_t r = (int64_t)(r0 + i) * B + q;
                 if (r < P.n_rows) {
                     const EpiRow e{(sids >> (8 * q)) & 0xff, efs[q], efs[q]};
-                    row_epilogue<NRHS, EPI>(P, natural_row(P, r), e, tab, acc[q], fpart, cpart);
+                    const int64_t nat = !P.perm ? r : P.perm_runs ? (int64_t)n0 + q : (int64_t)P.perm[r];
+                    row_epilogue<NRHS, EPI>(P, nat, e, tab, acc[q], fpart, cpart);
                 }
             }
         }
@@ -489,11 +494,10 @@ __device__ __forceinline__ void block_stream(const SpmvParams& P, int r0, int r1
 }
 
 // Per-workgroup partial of the objective / curvature (fixed order).
-template <int NRHS, int EPI>
-__device__ __forceinline__ void workgroup_partials(const SpmvParams& P, int lane, int wid, float (&fpart)[NRHS],
-                                                   double cpart) {
+template <int NRHS, int EPI, int kWaves>
+__device__ __forceinline__ void workgroup_partials_n(const SpmvParams& P, int lane, int wid, float (&fpart)[NRHS],
+                                                     double cpart) {
     if constexpr (EPI == EPI_OBJ || EPI == EPI_CURV) {
-        constexpr int kWaves = kSpmvThreads / kWaveSize;
         __shared__ float sp[kWaves][NRHS];
         __shared__ double sd[kWaves];
         if constexpr (EPI == EPI_OBJ) {
@@ -525,6 +529,11 @@ __device__ __forceinline__ void workgroup_partials(const SpmvParams& P, int lane
     }
 }
 
+template <int NRHS, int EPI>
+__device__ __forceinline__ void workgroup_partials(const SpmvParams& P, int lane, int wid, float (&fpart)[NRHS],
+                                                   double cpart) {
+    workgroup_partials_n<NRHS, EPI, kSpmvThreads / kWaveSize>(P, lane, wid, fpart, cpart);
+}
 
 // Products on the panel layout (spmv_panel.hip): x is the input vector with
 // nrhs values per column; P carries the outputs and epilogue inputs; the

@@ -5,7 +5,7 @@
 // the price).  Each panel lists the distinct columns its rows touch, and the
 // stored column indices are positions in that list (16 bits).  A workgroup
 // takes one panel at a time: it copies the panel's slice of the input vector
-// into LDS (one coalesced pass over the sorted list), then its four waves run
+// into LDS (one coalesced pass over the sorted list), then its eight waves run
 // the block-row arithmetic of the CSR row kernel with gathers served by LDS.
 // The gathers thus leave the L1/L2 request path, which bounds the CSR kernels:
 // there a gathered value costs a cache-line request of its own, here a staged
@@ -30,15 +30,17 @@ struct PanelParams {
     int64_t n_panels;
 };
 
+// Eight waves share one LDS slice, so the slice does not cap occupancy.
+constexpr int kPanelThreads = 512;
+
 template <int ST, int R, int EPI, int B>
-__global__ __launch_bounds__(kSpmvThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void spmv_panel_kernel(
+__global__ __launch_bounds__(kPanelThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void spmv_panel_kernel(
     SpmvParams P, PanelParams Q) {
-    constexpr int kWaves = kSpmvThreads / kWaveSize;
+    constexpr int kWaves = kPanelThreads / kWaveSize;
     extern __shared__ float xs[];
     __shared__ f32x4 s_tab[(EPI == EPI_OBJ || EPI == EPI_CURV) ? 256 : 1];
     if constexpr (EPI == EPI_OBJ || EPI == EPI_CURV) {
-        static_assert(kSpmvThreads == 256, "one table row per thread");
-        s_tab[threadIdx.x] = reinterpret_cast<const f32x4*>(P.table)[threadIdx.x];
+        if (threadIdx.x < 256) s_tab[threadIdx.x] = reinterpret_cast<const f32x4*>(P.table)[threadIdx.x];
     }
     const int lane = threadIdx.x & (kWaveSize - 1);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWaveSize);
@@ -50,7 +52,7 @@ __global__ __launch_bounds__(kSpmvThreads) __attribute__((amdgpu_waves_per_eu(8,
         const int64_t u0 = Q.panel_u[p];
         const int nu = (int)(Q.panel_u[p + 1] - u0);
         __syncthreads();                              // the previous panel's gathers are done
-        for (int i = threadIdx.x; i < nu; i += kSpmvThreads) {
+        for (int i = threadIdx.x; i < nu; i += kPanelThreads) {
             const int64_t j = Q.ulist[u0 + i];
 #pragma unroll
             for (int h = 0; h < R; ++h) xs[i * R + h] = Q.x[j * Q.ldx + h];
@@ -61,7 +63,7 @@ __global__ __launch_bounds__(kSpmvThreads) __attribute__((amdgpu_waves_per_eu(8,
             block_rows<ST, R, EPI, false, B, true>(P, P.blocks[q], P.blocks[q + 1], lane, s_tab, fpart, cpart, xs,
                                                    Q.col16);
     }
-    workgroup_partials<R, EPI>(P, lane, wid, fpart, cpart);
+    workgroup_partials_n<R, EPI, kWaves>(P, lane, wid, fpart, cpart);
 }
 
 // Largest LDS slice a launch uses; with the objective table (4 KB) and the
@@ -70,7 +72,7 @@ constexpr size_t kPanelLdsBytes = 56 * 1024;
 
 template <int ST, int R, int EPI>
 static void launch_chunk(int B, int nwg, size_t lds, const SpmvParams& P, const PanelParams& Q, hipStream_t s) {
-    dim3 grid(nwg), block(kSpmvThreads);
+    dim3 grid(nwg), block(kPanelThreads);
     if (B == 4) hipLaunchKernelGGL((spmv_panel_kernel<ST, R, EPI, 4>), grid, block, lds, s, P, Q);
     else if (B == 2) hipLaunchKernelGGL((spmv_panel_kernel<ST, R, EPI, 2>), grid, block, lds, s, P, Q);
     else hipLaunchKernelGGL((spmv_panel_kernel<ST, R, EPI, 1>), grid, block, lds, s, P, Q);
