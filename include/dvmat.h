@@ -91,7 +91,8 @@ typedef struct {
     int64_t dose_panel_cols_total, price_panel_cols_total; /* sum of the panels' column lists */
 } dvmat_ddc_info_t;
 
-/* Build options of the device layout.  block_rows B in {1, 2, 4}: B
+/* Build options of the device layout.  block_rows B in {1, 2, 4} (0: the
+ * default for the layout and storage): B
  * consecutive rows form a block row that stores the union of their columns
  * once, with B values per column (zeros where a row lacks it), so one index
  * load and one gather of the input vector serve B rows.  Neighbouring voxels
@@ -133,12 +134,12 @@ typedef struct {
     int32_t panel_cols;
 } dvmat_build_opts;
 
-/* Fill opts with the defaults for a storage type (DVMAT_F32/F16/BF16): the
- * fastest measured CSR layout, dose B = 2 at 4-byte values and 4 at 2-byte
- * values, price B = 1 at 4-byte and 2 at 2-byte values, price rows in
- * first-column order; layout CSR with zero grids (a caller that knows the
- * voxel and beamlet grids sets layout 1, the grids and tiles), panel_cols
- * 8192.  Environment variables DVMAT_DOSE_B, DVMAT_PRICE_B, DVMAT_INTERLEAVE,
+/* Fill opts with the defaults for a storage type (DVMAT_F32/F16/BF16): block
+ * rows 0, which create resolves to the fastest measured for the layout (CSR:
+ * dose B = 2 at 4-byte and 4 at 2-byte values, price B = 1 and 2; panels:
+ * dose B = 1 and 2, price B = 1), price rows in first-column order, layout
+ * CSR with zero grids (a caller that knows the voxel and beamlet grids sets
+ * layout 1, the grids and tiles), panel_cols 8192.  Environment variables DVMAT_DOSE_B, DVMAT_PRICE_B, DVMAT_INTERLEAVE,
  * DVMAT_BLOCK_NNZ, DVMAT_DOSE_ORDER, DVMAT_PRICE_ORDER, DVMAT_PANEL_COLS
  * override single fields.  DVMAT_E_ARG for an unknown storage. */
 dvmat_status dvmat_ddc_default_opts(int32_t storage, dvmat_build_opts* opts);

@@ -552,13 +552,9 @@ dvmat_status dvmat_ddc_default_opts(int32_t storage, dvmat_build_opts* opts) {
     if (!opts) return set_error(DVMAT_E_ARG, "dvmat_ddc_default_opts: NULL argument");
     if (storage != DVMAT_F32 && storage != DVMAT_F16 && storage != DVMAT_BF16)
         return set_error(DVMAT_E_ARG, "dvmat_ddc_default_opts: unknown storage %d", storage);
-    // Fastest measured on the full-scale single-arc workload: with 4-byte
-    // values B = 2 stores fewer bytes per non-zero than B = 4 (the union of 4
-    // voxel rows is looser), with 2-byte values the gathers saved by B = 4
-    // win.  Beamlet rows sorted by first voxel keep their gathers local.
-    const bool f32 = storage == DVMAT_F32;
-    opts->dose_block_rows = f32 ? 2 : 4;
-    opts->price_block_rows = f32 ? 1 : 2;
+    // Beamlet rows sorted by first voxel keep their gathers local (CSR).
+    opts->dose_block_rows = 0;          // 0: chosen at create for the layout and storage
+    opts->price_block_rows = 0;
     opts->interleave = 1;
     opts->unit_entries = 2048;
     opts->dose_row_order = 0;
@@ -594,6 +590,16 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
         o = *opts;
     } else if (dvmat_status st = dvmat_ddc_default_opts(storage, &o)) {
         return st;
+    }
+    // Block rows left at 0: the fastest measured on the full-scale single-arc
+    // workload.  CSR: with 4-byte values B = 2 stores fewer bytes per non-zero
+    // than B = 4 (the union of 4 voxel rows is looser), with 2-byte values the
+    // gathers B = 4 saves win.  Panels: gathers are cheap LDS reads, so the
+    // smaller block rows win (dose B = 1 at 4-byte, 2 at 2-byte values).
+    {
+        const bool f32 = storage == DVMAT_F32;
+        if (o.dose_block_rows == 0) o.dose_block_rows = o.dose_layout == 1 ? (f32 ? 1 : 2) : (f32 ? 2 : 4);
+        if (o.price_block_rows == 0) o.price_block_rows = o.price_layout == 1 ? 1 : (f32 ? 1 : 2);
     }
     auto okB = [](int b) { return b == 1 || b == 2 || b == 4; };
     if (!okB(o.dose_block_rows) || !okB(o.price_block_rows) || (o.interleave != 0 && o.interleave != 1) ||

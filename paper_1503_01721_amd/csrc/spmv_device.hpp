@@ -95,10 +95,26 @@ __device__ __forceinline__ void fma4(float (&acc)[NRHS], const SpmvParams& P, f3
     fma_gather<NRHS>(acc, P.x, v.w, c.w);
 }
 
+// Sum over the 64 lanes of a wave, in a fixed order, returned to every lane.
+// Lane permutes within each row of 16 lanes run on the vector ALU (DPP: swap
+// neighbours, swap pairs, mirror 8, mirror 16), so every lane of a row holds
+// the row's sum; the four row sums are then read as scalars and added.  No
+// LDS traffic, unlike a shuffle butterfly (the panel kernel's gathers use LDS).
+template <int CTRL>
+__device__ __forceinline__ float dpp_step(float v) {
+    return v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    v = dpp_step<0xB1>(v);    // quad_perm [1,0,3,2]
+    v = dpp_step<0x4E>(v);    // quad_perm [2,3,0,1]
+    v = dpp_step<0x141>(v);   // row_half_mirror
+    v = dpp_step<0x140>(v);   // row_mirror
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return (r0 + r1) + (r2 + r3);
 }
 
 __device__ __forceinline__ double wave_sum_d(double v) {
@@ -290,10 +306,12 @@ __device__ __forceinline__ void block_rows(const SpmvParams& P, int r0, int r1, 
             const i32x4 c0 = cols(k);
             fma4_blocked<NRHS, B, SCALE_X>(acc, P, xsrc, V0, c0);
         }
+        if (e1 > e0) {                                   // an empty block row sums to zero
 #pragma unroll
-        for (int q = 0; q < B; ++q)
+            for (int q = 0; q < B; ++q)
 #pragma unroll
-            for (int h = 0; h < NRHS; ++h) acc[q][h] = wave_sum(acc[q][h]);
+                for (int h = 0; h < NRHS; ++h) acc[q][h] = wave_sum(acc[q][h]);
+        }
         const int sids = __builtin_amdgcn_readlane(sid4, i);
         const int n0 = __builtin_amdgcn_readlane(nat0, i);
         float efs[B];

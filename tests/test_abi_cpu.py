@@ -133,23 +133,26 @@ def test_build_options(dv):
     opts = dv.BuildOpts()
     for storage in (0, 1, 2):
         assert dv.lib.dvmat_ddc_default_opts(storage, ctypes.byref(opts)) == 0
-        assert opts.dose_block_rows in (1, 2, 4) and opts.price_block_rows in (1, 2, 4) and opts.interleave in (0, 1)
+        assert opts.dose_block_rows in (0, 1, 2, 4) and opts.price_block_rows in (0, 1, 2, 4)
+        assert opts.interleave in (0, 1)
     assert dv.lib.dvmat_ddc_default_opts(7, ctypes.byref(opts)) == -1
     plan = synth.PLANS["small_cp8_bl6x6_vox16"]
     d = synth.generate_ddc(plan)
     row = np.ascontiguousarray(d["row"]); col = np.ascontiguousarray(d["col"]); val = np.ascontiguousarray(d["val"])
     P = ctypes.c_void_p
-    for bd, bp in ((1, 1), (2, 4), (4, 2), (3, 1), (1, 0)):
+    # 0 = the default for the layout and storage (CSR, FP32 here: dose 2, price 1)
+    for bd, bp in ((1, 1), (2, 4), (4, 2), (3, 1), (1, 8), (0, 0)):
         o = dv.BuildOpts()
         assert dv.lib.dvmat_ddc_default_opts(0, ctypes.byref(o)) == 0
         o.dose_block_rows, o.price_block_rows, o.price_row_order = bd, bp, 1
         h = ctypes.c_void_p()
         code = dv.lib.dvmat_ddc_create_ex(plan.n_vox, plan.n_bl, len(val), row.ctypes.data_as(P), col.ctypes.data_as(P),
                                           val.ctypes.data_as(P), 0, ctypes.byref(o), ctypes.byref(h))
-        if bd not in (1, 2, 4) or bp not in (1, 2, 4):
+        if bd not in (0, 1, 2, 4) or bp not in (0, 1, 2, 4):
             assert code == -1
             continue
         assert code == 0
+        bd, bp = bd or 2, bp or 1
         info = dv.DdcInfo()
         dv.lib.dvmat_ddc_info(h, ctypes.byref(info))
         assert info.nnz == len(val) and info.dose_block_rows == bd and info.price_block_rows == bp
