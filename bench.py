@@ -44,11 +44,20 @@ def algorithmic_bytes(info, nrhs=1):
     return dict(dose=dose_obj, price=price, curv=curv)
 
 
-def read_traffic(kernel, workload, storage):
+def products_source_sha():
+    """Hash of the sources the product kernels are compiled from (a counter
+    summary taken on other sources is stale)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("spmv_device.hpp", "spmv.hip", "spmv_panel.hip", "common.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1503_01721_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel, workload, storage, layout):
     """HBM traffic per launch from the committed counter summary, if it was taken
     on the current kernel source; else None."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}_{storage}.txt")
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}_{storage}_{layout}.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -56,9 +65,8 @@ def read_traffic(kernel, workload, storage):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_1503_01721_amd", "csrc", "spmv.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if kv.get("spmv_source_sha256_16") != sha:
+    sha = products_source_sha()
+    if kv.get("products_source_sha256_16") != sha:
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -386,8 +394,10 @@ def main():
     dom = "price" if mean_price >= mean_dose else "dose"
     dom_ms = mean_price if dom == "price" else mean_dose
     achieved = ab[dom] / (dom_ms * 1e-3) / 1e9
-    kname = "spmv_kernel (price, CSR of D^T)" if dom == "price" else "spmv_kernel (dose, CSR of D, objective epilogue)"
-    traffic = read_traffic(dom, plan.name, args.storage)
+    kfn = "spmv_panel_kernel" if args.layout == "panel" else "spmv_kernel"
+    kname = (f"{kfn} (price, D^T in the {args.layout} layout)" if dom == "price"
+             else f"{kfn} (dose, D in the {args.layout} layout, objective epilogue)")
+    traffic = read_traffic(dom, plan.name, args.storage, args.layout)
     log(f"mean dose call {mean_dose:.3f} ms ({ab['dose'] / mean_dose / 1e6:.0f} GB/s), "
         f"mean price call {mean_price:.3f} ms ({ab['price'] / mean_price / 1e6:.0f} GB/s)")
 
