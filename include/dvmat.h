@@ -89,6 +89,7 @@ typedef struct {
     int64_t dose_panels, price_panels;          /* panels (layout 1), else 0                */
     int64_t dose_panel_cols, price_panel_cols;  /* largest column list of a panel           */
     int64_t dose_panel_cols_total, price_panel_cols_total; /* sum of the panels' column lists */
+    int64_t dose_panel_parts, price_panel_parts;  /* workgroup tasks: runs of a panel's units */
 } dvmat_ddc_info_t;
 
 /* Build options of the device layout.  block_rows B in {1, 2, 4} (0: the
@@ -120,7 +121,10 @@ typedef struct {
  * split along the row order).  A zero grid keeps the natural row order and
  * cuts panels greedily.  With block rows, tile[0] must be a multiple of B.
  * If a single block row has more than panel_cols distinct columns the
- * orientation is built as CSR (dvmat_ddc_info reports the layout built). */
+ * orientation is built as CSR (dvmat_ddc_info reports the layout built).
+ * part_entries: a workgroup takes one part of a panel at a time, a run of
+ * the panel's work units holding up to this many stored values (each part
+ * stages the whole panel slice), so large panels are shared out. */
 typedef struct {
     int32_t dose_block_rows;
     int32_t price_block_rows;
@@ -132,6 +136,7 @@ typedef struct {
     int32_t dose_grid[3], price_grid[3];
     int32_t dose_tile[3], price_tile[3];
     int32_t panel_cols;
+    int32_t part_entries;
 } dvmat_build_opts;
 
 /* Fill opts with the defaults for a storage type (DVMAT_F32/F16/BF16): block
@@ -139,7 +144,7 @@ typedef struct {
  * dose B = 2 at 4-byte and 4 at 2-byte values, price B = 1 and 2; panels:
  * dose B = 1 and 2, price B = 1), price rows in first-column order, layout
  * CSR with zero grids (a caller that knows the voxel and beamlet grids sets
- * layout 1, the grids and tiles), panel_cols 8192.  Environment variables DVMAT_DOSE_B, DVMAT_PRICE_B, DVMAT_INTERLEAVE,
+ * layout 1, the grids and tiles), panel_cols 8192, part_entries 131072.  Environment variables DVMAT_DOSE_B, DVMAT_PRICE_B, DVMAT_INTERLEAVE,
  * DVMAT_BLOCK_NNZ, DVMAT_DOSE_ORDER, DVMAT_PRICE_ORDER, DVMAT_PANEL_COLS
  * override single fields.  DVMAT_E_ARG for an unknown storage. */
 dvmat_status dvmat_ddc_default_opts(int32_t storage, dvmat_build_opts* opts);
@@ -169,7 +174,8 @@ dvmat_status dvmat_ddc_info(dvmat_ddc ddc, dvmat_ddc_info_t* info);
  * values (storage type, B per position), 3 = work units (int32 first block
  * rows), 4 = row at each stored position (int32; empty for natural order),
  * 5 = panel column lists (int32), 6 = panel offsets into them (int64), 7 =
- * first work unit of each panel (int32).  *size receives the array's byte
+ * first work unit of each panel (int32), 8 = first work unit of each part
+ * (int32), 9 = panel of each part (int32).  *size receives the array's byte
  * size; dst (host, may be NULL to query) must hold cap >= *size bytes. */
 dvmat_status dvmat_ddc_layout_array(dvmat_ddc ddc, int32_t orientation, int32_t which, void* dst, size_t cap,
                                     size_t* size);

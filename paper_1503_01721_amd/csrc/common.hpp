@@ -66,6 +66,9 @@ struct CsrDev {
     const int32_t* ulist = nullptr;    // concatenated sorted column lists of the panels
     const int64_t* panel_u = nullptr;  // [n_panels + 1] offsets into ulist
     const int32_t* panel_units = nullptr;  // [n_panels + 1] first work unit of each panel
+    int64_t n_parts = 0;
+    const int32_t* part_units = nullptr;   // [n_parts + 1] first work unit of each part
+    const int32_t* part_panel = nullptr;   // [n_parts] panel of each part
 };
 
 // Host staging of one orientation before bind.
@@ -85,6 +88,7 @@ struct CsrHost {
     std::vector<int32_t> ulist;
     std::vector<int64_t> panel_u;
     std::vector<int32_t> panel_units;
+    std::vector<int32_t> part_units, part_panel;
     int64_t max_panel_cols = 0;
 };
 
@@ -109,6 +113,7 @@ struct dvmat_ddc_s {
     size_t off_price_rowptr = 0, off_price_col = 0, off_price_val = 0, off_price_blocks = 0, off_price_perm = 0;
     size_t off_dose_ulist = 0, off_dose_panel_u = 0, off_dose_panel_units = 0;
     size_t off_price_ulist = 0, off_price_panel_u = 0, off_price_panel_units = 0;
+    size_t off_dose_part_units = 0, off_dose_part_panel = 0, off_price_part_units = 0, off_price_part_panel = 0;
     size_t off_scale = 0, off_xs = 0;
     int64_t dose_panel_cols_total = 0, price_panel_cols_total = 0;
 };

@@ -272,7 +272,7 @@ static void cut_units(const CsrHost& out, int64_t b0, int64_t b1, int64_t unit_c
 // DVMAT_E_SHAPE (no error text) when a single block row has more than cap
 // columns: the caller then keeps the CSR layout.
 static dvmat_status build_panels(CsrHost& out, int64_t n_cols, const std::vector<int32_t>& tile_of_pos, int64_t cap,
-                                 int64_t unit_cap) {
+                                 int64_t unit_cap, int64_t part_cap) {
     const int64_t n_br = out.n_brows;
     const int B = out.B;
     auto tile_of_br = [&](int64_t br) -> int64_t { return tile_of_pos.empty() ? 0 : tile_of_pos[br * B]; };
@@ -390,14 +390,33 @@ static dvmat_status build_panels(CsrHost& out, int64_t n_cols, const std::vector
         if (pstart[p + 1] > pstart[p]) cut_units(out, pstart[p], pstart[p + 1], unit_cap, out.blocks);
         out.panel_units.push_back((int32_t)out.blocks.size() - 1);
     }
+    // parts: runs of a panel's units up to part_cap stored values (a panel
+    // without units is one empty part, so every panel is visited)
+    out.part_units.assign(1, 0);
+    out.part_panel.clear();
+    for (int64_t p = 0; p < n_pan; ++p) {
+        const int32_t q0 = out.panel_units[p], q1 = out.panel_units[p + 1];
+        int64_t acc = 0;
+        for (int32_t q = q0; q < q1; ++q) {
+            const int64_t lq = (out.rowptr[out.blocks[q + 1]] - out.rowptr[out.blocks[q]]) * out.B;
+            if (q > q0 && acc + lq > part_cap) {
+                out.part_units.push_back(q);
+                out.part_panel.push_back((int32_t)p);
+                acc = 0;
+            }
+            acc += lq;
+        }
+        out.part_units.push_back(q1);
+        out.part_panel.push_back((int32_t)p);
+    }
     out.layout = 1;
     phase("panel units");
     return DVMAT_OK;
 }
 
 static dvmat_status build_blocked(const SortedRows& sr, int64_t n_rows, int64_t n_cols, int B, bool interleave,
-                                  int64_t unit_cap, const OrientOpts& oo, int64_t panel_cols, CsrHost& out,
-                                  std::vector<float>& fvalb) {
+                                  int64_t unit_cap, const OrientOpts& oo, int64_t panel_cols, int64_t part_cap,
+                                  CsrHost& out, std::vector<float>& fvalb) {
     std::vector<int32_t> tile_of_pos;
     phase("start orientation");
     dvmat_status st0 = order_rows(sr, n_rows, B, oo, out.perm, tile_of_pos);
@@ -491,7 +510,7 @@ static dvmat_status build_blocked(const SortedRows& sr, int64_t n_rows, int64_t 
         out.blocks.push_back(0);
         bool csr = oo.layout != 1;
         if (!csr) {
-            const dvmat_status sp = build_panels(out, n_cols, tile_of_pos, panel_cols, unit_cap);
+            const dvmat_status sp = build_panels(out, n_cols, tile_of_pos, panel_cols, unit_cap, part_cap);
             if (sp == DVMAT_E_SHAPE) csr = true;             // a block row wider than the panel budget
             else if (sp) return sp;
         }
@@ -566,7 +585,9 @@ dvmat_status dvmat_ddc_default_opts(int32_t storage, dvmat_build_opts* opts) {
         opts->dose_tile[i] = opts->price_tile[i] = 0;
     }
     opts->panel_cols = 8192;
+    opts->part_entries = 131072;
     if (const char* e = std::getenv("DVMAT_PANEL_COLS")) opts->panel_cols = std::atoi(e);
+    if (const char* e = std::getenv("DVMAT_PART_ENTRIES")) opts->part_entries = std::atoi(e);
     if (const char* e = std::getenv("DVMAT_DOSE_ORDER")) opts->dose_row_order = std::atoi(e);
     if (const char* e = std::getenv("DVMAT_PRICE_ORDER")) opts->price_row_order = std::atoi(e);
     if (const char* e = std::getenv("DVMAT_DOSE_B")) opts->dose_block_rows = std::atoi(e);
@@ -605,7 +626,8 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
     if (!okB(o.dose_block_rows) || !okB(o.price_block_rows) || (o.interleave != 0 && o.interleave != 1) ||
         o.unit_entries < 4 || o.unit_entries > (1 << 24) || (o.dose_row_order != 0 && o.dose_row_order != 1) ||
         (o.price_row_order != 0 && o.price_row_order != 1) || (o.dose_layout != 0 && o.dose_layout != 1) ||
-        (o.price_layout != 0 && o.price_layout != 1) || o.panel_cols < 1 || o.panel_cols > 65536)
+        (o.price_layout != 0 && o.price_layout != 1) || o.panel_cols < 1 || o.panel_cols > 65536 ||
+        o.part_entries < 1)
         return set_error(DVMAT_E_ARG, "dvmat_ddc_create: bad build options (block rows %d/%d, interleave %d, unit %d)",
                          o.dose_block_rows, o.price_block_rows, o.interleave, o.unit_entries);
     *out = nullptr;
@@ -691,7 +713,7 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
             for (auto& s : d->host_scale)
                 if (!(s > 0.0f)) s = 1.0f;
         }
-        if ((st = build_blocked(sr, n_vox, n_bl, o.dose_block_rows, o.interleave != 0, o.unit_entries, dose_oo, o.panel_cols,
+        if ((st = build_blocked(sr, n_vox, n_bl, o.dose_block_rows, o.interleave != 0, o.unit_entries, dose_oo, o.panel_cols, o.part_entries,
                                 d->host_dose, fvalb))) {
             delete d;
             return st;
@@ -710,7 +732,7 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
         std::vector<float> fvalb;
         if ((st = sort_rows(n_bl, nnz, col_bl, row_vox, val, sr))) { delete d; return st; }
         phase("sort price rows");
-        if ((st = build_blocked(sr, n_bl, n_vox, o.price_block_rows, o.interleave != 0, o.unit_entries, price_oo, o.panel_cols,
+        if ((st = build_blocked(sr, n_bl, n_vox, o.price_block_rows, o.interleave != 0, o.unit_entries, price_oo, o.panel_cols, o.part_entries,
                                 d->host_price, fvalb))) {
             delete d;
             return st;
@@ -735,6 +757,8 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
     d->off_dose_ulist = take(hd.ulist.size() * 4);
     d->off_dose_panel_u = take(hd.panel_u.size() * 8);
     d->off_dose_panel_units = take(hd.panel_units.size() * 4);
+    d->off_dose_part_units = take(hd.part_units.size() * 4);
+    d->off_dose_part_panel = take(hd.part_panel.size() * 4);
     d->off_price_rowptr = take(hp.rowptr.size() * 8);
     d->off_price_col = take(hp.layout == 1 ? hp.col16.size() * 2 : hp.col.size() * 4);
     d->off_price_val = take(hp.val.size());
@@ -743,6 +767,8 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
     d->off_price_ulist = take(hp.ulist.size() * 4);
     d->off_price_panel_u = take(hp.panel_u.size() * 8);
     d->off_price_panel_units = take(hp.panel_units.size() * 4);
+    d->off_price_part_units = take(hp.part_units.size() * 4);
+    d->off_price_part_panel = take(hp.part_panel.size() * 4);
     if (storage != DVMAT_F32) {
         d->off_scale = take(n_bl * 4);
         d->off_xs = take(n_bl * 4 * kMaxRhs);
@@ -754,6 +780,7 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
     d->dose.layout = hd.layout;
     d->dose.n_panels = hd.layout == 1 ? (int64_t)hd.panel_u.size() - 1 : 0;
     d->dose.max_panel_cols = hd.max_panel_cols;
+    d->dose.n_parts = hd.layout == 1 ? (int64_t)hd.part_panel.size() : 0;
     d->dose_panel_cols_total = hd.ulist.size();
     d->dose.n_blocks = (int64_t)hd.blocks.size() - 1;
     d->dose.nonempty = hd.nonempty;
@@ -765,6 +792,7 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
     if (hd.layout == 1) d->dose_cfg.kind = KIND_PANEL;
     if (hp.layout == 1) d->price_cfg.kind = KIND_PANEL;
     d->price.max_panel_cols = hp.max_panel_cols;
+    d->price.n_parts = hp.layout == 1 ? (int64_t)hp.part_panel.size() : 0;
     d->price_panel_cols_total = hp.ulist.size();
     d->price.n_blocks = (int64_t)hp.blocks.size() - 1;
     d->price.nonempty = hp.nonempty;
@@ -803,6 +831,8 @@ dvmat_status dvmat_ddc_info(dvmat_ddc d, dvmat_ddc_info_t* info) {
     info->dose_panel_cols = d->dose.max_panel_cols;
     info->price_panel_cols = d->price.max_panel_cols;
     info->dose_panel_cols_total = d->dose_panel_cols_total;
+    info->dose_panel_parts = d->dose.n_parts;
+    info->price_panel_parts = d->price.n_parts;
     info->price_panel_cols_total = d->price_panel_cols_total;
     return DVMAT_OK;
 }
@@ -829,6 +859,8 @@ dvmat_status dvmat_ddc_bind(dvmat_ddc d, void* ws, size_t bytes, dvmat_stream st
         if ((st = up(d->off_dose_ulist, hd.ulist.data(), hd.ulist.size() * 4))) return st;
         if ((st = up(d->off_dose_panel_u, hd.panel_u.data(), hd.panel_u.size() * 8))) return st;
         if ((st = up(d->off_dose_panel_units, hd.panel_units.data(), hd.panel_units.size() * 4))) return st;
+        if ((st = up(d->off_dose_part_units, hd.part_units.data(), hd.part_units.size() * 4))) return st;
+        if ((st = up(d->off_dose_part_panel, hd.part_panel.data(), hd.part_panel.size() * 4))) return st;
     } else if ((st = up(d->off_dose_col, hd.col.data(), hd.col.size() * 4))) {
         return st;
     }
@@ -841,6 +873,8 @@ dvmat_status dvmat_ddc_bind(dvmat_ddc d, void* ws, size_t bytes, dvmat_stream st
         if ((st = up(d->off_price_ulist, hp.ulist.data(), hp.ulist.size() * 4))) return st;
         if ((st = up(d->off_price_panel_u, hp.panel_u.data(), hp.panel_u.size() * 8))) return st;
         if ((st = up(d->off_price_panel_units, hp.panel_units.data(), hp.panel_units.size() * 4))) return st;
+        if ((st = up(d->off_price_part_units, hp.part_units.data(), hp.part_units.size() * 4))) return st;
+        if ((st = up(d->off_price_part_panel, hp.part_panel.data(), hp.part_panel.size() * 4))) return st;
     } else if ((st = up(d->off_price_col, hp.col.data(), hp.col.size() * 4))) {
         return st;
     }
@@ -857,6 +891,8 @@ dvmat_status dvmat_ddc_bind(dvmat_ddc d, void* ws, size_t bytes, dvmat_stream st
         d->dose.ulist = reinterpret_cast<const int32_t*>(base + d->off_dose_ulist);
         d->dose.panel_u = reinterpret_cast<const int64_t*>(base + d->off_dose_panel_u);
         d->dose.panel_units = reinterpret_cast<const int32_t*>(base + d->off_dose_panel_units);
+        d->dose.part_units = reinterpret_cast<const int32_t*>(base + d->off_dose_part_units);
+        d->dose.part_panel = reinterpret_cast<const int32_t*>(base + d->off_dose_part_panel);
     }
     d->dose.val = base + d->off_dose_val;
     d->dose.blocks = reinterpret_cast<const int32_t*>(base + d->off_dose_blocks);
@@ -869,6 +905,8 @@ dvmat_status dvmat_ddc_bind(dvmat_ddc d, void* ws, size_t bytes, dvmat_stream st
         d->price.ulist = reinterpret_cast<const int32_t*>(base + d->off_price_ulist);
         d->price.panel_u = reinterpret_cast<const int64_t*>(base + d->off_price_panel_u);
         d->price.panel_units = reinterpret_cast<const int32_t*>(base + d->off_price_panel_units);
+        d->price.part_units = reinterpret_cast<const int32_t*>(base + d->off_price_part_units);
+        d->price.part_panel = reinterpret_cast<const int32_t*>(base + d->off_price_part_panel);
     }
     d->price.val = base + d->off_price_val;
     d->price.blocks = reinterpret_cast<const int32_t*>(base + d->off_price_blocks);
@@ -906,6 +944,8 @@ dvmat_status dvmat_ddc_layout_array(dvmat_ddc d, int32_t orientation, int32_t wh
         case 5: src = h.ulist.data(); n = h.ulist.size() * 4; break;
         case 6: src = h.panel_u.data(); n = h.panel_u.size() * 8; break;
         case 7: src = h.panel_units.data(); n = h.panel_units.size() * 4; break;
+        case 8: src = h.part_units.data(); n = h.part_units.size() * 4; break;
+        case 9: src = h.part_panel.data(); n = h.part_panel.size() * 4; break;
         default: return set_error(DVMAT_E_ARG, "dvmat_ddc_layout_array: which %d", which);
     }
     *size = n;

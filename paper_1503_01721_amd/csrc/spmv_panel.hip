@@ -4,7 +4,8 @@
 // grid for the dose; neighbouring beamlets at neighbouring gantry angles for
 // the price).  Each panel lists the distinct columns its rows touch, and the
 // stored column indices are positions in that list (16 bits).  A workgroup
-// takes one panel at a time: it copies the panel's slice of the input vector
+// takes one part of a panel at a time (a run of its work units, so that large
+// panels are shared out): it copies the panel's slice of the input vector
 // into LDS (one coalesced pass over the sorted list), then its eight waves run
 // the block-row arithmetic of the CSR row kernel with gathers served by LDS.
 // The gathers thus leave the L1/L2 request path, which bounds the CSR kernels:
@@ -26,8 +27,9 @@ struct PanelParams {
     const uint16_t* col16;
     const int32_t* ulist;
     const int64_t* panel_u;
-    const int32_t* panel_units;
-    int64_t n_panels;
+    const int32_t* part_units;
+    const int32_t* part_panel;
+    int64_t n_parts;
 };
 
 // Eight waves share one LDS slice, so the slice does not cap occupancy.
@@ -48,7 +50,8 @@ __global__ __launch_bounds__(kPanelThreads) __attribute__((amdgpu_waves_per_eu(8
 #pragma unroll
     for (int h = 0; h < R; ++h) fpart[h] = 0.0f;
     double cpart = 0.0;
-    for (int64_t p = blockIdx.x; p < Q.n_panels; p += gridDim.x) {
+    for (int64_t t = blockIdx.x; t < Q.n_parts; t += gridDim.x) {
+        const int p = Q.part_panel[t];
         const int64_t u0 = Q.panel_u[p];
         const int nu = (int)(Q.panel_u[p + 1] - u0);
         __syncthreads();                              // the previous panel's gathers are done
@@ -58,7 +61,7 @@ __global__ __launch_bounds__(kPanelThreads) __attribute__((amdgpu_waves_per_eu(8
             for (int h = 0; h < R; ++h) xs[i * R + h] = Q.x[j * Q.ldx + h];
         }
         __syncthreads();
-        const int q0 = Q.panel_units[p], q1 = Q.panel_units[p + 1];
+        const int q0 = Q.part_units[t], q1 = Q.part_units[t + 1];
         for (int q = q0 + wid; q < q1; q += kWaves)
             block_rows<ST, R, EPI, false, B, true>(P, P.blocks[q], P.blocks[q + 1], lane, s_tab, fpart, cpart, xs,
                                                    Q.col16);
@@ -95,9 +98,9 @@ template <int EPI>
 dvmat_status launch_panel(const KernelCfg& cfg, int storage, const CsrDev& c, const SpmvParams& P0, const float* x,
                           int nrhs, hipStream_t s, int* nwg_out) {
     const int64_t want = std::max(1, cfg.workgroups);
-    const int nwg = (int)std::max<int64_t>(1, std::min<int64_t>(want, c.n_panels));
+    const int nwg = (int)std::max<int64_t>(1, std::min<int64_t>(want, c.n_parts));
     *nwg_out = nwg;
-    if (c.n_panels == 0) return DVMAT_OK;
+    if (c.n_parts == 0) return DVMAT_OK;
     const size_t per_rhs = (size_t)std::max<int64_t>(c.max_panel_cols, 1) * sizeof(float);
     if (per_rhs > kPanelLdsBytes)
         return set_error(DVMAT_E_SHAPE, "panel of %lld columns exceeds the LDS slice", (long long)c.max_panel_cols);
@@ -106,8 +109,9 @@ dvmat_status launch_panel(const KernelCfg& cfg, int storage, const CsrDev& c, co
     Q.col16 = c.col16;
     Q.ulist = c.ulist;
     Q.panel_u = c.panel_u;
-    Q.panel_units = c.panel_units;
-    Q.n_panels = c.n_panels;
+    Q.part_units = c.part_units;
+    Q.part_panel = c.part_panel;
+    Q.n_parts = c.n_parts;
     for (int h0 = 0; h0 < nrhs;) {
         int R = 8;
         while (R > 1 && (R > nrhs - h0 || per_rhs * R > kPanelLdsBytes)) R >>= 1;

@@ -49,7 +49,8 @@ class DdcInfo(ctypes.Structure):
                 ("dose_layout", ctypes.c_int32), ("price_layout", ctypes.c_int32),
                 ("dose_panels", ctypes.c_int64), ("price_panels", ctypes.c_int64),
                 ("dose_panel_cols", ctypes.c_int64), ("price_panel_cols", ctypes.c_int64),
-                ("dose_panel_cols_total", ctypes.c_int64), ("price_panel_cols_total", ctypes.c_int64)]
+                ("dose_panel_cols_total", ctypes.c_int64), ("price_panel_cols_total", ctypes.c_int64),
+                ("dose_panel_parts", ctypes.c_int64), ("price_panel_parts", ctypes.c_int64)]
 
 
 class BuildOpts(ctypes.Structure):
@@ -59,7 +60,7 @@ class BuildOpts(ctypes.Structure):
                 ("dose_layout", ctypes.c_int32), ("price_layout", ctypes.c_int32),
                 ("dose_grid", ctypes.c_int32 * 3), ("price_grid", ctypes.c_int32 * 3),
                 ("dose_tile", ctypes.c_int32 * 3), ("price_tile", ctypes.c_int32 * 3),
-                ("panel_cols", ctypes.c_int32)]
+                ("panel_cols", ctypes.c_int32), ("part_entries", ctypes.c_int32)]
 
 
 # Panel tiles used when the grids are known: 8x8x8 voxels (dose); 4 beamlet
@@ -204,7 +205,8 @@ class DDC:
     def __init__(self, row, col, val, n_vox: int, n_bl: int, storage: str = "f32", device="cuda",
                  dose_block_rows=None, price_block_rows=None, interleave=None, unit_entries=None,
                  dose_row_order=None, price_row_order=None, dose_grid=None, price_grid=None,
-                 dose_layout=None, price_layout=None, dose_tile=None, price_tile=None, panel_cols=None):
+                 dose_layout=None, price_layout=None, dose_tile=None, price_tile=None, panel_cols=None,
+                 part_entries=None):
         """COO (row = voxel, col = beamlet) to the device layouts.
 
         dose_grid / price_grid: the voxel grid (nx, ny, nz) and the beamlet grid
@@ -223,7 +225,7 @@ class DDC:
         for name, v in (("dose_block_rows", dose_block_rows), ("price_block_rows", price_block_rows),
                         ("interleave", interleave), ("unit_entries", unit_entries),
                         ("dose_row_order", dose_row_order), ("price_row_order", price_row_order),
-                        ("panel_cols", panel_cols)):
+                        ("panel_cols", panel_cols), ("part_entries", part_entries)):
             if v is not None:
                 setattr(opts, name, int(v))
         for side, grid, lay, tile, dflt in (("dose", dose_grid, dose_layout, dose_tile, DOSE_TILE),

@@ -590,7 +590,8 @@ def test_panel_layout_plain_method_workload(dv, plan1, storage, B, panel_cols):
     right-hand sides (the last two in chunks that fit LDS)."""
     d, sid, table, _, obj = plan1
     ddc = dv.DDC(d["row"], d["col"], d["val"], PLAN1.n_vox, PLAN1.n_bl, storage=storage,
-                 dose_block_rows=B[0], price_block_rows=B[1], panel_cols=panel_cols, **PLAN1.grids)
+                 dose_block_rows=B[0], price_block_rows=B[1], panel_cols=panel_cols,
+                 part_entries=131072 if panel_cols == 8192 else 20000, **PLAN1.grids)
     info = ddc.info
     # beamlet rows here touch up to ~1300 voxels: a budget of 1000 keeps the
     # price matrix in CSR (and splits the dose tiles), 2500 splits the price tiles
@@ -654,9 +655,9 @@ def test_panel_layout_unstructured(dv, wg):
     r = np.concatenate([r, r[:100]])
     c = np.concatenate([c, c[:100]])
     v = rng.uniform(0.001, 1, len(r)).astype(np.float32)
-    for cap, want in ((2048, (1, 1)), (1000, (0, 1))):
+    for cap, want, part in ((2048, (1, 1), 131072), (1000, (0, 1), 131072), (2048, (1, 1), 3000)):
         ddc = dv.DDC(r, c, v, n_vox, n_bl, dose_block_rows=2, dose_layout="panel", price_layout="panel",
-                     panel_cols=cap)
+                     panel_cols=cap, part_entries=part)
         assert (ddc.info.dose_layout, ddc.info.price_layout) == want
         if want[0] == 1:
             ddc.set_kernel("dose", "panel", wg)

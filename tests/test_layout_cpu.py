@@ -70,6 +70,13 @@ def _rebuild(dv, h, info, orient, n_rows, n_cols):
         n_pan = len(pu) - 1
         assert n_pan == (info.dose_panels if orient == 0 else info.price_panels)
         assert punits[0] == 0 and punits[-1] == len(units) - 1 and np.all(np.diff(punits) >= 0)
+        # parts: runs of units inside one panel, covering every panel in order
+        parts = _array(dv, h, orient, 8, np.int32)
+        ppan = _array(dv, h, orient, 9, np.int32)
+        assert len(parts) == len(ppan) + 1 == (info.dose_panel_parts if orient == 0 else info.price_panel_parts) + 1
+        assert parts[0] == 0 and parts[-1] == len(units) - 1 and np.all(np.diff(parts) >= 0)
+        assert np.all(np.diff(ppan) >= 0) and np.array_equal(np.unique(ppan), np.arange(n_pan))
+        assert np.all(parts[:-1] >= punits[ppan]) and np.all(parts[1:] <= punits[ppan + 1])
         gcol = np.empty(n_pos, np.int64)
         sizes = np.diff(pu)
         assert sizes.max(initial=0) == (info.dose_panel_cols if orient == 0 else info.price_panel_cols)
@@ -100,7 +107,8 @@ def _dense(row, col, val, n_vox, n_bl):
     return D
 
 
-def _opts(dv, B=(1, 1), layout=(0, 0), grids=None, tiles=None, panel_cols=8192, order=(0, 0), interleave=1):
+def _opts(dv, B=(1, 1), layout=(0, 0), grids=None, tiles=None, panel_cols=8192, order=(0, 0), interleave=1,
+          part_entries=131072):
     o = dv.BuildOpts()
     assert dv.lib.dvmat_ddc_default_opts(0, ctypes.byref(o)) == 0
     o.dose_block_rows, o.price_block_rows = B
@@ -108,6 +116,7 @@ def _opts(dv, B=(1, 1), layout=(0, 0), grids=None, tiles=None, panel_cols=8192, 
     o.dose_row_order, o.price_row_order = order
     o.interleave = interleave
     o.panel_cols = panel_cols
+    o.part_entries = part_entries
     if grids is not None:
         o.dose_grid[:] = grids["dose_grid"]
         o.price_grid[:] = grids["price_grid"]
@@ -152,8 +161,10 @@ def test_panel_layout_rebuilds_the_matrix(dv, small, B):
 def test_panel_budget_splits_tiles(dv, small):
     row, col, val = small
     info, ld, lp = _check_both(dv, row, col, val, PLAN.n_vox, PLAN.n_bl,
-                               _opts(dv, (2, 1), (1, 1), PLAN.grids, (dv.DOSE_TILE, dv.PRICE_TILE), panel_cols=900))
+                               _opts(dv, (2, 1), (1, 1), PLAN.grids, (dv.DOSE_TILE, dv.PRICE_TILE), panel_cols=900,
+                                     part_entries=2000))
     assert (ld, lp) == (1, 1)
+    assert info.dose_panel_parts > info.dose_panels and info.price_panel_parts > info.price_panels
     assert info.dose_panel_cols <= 900 and info.price_panel_cols <= 900
     # the default tiles give 6 price panels here; the budget splits them
     assert info.price_panels > 6
