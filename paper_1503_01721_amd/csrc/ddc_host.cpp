@@ -584,7 +584,7 @@ dvmat_status dvmat_ddc_default_opts(int32_t storage, dvmat_build_opts* opts) {
         opts->dose_grid[i] = opts->price_grid[i] = 0;
         opts->dose_tile[i] = opts->price_tile[i] = 0;
     }
-    opts->panel_cols = 8192;
+    opts->panel_cols = 12288;
     opts->part_entries = 131072;
     if (const char* e = std::getenv("DVMAT_PANEL_COLS")) opts->panel_cols = std::atoi(e);
     if (const char* e = std::getenv("DVMAT_PART_ENTRIES")) opts->part_entries = std::atoi(e);

@@ -270,6 +270,15 @@ __device__ __forceinline__ void block_rows(const SpmvParams& P, int r0, int r1, 
         ef[q] = EPI == EPI_CURV ? e.zr : e.rs;
     }
     const int nat0 = P.perm && P.perm_runs ? P.perm[(int64_t)(r0 + li) * B] : 0;
+    // Small blocks keep each block row's sums in the lane of that block row and
+    // finish all rows together after the unit; larger ones finish each block
+    // row in lane 0 (registers).
+    constexpr bool kLaneEpilogue = B * NRHS <= 4;
+    float mine[kLaneEpilogue ? B : 1][kLaneEpilogue ? NRHS : 1];
+#pragma unroll
+    for (int q = 0; q < (kLaneEpilogue ? B : 1); ++q)
+#pragma unroll
+        for (int h = 0; h < (kLaneEpilogue ? NRHS : 1); ++h) mine[q][h] = 0.0f;
     for (int i = 0; i < nbr; ++i) {
         const int64_t e0 = base + __builtin_amdgcn_readlane(rel, i);
         const int64_t e1 = i + 1 < nbr ? base + __builtin_amdgcn_readlane(rel, i + 1) : last;
@@ -312,19 +321,43 @@ __device__ __forceinline__ void block_rows(const SpmvParams& P, int r0, int r1, 
 #pragma unroll
                 for (int h = 0; h < NRHS; ++h) acc[q][h] = wave_sum(acc[q][h]);
         }
-        const int sids = __builtin_amdgcn_readlane(sid4, i);
-        const int n0 = __builtin_amdgcn_readlane(nat0, i);
-        float efs[B];
+        if constexpr (kLaneEpilogue) {
+            // the sums are wave-uniform: lane i keeps block row i's
+            if (lane == i) {
 #pragma unroll
-        for (int q = 0; q < B; ++q) efs[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ef[q]), i));
-        if (lane == 0) {
+                for (int q = 0; q < B; ++q)
+#pragma unroll
+                    for (int h = 0; h < NRHS; ++h) mine[q][h] = acc[q][h];
+            }
+        } else {
+            const int sids = __builtin_amdgcn_readlane(sid4, i);
+            const int n0 = __builtin_amdgcn_readlane(nat0, i);
+            float efs[B];
+#pragma unroll
+            for (int q = 0; q < B; ++q) efs[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ef[q]), i));
+            if (lane == 0) {
+#pragma unroll
+                for (int q = 0; q < B; ++q) {
+                    const int64_t r = (int64_t)(r0 + i) * B + q;
+                    if (r < P.n_rows) {
+                        const EpiRow e{(sids >> (8 * q)) & 0xff, efs[q], efs[q]};
+                        const int64_t nat = !P.perm ? r : P.perm_runs ? (int64_t)n0 + q : (int64_t)P.perm[r];
+                        row_epilogue<NRHS, EPI>(P, nat, e, tab, acc[q], fpart, cpart);
+                    }
+                }
+            }
+        }
+    }
+    if constexpr (kLaneEpilogue) {
+        // every lane finishes its own block row: coalesced stores, parallel epilogue
+        if (lane < nbr) {
 #pragma unroll
             for (int q = 0; q < B; ++q) {
-                const int64_t r = (int64_t)(r0 + i) * B + q;
+                const int64_t r = (int64_t)(r0 + lane) * B + q;
                 if (r < P.n_rows) {
-                    const EpiRow e{(sids >> (8 * q)) & 0xff, efs[q], efs[q]};
-                    const int64_t nat = !P.perm ? r : P.perm_runs ? (int64_t)n0 + q : (int64_t)P.perm[r];
-                    row_epilogue<NRHS, EPI>(P, nat, e, tab, acc[q], fpart, cpart);
+                    const EpiRow e{(sid4 >> (8 * q)) & 0xff, ef[q], ef[q]};
+                    const int64_t nat = !P.perm ? r : P.perm_runs ? (int64_t)nat0 + q : (int64_t)P.perm[r];
+                    row_epilogue<NRHS, EPI>(P, nat, e, tab, mine[q], fpart, cpart);
                 }
             }
         }

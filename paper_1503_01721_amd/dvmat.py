@@ -63,9 +63,9 @@ class BuildOpts(ctypes.Structure):
                 ("panel_cols", ctypes.c_int32), ("part_entries", ctypes.c_int32)]
 
 
-# Panel tiles used when the grids are known: 8x8x8 voxels (dose); 4 beamlet
+# Panel tiles used when the grids are known: 16x8x8 voxels (dose); 4 beamlet
 # columns x 2 MLC rows x 8 control points (price).
-DOSE_TILE = (8, 8, 8)
+DOSE_TILE = (16, 8, 8)
 PRICE_TILE = (4, 2, 8)
 LAYOUTS = {"csr": 0, "panel": 1}
 
