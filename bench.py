@@ -44,16 +44,6 @@ def algorithmic_bytes(info, nrhs=1):
     return dict(dose=dose_obj, price=price, curv=curv)
 
 
-def products_source_sha():
-    """Hash of the sources the product kernels are compiled from (a counter
-    summary taken on other sources is stale)."""
-    import hashlib
-    h = hashlib.sha256()
-    for name in ("spmv_device.hpp", "spmv.hip", "spmv_panel.hip", "common.hpp"):
-        h.update(open(os.path.join(ROOT, "paper_1503_01721_amd", "csrc", name), "rb").read())
-    return h.hexdigest()[:16]
-
-
 def read_traffic(kernel, workload, storage, layout):
     """HBM traffic per launch from the committed counter summary, if it was taken
     on the current kernel source; else None."""
@@ -65,8 +55,8 @@ def read_traffic(kernel, workload, storage, layout):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    sha = products_source_sha()
-    if kv.get("products_source_sha256_16") != sha:
+    from paper_1503_01721_amd.profiling import products_source_sha
+    if kv.get("products_source_sha256_16") != products_source_sha():
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
