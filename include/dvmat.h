@@ -101,7 +101,8 @@ typedef struct {
  * beamlets overlap less.  Defaults depend on the storage type (below).
  * interleave (0/1, default 1): store the entries of each 256-entry chunk of a
  * block row interleaved so that each gather instruction of a wave covers
- * consecutive columns.  unit_entries: stored values per work unit (default 2048).
+ * consecutive columns.  unit_entries: stored values per work unit (0: 2048
+ * for CSR, 8192 when an orientation uses panels).
  * row_order: 0 = natural; 1 = rows stored in order of their first column
  * (empty rows last), so rows that read the same part of the input vector run
  * together (for the price matrix: beamlets covering the same slab of voxels,

@@ -575,7 +575,7 @@ dvmat_status dvmat_ddc_default_opts(int32_t storage, dvmat_build_opts* opts) {
     opts->dose_block_rows = 0;          // 0: chosen at create for the layout and storage
     opts->price_block_rows = 0;
     opts->interleave = 1;
-    opts->unit_entries = 2048;
+    opts->unit_entries = 0;             // 0: 2048 for CSR, 8192 for panels
     opts->dose_row_order = 0;
     opts->price_row_order = 1;
     opts->dose_layout = 0;
@@ -621,6 +621,9 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
         const bool f32 = storage == DVMAT_F32;
         if (o.dose_block_rows == 0) o.dose_block_rows = o.dose_layout == 1 ? (f32 ? 1 : 2) : (f32 ? 2 : 4);
         if (o.price_block_rows == 0) o.price_block_rows = o.price_layout == 1 ? 1 : (f32 ? 1 : 2);
+        // work units: on panels the gathers are cheap and each unit's start
+        // (bounds, row pointers, epilogue inputs) is the cost to amortise
+        if (o.unit_entries == 0) o.unit_entries = (o.dose_layout == 1 || o.price_layout == 1) ? 8192 : 2048;
     }
     auto okB = [](int b) { return b == 1 || b == 2 || b == 4; };
     if (!okB(o.dose_block_rows) || !okB(o.price_block_rows) || (o.interleave != 0 && o.interleave != 1) ||

@@ -108,7 +108,7 @@ def _dense(row, col, val, n_vox, n_bl):
 
 
 def _opts(dv, B=(1, 1), layout=(0, 0), grids=None, tiles=None, panel_cols=8192, order=(0, 0), interleave=1,
-          part_entries=131072):
+          part_entries=131072, unit_entries=0):
     o = dv.BuildOpts()
     assert dv.lib.dvmat_ddc_default_opts(0, ctypes.byref(o)) == 0
     o.dose_block_rows, o.price_block_rows = B
@@ -117,6 +117,7 @@ def _opts(dv, B=(1, 1), layout=(0, 0), grids=None, tiles=None, panel_cols=8192, 
     o.interleave = interleave
     o.panel_cols = panel_cols
     o.part_entries = part_entries
+    o.unit_entries = unit_entries
     if grids is not None:
         o.dose_grid[:] = grids["dose_grid"]
         o.price_grid[:] = grids["price_grid"]
@@ -163,7 +164,7 @@ def test_panel_budget_splits_tiles(dv, small):
     row, col, val = small
     info, ld, lp = _check_both(dv, row, col, val, PLAN.n_vox, PLAN.n_bl,
                                _opts(dv, (2, 1), (1, 1), PLAN.grids, (dv.DOSE_TILE, dv.PRICE_TILE), panel_cols=900,
-                                     part_entries=2000))
+                                     part_entries=2000, unit_entries=256))
     assert (ld, lp) == (1, 1)
     assert info.dose_panel_parts > info.dose_panels and info.price_panel_parts > info.price_panels
     assert info.dose_panel_cols <= 900 and info.price_panel_cols <= 900
