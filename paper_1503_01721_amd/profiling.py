@@ -23,7 +23,7 @@ import os
 import statistics
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-PRODUCT_SOURCES = ("spmv_device.hpp", "spmv.hip", "spmv_panel.hip", "common.hpp")
+PRODUCT_SOURCES = ("spmv_device.hpp", "spmv.hip", "spmv_panel.hip", "common.hpp", "ddc_host.cpp")
 
 
 def products_source_sha() -> str:
