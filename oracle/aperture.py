@@ -77,6 +77,92 @@ def select(p, n_cp, n_rows, n_cols, occupied):
     return dict(L=L, R=R, cp_price=cp_price, best=best, best_price=best_price)
 
 
+# ---------------------------------------------------------------- leaf windows
+#
+# Sec. 2.1: candidate apertures must be deliverable from the apertures already
+# chosen at the neighbouring control points (the leaves travel a bounded
+# distance between control points).  Readings: the bound is a maximum leaf
+# travel of `travel` beamlets per control-point step; it gives each leaf row a
+# window (Lmin, Lmax, Rmin, Rmax) of allowed leaf positions, intersected over
+# the occupied neighbours k-1 and k+1; an opening [L, R) is allowed iff
+# Lmin <= L <= Lmax and Rmin <= R <= Rmax; a closed row parks both leaves at
+# one allowed position p (L = R = p, sum 0).  Ties as above: smallest sum,
+# then shortest, then smallest L (so a closed row parks at the smallest
+# allowed p; with the full window that is (0, 0)).  A row with no allowed
+# opening makes its control point infeasible: price +inf, L = R = 0.
+
+def full_windows(n_cp, n_rows, n_cols):
+    w = np.zeros((n_cp, n_rows, 4), np.int32)
+    w[..., 1] = n_cols
+    w[..., 3] = n_cols
+    return w
+
+
+def leaf_windows(n_cp, n_rows, n_cols, occupied, L, R, travel):
+    """Windows [n_cp, n_rows, 4] (Lmin, Lmax, Rmin, Rmax) from the openings L, R
+    [n_cp, n_rows] of the occupied control points."""
+    occ = np.asarray(occupied, bool)
+    w = full_windows(n_cp, n_rows, n_cols)
+    for k in range(n_cp):
+        for nb in (k - 1, k + 1):
+            if 0 <= nb < n_cp and occ[nb]:
+                for r in range(n_rows):
+                    w[k, r, 0] = max(w[k, r, 0], L[nb][r] - travel)
+                    w[k, r, 1] = min(w[k, r, 1], L[nb][r] + travel)
+                    w[k, r, 2] = max(w[k, r, 2], R[nb][r] - travel)
+                    w[k, r, 3] = min(w[k, r, 3], R[nb][r] + travel)
+    return w
+
+
+def allowed(state, win):
+    (a, b), (lmin, lmax, rmin, rmax) = state, win
+    return lmin <= a <= lmax and rmin <= b <= rmax
+
+
+def best_row_windowed(row, win):
+    """Best allowed opening of one row by enumeration: (L, R, sum) or None."""
+    row = np.asarray(row, np.float64)
+    best = None
+    for (a, b) in states(len(row)):
+        if not allowed((a, b), win):
+            continue
+        key = (row[a:b].sum(), b - a, a)
+        if best is None or key < best[0]:
+            best = (key, a, b)
+    if best is None:
+        return None
+    return best[1], best[2], best[0][0]
+
+
+def select_windowed(p, n_cp, n_rows, n_cols, occupied, windows):
+    """Aperture selection with leaf windows [n_cp, n_rows, 4] (rows independent)."""
+    P = np.asarray(p, np.float64).reshape(n_cp, n_rows, n_cols)
+    occ = np.asarray(occupied, bool)
+    L = np.zeros((n_cp, n_rows), np.int32)
+    R = np.zeros((n_cp, n_rows), np.int32)
+    cp_price = np.full(n_cp, np.inf)
+    for k in range(n_cp):
+        if occ[k]:
+            continue
+        rows = [best_row_windowed(P[k, r], windows[k][r]) for r in range(n_rows)]
+        if any(x is None for x in rows):
+            continue
+        L[k] = [x[0] for x in rows]
+        R[k] = [x[1] for x in rows]
+        cp_price[k] = sum(x[2] for x in rows)
+    return _pick(L, R, cp_price, occ)
+
+
+def _pick(L, R, cp_price, occ):
+    best, best_price = -1, np.inf
+    for k in range(len(cp_price)):
+        if not occ[k] and cp_price[k] < best_price:
+            best, best_price = k, cp_price[k]
+    if best >= 0 and not best_price < 0.0:
+        best = -1
+    return dict(L=L, R=R, cp_price=cp_price, best=best, best_price=best_price)
+
+
 def best_aperture_bruteforce(p_cp):
     """Best whole aperture of one control point by enumerating the Cartesian
     product of every row's openings (tiny grids only).  p_cp: [n_rows, n_cols].
@@ -122,7 +208,7 @@ def compatible(a, b):
     return a[0] <= b[1] and b[0] <= a[1]
 
 
-def best_aperture_interdigitated_bruteforce(p_cp):
+def best_aperture_interdigitated_bruteforce(p_cp, windows=None):
     """Exhaustive search over the Cartesian product of row openings (tiny grids)."""
     p_cp = np.asarray(p_cp, np.float64)
     n_rows, n = p_cp.shape
@@ -130,6 +216,8 @@ def best_aperture_interdigitated_bruteforce(p_cp):
     sums = [[p_cp[r, a:b].sum() for (a, b) in st] for r in range(n_rows)]
     best, arg = np.inf, None
     for combo in itertools.product(range(len(st)), repeat=n_rows):
+        if windows is not None and any(not allowed(st[combo[r]], windows[r]) for r in range(n_rows)):
+            continue
         if any(not compatible(st[combo[r]], st[combo[r + 1]]) for r in range(n_rows - 1)):
             continue
         s = sum(sums[r][combo[r]] for r in range(n_rows))
@@ -138,16 +226,20 @@ def best_aperture_interdigitated_bruteforce(p_cp):
     return best, arg
 
 
-def best_aperture_interdigitated(p_cp):
+def best_aperture_interdigitated(p_cp, windows=None):
     """Best aperture of one control point under interdigitation, by dynamic
     programming over the leaf rows: value[r][s] = rowsum_r(s) + min over
-    states s' of row r-1 compatible with s of value[r-1][s'].
-    Returns (price, openings [(L, R)] per row)."""
+    states s' of row r-1 compatible with s of value[r-1][s'] (states outside
+    a row's leaf window cost +inf).
+    Returns (price, openings [(L, R)] per row); price +inf if infeasible."""
     p_cp = np.asarray(p_cp, np.float64)
     n_rows, n = p_cp.shape
     st = states(n)
     cs = np.concatenate([np.zeros((n_rows, 1)), np.cumsum(p_cp, axis=1)], axis=1)
     rowsum = np.array([[cs[r, b] - cs[r, a] for (a, b) in st] for r in range(n_rows)])
+    if windows is not None:
+        for r in range(n_rows):
+            rowsum[r, [not allowed(x, windows[r]) for x in st]] = np.inf
     value = [rowsum[0].copy()]
     choice = []
     comp = np.array([[compatible(s1, s2) for s2 in st] for s1 in st])   # [prev, cur]
@@ -165,8 +257,9 @@ def best_aperture_interdigitated(p_cp):
     return float(value[-1][last]), [st[i] for i in path]
 
 
-def select_interdigitated(p, n_cp, n_rows, n_cols, occupied):
-    """Aperture selection under interdigitation over the unoccupied control points."""
+def select_interdigitated(p, n_cp, n_rows, n_cols, occupied, windows=None):
+    """Aperture selection under interdigitation over the unoccupied control
+    points (optionally within leaf windows [n_cp, n_rows, 4])."""
     P = np.asarray(p, np.float64).reshape(n_cp, n_rows, n_cols)
     occ = np.asarray(occupied, bool)
     L = np.zeros((n_cp, n_rows), np.int32)
@@ -175,7 +268,9 @@ def select_interdigitated(p, n_cp, n_rows, n_cols, occupied):
     for k in range(n_cp):
         if occ[k]:
             continue
-        v, path = best_aperture_interdigitated(P[k])
+        v, path = best_aperture_interdigitated(P[k], None if windows is None else windows[k])
+        if not np.isfinite(v):
+            continue
         cp_price[k] = v
         L[k] = [a for a, _ in path]
         R[k] = [b for _, b in path]

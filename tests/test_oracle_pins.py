@@ -4,6 +4,7 @@ Each test checks the oracle against something other than itself: dense
 brute force, identities, closed forms, finite differences, exhaustive
 enumeration, library least-squares solvers, or printed numbers of the paper.
 """
+import itertools
 import json
 import math
 import os
@@ -497,3 +498,84 @@ def test_interdigitation_binds_on_hand_built_case():
     v, path = ap.best_aperture_interdigitated(p_cp)
     assert v == -19.0            # e.g. row 0 takes [0, 3): -9, row 1 takes [3, 5): -10
     assert ap.compatible(path[0], path[1])
+
+
+# ---------------------------------------------------------------- leaf windows
+
+def test_windowed_row_hand_worked():
+    row = [-1.0, -2.0, 3.0, -4.0]
+    # unconstrained: [3, 4) with -4 beats the whole row (-4, longer)
+    assert ap.best_row_windowed(row, (0, 4, 0, 4)) == (3, 4, -4.0)
+    # L in [1, 2], R in [2, 3]: [1, 2) = -2 is the best allowed opening
+    assert ap.best_row_windowed(row, (1, 2, 2, 3)) == (1, 2, -2.0)
+    # both leaves pinned to 2: the row closes there
+    assert ap.best_row_windowed(row, (2, 2, 2, 2)) == (2, 2, 0.0)
+    # a closed row parks at the smallest position allowed to both leaves
+    assert ap.best_row_windowed([1.0, 1.0, 1.0], (1, 3, 2, 3)) == (2, 2, 0.0)
+    # no opening allowed: Lmin > Rmax
+    assert ap.best_row_windowed(row, (3, 4, 0, 2)) is None
+
+
+def test_leaf_windows_from_neighbours_hand_worked():
+    L = [[2], [0], [6]]
+    R = [[5], [0], [9]]
+    w = ap.leaf_windows(3, 1, 10, [True, False, True], L, R, 2)
+    assert w[1, 0].tolist() == [4, 4, 7, 7]           # both neighbours, travel 2
+    assert w[0, 0].tolist() == [0, 10, 0, 10]         # neighbour 1 unoccupied
+    assert w[2, 0].tolist() == [0, 10, 0, 10]
+    w = ap.leaf_windows(3, 1, 10, [True, False, False], L, R, 3)
+    assert w[1, 0].tolist() == [0, 5, 2, 8]
+    # the pinned windows select exactly that opening, or close the row where allowed
+    p = np.array([1.0] * 10)
+    out = ap.select_windowed(np.tile(p, 3), 3, 1, 10, [True, False, True],
+                              ap.leaf_windows(3, 1, 10, [True, False, True], L, R, 2))
+    assert (out["L"][1, 0], out["R"][1, 0]) == (4, 7) and out["cp_price"][1] == 3.0
+
+
+def test_full_windows_reproduce_the_unconstrained_selection():
+    rng = np.random.default_rng(41)
+    for _ in range(20):
+        n_cp, n_rows, n_cols = 5, 3, 7
+        p = rng.integers(-3, 4, size=n_cp * n_rows * n_cols).astype(np.float64)
+        occ = rng.random(n_cp) < 0.3
+        a = ap.select(p, n_cp, n_rows, n_cols, occ)
+        b = ap.select_windowed(p, n_cp, n_rows, n_cols, occ, ap.full_windows(n_cp, n_rows, n_cols))
+        assert np.array_equal(a["L"], b["L"]) and np.array_equal(a["R"], b["R"])
+        assert np.array_equal(a["cp_price"], b["cp_price"]) and a["best"] == b["best"]
+        c = ap.select_interdigitated(p, n_cp, n_rows, n_cols, occ)
+        d = ap.select_interdigitated(p, n_cp, n_rows, n_cols, occ, ap.full_windows(n_cp, n_rows, n_cols))
+        assert np.array_equal(c["cp_price"], d["cp_price"]) and np.array_equal(c["L"], d["L"])
+
+
+def _random_windows(rng, n_cp, n_rows, n_cols):
+    w = np.zeros((n_cp, n_rows, 4), np.int32)
+    for k in range(n_cp):
+        for r in range(n_rows):
+            a, b = sorted(rng.integers(0, n_cols + 1, 2))
+            c, d = sorted(rng.integers(0, n_cols + 1, 2))
+            w[k, r] = (a, b, c, d)
+    return w
+
+
+def test_windowed_selection_against_exhaustive_search():
+    rng = np.random.default_rng(42)
+    for _ in range(30):
+        n_rows, n_cols = 3, 4
+        P = rng.integers(-3, 4, size=(1, n_rows, n_cols)).astype(np.float64)
+        w = _random_windows(rng, 1, n_rows, n_cols)
+        out = ap.select_windowed(P.ravel(), 1, n_rows, n_cols, [False], w)
+        # whole apertures: every combination of allowed row openings
+        st = ap.states(n_cols)
+        best = np.inf
+        for combo in itertools.product(st, repeat=n_rows):
+            if all(ap.allowed(combo[r], w[0, r]) for r in range(n_rows)):
+                best = min(best, sum(P[0, r, a:b].sum() for r, (a, b) in enumerate(combo)))
+        assert out["cp_price"][0] == best
+        # interdigitated within the same windows: DP against exhaustive search
+        v, path = ap.best_aperture_interdigitated(P[0], w[0])
+        vb, arg = ap.best_aperture_interdigitated_bruteforce(P[0], w[0])
+        assert v == vb
+        if np.isfinite(v):
+            assert all(ap.allowed(path[r], w[0, r]) for r in range(n_rows))
+            assert all(ap.compatible(path[r], path[r + 1]) for r in range(n_rows - 1))
+            assert sum(P[0, r, a:b].sum() for r, (a, b) in enumerate(path)) == v
