@@ -268,15 +268,22 @@ dvmat_status dvmat_dose_curvature(dvmat_ddc ddc, const float* x_dir, dvmat_obj o
 typedef struct { int32_t n_cp, n_rows, n_cols; } dvmat_geom;
 
 /* p: device float[n_cp*n_rows*n_cols]; occupied: device uint8[n_cp] (nonzero =
- * occupied, nullable = none); L, R: device int32[n_cp][n_rows] (occupied
- * control points get 0, 0); cp_price: device float[n_cp] (+inf if occupied);
- * best: device int32[1] = the chosen control point, or -1 when no unoccupied
- * control point has a price < 0 (the column generation stops, Sec. 2.1);
- * best_price: device float[1] (the smallest price, +inf if all are occupied).
- * Limits: n_cols <= 1024 and n_rows*(n_cols+1) <= 16384 (one control point's
- * prices are staged in 64 KiB of LDS). */
+ * occupied, nullable = none); leaf_window: device int32[n_cp][n_rows][4]
+ * (Lmin, Lmax, Rmin, Rmax; nullable = no limits): an opening [L, R) is
+ * allowed iff Lmin <= L <= Lmax and Rmin <= R <= Rmax, a closed row parks at
+ * the smallest position allowed to both leaves (Sec. 2.1: candidates must be
+ * deliverable after the apertures at occupied neighbouring control points;
+ * see dvmat_leaf_windows); a control point with a row that has no allowed
+ * opening is infeasible (price +inf).  L, R: device int32[n_cp][n_rows]
+ * (occupied and infeasible control points get 0, 0); cp_price: device
+ * float[n_cp] (+inf if occupied or infeasible); best: device int32[1] = the
+ * chosen control point, or -1 when no control point has a price < 0 (the
+ * column generation stops, Sec. 2.1); best_price: device float[1] (the
+ * smallest price, +inf if none is feasible).  Limits: n_cols <= 1024 and
+ * n_rows*(n_cols+1) <= 16384 (one control point's prices are staged in
+ * 64 KiB of LDS). */
 dvmat_status dvmat_aperture_select(dvmat_geom geom, const float* p, const uint8_t* occupied,
-                                   int32_t* L, int32_t* R, float* cp_price,
+                                   const int32_t* leaf_window, int32_t* L, int32_t* R, float* cp_price,
                                    int32_t* best, float* best_price, dvmat_stream stream);
 
 /* Aperture selection under the interdigitation constraint of Sec. 2.2.2,
@@ -284,12 +291,25 @@ dvmat_status dvmat_aperture_select(dvmat_geom geom, const float* p, const uint8_
  * L_{r+1} <= R_r, so the rows are coupled; a closed row may park at any
  * position p (L = R = p, sum 0).  Exact minimum over all feasible apertures
  * by dynamic programming over the rows (state = one row's opening); ties go to
- * the smallest state index, states ordered by L then R.  Outputs as
- * dvmat_aperture_select.  n_cols <= 96 (the row DP works in LDS); d_workspace: device memory of
+ * the smallest state index, states ordered by L then R.  Leaf windows and
+ * outputs as dvmat_aperture_select.  n_cols <= 96 (the row DP works in LDS); d_workspace: device memory of
  * dvmat_aperture_select_ws_size bytes (per-row state values for backtracking). */
 dvmat_status dvmat_aperture_select_ws_size(dvmat_geom geom, size_t* bytes);
+
+/* Leaf windows from the apertures at occupied control points (Sec. 2.1):
+ * occupied device uint8[n_cp]; L, R device int32[n_cp][n_rows], the openings
+ * of the aperture at each occupied control point (other entries are not
+ * read); travel: the largest leaf movement between adjacent control points,
+ * in beamlets (a reading: the paper bounds it through gantry speed and leaf
+ * speed, parameters given in references it cites).  Writes leaf_window
+ * device int32[n_cp][n_rows][4]: for each row, each leaf within travel of
+ * its position at the occupied neighbours k-1 and k+1, intersected with
+ * [0, n_cols]. */
+dvmat_status dvmat_leaf_windows(dvmat_geom geom, const uint8_t* occupied, const int32_t* L, const int32_t* R,
+                                int32_t travel, int32_t* leaf_window, dvmat_stream stream);
 dvmat_status dvmat_aperture_select_interdigitated(dvmat_geom geom, const float* p, const uint8_t* occupied,
-                                                  int32_t* L, int32_t* R, float* cp_price,
+                                                  const int32_t* leaf_window, int32_t* L, int32_t* R,
+                                                  float* cp_price,
                                                   int32_t* best, float* best_price,
                                                   void* d_workspace, size_t bytes, dvmat_stream stream);
 

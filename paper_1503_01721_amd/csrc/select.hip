@@ -20,12 +20,26 @@
 
 namespace dvmat {
 
+// Leaf window of one row: (Lmin, Lmax, Rmin, Rmax), clamped to [0, n]; the
+// full window when none is given.
+struct Window {
+    int lmin, lmax, rmin, rmax;
+};
+
+__device__ __forceinline__ Window row_window(const int32_t* win, int64_t kr, int n) {
+    if (!win) return Window{0, n, 0, n};
+    const int4 w = reinterpret_cast<const int4*>(win)[kr];
+    return Window{max(w.x, 0), min(w.y, n), max(w.z, 0), min(w.w, n)};
+}
+
 __global__ __launch_bounds__(256) void select_rows_kernel(int n_rows, int n_cols, const float* __restrict__ p,
-                                                          const uint8_t* __restrict__ occ, int32_t* __restrict__ L,
+                                                          const uint8_t* __restrict__ occ,
+                                                          const int32_t* __restrict__ win, int32_t* __restrict__ L,
                                                           int32_t* __restrict__ R, float* __restrict__ cp_price) {
     extern __shared__ float sm[];
     float* sp = sm;                          // [n_rows * n_cols]
     float* rowsum = sm + n_rows * n_cols;    // [n_rows]
+    __shared__ int infeasible;
     const int k = blockIdx.x;
     const int per_cp = n_rows * n_cols;
     const bool occupied = occ != nullptr && occ[k] != 0;
@@ -37,41 +51,78 @@ __global__ __launch_bounds__(256) void select_rows_kernel(int n_rows, int n_cols
         if (threadIdx.x == 0) cp_price[k] = INFINITY;
         return;
     }
+    if (threadIdx.x == 0) infeasible = 0;
     const float* pk = p + (int64_t)k * per_cp;
     for (int i = threadIdx.x; i < per_cp; i += blockDim.x) sp[i] = pk[i];
     __syncthreads();
     for (int r = threadIdx.x; r < n_rows; r += blockDim.x) {
         const float* row = sp + r * n_cols;
+        const Window w = row_window(win, (int64_t)k * n_rows + r, n_cols);
+        // R runs 0..n; before R is considered, L = R joins the running maximum
+        // of prefix sums over allowed L (last index of the maximum = shortest)
         float prefix = 0.0f;
         float max_prefix = 0.0f;
-        int arg_l = 0;
-        float best_s = 0.0f;
+        int arg_l = -1;
+        float best_s = INFINITY;
         int best_l = 0, best_r = 0, best_len = 0;
-        for (int rr = 1; rr <= n_cols; ++rr) {
-            prefix += row[rr - 1];
-            const float s = prefix - max_prefix;
-            const int len = rr - arg_l;
-            if (s < best_s || (s == best_s && len < best_len)) {
-                best_s = s;
-                best_l = arg_l;
-                best_r = rr;
-                best_len = len;
-            }
-            if (prefix >= max_prefix) {
+        for (int rr = 0; rr <= n_cols; ++rr) {
+            if (rr > 0) prefix += row[rr - 1];
+            if (rr >= w.lmin && rr <= w.lmax && (arg_l < 0 || prefix >= max_prefix)) {
                 max_prefix = prefix;
                 arg_l = rr;
             }
+            if (rr >= w.rmin && rr <= w.rmax && arg_l >= 0) {
+                const float s = prefix - max_prefix;
+                const int len = rr - arg_l;
+                if (s < best_s || (s == best_s && len < best_len)) {
+                    best_s = s;
+                    best_l = arg_l;
+                    best_r = rr;
+                    best_len = len;
+                }
+            }
         }
+        if (best_s == INFINITY) atomicOr(&infeasible, 1);    // LDS flag: no allowed opening
         L[(int64_t)k * n_rows + r] = best_l;
         R[(int64_t)k * n_rows + r] = best_r;
         rowsum[r] = best_s;
     }
     __syncthreads();
+    if (infeasible) {
+        for (int r = threadIdx.x; r < n_rows; r += blockDim.x) {
+            L[(int64_t)k * n_rows + r] = 0;
+            R[(int64_t)k * n_rows + r] = 0;
+        }
+        if (threadIdx.x == 0) cp_price[k] = INFINITY;
+        return;
+    }
     if (threadIdx.x == 0) {
         float s = 0.0f;
         for (int r = 0; r < n_rows; ++r) s += rowsum[r];
         cp_price[k] = s;
     }
+}
+
+// Leaf windows from the openings L, R [n_cp][n_rows] of the occupied
+// neighbouring control points k-1 and k+1: each leaf within travel beamlets.
+__global__ __launch_bounds__(256) void leaf_windows_kernel(int n_cp, int n_rows, int n_cols,
+                                                           const uint8_t* __restrict__ occ,
+                                                           const int32_t* __restrict__ L,
+                                                           const int32_t* __restrict__ R, int travel,
+                                                           int32_t* __restrict__ win) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_cp * n_rows) return;
+    const int k = (int)(i / n_rows), r = (int)(i % n_rows);
+    int4 w = make_int4(0, n_cols, 0, n_cols);
+    for (int nb = k - 1; nb <= k + 1; nb += 2) {
+        if (nb < 0 || nb >= n_cp || !occ[nb]) continue;
+        const int64_t j = (int64_t)nb * n_rows + r;
+        w.x = max(w.x, L[j] - travel);
+        w.y = min(w.y, L[j] + travel);
+        w.z = max(w.z, R[j] - travel);
+        w.w = min(w.w, R[j] + travel);
+    }
+    reinterpret_cast<int4*>(win)[i] = w;
 }
 
 __global__ __launch_bounds__(256) void select_best_kernel(int n_cp, const float* __restrict__ cp_price,
@@ -123,6 +174,7 @@ __device__ __forceinline__ int tri_index(int L, int R, int n) { return L * (n + 
 
 __global__ __launch_bounds__(256) void select_interdig_kernel(int n_rows, int n, const float* __restrict__ p,
                                                               const uint8_t* __restrict__ occ,
+                                                              const int32_t* __restrict__ win,
                                                               int32_t* __restrict__ L, int32_t* __restrict__ R,
                                                               float* __restrict__ cp_price,
                                                               float* __restrict__ hist) {
@@ -182,6 +234,10 @@ __global__ __launch_bounds__(256) void select_interdig_kernel(int n_rows, int n,
             const int Ro = Lo + (s - off);
             float v = pre[Ro] - pre[Lo];
             if (r > 0) v += grid[Ro * W + Lo];
+            if (win) {
+                const Window w = row_window(win, (int64_t)k * n_rows + r, n);
+                if (Lo < w.lmin || Lo > w.lmax || Ro < w.rmin || Ro > w.rmax) v = INFINITY;   // outside the leaf window
+            }
             cur[s] = v;
             hk[(int64_t)r * S + s] = v;
         }
@@ -209,6 +265,13 @@ __global__ __launch_bounds__(256) void select_interdig_kernel(int n_rows, int n,
         state = ri[0];
     }
     __syncthreads();
+    if (!(rv[0] < INFINITY)) {                       // no aperture fits the leaf windows
+        for (int r = tid; r < n_rows; r += blockDim.x) {
+            L[(int64_t)k * n_rows + r] = 0;
+            R[(int64_t)k * n_rows + r] = 0;
+        }
+        return;
+    }
     for (int r = n_rows - 1; r >= 0; --r) {
         const int s = state;
         int Ls = 0, off = 0;
@@ -251,9 +314,9 @@ __global__ __launch_bounds__(256) void select_interdig_kernel(int n_rows, int n,
 
 using namespace dvmat;
 
-extern "C" dvmat_status dvmat_aperture_select(dvmat_geom geom, const float* p, const uint8_t* occupied, int32_t* L,
-                                              int32_t* R, float* cp_price, int32_t* best, float* best_price,
-                                              dvmat_stream stream) {
+extern "C" dvmat_status dvmat_aperture_select(dvmat_geom geom, const float* p, const uint8_t* occupied,
+                                              const int32_t* leaf_window, int32_t* L, int32_t* R, float* cp_price,
+                                              int32_t* best, float* best_price, dvmat_stream stream) {
     if (geom.n_cp < 1 || geom.n_rows < 1 || geom.n_cols < 1)
         return set_error(DVMAT_E_SHAPE, "dvmat_aperture_select: geometry %d x %d x %d", geom.n_cp, geom.n_rows,
                          geom.n_cols);
@@ -265,7 +328,7 @@ extern "C" dvmat_status dvmat_aperture_select(dvmat_geom geom, const float* p, c
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const size_t lds = ((size_t)geom.n_rows * geom.n_cols + geom.n_rows) * sizeof(float);
     hipLaunchKernelGGL(select_rows_kernel, dim3(geom.n_cp), dim3(256), lds, s, geom.n_rows, geom.n_cols, p, occupied,
-                       L, R, cp_price);
+                       leaf_window, L, R, cp_price);
     hipLaunchKernelGGL(select_best_kernel, dim3(1), dim3(256), 0, s, geom.n_cp, cp_price, best, best_price);
     return check_hip(hipGetLastError(), "dvmat_aperture_select launch");
 }
@@ -281,7 +344,7 @@ extern "C" dvmat_status dvmat_aperture_select_ws_size(dvmat_geom geom, size_t* b
 }
 
 extern "C" dvmat_status dvmat_aperture_select_interdigitated(dvmat_geom geom, const float* p, const uint8_t* occupied,
-                                                             int32_t* L, int32_t* R, float* cp_price, int32_t* best,
+                                                             const int32_t* leaf_window, int32_t* L, int32_t* R, float* cp_price, int32_t* best,
                                                              float* best_price, void* d_workspace, size_t bytes,
                                                              dvmat_stream stream) {
     size_t need = 0;
@@ -296,7 +359,22 @@ extern "C" dvmat_status dvmat_aperture_select_interdigitated(dvmat_geom geom, co
     const int S = W * (W + 1) / 2;
     const size_t lds = ((size_t)W * W + S + W) * sizeof(float);
     hipLaunchKernelGGL(select_interdig_kernel, dim3(geom.n_cp), dim3(256), lds, s, geom.n_rows, geom.n_cols, p,
-                       occupied, L, R, cp_price, static_cast<float*>(d_workspace));
+                       occupied, leaf_window, L, R, cp_price, static_cast<float*>(d_workspace));
     hipLaunchKernelGGL(select_best_kernel, dim3(1), dim3(256), 0, s, geom.n_cp, cp_price, best, best_price);
     return check_hip(hipGetLastError(), "dvmat_aperture_select_interdigitated launch");
+}
+
+extern "C" dvmat_status dvmat_leaf_windows(dvmat_geom geom, const uint8_t* occupied, const int32_t* L,
+                                           const int32_t* R, int32_t travel, int32_t* leaf_window,
+                                           dvmat_stream stream) {
+    if (geom.n_cp < 1 || geom.n_rows < 1 || geom.n_cols < 1)
+        return set_error(DVMAT_E_SHAPE, "dvmat_leaf_windows: geometry %d x %d x %d", geom.n_cp, geom.n_rows,
+                         geom.n_cols);
+    if (!occupied || !L || !R || !leaf_window) return set_error(DVMAT_E_ARG, "dvmat_leaf_windows: NULL argument");
+    if (travel < 0) return set_error(DVMAT_E_ARG, "dvmat_leaf_windows: travel %d < 0", travel);
+    const int64_t n = (int64_t)geom.n_cp * geom.n_rows;
+    hipLaunchKernelGGL(leaf_windows_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       reinterpret_cast<hipStream_t>(stream), geom.n_cp, geom.n_rows, geom.n_cols, occupied, L, R,
+                       travel, leaf_window);
+    return check_hip(hipGetLastError(), "dvmat_leaf_windows launch");
 }

@@ -111,9 +111,10 @@ _SIGNATURES = {
                                     ctypes.POINTER(_P), _I32, _I32, _P]),
     "dvmat_batch_set_kernel": (_I32, [_P, _I32, _I32, _I32]),
     "dvmat_batch_info": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I32)]),
-    "dvmat_aperture_select": (_I32, [Geom, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "dvmat_aperture_select": (_I32, [Geom, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "dvmat_leaf_windows": (_I32, [Geom, _P, _P, _P, _I32, _P, _P]),
     "dvmat_aperture_select_ws_size": (_I32, [Geom, ctypes.POINTER(_SZ)]),
-    "dvmat_aperture_select_interdigitated": (_I32, [Geom, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "dvmat_aperture_select_interdigitated": (_I32, [Geom, _P, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "dvmat_bb_workspace_size": (_I32, [Geom, _I32, ctypes.POINTER(_SZ)]),
     "dvmat_bb_create": (_I32, [Geom, _I32, BBParams, _P, _SZ, _P, ctypes.POINTER(_P)]),
     "dvmat_bb_destroy": (None, [_P]),
@@ -392,27 +393,45 @@ class ApertureSelector:
         self.best = torch.empty(1, dtype=torch.int32, device=dev)
         self.best_price = torch.empty(1, dtype=torch.float32, device=dev)
 
-    def __call__(self, p, occupied=None, stream=None):
+    def __call__(self, p, occupied=None, stream=None, windows=None):
+        """windows: device int32 [n_cp, n_rows, 4] leaf windows (Lmin, Lmax, Rmin, Rmax) or None."""
         g = self.geom
         _need(p, g.n_cp * g.n_rows * g.n_cols, name="p")
         if not isinstance(occupied, ctypes.c_void_p):
             _need(occupied, g.n_cp, torch.uint8, name="occupied")
         occ = occupied if isinstance(occupied, ctypes.c_void_p) else _ptr(occupied)
+        _need(windows, g.n_cp * g.n_rows * 4, torch.int32, name="windows")
+        win = _ptr(windows)
         if self.interdigitated:
             _check(lib.dvmat_aperture_select_interdigitated(
-                self.geom, _ptr(p), occ, _ptr(self.L), _ptr(self.R), _ptr(self.cp_price), _ptr(self.best),
+                self.geom, _ptr(p), occ, win, _ptr(self.L), _ptr(self.R), _ptr(self.cp_price), _ptr(self.best),
                 _ptr(self.best_price), _ptr(self.ws), self.ws.numel(), _stream(stream)))
             return self
-        _check(lib.dvmat_aperture_select(self.geom, _ptr(p), occ, _ptr(self.L), _ptr(self.R),
+        _check(lib.dvmat_aperture_select(self.geom, _ptr(p), occ, win, _ptr(self.L), _ptr(self.R),
                                          _ptr(self.cp_price), _ptr(self.best), _ptr(self.best_price),
                                          _stream(stream)))
         return self
 
 
-def aperture_select(p, n_cp, n_rows, n_cols, occupied=None, interdigitated=False):
+def aperture_select(p, n_cp, n_rows, n_cols, occupied=None, interdigitated=False, windows=None):
     sel = ApertureSelector(n_cp, n_rows, n_cols, device=p.device, interdigitated=interdigitated)
-    sel(p, occupied)
+    sel(p, occupied, windows=windows)
     return dict(L=sel.L, R=sel.R, cp_price=sel.cp_price, best=sel.best, best_price=sel.best_price)
+
+
+def leaf_windows(n_cp, n_rows, n_cols, occupied, L, R, travel, out=None, stream=None):
+    """Leaf windows [n_cp, n_rows, 4] from the openings L, R [n_cp, n_rows] at
+    the occupied control points (each leaf within travel beamlets of its
+    position at the occupied neighbours)."""
+    geom = Geom(n_cp, n_rows, n_cols)
+    _need(occupied, n_cp, torch.uint8, name="occupied")
+    _need(L, n_cp * n_rows, torch.int32, name="L")
+    _need(R, n_cp * n_rows, torch.int32, name="R")
+    if out is None:
+        out = torch.empty((n_cp, n_rows, 4), dtype=torch.int32, device=L.device)
+    _need(out, n_cp * n_rows * 4, torch.int32, name="out")
+    _check(lib.dvmat_leaf_windows(geom, _ptr(occupied), _ptr(L), _ptr(R), int(travel), _ptr(out), _stream(stream)))
+    return out
 
 
 class BB:

@@ -116,12 +116,14 @@ def test_bb_and_select_argument_checks(dv):
     assert dv.lib.dvmat_bb_workspace_size(g, 4, ctypes.byref(n)) == 0 and n.value > 0
     assert dv.lib.dvmat_bb_workspace_size(dv.Geom(0, 3, 5), 1, ctypes.byref(n)) == -2
     big = dv.Geom(2, 200, 200)
-    assert dv.lib.dvmat_aperture_select(big, None, None, None, None, None, None, None, None) == -2
-    assert dv.lib.dvmat_aperture_select(g, None, None, None, None, None, None, None, None) == -1
+    assert dv.lib.dvmat_aperture_select(big, None, None, None, None, None, None, None, None, None) == -2
+    assert dv.lib.dvmat_aperture_select(g, None, None, None, None, None, None, None, None, None) == -1
+    assert dv.lib.dvmat_leaf_windows(g, None, None, None, 1, None, None) == -1
+    assert dv.lib.dvmat_leaf_windows(dv.Geom(0, 3, 5), None, None, None, 1, None, None) == -2
     assert dv.lib.dvmat_aperture_select_ws_size(dv.Geom(4, 3, 5), ctypes.byref(n)) == 0
     assert n.value == 4 * 3 * (6 * 7 // 2) * 4                  # one FP32 value per row state
     assert dv.lib.dvmat_aperture_select_ws_size(dv.Geom(4, 3, 97), ctypes.byref(n)) == -2
-    assert dv.lib.dvmat_aperture_select_interdigitated(g, None, None, None, None, None, None, None, None,
+    assert dv.lib.dvmat_aperture_select_interdigitated(g, None, None, None, None, None, None, None, None, None,
                                                        0, None) == -1
     assert dv.lib.dvmat_obj_workspace_size(0, ctypes.byref(n)) == -1
     assert dv.lib.dvmat_obj_workspace_size(5, ctypes.byref(n)) == 0

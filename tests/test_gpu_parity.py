@@ -314,6 +314,86 @@ def test_aperture_select_interdigitated_widest_rows(dv):
     assert np.array_equal(out["R"].cpu().numpy(), ref["R"])
 
 
+def _random_windows(rng, n_cp, n_rows, n_cols, p_wide=0.5):
+    w = np.zeros((n_cp, n_rows, 4), np.int32)
+    for k in range(n_cp):
+        for r in range(n_rows):
+            if rng.random() < p_wide:
+                w[k, r] = (0, n_cols, 0, n_cols)
+            else:
+                a, b = sorted(rng.integers(0, n_cols + 1, 2))
+                c, d = sorted(rng.integers(0, n_cols + 1, 2))
+                w[k, r] = (a, b, c, d)
+    return w
+
+
+def test_leaf_windows_kernel_matches_oracle(dv):
+    rng = np.random.default_rng(51)
+    n_cp, n_rows, n_cols = 37, 9, 23
+    occ = (rng.random(n_cp) < 0.5).astype(np.uint8)
+    L = rng.integers(0, n_cols + 1, (n_cp, n_rows)).astype(np.int32)
+    R = np.maximum(L, rng.integers(0, n_cols + 1, (n_cp, n_rows))).astype(np.int32)
+    for travel in (0, 1, 3, 100):
+        ref = oap.leaf_windows(n_cp, n_rows, n_cols, occ.astype(bool), L, R, travel)
+        out = dv.leaf_windows(n_cp, n_rows, n_cols, cuda(occ), cuda(L), cuda(R), travel)
+        assert np.array_equal(out.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("interdigitated", [False, True])
+def test_windowed_selection_exact_integer_prices(dv, interdigitated):
+    rng = np.random.default_rng(52 + interdigitated)
+    n_cp, n_rows, n_cols = 19, 6, 9
+    for trial in range(3):
+        p = rng.integers(-5, 6, size=(n_cp, n_rows, n_cols)).astype(np.float32)
+        p[rng.random(p.shape) < 0.3] = 0.0
+        occ = (rng.random(n_cp) < 0.2).astype(np.uint8)
+        w = _random_windows(rng, n_cp, n_rows, n_cols, p_wide=0.7)
+        if interdigitated:
+            ref = oap.select_interdigitated(p.ravel(), n_cp, n_rows, n_cols, occ.astype(bool), w)
+        else:
+            ref = oap.select_windowed(p.ravel(), n_cp, n_rows, n_cols, occ.astype(bool), w)
+        out = dv.aperture_select(cuda(p.ravel()), n_cp, n_rows, n_cols, cuda(occ), interdigitated=interdigitated,
+                                 windows=cuda(w))
+        assert np.array_equal(out["cp_price"].cpu().numpy().astype(np.float64), ref["cp_price"])
+        assert np.array_equal(out["L"].cpu().numpy(), ref["L"])
+        assert np.array_equal(out["R"].cpu().numpy(), ref["R"])
+        assert int(out["best"].cpu()[0]) == ref["best"]
+        assert np.isinf(ref["cp_price"]).sum() > occ.sum() or trial > 0 or interdigitated
+    # the full window gives the unconstrained selection
+    full = oap.full_windows(n_cp, n_rows, n_cols)
+    a = dv.aperture_select(cuda(p.ravel()), n_cp, n_rows, n_cols, cuda(occ), interdigitated=interdigitated)
+    b = dv.aperture_select(cuda(p.ravel()), n_cp, n_rows, n_cols, cuda(occ), interdigitated=interdigitated,
+                           windows=cuda(full))
+    for key in ("L", "R", "cp_price", "best"):
+        assert torch.equal(a[key], b[key])
+
+
+def test_windowed_selection_real_prices(dv, plan1):
+    d, sid, table, ddc, obj = plan1
+    z, g, F = ddc.dose(torch.zeros(PLAN1.n_bl, device="cuda"), obj, with_grad=True)
+    p = ddc.price(g)
+    p64 = p.cpu().numpy().astype(np.float64)
+    n_cp, n_rows, n_cols = PLAN1.n_cp, PLAN1.n_rows, PLAN1.n_cols
+    rng = np.random.default_rng(53)
+    occ = np.zeros(n_cp, bool)
+    occ[rng.choice(n_cp, 6, replace=False)] = True
+    base = oap.select(p64, n_cp, n_rows, n_cols, np.zeros(n_cp, bool))
+    L, R = base["L"], base["R"]
+    for travel in (1, 3):
+        w = oap.leaf_windows(n_cp, n_rows, n_cols, occ, L, R, travel)
+        ref = oap.select_windowed(p64, n_cp, n_rows, n_cols, occ, w)
+        out = dv.aperture_select(p, n_cp, n_rows, n_cols, cuda(occ.astype(np.uint8)), windows=cuda(w))
+        Lg, Rg = out["L"].cpu().numpy(), out["R"].cpu().numpy()
+        P = p64.reshape(n_cp, n_rows, n_cols)
+        bound = 64 * 2.0 ** -24 * np.abs(P).sum(axis=2)
+        for k in np.nonzero(~occ)[0]:
+            for r in range(n_rows):
+                assert oap.allowed((Lg[k, r], Rg[k, r]), w[k, r])
+                s = P[k, r, Lg[k, r]:Rg[k, r]].sum()
+                s_ref = P[k, r, ref["L"][k, r]:ref["R"][k, r]].sum()
+                assert abs(s - s_ref) <= bound[k, r]
+
+
 # ---------------------------------------------------------------- master problem
 
 def _device_apertures(dv, plan, m, seed, lo, hi, max_iter, eps_f=0.0, eps_step=0.0):
