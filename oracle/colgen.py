@@ -9,7 +9,10 @@ Readings where the paper is silent: a new aperture starts at its lower bound
 and the other rates keep their values (warm start); the loop stops when the
 best aperture price is >= 0, when every control point is occupied, or after
 max_cg iterations; the prices used by the next pricing step are those at the
-master problem's final iterate.
+master problem's final iterate.  Options: the interdigitation constraint
+(Sec. 2.2.2) and leaf windows from the apertures at occupied neighbouring
+control points (Sec. 2.1, maximum leaf travel per control-point step; the
+readings are in aperture.py).
 """
 from __future__ import annotations
 
@@ -21,8 +24,20 @@ from . import objective as obj
 from . import products
 
 
+def select_aperture(p, n_cp, n_rows, n_cols, occupied, L_all, R_all, interdigitated=False, leaf_travel=None):
+    """The aperture selection of one iteration under the chosen constraints."""
+    windows = None
+    if leaf_travel is not None:
+        windows = ap.leaf_windows(n_cp, n_rows, n_cols, occupied, L_all, R_all, leaf_travel)
+    if interdigitated:
+        return ap.select_interdigitated(p, n_cp, n_rows, n_cols, occupied, windows)
+    if windows is not None:
+        return ap.select_windowed(p, n_cp, n_rows, n_cols, occupied, windows)
+    return ap.select(p, n_cp, n_rows, n_cols, occupied)
+
+
 def run(row, col, val, n_vox, n_cp, n_rows, n_cols, sid, table, max_cg,
-        params=bb.BBParams(), lo=0.0, hi=np.inf, form="D"):
+        params=bb.BBParams(), lo=0.0, hi=np.inf, form="D", interdigitated=False, leaf_travel=None):
     """Returns dict(apertures=[(cp, L, R)], y, z, F, log=[per-iteration dicts])."""
     n_bl = n_cp * n_rows * n_cols
     apset = bb.ApertureSet(n_cp, n_rows, n_cols)
@@ -32,12 +47,15 @@ def run(row, col, val, n_vox, n_cp, n_rows, n_cols, sid, table, max_cg,
     p = products.price(row, col, val, obj.gradient(z, sid, table), n_bl)
     log = []
     DA_cols = []
+    L_all = np.zeros((n_cp, n_rows), np.int32)
+    R_all = np.zeros((n_cp, n_rows), np.int32)
     for it in range(max_cg):
-        sel = ap.select(p, n_cp, n_rows, n_cols, occupied)
+        sel = select_aperture(p, n_cp, n_rows, n_cols, occupied, L_all, R_all, interdigitated, leaf_travel)
         if sel["best"] < 0:
             break
         k = sel["best"]
         occupied[k] = True
+        L_all[k], R_all[k] = sel["L"][k], sel["R"][k]
         apset.add(k, sel["L"][k], sel["R"][k])
         y = np.append(y, lo)
         if form == "DA":

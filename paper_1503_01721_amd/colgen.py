@@ -14,6 +14,11 @@ form (Eq. 6): each chosen aperture's dose vector DA_k = D 1_{A_k} (Eq. 5) is
 formed once and the iterations read only those m columns.  Both compute the
 same iterates up to rounding.
 
+Aperture options: the interdigitation constraint of the MLC leaves (Sec.
+2.2.2) and leaf windows that keep a candidate deliverable after the apertures
+already chosen at the neighbouring control points (Sec. 2.1): each leaf within
+leaf_travel beamlets of its position there.
+
 Per iteration the host reads back one small record (chosen control point,
 its price, the solve's flags and F); all other data stays on the device.
 """
@@ -41,7 +46,8 @@ class ColumnGeneration:
 
     def __init__(self, ddc: dvmat.DDC, obj: dvmat.Objective, n_cp: int, n_rows: int, n_cols: int,
                  max_apertures: Optional[int] = None, bb_steps: int = 50, eps_f: float = 1e-5,
-                 eps_step: float = 1e-7, lo: float = 0.0, hi: float = float("inf"), form: str = "D"):
+                 eps_step: float = 1e-7, lo: float = 0.0, hi: float = float("inf"), form: str = "D",
+                 interdigitated: bool = False, leaf_travel: Optional[int] = None):
         if form not in ("D", "DA"):
             raise ValueError("form must be 'D' or 'DA'")
         self.form = form
@@ -55,7 +61,13 @@ class ColumnGeneration:
         self.lo, self.hi = lo, hi
         self.bb = dvmat.BB(n_cp, n_rows, n_cols, self.max_apertures, max_iter=bb_steps, eps_f=eps_f,
                            eps_step=eps_step, device=dev)
-        self.sel = dvmat.ApertureSelector(n_cp, n_rows, n_cols, device=dev)
+        self.sel = dvmat.ApertureSelector(n_cp, n_rows, n_cols, device=dev, interdigitated=interdigitated)
+        self.leaf_travel = leaf_travel
+        if leaf_travel is not None:
+            i32 = dict(dtype=torch.int32, device=dev)
+            self.ap_L = torch.zeros((n_cp, n_rows), **i32)       # openings of the chosen apertures
+            self.ap_R = torch.zeros((n_cp, n_rows), **i32)
+            self.windows = torch.empty((n_cp, n_rows, 4), **i32)
         f32 = dict(dtype=torch.float32, device=dev)
         self.x = torch.zeros(ddc.n_bl, **f32)
         self.x_dir = torch.zeros(ddc.n_bl, **f32)
@@ -86,7 +98,11 @@ class ColumnGeneration:
 
     def select(self):
         """Pricing problem, second step (device); returns the selector."""
-        return self.sel(self.p, self.bb.occupied_ptr)
+        if self.leaf_travel is None:
+            return self.sel(self.p, self.bb.occupied_ptr)
+        dvmat.leaf_windows(self.n_cp, self.n_rows, self.n_cols, self.bb.occupied_ptr, self.ap_L, self.ap_R,
+                           self.leaf_travel, out=self.windows)
+        return self.sel(self.p, self.bb.occupied_ptr, windows=self.windows)
 
     def _master_problem_da(self, steps):
         m = self.bb.count
@@ -144,6 +160,9 @@ class ColumnGeneration:
             self.done = True
             return None
         self.bb.add_aperture(best, self.sel.L[best], self.sel.R[best], self.lo, self.hi)
+        if self.leaf_travel is not None:
+            self.ap_L[best].copy_(self.sel.L[best])
+            self.ap_R[best].copy_(self.sel.R[best])
         if self.form == "DA":
             self._append_da_column(best)
         self.master_problem()

@@ -424,13 +424,15 @@ def leaf_windows(n_cp, n_rows, n_cols, occupied, L, R, travel, out=None, stream=
     the occupied control points (each leaf within travel beamlets of its
     position at the occupied neighbours)."""
     geom = Geom(n_cp, n_rows, n_cols)
-    _need(occupied, n_cp, torch.uint8, name="occupied")
+    if not isinstance(occupied, ctypes.c_void_p):
+        _need(occupied, n_cp, torch.uint8, name="occupied")
+    occ = occupied if isinstance(occupied, ctypes.c_void_p) else _ptr(occupied)
     _need(L, n_cp * n_rows, torch.int32, name="L")
     _need(R, n_cp * n_rows, torch.int32, name="R")
     if out is None:
         out = torch.empty((n_cp, n_rows, 4), dtype=torch.int32, device=L.device)
     _need(out, n_cp * n_rows * 4, torch.int32, name="out")
-    _check(lib.dvmat_leaf_windows(geom, _ptr(occupied), _ptr(L), _ptr(R), int(travel), _ptr(out), _stream(stream)))
+    _check(lib.dvmat_leaf_windows(geom, occ, _ptr(L), _ptr(R), int(travel), _ptr(out), _stream(stream)))
     return out
 
 

@@ -471,8 +471,9 @@ def test_bb_box_bounds_and_stop_rule(dv, plan1):
             assert np.array_equal(gpu["y"][t], gpu["y"][s0])
 
 
-@pytest.mark.parametrize("form", ["D", "DA"])
-def test_column_generation_matches_oracle(dv, plan1, form):
+@pytest.mark.parametrize("form,interdigitated,travel", [("D", False, None), ("DA", False, None),
+                                                        ("D", True, None), ("D", False, 2), ("DA", True, 3)])
+def test_column_generation_matches_oracle(dv, plan1, form, interdigitated, travel):
     """Each GPU column-generation iteration checked against the oracle from
     the same state: the prices the selection sees, the selection's optimality
     (within the price error bound: near-ties between control points make an
@@ -481,10 +482,13 @@ def test_column_generation_matches_oracle(dv, plan1, form):
     from paper_1503_01721_amd.colgen import ColumnGeneration
     d, sid, table, ddc, obj = plan1
     n_cp, n_rows, n_cols = PLAN1.n_cp, PLAN1.n_rows, PLAN1.n_cols
-    cg = ColumnGeneration(ddc, obj, n_cp, n_rows, n_cols, bb_steps=50, eps_f=0.0, eps_step=0.0, form=form)
+    cg = ColumnGeneration(ddc, obj, n_cp, n_rows, n_cols, bb_steps=50, eps_f=0.0, eps_step=0.0, form=form,
+                          interdigitated=interdigitated, leaf_travel=travel)
     cg.start()
     apset = obb.ApertureSet(n_cp, n_rows, n_cols)
     occupied = np.zeros(n_cp, bool)
+    L_all = np.zeros((n_cp, n_rows), np.int32)
+    R_all = np.zeros((n_cp, n_rows), np.int32)
     y = np.zeros(0)
     F_prev = oobj.objective(np.zeros(PLAN1.n_vox), sid, table)
     for it in range(6):
@@ -497,9 +501,14 @@ def test_column_generation_matches_oracle(dv, plan1, form):
         assert np.abs(p_gpu - p_ref).max() <= 1e-4 * scale, it
         rec = cg.iteration()
         assert rec is not None
-        sel = oap.select(p_ref, n_cp, n_rows, n_cols, occupied)
+        sel = ocg.select_aperture(p_ref, n_cp, n_rows, n_cols, occupied, L_all, R_all, interdigitated, travel)
         L = cg.sel.L.cpu().numpy()[rec.cp]
         R = cg.sel.R.cpu().numpy()[rec.cp]
+        if travel is not None:
+            w = oap.leaf_windows(n_cp, n_rows, n_cols, occupied, L_all, R_all, travel)
+            assert all(oap.allowed((L[r], R[r]), w[rec.cp, r]) for r in range(n_rows))
+        if interdigitated:
+            assert all(oap.compatible((L[r], R[r]), (L[r + 1], R[r + 1])) for r in range(n_rows - 1))
         P = p_ref.reshape(n_cp, n_rows, n_cols)[rec.cp]
         chosen = sum(P[r, L[r]:R[r]].sum() for r in range(n_rows))
         tol = 1e-4 * scale * n_rows * n_cols
@@ -507,6 +516,7 @@ def test_column_generation_matches_oracle(dv, plan1, form):
         assert chosen <= sel["best_price"] + tol, (it, rec.cp, sel["best"], chosen, sel["best_price"])
         assert abs(rec.best_price - chosen) <= tol
         occupied[rec.cp] = True
+        L_all[rec.cp], R_all[rec.cp] = L, R
         apset.add(rec.cp, L, R)
         # master problem from the GPU's warm start, 50 steps on both sides
         y0 = np.append(y, 0.0)

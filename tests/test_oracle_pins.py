@@ -452,6 +452,35 @@ def test_column_generation_d_and_da_forms_agree(tiny):
     assert r1["F"] == pytest.approx(r2["F"], rel=1e-8)
 
 
+def test_column_generation_with_aperture_constraints(tiny):
+    """Interdigitation and leaf windows in the loop: every chosen aperture
+    obeys them (windows built from the apertures chosen before it), the
+    objective still decreases, and the constraints never price better than
+    the unconstrained loop's first choice."""
+    d, sid, table = tiny
+    kw = dict(params=bb.BBParams(max_iter=100, eps_f=1e-12, eps_step=1e-12), max_cg=4)
+    free = colgen.run(d["row"], d["col"], d["val"], TINY.n_vox, TINY.n_cp, TINY.n_rows, TINY.n_cols, sid, table,
+                      **kw)
+    for inter, travel in ((True, None), (False, 1), (True, 1)):
+        res = colgen.run(d["row"], d["col"], d["val"], TINY.n_vox, TINY.n_cp, TINY.n_rows, TINY.n_cols, sid,
+                         table, interdigitated=inter, leaf_travel=travel, **kw)
+        assert len(res["log"]) >= 2
+        Fs = [obj.objective(np.zeros(TINY.n_vox), sid, table)] + [r["F"] for r in res["log"]]
+        assert all(b < a for a, b in zip(Fs, Fs[1:]))
+        assert res["log"][0]["best_price"] >= free["log"][0]["best_price"] - 1e-12
+        occupied = np.zeros(TINY.n_cp, bool)
+        L_all = np.zeros((TINY.n_cp, TINY.n_rows), np.int32)
+        R_all = np.zeros((TINY.n_cp, TINY.n_rows), np.int32)
+        for cp, L, R in res["apertures"]:
+            if inter:
+                assert all(ap.compatible((L[r], R[r]), (L[r + 1], R[r + 1])) for r in range(TINY.n_rows - 1))
+            if travel is not None:
+                w = ap.leaf_windows(TINY.n_cp, TINY.n_rows, TINY.n_cols, occupied, L_all, R_all, travel)
+                assert all(ap.allowed((L[r], R[r]), w[cp, r]) for r in range(TINY.n_rows))
+            occupied[cp] = True
+            L_all[cp], R_all[cp] = L, R
+
+
 # ---------------------------------------------------------------- the paper's printed sizes
 
 def test_table2_sizes_pin_fp32_int32_and_gib(golden_dir):
