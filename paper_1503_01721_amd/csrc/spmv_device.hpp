@@ -5,8 +5,6 @@
 
 #include "common.hpp"
 
-#include <type_traits>
-
 namespace dvmat {
 
 
@@ -14,7 +12,6 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 enum Epi { EPI_PLAIN = 0, EPI_OBJ = 1, EPI_CURV = 2, EPI_SCALE = 3 };
 
@@ -41,6 +38,7 @@ struct SpmvParams {
 };
 
 __device__ __forceinline__ i32x4 load_cols16(const uint16_t* col16, int64_t k) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
     const u32x2 w = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(col16) + (k >> 2));
     return i32x4{(int)(w.x & 0xffffu), (int)(w.x >> 16), (int)(w.y & 0xffffu), (int)(w.y >> 16)};
 }
@@ -250,16 +248,9 @@ __device__ __forceinline__ void block_rows(const SpmvParams& P, int r0, int r1, 
                                            float (&fpart)[NRHS], double& cpart, const float* xsrc = nullptr,
                                            const uint16_t* col16 = nullptr) {
     if constexpr (!LDSG) xsrc = P.x;
-    // column indices as loaded: 4 x 16 bits packed in two registers (panels)
-    // or 4 x int32; unpacked only at the gathers, so batched steps stay small
-    using ColRaw = typename std::conditional<LDSG, u32x2, i32x4>::type;
-    auto cols_raw = [&](int64_t k) -> ColRaw {
-        if constexpr (LDSG) return __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(col16) + (k >> 2));
+    auto cols = [&](int64_t k) -> i32x4 {
+        if constexpr (LDSG) return load_cols16(col16, k);
         else return load_cols(P.col, k);
-    };
-    auto unpack = [](ColRaw w) -> i32x4 {
-        if constexpr (LDSG) return i32x4{(int)(w.x & 0xffffu), (int)(w.x >> 16), (int)(w.y & 0xffffu), (int)(w.y >> 16)};
-        else return w;
     };
     const int nbr = r1 - r0;                              // 1 .. kBlockRowsMax
     const int li = lane < nbr ? lane : nbr - 1;
@@ -296,26 +287,33 @@ __device__ __forceinline__ void block_rows(const SpmvParams& P, int r0, int r1, 
         for (int q = 0; q < B; ++q)
 #pragma unroll
             for (int h = 0; h < NRHS; ++h) acc[q][h] = 0.0f;
-        // Steps of 256 block entries (4 per lane) go out in batches of kSteps
-        // loads before any gather, lanes past the row's end predicated off:
-        // a dose row (~600 entries) is one round trip to memory.  The batch
-        // shrinks where a step already holds many value registers (values are
-        // widened to FP32 on load: 4 registers per block row and step).
-        constexpr int kSteps = B == 1 ? 4 : (B == 2 ? 2 : 1);
-        for (int64_t kb = e0; kb < e1; kb += 256 * kSteps) {
-            f32x4 V[kSteps][B];
-            ColRaw c[kSteps];
-#pragma unroll
-            for (int t = 0; t < kSteps; ++t) {
-                const int64_t k = kb + t * 256 + lane * 4;
-                if (k < e1) {
-                    load_block_vals<ST, B>(P.val, k, V[t]);
-                    c[t] = cols_raw(k);
-                }
+        int64_t k = e0 + lane * 4;
+        // two steps in flight unless a step already holds 64 bytes of values
+        // per lane (FP32 with 4 rows per block row): registers, not bytes, bind there
+        constexpr bool kTwoSteps = (ST == DVMAT_F32 ? 4 : 2) * B < 16;
+        if constexpr (kTwoSteps) {
+            for (; k + 256 < e1; k += 512) {
+                f32x4 V0[B], V1[B];
+                load_block_vals<ST, B>(P.val, k, V0);
+                const i32x4 c0 = cols(k);
+                load_block_vals<ST, B>(P.val, k + 256, V1);
+                const i32x4 c1 = cols(k + 256);
+                fma4_blocked<NRHS, B, SCALE_X>(acc, P, xsrc, V0, c0);
+                fma4_blocked<NRHS, B, SCALE_X>(acc, P, xsrc, V1, c1);
             }
-#pragma unroll
-            for (int t = 0; t < kSteps; ++t)
-                if (kb + t * 256 + lane * 4 < e1) fma4_blocked<NRHS, B, SCALE_X>(acc, P, xsrc, V[t], unpack(c[t]));
+        } else {
+            for (; k + 256 < e1; k += 256) {
+                f32x4 V0[B];
+                load_block_vals<ST, B>(P.val, k, V0);
+                const i32x4 c0 = cols(k);
+                fma4_blocked<NRHS, B, SCALE_X>(acc, P, xsrc, V0, c0);
+            }
+        }
+        if (k < e1) {
+            f32x4 V0[B];
+            load_block_vals<ST, B>(P.val, k, V0);
+            const i32x4 c0 = cols(k);
+            fma4_blocked<NRHS, B, SCALE_X>(acc, P, xsrc, V0, c0);
         }
         if (e1 > e0) {                                   // an empty block row sums to zero
 #pragma unroll
