@@ -120,7 +120,9 @@ def bench_batched(args):
         d = synth.generate_ddc(p)
         t_gen += time.perf_counter() - t
         t = time.perf_counter()
-        ddcs.append(dvmat.DDC(d["row"], d["col"], d["val"], p.n_vox, p.n_bl, storage=storage))
+        layout = {} if args.layout == "csr" else dict(dose_block_rows=1, price_block_rows=1, panel_cols=1792,
+                                                       **p.grids)
+        ddcs.append(dvmat.DDC(d["row"], d["col"], d["val"], p.n_vox, p.n_bl, storage=storage, **layout))
         t_build += time.perf_counter() - t
         del d
         if i % 8 == 7 or i == len(plans) - 1:
@@ -181,6 +183,7 @@ def bench_batched(args):
         "ms_per_step": round(t_batched * 1e3, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": storage, "data": "synthetic",
         "config": {"workload": f"{len(plans)} uneven plans x {nrhs} right-hand sides", "nnz_total": int(nnz),
+                   "layout": args.layout,
                    "storage": storage, "nrhs": nrhs, "algorithmic_bytes_per_step": int(total),
                    "one_plan_at_a_time_gbs": round(gbs_s, 2), "one_plan_at_a_time_ms": round(t_seq * 1e3, 3),
                    "speedup_vs_one_plan_at_a_time": round(t_seq / t_batched, 3),

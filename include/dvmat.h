@@ -396,7 +396,12 @@ dvmat_status dvmat_bb_get_y(dvmat_bb bb, float* y, dvmat_stream stream);
  * plan form one work list that a single persistent grid walks, so plans of
  * very different sizes share the GPU without a launch per plan.  (The paper
  * suggests lending idle GPUs to another plan, Sec. 4; here the plans share
- * one GPU.)  All plans must be bound and share a storage type; n <= 64.
+ * one GPU.)  All plans must be bound and share a storage type, the block
+ * rows and, per orientation, the layout; n <= 64.  With panels the work list
+ * is the plans' panel parts, each staging its panel's slice of the input
+ * vectors in LDS; right-hand sides beyond what LDS holds go in chunks, one
+ * launch each (plans built with panel_cols <= 1792 keep 8 right-hand sides in
+ * one launch).
  * ---------------------------------------------------------------------- */
 typedef struct dvmat_batch_s* dvmat_batch;
 
@@ -421,7 +426,7 @@ dvmat_status dvmat_batch_autotune(dvmat_batch batch, const float* const* xs, flo
                                   dvmat_stream stream);
 /* Launch shape by hand (as dvmat_ddc_set_kernel). */
 dvmat_status dvmat_batch_set_kernel(dvmat_batch batch, int32_t orientation, int32_t kind, int32_t workgroups);
-/* Total row blocks of the dose and price work lists; cfg (nullable) receives
+/* Total work units (CSR) or panel parts of the dose and price work lists; cfg (nullable) receives
  * {dose kernel, dose workgroups, price kernel, price workgroups}. */
 dvmat_status dvmat_batch_info(dvmat_batch batch, int64_t* dose_blocks, int64_t* price_blocks, int32_t* cfg);
 

@@ -72,26 +72,6 @@ __global__ __launch_bounds__(kSpmvThreads) __attribute__((amdgpu_waves_per_eu(8,
 
 // ---- batched launch over many plans ----------------------------------------
 
-struct PlanDev {
-    const int64_t* rowptr;
-    const int32_t* col;
-    const void* val;
-    const int32_t* blocks;
-    const float* scale;   // per-beamlet scale (16-bit storage) or nullptr
-    const int32_t* perm;  // stored position -> row, or nullptr
-    int64_t n_rows;       // rows of the orientation
-    int64_t block_base;   // first global block of this plan
-    int64_t n_blocks;
-};
-
-struct BatchParams {
-    const PlanDev* plans;     // device [n_plans]
-    int n_plans;
-    int64_t total_blocks;
-    const float* x[kMaxBatch];
-    float* y[kMaxBatch];
-};
-
 template <int KIND, int ST, int NRHS, int EPI, bool SCALE_X, int BR>
 __global__ __launch_bounds__(kSpmvThreads) void spmv_batch_kernel(BatchParams B) {
     constexpr int kWaves = kSpmvThreads / kWaveSize;
@@ -346,9 +326,11 @@ struct dvmat_batch_s {
     std::vector<int64_t> n_vox, n_bl;
     dvmat::PlanDev* dose_plans = nullptr;    // device
     dvmat::PlanDev* price_plans = nullptr;   // device
-    int64_t dose_blocks = 0, price_blocks = 0;
+    int64_t dose_blocks = 0, price_blocks = 0;    // work units (CSR) or parts (panels) of all plans
     dvmat::KernelCfg dose_cfg{}, price_cfg{};
     int dose_B = 1, price_B = 1;
+    int dose_layout = 0, price_layout = 0;
+    int64_t dose_max_cols = 0, price_max_cols = 0; // largest panel column list over the plans
 };
 
 namespace dvmat {
@@ -405,6 +387,10 @@ static dvmat_status batch_call(dvmat_batch_s* bt, bool dose, const KernelCfg& cf
         B.x[i] = in[i];
         B.y[i] = out[i];
     }
+    if ((dose ? bt->dose_layout : bt->price_layout) == 1)
+        return launch_batch_panel(bt->storage, dose ? bt->dose_B : bt->price_B,
+                                  !dose && bt->storage != DVMAT_F32, dose && bt->storage != DVMAT_F32,
+                                  dose ? bt->dose_max_cols : bt->price_max_cols, B, nrhs, cfg.workgroups, s);
     if (dose) launch_batch<true>(bt, cfg, B, nrhs, s);
     else launch_batch<false>(bt, cfg, B, nrhs, s);
     return check_hip(hipGetLastError(), fn);
@@ -632,7 +618,7 @@ dvmat_status dvmat_batch_create(const dvmat_ddc* ddcs, int32_t n, void* ws, size
     if (reinterpret_cast<uintptr_t>(ws) % kAlign) return set_error(DVMAT_E_ARG, "dvmat_batch_create: workspace misaligned");
     if (bytes < need) return set_error(DVMAT_E_NOMEM, "dvmat_batch_create: workspace %zu < %zu bytes", bytes, need);
     std::vector<PlanDev> dp(n), pp(n);
-    int64_t bd = 0, bp = 0;
+    int64_t bd = 0, bp = 0, max_cols_d = 0, max_cols_p = 0;
     for (int i = 0; i < n; ++i) {
         const dvmat_ddc_s* d = ddcs[i];
         if ((st = check_ddc(d, "dvmat_batch_create"))) return st;
@@ -640,14 +626,33 @@ dvmat_status dvmat_batch_create(const dvmat_ddc* ddcs, int32_t n, void* ws, size
             return set_error(DVMAT_E_ARG, "dvmat_batch_create: plan %d has a different storage type", i);
         if (d->dose.B != ddcs[0]->dose.B || d->price.B != ddcs[0]->price.B)
             return set_error(DVMAT_E_ARG, "dvmat_batch_create: plan %d has a different block-row layout", i);
-        if (d->dose.layout != 0 || d->price.layout != 0)
-            return set_error(DVMAT_E_ARG, "dvmat_batch_create: plan %d is not in the CSR layout", i);
-        dp[i] = PlanDev{d->dose.rowptr, d->dose.col, d->dose.val, d->dose.blocks, d->scale, d->dose.perm,
-                        d->dose.n_rows, bd, d->dose.n_blocks};
-        pp[i] = PlanDev{d->price.rowptr, d->price.col, d->price.val, d->price.blocks, d->scale, d->price.perm,
-                        d->price.n_rows, bp, d->price.n_blocks};
-        bd += d->dose.n_blocks;
-        bp += d->price.n_blocks;
+        if (d->dose.layout != ddcs[0]->dose.layout || d->price.layout != ddcs[0]->price.layout)
+            return set_error(DVMAT_E_ARG, "dvmat_batch_create: plan %d has a different layout (CSR / panels)", i);
+        auto plan = [](const CsrDev& c, const float* scale, int64_t base) {
+            PlanDev q{};
+            q.rowptr = c.rowptr;
+            q.col = c.col;
+            q.val = c.val;
+            q.blocks = c.blocks;
+            q.scale = scale;
+            q.perm = c.perm;
+            q.perm_runs = c.perm_runs;
+            q.n_rows = c.n_rows;
+            q.block_base = base;
+            q.n_blocks = c.layout == 1 ? c.n_parts : c.n_blocks;
+            q.col16 = c.col16;
+            q.ulist = c.ulist;
+            q.panel_u = c.panel_u;
+            q.part_units = c.part_units;
+            q.part_panel = c.part_panel;
+            return q;
+        };
+        dp[i] = plan(d->dose, d->scale, bd);
+        pp[i] = plan(d->price, d->scale, bp);
+        bd += dp[i].n_blocks;
+        bp += pp[i].n_blocks;
+        max_cols_d = std::max<int64_t>(max_cols_d, d->dose.max_panel_cols);
+        max_cols_p = std::max<int64_t>(max_cols_p, d->price.max_panel_cols);
     }
     dvmat_batch_s* bt = new (std::nothrow) dvmat_batch_s();
     if (!bt) return set_error(DVMAT_E_NOMEM, "dvmat_batch_create: host allocation failed");
@@ -660,8 +665,14 @@ dvmat_status dvmat_batch_create(const dvmat_ddc* ddcs, int32_t n, void* ws, size
     bt->price_plans = reinterpret_cast<PlanDev*>(base + align_up((size_t)n * sizeof(PlanDev)));
     bt->dose_blocks = bd;
     bt->price_blocks = bp;
+    bt->dose_layout = ddcs[0]->dose.layout;
+    bt->price_layout = ddcs[0]->price.layout;
+    bt->dose_max_cols = max_cols_d;
+    bt->price_max_cols = max_cols_p;
     bt->dose_cfg = default_cfg();
     bt->price_cfg = default_cfg();
+    if (bt->dose_layout == 1) bt->dose_cfg.kind = KIND_PANEL;
+    if (bt->price_layout == 1) bt->price_cfg.kind = KIND_PANEL;
     for (int i = 0; i < n; ++i) {
         bt->n_vox.push_back(ddcs[i]->n_vox);
         bt->n_bl.push_back(ddcs[i]->n_bl);
@@ -699,11 +710,11 @@ dvmat_status dvmat_batch_autotune(dvmat_batch b, const float* const* xs, float* 
     KernelCfg best{};
     float ms = 0.0f;
     dvmat_status st = tune([&](const KernelCfg& c) { return batch_call(b, true, c, xs, nrhs, zs, s, "dvmat_batch_autotune"); },
-                           reps, s, &best, &ms, b->dose_B, false);
+                           reps, s, &best, &ms, b->dose_B, false, b->dose_layout == 1);
     if (st) return st;
     b->dose_cfg = best;
     st = tune([&](const KernelCfg& c) { return batch_call(b, false, c, gs, nrhs, ps, s, "dvmat_batch_autotune"); },
-              reps, s, &best, &ms, b->price_B, false);
+              reps, s, &best, &ms, b->price_B, false, b->price_layout == 1);
     if (st) return st;
     b->price_cfg = best;
     return DVMAT_OK;
@@ -711,9 +722,17 @@ dvmat_status dvmat_batch_autotune(dvmat_batch b, const float* const* xs, float* 
 
 dvmat_status dvmat_batch_set_kernel(dvmat_batch b, int32_t orientation, int32_t kind, int32_t workgroups) {
     if (!b) return set_error(DVMAT_E_ARG, "dvmat_batch_set_kernel: NULL handle");
-    if (kind != 0 && kind != 1) return set_error(DVMAT_E_ARG, "dvmat_batch_set_kernel: kind %d", kind);
+    if (kind != KIND_ROW && kind != KIND_STREAM && kind != KIND_PANEL)
+        return set_error(DVMAT_E_ARG, "dvmat_batch_set_kernel: kind %d", kind);
     if (workgroups < kNumXcd || workgroups > kMaxSpmvWorkgroups)
         return set_error(DVMAT_E_ARG, "dvmat_batch_set_kernel: workgroups %d not in [8, 8192]", workgroups);
+    if (orientation == 0 || orientation == 1) {
+        const int layout = orientation == 0 ? b->dose_layout : b->price_layout;
+        if ((kind == KIND_PANEL) != (layout == 1))
+            return set_error(DVMAT_E_ARG, "dvmat_batch_set_kernel: kind 3 (panel) goes with the panel layout and only there");
+        if (kind == KIND_STREAM && (orientation == 0 ? b->dose_B : b->price_B) != 1)
+            return set_error(DVMAT_E_ARG, "dvmat_batch_set_kernel: the stream kernel needs one row per block row");
+    }
     KernelCfg c{kind, workgroups};
     if (orientation == 0) b->dose_cfg = c;
     else if (orientation == 1) b->price_cfg = c;

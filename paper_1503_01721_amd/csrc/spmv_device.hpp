@@ -586,6 +586,41 @@ __device__ __forceinline__ void workgroup_partials(const SpmvParams& P, int lane
     workgroup_partials_n<NRHS, EPI, kSpmvThreads / kWaveSize>(P, lane, wid, fpart, cpart);
 }
 
+// One plan of a batched launch: its orientation's arrays, and its first
+// global work unit (CSR) or part (panels) in the batch's work list.
+struct PlanDev {
+    const int64_t* rowptr;
+    const int32_t* col;
+    const void* val;
+    const int32_t* blocks;
+    const float* scale;   // per-beamlet scale (16-bit storage) or nullptr
+    const int32_t* perm;  // stored position -> row, or nullptr
+    int64_t n_rows;       // rows of the orientation
+    int64_t block_base;   // first global unit (CSR) or part (panels) of this plan
+    int64_t n_blocks;     // units (CSR) or parts (panels)
+    int perm_runs;
+    // panel layout
+    const uint16_t* col16;
+    const int32_t* ulist;
+    const int64_t* panel_u;
+    const int32_t* part_units;
+    const int32_t* part_panel;
+};
+
+struct BatchParams {
+    const PlanDev* plans;     // device [n_plans]
+    int n_plans;
+    int64_t total_blocks;     // units (CSR) or parts (panels) over all plans
+    const float* x[kMaxBatch];
+    float* y[kMaxBatch];
+};
+
+// Batched products on the panel layout (spmv_panel.hip): right-hand sides
+// [h0, h0 + chunk) of nrhs, chunk by chunk; scale_stage multiplies the staged
+// slice by the per-beamlet scale (16-bit dose).
+dvmat_status launch_batch_panel(int storage, int B, int epi_scale, bool scale_stage, int64_t max_panel_cols,
+                                const BatchParams& Bp, int nrhs, int workgroups, hipStream_t s);
+
 // Products on the panel layout (spmv_panel.hip): x is the input vector with
 // nrhs values per column; P carries the outputs and epilogue inputs; the
 // number of workgroups launched is returned in nwg (for the partial sums).

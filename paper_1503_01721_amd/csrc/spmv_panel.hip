@@ -130,6 +130,101 @@ dvmat_status launch_panel(const KernelCfg& cfg, int storage, const CsrDev& c, co
     return check_hip(hipGetLastError(), "panel launch");
 }
 
+// ---- batched launch over many plans in the panel layout -------------------
+//
+// The parts of all plans form one work list; a workgroup's cursor over the
+// plans only moves forward.  The dose of 16-bit storage multiplies the staged
+// slice by the per-beamlet scale (the values hold D_ij / s_j).
+template <int ST, int R, int EPI, int B, bool SCALE_STAGE>
+__global__ __launch_bounds__(kPanelThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void spmv_batch_panel_kernel(
+    BatchParams Bp, int h0, int nrhs) {
+    constexpr int kWaves = kPanelThreads / kWaveSize;
+    static_assert(EPI == EPI_PLAIN || EPI == EPI_SCALE, "the batched launch has no objective epilogue");
+    extern __shared__ float xs[];
+    const int lane = threadIdx.x & (kWaveSize - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWaveSize);
+    float fpart[R];
+#pragma unroll
+    for (int h = 0; h < R; ++h) fpart[h] = 0.0f;
+    double cpart = 0.0;
+    int p = 0;
+    for (int64_t t = blockIdx.x; t < Bp.total_blocks; t += gridDim.x) {
+        while (p + 1 < Bp.n_plans && Bp.plans[p + 1].block_base <= t) ++p;      // t only grows
+        const PlanDev& pd = Bp.plans[p];
+        const int64_t tl = t - pd.block_base;
+        const int pan = pd.part_panel[tl];
+        const int64_t u0 = pd.panel_u[pan];
+        const int nu = (int)(pd.panel_u[pan + 1] - u0);
+        const float* x = Bp.x[p];
+        __syncthreads();                              // the previous part's gathers are done
+        for (int i = threadIdx.x; i < nu; i += kPanelThreads) {
+            const int64_t j = pd.ulist[u0 + i];
+            const float sc = SCALE_STAGE ? pd.scale[j] : 1.0f;
+#pragma unroll
+            for (int h = 0; h < R; ++h) xs[i * R + h] = x[j * nrhs + h0 + h] * sc;
+        }
+        __syncthreads();
+        SpmvParams P{};
+        P.n_rows = pd.n_rows;
+        P.perm = pd.perm;
+        P.perm_runs = pd.perm_runs;
+        P.rowptr = pd.rowptr;
+        P.val = pd.val;
+        P.blocks = pd.blocks;
+        P.y = Bp.y[p] + h0;
+        P.ld = nrhs;
+        P.row_scale = pd.scale;
+        const int q0 = pd.part_units[tl], q1 = pd.part_units[tl + 1];
+        for (int q = q0 + wid; q < q1; q += kWaves)
+            block_rows<ST, R, EPI, false, B, true>(P, P.blocks[q], P.blocks[q + 1], lane, nullptr, fpart, cpart, xs,
+                                                   pd.col16);
+    }
+}
+
+template <int ST, int R, int EPI, bool SCALE_STAGE>
+static void launch_batch_chunk(int B, int nwg, size_t lds, const BatchParams& Bp, int h0, int nrhs, hipStream_t s) {
+    dim3 grid(nwg), block(kPanelThreads);
+    if (B == 4) hipLaunchKernelGGL((spmv_batch_panel_kernel<ST, R, EPI, 4, SCALE_STAGE>), grid, block, lds, s, Bp, h0, nrhs);
+    else if (B == 2) hipLaunchKernelGGL((spmv_batch_panel_kernel<ST, R, EPI, 2, SCALE_STAGE>), grid, block, lds, s, Bp, h0, nrhs);
+    else hipLaunchKernelGGL((spmv_batch_panel_kernel<ST, R, EPI, 1, SCALE_STAGE>), grid, block, lds, s, Bp, h0, nrhs);
+}
+
+template <int ST, int EPI, bool SCALE_STAGE>
+static void launch_batch_r(int R, int B, int nwg, size_t lds, const BatchParams& Bp, int h0, int nrhs, hipStream_t s) {
+    if (R == 8) launch_batch_chunk<ST, 8, EPI, SCALE_STAGE>(B, nwg, lds, Bp, h0, nrhs, s);
+    else if (R == 4) launch_batch_chunk<ST, 4, EPI, SCALE_STAGE>(B, nwg, lds, Bp, h0, nrhs, s);
+    else if (R == 2) launch_batch_chunk<ST, 2, EPI, SCALE_STAGE>(B, nwg, lds, Bp, h0, nrhs, s);
+    else launch_batch_chunk<ST, 1, EPI, SCALE_STAGE>(B, nwg, lds, Bp, h0, nrhs, s);
+}
+
+dvmat_status launch_batch_panel(int storage, int B, int epi_scale, bool scale_stage, int64_t max_panel_cols,
+                                const BatchParams& Bp, int nrhs, int workgroups, hipStream_t s) {
+    const int nwg = (int)std::max<int64_t>(1, std::min<int64_t>(std::max(1, workgroups), Bp.total_blocks));
+    if (Bp.total_blocks == 0) return DVMAT_OK;
+    const size_t per_rhs = (size_t)std::max<int64_t>(max_panel_cols, 1) * sizeof(float);
+    if (per_rhs > kPanelLdsBytes)
+        return set_error(DVMAT_E_SHAPE, "panel of %lld columns exceeds the LDS slice", (long long)max_panel_cols);
+    for (int h0 = 0; h0 < nrhs;) {
+        int R = 8;
+        while (R > 1 && (R > nrhs - h0 || per_rhs * R > kPanelLdsBytes)) R >>= 1;
+        const size_t lds = per_rhs * R;
+#define DVMAT_BATCH_ST(STT)                                                                          \
+        if (epi_scale) launch_batch_r<STT, EPI_SCALE, false>(R, B, nwg, lds, Bp, h0, nrhs, s);       \
+        else if (scale_stage) launch_batch_r<STT, EPI_PLAIN, true>(R, B, nwg, lds, Bp, h0, nrhs, s); \
+        else launch_batch_r<STT, EPI_PLAIN, false>(R, B, nwg, lds, Bp, h0, nrhs, s);
+        if (storage == DVMAT_F32) {
+            launch_batch_r<DVMAT_F32, EPI_PLAIN, false>(R, B, nwg, lds, Bp, h0, nrhs, s);
+        } else if (storage == DVMAT_F16) {
+            DVMAT_BATCH_ST(DVMAT_F16)
+        } else {
+            DVMAT_BATCH_ST(DVMAT_BF16)
+        }
+#undef DVMAT_BATCH_ST
+        h0 += R;
+    }
+    return check_hip(hipGetLastError(), "batched panel launch");
+}
+
 template dvmat_status launch_panel<EPI_PLAIN>(const KernelCfg&, int, const CsrDev&, const SpmvParams&, const float*,
                                               int, hipStream_t, int*);
 template dvmat_status launch_panel<EPI_OBJ>(const KernelCfg&, int, const CsrDev&, const SpmvParams&, const float*, int,

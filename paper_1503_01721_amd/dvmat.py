@@ -658,7 +658,7 @@ class Batch:
 
     def set_kernel(self, orientation: str, kind: str, workgroups: int):
         _check(lib.dvmat_batch_set_kernel(self._h, {"dose": 0, "price": 1}[orientation],
-                                          {"row": 0, "stream": 1}[kind], int(workgroups)))
+                                          KERNEL_KINDS.index(kind), int(workgroups)))
         return self.info()
 
     def info(self):

@@ -108,3 +108,95 @@ def test_batch_graph_capture_replays(plans):
             assert torch.equal(a, b), rep
         for a, b in zip(pt, p_eager):
             assert torch.equal(a, b), rep
+
+
+def _panel_ddcs(storage, cap=1792):
+    """The same plans in the panel layout: tiles of the plans' grids, greedy
+    panels in natural order for the unstructured matrix; a column budget that
+    lets 8 right-hand sides share LDS."""
+    from paper_1503_01721_amd import dvmat
+    names = ["tiny_cp4_bl3x4_vox8", "small_cp8_bl6x6_vox16", "cp20_bl20x20_vox32", "cp64_bl12x12_vox40"]
+    out = []
+    for n in names:
+        pl = synth.PLANS[n]
+        d = synth.generate_ddc(pl)
+        out.append((pl.n_vox, pl.n_bl, d, dvmat.DDC(d["row"], d["col"], d["val"], pl.n_vox, pl.n_bl, storage=storage,
+                                                     dose_block_rows=1, price_block_rows=1, panel_cols=cap,
+                                                     **pl.grids)))
+    d = synth.random_sparse(3001, 517, 0.02, 5, empty_rows=300, empty_cols=40)
+    out.append((3001, 517, d, dvmat.DDC(d["row"], d["col"], d["val"], 3001, 517, storage=storage, dose_block_rows=1,
+                                        price_block_rows=1, dose_layout="panel", price_layout="panel", panel_cols=cap)))
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("nrhs", [1, 2, 8])
+def test_batch_panel_layout_matches_oracle(storage, nrhs):
+    from paper_1503_01721_amd import dvmat
+    items = _panel_ddcs(storage)
+    for _, _, _, x in items:
+        assert (x.info.dose_layout, x.info.price_layout) == (1, 1)
+    batch = dvmat.Batch([x for *_, x in items])
+    info = batch.info()
+    assert info["dose_kernel"] == 3 and info["price_kernel"] == 3
+    assert info["dose_blocks"] == sum(x.info.dose_panel_parts for *_, x in items)
+    rng = np.random.default_rng(200 + nrhs)
+    xs = [rng.random((nb, nrhs) if nrhs > 1 else nb).astype(np.float32) for nv, nb, _, _ in items]
+    gs = [rng.standard_normal((nv, nrhs) if nrhs > 1 else nv).astype(np.float32) for nv, nb, _, _ in items]
+    zt = [torch.empty((nv, nrhs) if nrhs > 1 else nv, device="cuda") for nv, nb, _, _ in items]
+    pt = [torch.empty((nb, nrhs) if nrhs > 1 else nb, device="cuda") for nv, nb, _, _ in items]
+    for wg in (8, 8192):
+        batch.set_kernel("dose", "panel", wg)
+        batch.set_kernel("price", "panel", wg)
+        batch.dose_([torch.from_numpy(x).cuda() for x in xs], zt)
+        batch.price_([torch.from_numpy(g).cuda() for g in gs], pt)
+        for (nv, nb, d, one), x, g, z, p in zip(items, xs, gs, zt, pt):
+            val = _dequant(d, nb, storage)
+            z_ref = oprod.dose(d["row"], d["col"], val, x, nv)
+            p_ref = oprod.price(d["row"], d["col"], val, g, nb)
+            assert np.abs(z.cpu().numpy() - z_ref).max() <= TOL * max(np.abs(z_ref).max(), 1e-30)
+            scale = oprod.price(d["row"], d["col"], np.abs(val), np.abs(g), nb).max()
+            assert np.abs(p.cpu().numpy() - p_ref).max() <= TOL * scale
+            assert torch.allclose(one.dose(torch.from_numpy(x).cuda()), z, rtol=1e-6,
+                                  atol=1e-6 * float(z.abs().max()))
+    # a CSR plan and panel plans do not mix
+    d = items[0][2]
+    csr = dvmat.DDC(d["row"], d["col"], d["val"], items[0][0], items[0][1], storage=storage)
+    with pytest.raises(dvmat.DvmatError):
+        dvmat.Batch([items[1][3], csr])
+
+
+def test_batch_panel_graph_capture_replays():
+    from paper_1503_01721_amd import dvmat
+    items = _panel_ddcs("f16")
+    batch = dvmat.Batch([x for *_, x in items])
+    rng = np.random.default_rng(8)
+    xt = [torch.from_numpy(rng.random((nb, 8)).astype(np.float32)).cuda() for nv, nb, _, _ in items]
+    gt = [torch.from_numpy(rng.standard_normal((nv, 8)).astype(np.float32)).cuda() for nv, nb, _, _ in items]
+    zt = [torch.empty((nv, 8), device="cuda") for nv, nb, _, _ in items]
+    pt = [torch.empty((nb, 8), device="cuda") for nv, nb, _, _ in items]
+    batch.dose_(xt, zt)
+    batch.price_(gt, pt)
+    torch.cuda.synchronize()
+    z_eager = [z.clone() for z in zt]
+    p_eager = [p.clone() for p in pt]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            batch.dose_(xt, zt)
+            batch.price_(gt, pt)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        for z in zt:
+            z.fill_(-1.0)
+        for p in pt:
+            p.fill_(-1.0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(zt, z_eager):
+            assert torch.equal(a, b), rep
+        for a, b in zip(pt, p_eager):
+            assert torch.equal(a, b), rep
