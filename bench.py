@@ -120,7 +120,7 @@ def bench_batched(args):
         d = synth.generate_ddc(p)
         t_gen += time.perf_counter() - t
         t = time.perf_counter()
-        layout = {} if args.layout == "csr" else dict(dose_block_rows=1, price_block_rows=1, panel_cols=1792,
+        layout = {} if args.layout == "csr" else dict(dose_block_rows=1, price_block_rows=1, panel_cols=3584,
                                                        **p.grids)
         ddcs.append(dvmat.DDC(d["row"], d["col"], d["val"], p.n_vox, p.n_bl, storage=storage, **layout))
         t_build += time.perf_counter() - t

@@ -400,8 +400,8 @@ dvmat_status dvmat_bb_get_y(dvmat_bb bb, float* y, dvmat_stream stream);
  * rows and, per orientation, the layout; n <= 64.  With panels the work list
  * is the plans' panel parts, each staging its panel's slice of the input
  * vectors in LDS; right-hand sides beyond what LDS holds go in chunks, one
- * launch each (plans built with panel_cols <= 1792 keep 8 right-hand sides in
- * one launch).
+ * launch each (plans built with panel_cols <= 3584 take 4 right-hand sides per
+ * launch).
  * ---------------------------------------------------------------------- */
 typedef struct dvmat_batch_s* dvmat_batch;
 

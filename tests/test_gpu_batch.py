@@ -110,10 +110,10 @@ def test_batch_graph_capture_replays(plans):
             assert torch.equal(a, b), rep
 
 
-def _panel_ddcs(storage, cap=1792):
+def _panel_ddcs(storage, cap=3584):
     """The same plans in the panel layout: tiles of the plans' grids, greedy
     panels in natural order for the unstructured matrix; a column budget that
-    lets 8 right-hand sides share LDS."""
+    lets 4 right-hand sides share LDS (8 go in two chunks)."""
     from paper_1503_01721_amd import dvmat
     names = ["tiny_cp4_bl3x4_vox8", "small_cp8_bl6x6_vox16", "cp20_bl20x20_vox32", "cp64_bl12x12_vox40"]
     out = []
