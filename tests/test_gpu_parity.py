@@ -771,8 +771,8 @@ def test_panel_layout_kind_checks_and_batch(dv, plan1):
     csr = dv.DDC(d["row"], d["col"], d["val"], PLAN1.n_vox, PLAN1.n_bl)
     with pytest.raises(dv.DvmatError):
         csr.set_kernel("dose", "panel", 1024)
-    with pytest.raises(dv.DvmatError):
-        dv.Batch([ddc])
+    with pytest.raises(dv.DvmatError):                  # CSR and panel plans do not mix in a batch
+        dv.Batch([ddc, csr])
     info = ddc.autotune(reps=2)
     assert info.dose_kernel == 3 and info.price_kernel == 3 and info.dose_tuned_ms > 0
 
