@@ -120,8 +120,11 @@ def bench_batched(args):
         d = synth.generate_ddc(p)
         t_gen += time.perf_counter() - t
         t = time.perf_counter()
-        layout = {} if args.layout == "csr" else dict(dose_block_rows=1, price_block_rows=1, panel_cols=3584,
-                                                       **p.grids)
+        # multi-vector panels pay where a slice serves many rows: the dose (a
+        # voxel tile touches few beamlets); a beamlet row alone touches ~2000
+        # voxels, so the price stays in CSR
+        layout = {} if args.layout == "csr" else dict(dose_block_rows=1, panel_cols=args.panel_cols,
+                                                       price_layout="csr", **p.grids)
         ddcs.append(dvmat.DDC(d["row"], d["col"], d["val"], p.n_vox, p.n_bl, storage=storage, **layout))
         t_build += time.perf_counter() - t
         del d
@@ -183,7 +186,8 @@ def bench_batched(args):
         "ms_per_step": round(t_batched * 1e3, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": storage, "data": "synthetic",
         "config": {"workload": f"{len(plans)} uneven plans x {nrhs} right-hand sides", "nnz_total": int(nnz),
-                   "layout": args.layout,
+                   "layout": args.layout if args.layout == "csr" else "panel (dose), csr (price)",
+                   "panel_cols": args.panel_cols,
                    "storage": storage, "nrhs": nrhs, "algorithmic_bytes_per_step": int(total),
                    "one_plan_at_a_time_gbs": round(gbs_s, 2), "one_plan_at_a_time_ms": round(t_seq * 1e3, 3),
                    "speedup_vs_one_plan_at_a_time": round(t_seq / t_batched, 3),
@@ -275,6 +279,8 @@ def main():
                          "right-hand sides in one launch vs one plan at a time; autograd: F(D B y) "
                          "forward + backward on the two-arc workload")
     ap.add_argument("--plans", type=int, default=48, help="plans in --mode batched")
+    ap.add_argument("--panel-cols", type=int, default=3584,
+                    help="column budget of the dose panels in --mode batched (3584: 4 right-hand sides per launch)")
     ap.add_argument("--form", default="D", choices=["D", "DA"],
                     help="master problem over the whole matrix (D, default: every BB iteration runs "
                          "a dose and a price product) or over the aperture dose vectors (DA)")
