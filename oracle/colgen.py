@@ -12,7 +12,9 @@ max_cg iterations; the prices used by the next pricing step are those at the
 master problem's final iterate.  Options: the interdigitation constraint
 (Sec. 2.2.2) and leaf windows from the apertures at occupied neighbouring
 control points (Sec. 2.1, maximum leaf travel per control-point step; the
-readings are in aperture.py).
+readings are in aperture.py); the machine model of Eq. (2), which sets the
+leaf travel and, after each new aperture, every aperture's rate box (Eq. 6;
+readings in machine.py).
 """
 from __future__ import annotations
 
@@ -20,6 +22,7 @@ import numpy as np
 
 from . import aperture as ap
 from . import bb
+from . import machine as mach
 from . import objective as obj
 from . import products
 
@@ -37,8 +40,13 @@ def select_aperture(p, n_cp, n_rows, n_cols, occupied, L_all, R_all, interdigita
 
 
 def run(row, col, val, n_vox, n_cp, n_rows, n_cols, sid, table, max_cg,
-        params=bb.BBParams(), lo=0.0, hi=np.inf, form="D", interdigitated=False, leaf_travel=None):
-    """Returns dict(apertures=[(cp, L, R)], y, z, F, log=[per-iteration dicts])."""
+        params=bb.BBParams(), lo=0.0, hi=np.inf, form="D", interdigitated=False, leaf_travel=None,
+        machine=None):
+    """Returns dict(apertures=[(cp, L, R)], y, z, F, log=[per-iteration dicts]).
+    With a machine model the boxes come from it and lo, hi are unused."""
+    if machine is not None:
+        t = mach.leaf_travel(machine, n_cols)
+        leaf_travel = t if leaf_travel is None else min(leaf_travel, t)
     n_bl = n_cp * n_rows * n_cols
     apset = bb.ApertureSet(n_cp, n_rows, n_cols)
     occupied = np.zeros(n_cp, bool)
@@ -57,7 +65,12 @@ def run(row, col, val, n_vox, n_cp, n_rows, n_cols, sid, table, max_cg,
         occupied[k] = True
         L_all[k], R_all[k] = sel["L"][k], sel["R"][k]
         apset.add(k, sel["L"][k], sel["R"][k])
-        y = np.append(y, lo)
+        if machine is not None:
+            _, lo_cp, hi_cp = mach.boxes(machine, occupied, L_all, R_all)
+            lo_k, hi_k = lo_cp[apset.cps], hi_cp[apset.cps]
+        else:
+            lo_k, hi_k = np.full(apset.m, lo), np.full(apset.m, hi)
+        y = np.append(y, lo_k[-1])
         if form == "DA":
             member = apset.owner == apset.m - 1
             DA_cols.append(products.aperture_ddc(row, col, val, member, n_vox))
@@ -65,10 +78,11 @@ def run(row, col, val, n_vox, n_cp, n_rows, n_cols, sid, table, max_cg,
         else:
             apply, adjoint = bb.d_form_ops(row, col, val, n_vox, n_bl, apset)
         m = apset.m
-        res = bb.solve(apply, adjoint, sid, table, y, np.full(m, lo), np.full(m, hi), params)
+        res = bb.solve(apply, adjoint, sid, table, y, lo_k, hi_k, params)
         y, z = res["y"], res["z"]
         p = products.price(row, col, val, obj.gradient(z, sid, table), n_bl)
         log.append(dict(it=it, cp=k, best_price=sel["best_price"], F=res["F"],
                         flags=res["flags"], bb_iters=res["iters"]))
     return dict(apertures=list(zip(apset.cps, apset.L, apset.R)), y=y, z=z,
-                F=float(obj.objective(z, sid, table)), log=log, price=p)
+                F=float(obj.objective(z, sid, table)), log=log, price=p, L=L_all, R=R_all,
+                occupied=occupied)

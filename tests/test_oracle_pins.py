@@ -608,3 +608,106 @@ def test_windowed_selection_against_exhaustive_search():
             assert all(ap.allowed(path[r], w[0, r]) for r in range(n_rows))
             assert all(ap.compatible(path[r], path[r + 1]) for r in range(n_rows - 1))
             assert sum(P[0, r, a:b].sum() for r, (a, b) in enumerate(path)) == v
+
+
+# ---------------------------------------------------------------- machine constraints (Eq. 2 -> Eq. 6 boxes)
+
+from oracle import machine as mach  # noqa: E402
+
+HAND_MACHINE = mach.Machine(gantry_step=2.0, speed_min=1.0, speed_max=6.0, speed_change=1.0,
+                            rate_min=2.0, rate_max=10.0, leaf_speed=3.0)
+
+
+def test_machine_boxes_hand_worked():
+    """Six control points, two leaf rows; points 1, 2, 4, 5 hold apertures.
+    Pair (1, 2): largest leaf move 1 -> speed bound 3*2/1 = 6 (= S^U, slack).
+    Pair (4, 5): moves 2, 0, 0, 3 -> bound 3*2/3 = 2 on s_4.  Pairs with an
+    empty point bind nothing.  With dS = 1 the bound 2 at point 4 caps its
+    neighbours at 3, 4, 5 and S^U = 6 beyond: S^U_k = 6, 5, 4, 3, 2, 3.  Rate
+    boxes: lo = 2 / S^U_k, hi = 10 / 1.  Leaf travel at S^L: 3*2/1 = 6."""
+    occ = np.array([0, 1, 1, 0, 1, 1], bool)
+    L = np.zeros((6, 2), np.int32)
+    R = np.zeros((6, 2), np.int32)
+    L[1], R[1] = (1, 2), (5, 6)
+    L[2], R[2] = (2, 2), (5, 7)
+    L[4], R[4] = (0, 3), (4, 8)
+    L[5], R[5] = (2, 3), (4, 5)
+    s_hi, lo, hi = mach.boxes(HAND_MACHINE, occ, L, R)
+    assert np.allclose(s_hi, [6, 5, 4, 3, 2, 3], rtol=0, atol=1e-15)
+    assert np.allclose(lo, [2 / 6, 2 / 5, 2 / 4, 2 / 3, 1.0, 2 / 3], rtol=1e-15)
+    assert np.all(hi == 10.0)
+    assert mach.leaf_travel(HAND_MACHINE, 8) == 6
+    assert mach.leaf_travel(HAND_MACHINE, 4) == 4          # never more than the row
+    # the bound sits on the speed of the first point of a pair: swapping the
+    # pair's roles would put it on point 5 instead
+    assert s_hi[4] == 2 and s_hi[5] == 3
+
+
+def test_machine_speed_bound_against_enumerated_profiles():
+    """S^U_k is the largest s_k over every speed profile that meets Eq. (2)'s
+    speed range, speed change and leaf-motion bounds: enumerate all profiles on
+    a 0.25 grid (dS a multiple of it, so the grid optimum is S^U_k floored to
+    the grid) for random apertures at four control points."""
+    rng = np.random.default_rng(77)
+    g = 0.25
+    for trial in range(12):
+        m = mach.Machine(gantry_step=1.0, speed_min=g, speed_max=4.0, speed_change=[0.5, 0.25, 1.0][trial % 3],
+                         rate_min=1.0, rate_max=2.0, leaf_speed=float(rng.choice([2.0, 3.0, 6.0])))
+        K, rows, cols = 4, 2, 8
+        occ = rng.random(K) < 0.8
+        L = rng.integers(0, cols, (K, rows)).astype(np.int32)
+        R = np.minimum(cols, L + rng.integers(0, cols, (K, rows))).astype(np.int32)
+        grid = np.arange(1, 17) * g                                   # 0.25 .. 4.0
+        prof = np.array(list(itertools.product(grid, repeat=K)))      # every profile
+        ok = np.all(np.abs(np.diff(prof, axis=1)) <= m.speed_change + 1e-12, axis=1)
+        for k in range(K - 1):
+            if occ[k] and occ[k + 1]:
+                d = max(np.abs(L[k] - L[k + 1]).max(), np.abs(R[k] - R[k + 1]).max())
+                if d:
+                    ok &= prof[:, k] <= m.leaf_speed * m.gantry_step / d + 1e-12
+        s_hi = mach.speed_upper(m, occ, L, R)
+        best = prof[ok].max(axis=0)
+        assert np.allclose(best, np.floor(s_hi / g + 1e-9) * g), (trial, best, s_hi)
+
+
+def test_machine_without_motion_limits_gives_eq6_constant_box():
+    """Infinitely fast leaves: the box of Eq. (6) is [R^L/S^U, R^U/S^L] at every point."""
+    m = mach.Machine(gantry_step=2.0, speed_min=0.5, speed_max=4.8, speed_change=0.3,
+                     rate_min=1.5, rate_max=6.0, leaf_speed=math.inf)
+    occ = np.ones(5, bool)
+    L = np.arange(10, dtype=np.int32).reshape(5, 2)
+    s_hi, lo, hi = mach.boxes(m, occ, L, L + 3)
+    assert np.all(s_hi == 4.8) and np.allclose(lo, 1.5 / 4.8) and np.allclose(hi, 6.0 / 0.5)
+    # no apertures at all: the same box
+    _, lo0, hi0 = mach.boxes(HAND_MACHINE, np.zeros(6, bool), np.zeros((6, 2)), np.zeros((6, 2)))
+    assert np.allclose(lo0, 2 / 6) and np.allclose(hi0, 10)
+
+
+def test_column_generation_with_machine_model(small):
+    """The machine model in the loop: every pair of consecutive chosen
+    apertures can move at the slowest gantry speed, every S^U_k >= S^L, each
+    rate lies in its final box, F decreases; on this plan the leaf-motion
+    bound and the lower rate bound both bind."""
+    d, sid, table = small
+    m = mach.Machine(gantry_step=1.0, speed_min=1.0, speed_max=4.0, speed_change=0.5,
+                     rate_min=2.0, rate_max=50.0, leaf_speed=2.0)
+    for inter in (False, True):
+        res = colgen.run(d["row"], d["col"], d["val"], SMALL.n_vox, SMALL.n_cp, SMALL.n_rows, SMALL.n_cols, sid,
+                         table, params=bb.BBParams(max_iter=50, eps_f=1e-12, eps_step=1e-12), max_cg=8, machine=m,
+                         interdigitated=inter)
+        assert len(res["log"]) >= 4
+        Fs = [obj.objective(np.zeros(SMALL.n_vox), sid, table)] + [r["F"] for r in res["log"]]
+        assert all(b < a for a, b in zip(Fs, Fs[1:]))
+        occ, L, R = res["occupied"], res["L"], res["R"]
+        t = mach.leaf_travel(m, SMALL.n_cols)
+        assert t == 2
+        for k in range(SMALL.n_cp - 1):
+            if occ[k] and occ[k + 1]:
+                assert mach.leaf_move(L[k], R[k], L[k + 1], R[k + 1]) <= t
+        s_hi, lo, hi = mach.boxes(m, occ, L, R)
+        assert np.all(s_hi >= m.speed_min) and np.all(lo <= hi)
+        assert s_hi.min() < m.speed_max                                  # a leaf-motion bound binds
+        cps = [a[0] for a in res["apertures"]]
+        y = res["y"]
+        assert np.all(y >= lo[cps] - 1e-12) and np.all(y <= hi[cps] + 1e-12)
+        assert np.any(np.abs(y - lo[cps]) <= 1e-12)                      # so does a lower rate bound
