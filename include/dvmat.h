@@ -301,7 +301,8 @@ dvmat_status dvmat_aperture_select_ws_size(dvmat_geom geom, size_t* bytes);
  * of the aperture at each occupied control point (other entries are not
  * read); travel: the largest leaf movement between adjacent control points,
  * in beamlets (a reading: the paper bounds it through gantry speed and leaf
- * speed, parameters given in references it cites).  Writes leaf_window
+ * speed, parameters given in references it cites; dvmat_machine_leaf_travel
+ * derives it from a machine model).  Writes leaf_window
  * device int32[n_cp][n_rows][4]: for each row, each leaf within travel of
  * its position at the occupied neighbours k-1 and k+1, intersected with
  * [0, n_cols]. */
@@ -312,6 +313,43 @@ dvmat_status dvmat_aperture_select_interdigitated(dvmat_geom geom, const float* 
                                                   float* cp_price,
                                                   int32_t* best, float* best_price,
                                                   void* d_workspace, size_t bytes, dvmat_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Machine constraints of Eq. (2) and the rate boxes they give the master
+ * problem, Eq. (6): y_k in [R^L / S^U_k, R^U / S^L_k].  The paper takes the
+ * parameter values from references it cites; here they are inputs.
+ * Readings: s_k is the gantry speed on the arc from control point k to k+1,
+ * so the leaf motion from A_k to A_{k+1} (d = the largest position change of
+ * any leaf, in beamlet widths, closed rows' leaves where the selection placed
+ * them) bounds s_k <= leaf_speed * gantry_step / d when both points hold
+ * apertures (no bound for d = 0); S^U_k is the largest speed at k of any
+ * profile within [S^L, S^U] that meets those bounds and |s_k - s_{k+1}| <=
+ * speed_change along the whole arc; S^L_k = S^L.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    float gantry_step;   /* angle between consecutive control points, > 0          */
+    float speed_min;     /* S^L >= 0 (0: no upper rate bound)                      */
+    float speed_max;     /* S^U > 0, >= S^L; may be +inf                            */
+    float speed_change;  /* largest |s_k - s_{k+1}|, >= 0; may be +inf              */
+    float rate_min;      /* R^L >= 0, finite                                        */
+    float rate_max;      /* R^U >= R^L; may be +inf                                 */
+    float leaf_speed;    /* leaf speed in beamlet widths per unit time, > 0; may be +inf */
+} dvmat_machine;
+
+/* Leaf travel for dvmat_leaf_windows (host, no GPU work): a candidate must be
+ * reachable from the apertures at occupied neighbours even at the slowest
+ * gantry speed, travel = floor(leaf_speed * gantry_step / speed_min) capped at
+ * n_cols (n_cols when speed_min = 0 or leaf_speed = +inf).  With it every
+ * S^U_k >= S^L and every box is non-empty.  DVMAT_E_ARG for a machine out of
+ * range. */
+dvmat_status dvmat_machine_leaf_travel(const dvmat_machine* m, int32_t n_cols, int32_t* travel);
+/* S^U_k and the box of every control point.  m: host pointer (read during the
+ * call); occupied device uint8[n_cp]; L, R device int32[n_cp][n_rows] (rows of
+ * unoccupied points are not read); speed_hi, lo, hi: device float[n_cp]
+ * (lo = rate_min / S^U_k, hi = rate_max / speed_min or +inf).  n_cp <= 8192;
+ * one workgroup, O(n_cp^2) work.  DVMAT_E_ARG / DVMAT_E_SHAPE on bad input. */
+dvmat_status dvmat_machine_boxes(dvmat_geom geom, const dvmat_machine* m, const uint8_t* occupied, const int32_t* L,
+                                 const int32_t* R, float* speed_hi, float* lo, float* hi, dvmat_stream stream);
 
 /* ------------------------------------------------------------------------
  * Master problem (Eq. 6) by Barzilai-Borwein steps (Eqs. 7-8, alternating)
@@ -363,6 +401,11 @@ dvmat_status dvmat_bb_occupancy(dvmat_bb bb, const uint8_t** d_occupied);
  * y0 (clamped to the box).  DVMAT_E_STATE if cp is occupied or the set is full. */
 dvmat_status dvmat_bb_add_aperture(dvmat_bb bb, int32_t cp, const int32_t* d_L, const int32_t* d_R,
                                    float lo, float hi, float y0, dvmat_stream stream);
+/* Replace the box of every aperture by that of its control point: lo_cp,
+ * hi_cp device float[n_cp] (e.g. from dvmat_machine_boxes); each rate is
+ * clipped into its new box (into hi_cp where lo_cp > hi_cp).  Values are not
+ * checked on the host: NaN boxes are the caller's error. */
+dvmat_status dvmat_bb_set_boxes(dvmat_bb bb, const float* lo_cp, const float* hi_cp, dvmat_stream stream);
 /* Start a master-problem solve (iteration counter, flags and F history reset). */
 dvmat_status dvmat_bb_begin(dvmat_bb bb, dvmat_stream stream);
 /* From the price p = D^T dF/dz at the current rates: the gradient in the

@@ -21,7 +21,7 @@ LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libdvmat.so")
 ARCH = os.environ.get("DVMAT_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["ddc_host.cpp", "spmv.hip", "spmv_panel.hip", "select.hip", "bb.hip", "da.hip"]
+SOURCES = ["ddc_host.cpp", "spmv.hip", "spmv_panel.hip", "select.hip", "machine.hip", "bb.hip", "da.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           f"-I{os.path.join(ROOT, 'include')}"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

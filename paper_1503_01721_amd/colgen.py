@@ -17,7 +17,9 @@ same iterates up to rounding.
 Aperture options: the interdigitation constraint of the MLC leaves (Sec.
 2.2.2) and leaf windows that keep a candidate deliverable after the apertures
 already chosen at the neighbouring control points (Sec. 2.1): each leaf within
-leaf_travel beamlets of its position there.
+leaf_travel beamlets of its position there.  A machine model (Eq. 2: gantry
+speed and dose-rate ranges, speed change, leaf speed) sets that travel and,
+after each new aperture, every aperture's rate box (Eq. 6).
 
 Per iteration the host reads back one small record (chosen control point,
 its price, the solve's flags and F); all other data stays on the device.
@@ -47,7 +49,8 @@ class ColumnGeneration:
     def __init__(self, ddc: dvmat.DDC, obj: dvmat.Objective, n_cp: int, n_rows: int, n_cols: int,
                  max_apertures: Optional[int] = None, bb_steps: int = 50, eps_f: float = 1e-5,
                  eps_step: float = 1e-7, lo: float = 0.0, hi: float = float("inf"), form: str = "D",
-                 interdigitated: bool = False, leaf_travel: Optional[int] = None):
+                 interdigitated: bool = False, leaf_travel: Optional[int] = None,
+                 machine: Optional[dvmat.Machine] = None):
         if form not in ("D", "DA"):
             raise ValueError("form must be 'D' or 'DA'")
         self.form = form
@@ -62,6 +65,11 @@ class ColumnGeneration:
         self.bb = dvmat.BB(n_cp, n_rows, n_cols, self.max_apertures, max_iter=bb_steps, eps_f=eps_f,
                            eps_step=eps_step, device=dev)
         self.sel = dvmat.ApertureSelector(n_cp, n_rows, n_cols, device=dev, interdigitated=interdigitated)
+        self.machine = machine
+        if machine is not None:
+            t = dvmat.machine_leaf_travel(machine, n_cols)
+            leaf_travel = t if leaf_travel is None else min(leaf_travel, t)
+            self.boxes = tuple(torch.empty(n_cp, dtype=torch.float32, device=dev) for _ in range(3))
         self.leaf_travel = leaf_travel
         if leaf_travel is not None:
             i32 = dict(dtype=torch.int32, device=dev)
@@ -163,6 +171,11 @@ class ColumnGeneration:
         if self.leaf_travel is not None:
             self.ap_L[best].copy_(self.sel.L[best])
             self.ap_R[best].copy_(self.sel.R[best])
+        if self.machine is not None:
+            # the new aperture tightens its neighbours' speed bounds: every box anew
+            dvmat.machine_boxes(self.n_cp, self.n_rows, self.n_cols, self.machine, self.bb.occupied_ptr,
+                                self.ap_L, self.ap_R, out=self.boxes)
+            self.bb.set_boxes(self.boxes[1], self.boxes[2])
         if self.form == "DA":
             self._append_da_column(best)
         self.master_problem()

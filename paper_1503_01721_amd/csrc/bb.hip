@@ -110,6 +110,17 @@ __global__ void bb_add_kernel(BBDev B, int slot, int cp, int n_rows, const int32
     }
 }
 
+// Boxes from per-control-point arrays; each rate clipped into its new box.
+__global__ void bb_set_boxes_kernel(BBDev B, int m, const float* __restrict__ lo_cp, const float* __restrict__ hi_cp) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < m; k += gridDim.x * blockDim.x) {
+        const int c = B.cp[k];
+        const float lo = lo_cp[c], hi = hi_cp[c];
+        B.lo[k] = lo;
+        B.hi[k] = hi;
+        B.y[k] = fminf(fmaxf(B.y[k], lo), hi);
+    }
+}
+
 __global__ void bb_begin_kernel(BBDev B) {
     if (threadIdx.x == 0) {
         B.state->t = 0;
@@ -417,6 +428,14 @@ dvmat_status dvmat_bb_add_aperture(dvmat_bb b, int32_t cp, const int32_t* dL, co
     b->occupied[cp] = 1;
     b->m++;
     return DVMAT_OK;
+}
+
+dvmat_status dvmat_bb_set_boxes(dvmat_bb b, const float* lo_cp, const float* hi_cp, dvmat_stream stream) {
+    if (!b || !lo_cp || !hi_cp) return set_error(DVMAT_E_ARG, "dvmat_bb_set_boxes: NULL argument");
+    if (b->m == 0) return DVMAT_OK;
+    hipLaunchKernelGGL(bb_set_boxes_kernel, dim3((unsigned)((b->m + 255) / 256)), dim3(256), 0,
+                       reinterpret_cast<hipStream_t>(stream), b->dev, b->m, lo_cp, hi_cp);
+    return check_hip(hipGetLastError(), "dvmat_bb_set_boxes launch");
 }
 
 dvmat_status dvmat_bb_begin(dvmat_bb b, dvmat_stream stream) {

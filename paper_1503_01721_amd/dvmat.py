@@ -78,6 +78,13 @@ class BBParams(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("eps_f", ctypes.c_float), ("eps_step", ctypes.c_float)]
 
 
+class Machine(ctypes.Structure):
+    """Machine parameters of Eq. (2) (dvmat_machine): gantry_step, speed_min,
+    speed_max, speed_change, rate_min, rate_max, leaf_speed."""
+    _fields_ = [(n, ctypes.c_float) for n in ("gantry_step", "speed_min", "speed_max", "speed_change", "rate_min",
+                                              "rate_max", "leaf_speed")]
+
+
 _P = ctypes.c_void_p
 _I32, _I64, _SZ, _F = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_float
 
@@ -114,6 +121,9 @@ _SIGNATURES = {
     "dvmat_aperture_select": (_I32, [Geom, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "dvmat_leaf_windows": (_I32, [Geom, _P, _P, _P, _I32, _P, _P]),
     "dvmat_aperture_select_ws_size": (_I32, [Geom, ctypes.POINTER(_SZ)]),
+    "dvmat_machine_leaf_travel": (_I32, [ctypes.POINTER(Machine), _I32, ctypes.POINTER(_I32)]),
+    "dvmat_machine_boxes": (_I32, [Geom, ctypes.POINTER(Machine), _P, _P, _P, _P, _P, _P, _P]),
+    "dvmat_bb_set_boxes": (_I32, [_P, _P, _P, _P]),
     "dvmat_aperture_select_interdigitated": (_I32, [Geom, _P, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "dvmat_bb_workspace_size": (_I32, [Geom, _I32, ctypes.POINTER(_SZ)]),
     "dvmat_bb_create": (_I32, [Geom, _I32, BBParams, _P, _SZ, _P, ctypes.POINTER(_P)]),
@@ -436,6 +446,32 @@ def leaf_windows(n_cp, n_rows, n_cols, occupied, L, R, travel, out=None, stream=
     return out
 
 
+def machine_leaf_travel(machine: Machine, n_cols: int) -> int:
+    """Leaf travel that keeps a candidate reachable at the slowest gantry speed."""
+    t = _I32()
+    _check(lib.dvmat_machine_leaf_travel(ctypes.byref(machine), int(n_cols), ctypes.byref(t)))
+    return t.value
+
+
+def machine_boxes(n_cp, n_rows, n_cols, machine: Machine, occupied, L, R, out=None, stream=None):
+    """(S^U_k, lo_k, hi_k) device float[n_cp] each: the rate boxes of Eq. (6)
+    that the machine model of Eq. (2) gives the apertures L, R [n_cp, n_rows]
+    at the occupied control points."""
+    geom = Geom(n_cp, n_rows, n_cols)
+    if not isinstance(occupied, ctypes.c_void_p):
+        _need(occupied, n_cp, torch.uint8, name="occupied")
+    occ = occupied if isinstance(occupied, ctypes.c_void_p) else _ptr(occupied)
+    _need(L, n_cp * n_rows, torch.int32, name="L")
+    _need(R, n_cp * n_rows, torch.int32, name="R")
+    if out is None:
+        out = tuple(torch.empty(n_cp, dtype=torch.float32, device=L.device) for _ in range(3))
+    for t, name in zip(out, ("speed_hi", "lo", "hi")):
+        _need(t, n_cp, name=name)
+    _check(lib.dvmat_machine_boxes(geom, ctypes.byref(machine), occ, _ptr(L), _ptr(R), _ptr(out[0]), _ptr(out[1]),
+                                   _ptr(out[2]), _stream(stream)))
+    return out
+
+
 class BB:
     """Device-resident master-problem state (aperture set, rates, BB history)."""
 
@@ -482,6 +518,12 @@ class BB:
         _need(R_row, self.geom.n_rows, torch.int32, name="R")
         _check(lib.dvmat_bb_add_aperture(self._h, int(cp), _ptr(L_row), _ptr(R_row), float(lo), float(hi),
                                          float(y0), _stream(stream)))
+
+    def set_boxes(self, lo_cp, hi_cp, stream=None):
+        """Every aperture takes the box of its control point (device float[n_cp])."""
+        _need(lo_cp, self.geom.n_cp, name="lo_cp")
+        _need(hi_cp, self.geom.n_cp, name="hi_cp")
+        _check(lib.dvmat_bb_set_boxes(self._h, _ptr(lo_cp), _ptr(hi_cp), _stream(stream)))
 
     def begin(self, stream=None):
         _check(lib.dvmat_bb_begin(self._h, _stream(stream)))

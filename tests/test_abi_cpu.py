@@ -162,3 +162,31 @@ def test_build_options(dv):
         assert info.nnz_pad_dose >= info.nnz and info.nnz_pad_dose % bd == 0
         assert info.nnz_pad_price >= info.nnz and info.nnz_pad_price % bp == 0
         dv.lib.dvmat_ddc_destroy(h)
+
+
+def test_machine_leaf_travel_and_argument_checks(dv):
+    """The leaf travel is host arithmetic: checked against the oracle here."""
+    import math
+
+    from oracle import machine as omach
+    cases = [(2.0, 1.0, 6.0, 1.0, 2.0, 10.0, 3.0, 8), (2.0, 1.0, 6.0, 1.0, 2.0, 10.0, 3.0, 4),
+             (1.0, 0.0, 4.0, 0.5, 0.0, 1.0, 2.0, 20), (1.0, 0.5, 4.0, 0.5, 0.0, 1.0, math.inf, 20),
+             (0.75, 0.5, 4.0, 0.25, 1.0, 2.0, 1.25, 40), (3.0, 0.25, math.inf, math.inf, 0.0, math.inf, 0.5, 100)]
+    for *vals, n_cols in cases:
+        m = dv.Machine(*vals)
+        assert dv.machine_leaf_travel(m, n_cols) == omach.leaf_travel(omach.Machine(*vals), n_cols)
+    t = ctypes.c_int32()
+    bad = [(0.0, 1, 2, 1, 0, 1, 1), (1, -1, 2, 1, 0, 1, 1), (1, 3, 2, 1, 0, 1, 1), (1, 1, 2, -1, 0, 1, 1),
+           (1, 1, 2, 1, 2, 1, 1), (1, 1, 2, 1, 0, 1, 0), (1, 1, 2, 1, math.nan, 1, 1), (1, 1, 2, 1, math.inf, math.inf, 1)]
+    for vals in bad:
+        assert dv.lib.dvmat_machine_leaf_travel(ctypes.byref(dv.Machine(*vals)), 10, ctypes.byref(t)) == -1, vals
+    good = dv.Machine(2, 1, 6, 1, 2, 10, 3)
+    assert dv.lib.dvmat_machine_leaf_travel(None, 10, ctypes.byref(t)) == -1
+    assert dv.lib.dvmat_machine_leaf_travel(ctypes.byref(good), 0, ctypes.byref(t)) == -1
+    g = dv.Geom(4, 3, 5)
+    assert dv.lib.dvmat_machine_boxes(g, ctypes.byref(good), None, None, None, None, None, None, None) == -1
+    assert dv.lib.dvmat_machine_boxes(g, ctypes.byref(dv.Machine(*bad[0])), None, None, None, None, None, None,
+                                      None) == -1
+    assert dv.lib.dvmat_machine_boxes(dv.Geom(8193, 3, 5), ctypes.byref(good), None, None, None, None, None, None,
+                                      None) == -2
+    assert dv.lib.dvmat_bb_set_boxes(None, None, None, None) == -1

@@ -822,3 +822,131 @@ def test_da_columns_and_eval(dv, plan1):
     da.curvature_(obj, torch.tensor(dirv, device="cuda"), z, curv)
     c_ref = oobj.curvature(DA @ dirv.astype(np.float64), z.cpu().numpy().astype(np.float64), sid, table)
     assert abs(float(curv.cpu()[0]) - c_ref) <= 3e-5 * c_ref
+
+
+# ---------------------------------------------------------------- machine constraints (Eq. 2 -> Eq. 6 boxes)
+
+from oracle import machine as omach  # noqa: E402
+
+
+MACHINES = [
+    (2.0, 1.0, 6.0, 1.0, 2.0, 10.0, 3.0),
+    (1.0, 0.5, 4.0, 0.25, 0.5, 8.0, 2.0),
+    (1.0, 0.0, 4.0, 0.0, 0.0, 1.0, 1.5),                       # no speed change allowed, no rate ceiling
+    (0.5, 0.25, float("inf"), float("inf"), 1.0, float("inf"), 0.75),
+    (1.0, 1.0, 3.0, 0.5, 1.0, 2.0, float("inf")),              # leaves never limit the gantry
+]
+
+
+def test_machine_boxes_hand_worked_case(dv):
+    occ = np.array([0, 1, 1, 0, 1, 1], np.uint8)
+    L = np.zeros((6, 2), np.int32)
+    R = np.zeros((6, 2), np.int32)
+    L[1], R[1] = (1, 2), (5, 6)
+    L[2], R[2] = (2, 2), (5, 7)
+    L[4], R[4] = (0, 3), (4, 8)
+    L[5], R[5] = (2, 3), (4, 5)
+    s, lo, hi = dv.machine_boxes(6, 2, 8, dv.Machine(*MACHINES[0]), cuda(occ), cuda(L), cuda(R))
+    assert s.cpu().tolist() == [6, 5, 4, 3, 2, 3]
+    assert np.allclose(lo.cpu().numpy(), [2 / 6, 2 / 5, 2 / 4, 2 / 3, 1.0, 2 / 3], rtol=1e-7)
+    assert np.all(hi.cpu().numpy() == 10)
+
+
+@pytest.mark.parametrize("n_cp,n_rows,n_cols", [(1, 3, 5), (2, 1, 4), (20, 20, 20), (180, 40, 40), (361, 7, 60),
+                                                (1000, 4, 12)])
+def test_machine_boxes_match_oracle(dv, n_cp, n_rows, n_cols):
+    rng = np.random.default_rng(n_cp * 7 + n_rows)
+    for i, vals in enumerate(MACHINES):
+        om = omach.Machine(*vals)
+        occ = (rng.random(n_cp) < [0.3, 0.7, 1.0, 0.5, 0.9][i]).astype(np.uint8)
+        L = rng.integers(0, n_cols + 1, (n_cp, n_rows)).astype(np.int32)
+        R = np.minimum(n_cols, L + rng.integers(0, n_cols + 1, (n_cp, n_rows))).astype(np.int32)
+        if i == 1:                                                  # small moves: many slack pairs
+            L = np.repeat(L[:1], n_cp, 0) + rng.integers(0, 2, (n_cp, n_rows)).astype(np.int32)
+            R = np.maximum(L, R)
+        s, lo, hi = (t.cpu().numpy().astype(np.float64)
+                     for t in dv.machine_boxes(n_cp, n_rows, n_cols, dv.Machine(*vals), cuda(occ), cuda(L), cuda(R)))
+        s_ref, lo_ref, hi_ref = omach.boxes(om, occ.astype(bool), L, R)
+        for a, b in ((s, s_ref), (lo, lo_ref), (hi, hi_ref)):
+            fin = np.isfinite(b)
+            assert np.array_equal(np.isfinite(a), fin), (i, n_cp)
+            assert np.allclose(a[fin], b[fin], rtol=2e-6, atol=0), (i, n_cp, np.abs(a[fin] / b[fin] - 1).max())
+
+
+def test_bb_set_boxes_moves_rates_into_the_boxes(dv):
+    n_cp, n_rows, n_cols = 8, 3, 5
+    bb = dv.BB(n_cp, n_rows, n_cols, 4)
+    L = cuda(np.zeros(n_rows, np.int32))
+    R = cuda(np.full(n_rows, n_cols, np.int32))
+    y0 = [0.5, 3.0, 1.0, 7.0]
+    for k, cp in enumerate((6, 1, 3, 0)):
+        bb.add_aperture(cp, L, R, 0.0, float("inf"), y0[k])
+    lo = np.linspace(0.8, 2.2, n_cp).astype(np.float32)
+    hi = np.full(n_cp, 4.0, np.float32)
+    hi[3] = 0.5                                                      # empty box at cp 3: the rate goes to hi
+    bb.set_boxes(cuda(lo), cuda(hi))
+    y = bb.y().cpu().numpy()
+    exp = [min(max(v, lo[c]), hi[c]) for v, c in zip(y0, (6, 1, 3, 0))]
+    assert np.array_equal(y, np.array(exp, np.float32))
+
+
+def test_column_generation_with_machine_matches_oracle(dv):
+    """The machine model in the GPU loop on the eight-point plan, checked per
+    iteration against the oracle from the same state: prices, the selection's
+    optimality within the leaf windows the machine implies, the boxes of
+    every control point, and the master problem's F; the leaf-motion and the
+    lower rate bounds both bind on this plan."""
+    from paper_1503_01721_amd.colgen import ColumnGeneration
+    d = synth.generate_ddc(SMALL)
+    sid, table = synth.structures(SMALL)
+    ddc = dv.DDC(d["row"], d["col"], d["val"], SMALL.n_vox, SMALL.n_bl)
+    obj = dv.Objective(sid, table)
+    n_cp, n_rows, n_cols = SMALL.n_cp, SMALL.n_rows, SMALL.n_cols
+    vals = (1.0, 1.0, 4.0, 0.5, 2.0, 50.0, 2.0)
+    om = omach.Machine(*vals)
+    travel = omach.leaf_travel(om, n_cols)
+    cg = ColumnGeneration(ddc, obj, n_cp, n_rows, n_cols, bb_steps=50, eps_f=0.0, eps_step=0.0,
+                          machine=dv.Machine(*vals))
+    assert cg.leaf_travel == travel == 2
+    cg.start()
+    apset = obb.ApertureSet(n_cp, n_rows, n_cols)
+    occupied = np.zeros(n_cp, bool)
+    L_all = np.zeros((n_cp, n_rows), np.int32)
+    R_all = np.zeros((n_cp, n_rows), np.int32)
+    y = np.zeros(0)
+    bound_hit = lo_hit = False
+    for it in range(n_cp):
+        z = oprod.dose(d["row"], d["col"], d["val"], apset.expand(y), SMALL.n_vox)
+        gz = oobj.gradient(z, sid, table)
+        p_ref = oprod.price(d["row"], d["col"], d["val"], gz, SMALL.n_bl)
+        scale = oprod.price(d["row"], d["col"], d["val"], np.abs(gz), SMALL.n_bl).max()
+        assert np.abs(cg.p.cpu().numpy() - p_ref).max() <= 1e-4 * scale, it
+        rec = cg.iteration()
+        if rec is None:
+            break
+        sel = ocg.select_aperture(p_ref, n_cp, n_rows, n_cols, occupied, L_all, R_all, False, travel)
+        L = cg.sel.L.cpu().numpy()[rec.cp]
+        R = cg.sel.R.cpu().numpy()[rec.cp]
+        w = oap.leaf_windows(n_cp, n_rows, n_cols, occupied, L_all, R_all, travel)
+        assert all(oap.allowed((L[r], R[r]), w[rec.cp, r]) for r in range(n_rows))
+        P = p_ref.reshape(n_cp, n_rows, n_cols)[rec.cp]
+        chosen = sum(P[r, L[r]:R[r]].sum() for r in range(n_rows))
+        tol = 1e-4 * scale * n_rows * n_cols
+        assert not occupied[rec.cp] and chosen <= sel["best_price"] + tol
+        occupied[rec.cp] = True
+        L_all[rec.cp], R_all[rec.cp] = L, R
+        apset.add(rec.cp, L, R)
+        s_ref, lo_ref, hi_ref = omach.boxes(om, occupied, L_all, R_all)
+        assert np.allclose(cg.boxes[0].cpu().numpy(), s_ref, rtol=1e-6)
+        assert np.allclose(cg.boxes[1].cpu().numpy(), lo_ref, rtol=1e-6)
+        assert np.allclose(cg.boxes[2].cpu().numpy(), hi_ref, rtol=1e-6)
+        bound_hit |= bool(s_ref.min() < om.speed_max)
+        lo_k, hi_k = lo_ref[apset.cps], hi_ref[apset.cps]
+        ref = obb.solve(obb.d_form_ops(d["row"], d["col"], d["val"], SMALL.n_vox, SMALL.n_bl, apset)[0],
+                        obb.d_form_ops(d["row"], d["col"], d["val"], SMALL.n_vox, SMALL.n_bl, apset)[1],
+                        sid, table, np.append(y, 0.0), lo_k, hi_k, obb.BBParams(max_iter=50, eps_f=0.0, eps_step=0.0))
+        assert rec.F == pytest.approx(ref["F"], rel=1e-4), it
+        y = cg.bb.y().cpu().numpy().astype(np.float64)
+        assert np.all(y >= lo_k * (1 - 1e-6)) and np.all(y <= hi_k * (1 + 1e-6))
+        lo_hit |= bool(np.any(np.abs(y - lo_k) <= 1e-6 * lo_k))
+    assert bound_hit and lo_hit
