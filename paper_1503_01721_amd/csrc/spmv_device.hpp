@@ -243,7 +243,8 @@ __device__ __forceinline__ void fma4_blocked(float (&acc)[B][NRHS], const SpmvPa
 // the short block rows of the dose do not each wait for them in turn.
 // LDSG: gather from a panel's slice of the vector in LDS (xsrc) through the
 // panel-local 16-bit column indices col16, instead of from P.x through P.col.
-template <int ST, int NRHS, int EPI, bool SCALE_X, int B, bool LDSG = false>
+// DEEP: four steps in flight where a row is long (one right-hand side, B = 1).
+template <int ST, int NRHS, int EPI, bool SCALE_X, int B, bool LDSG = false, bool DEEP = false>
 __device__ __forceinline__ void block_rows(const SpmvParams& P, int r0, int r1, int lane, const f32x4* tab,
                                            float (&fpart)[NRHS], double& cpart, const float* xsrc = nullptr,
                                            const uint16_t* col16 = nullptr) {
@@ -291,6 +292,24 @@ __device__ __forceinline__ void block_rows(const SpmvParams& P, int r0, int r1, 
         // two steps in flight unless a step already holds 64 bytes of values
         // per lane (FP32 with 4 rows per block row): registers, not bytes, bind there
         constexpr bool kTwoSteps = (ST == DVMAT_F32 ? 4 : 2) * B < 16;
+        constexpr bool kFourSteps = DEEP && kTwoSteps && B == 1 && NRHS == 1;
+        if constexpr (kFourSteps) {
+            for (; k + 768 < e1; k += 1024) {
+                f32x4 V0[B], V1[B], V2[B], V3[B];
+                load_block_vals<ST, B>(P.val, k, V0);
+                const i32x4 c0 = cols(k);
+                load_block_vals<ST, B>(P.val, k + 256, V1);
+                const i32x4 c1 = cols(k + 256);
+                load_block_vals<ST, B>(P.val, k + 512, V2);
+                const i32x4 c2 = cols(k + 512);
+                load_block_vals<ST, B>(P.val, k + 768, V3);
+                const i32x4 c3 = cols(k + 768);
+                fma4_blocked<NRHS, B, SCALE_X>(acc, P, xsrc, V0, c0);
+                fma4_blocked<NRHS, B, SCALE_X>(acc, P, xsrc, V1, c1);
+                fma4_blocked<NRHS, B, SCALE_X>(acc, P, xsrc, V2, c2);
+                fma4_blocked<NRHS, B, SCALE_X>(acc, P, xsrc, V3, c3);
+            }
+        }
         if constexpr (kTwoSteps) {
             for (; k + 256 < e1; k += 512) {
                 f32x4 V0[B], V1[B];

@@ -35,6 +35,39 @@ struct PanelParams {
 // Eight waves share one LDS slice, so the slice does not cap occupancy.
 constexpr int kPanelThreads = 512;
 
+// Copy a panel's slice of the input into LDS: xs[i*R + h] = x[list[i]*ldx + h]
+// (times scale[list[i]] when SCALE).  Each thread issues kDepth list loads,
+// then kDepth gathers, then the LDS writes, so a slice of several thousand
+// columns costs a few dependent round trips to memory instead of one per 512
+// columns.  Indexes past the list's end are clamped to its last entry (loads
+// stay in bounds, their values are not written).
+template <int R, bool SCALE>
+__device__ __forceinline__ void stage_slice(float* xs, const int32_t* __restrict__ list, int nu,
+                                            const float* __restrict__ x, int64_t ldx,
+                                            const float* __restrict__ scale) {
+    constexpr int kDepth = R <= 2 ? 8 : 4;
+    for (int i0 = threadIdx.x; i0 < nu; i0 += kDepth * kPanelThreads) {
+        int32_t j[kDepth];
+#pragma unroll
+        for (int u = 0; u < kDepth; ++u) j[u] = list[min(i0 + u * kPanelThreads, nu - 1)];
+        float v[kDepth][R];
+#pragma unroll
+        for (int u = 0; u < kDepth; ++u) {
+            const float sc = SCALE ? scale[j[u]] : 1.0f;
+#pragma unroll
+            for (int h = 0; h < R; ++h) v[u][h] = x[(int64_t)j[u] * ldx + h] * sc;
+        }
+#pragma unroll
+        for (int u = 0; u < kDepth; ++u) {
+            const int i = i0 + u * kPanelThreads;
+            if (i < nu) {
+#pragma unroll
+                for (int h = 0; h < R; ++h) xs[i * R + h] = v[u][h];
+            }
+        }
+    }
+}
+
 template <int ST, int R, int EPI, int B>
 __global__ __launch_bounds__(kPanelThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void spmv_panel_kernel(
     SpmvParams P, PanelParams Q) {
@@ -46,6 +79,10 @@ __global__ __launch_bounds__(kPanelThreads) __attribute__((amdgpu_waves_per_eu(8
     }
     const int lane = threadIdx.x & (kWaveSize - 1);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWaveSize);
+    // four steps in flight for the long rows of D^T (a beamlet reaches well
+    // over a thousand voxels); the dose's shorter voxel rows ran slower with
+    // the larger loop body
+    constexpr bool kDeep = EPI == EPI_PLAIN || EPI == EPI_SCALE;
     float fpart[R];
 #pragma unroll
     for (int h = 0; h < R; ++h) fpart[h] = 0.0f;
@@ -55,15 +92,11 @@ __global__ __launch_bounds__(kPanelThreads) __attribute__((amdgpu_waves_per_eu(8
         const int64_t u0 = Q.panel_u[p];
         const int nu = (int)(Q.panel_u[p + 1] - u0);
         __syncthreads();                              // the previous panel's gathers are done
-        for (int i = threadIdx.x; i < nu; i += kPanelThreads) {
-            const int64_t j = Q.ulist[u0 + i];
-#pragma unroll
-            for (int h = 0; h < R; ++h) xs[i * R + h] = Q.x[j * Q.ldx + h];
-        }
+        stage_slice<R, false>(xs, Q.ulist + u0, nu, Q.x, Q.ldx, nullptr);
         __syncthreads();
         const int q0 = Q.part_units[t], q1 = Q.part_units[t + 1];
         for (int q = q0 + wid; q < q1; q += kWaves)
-            block_rows<ST, R, EPI, false, B, true>(P, P.blocks[q], P.blocks[q + 1], lane, s_tab, fpart, cpart, xs,
+            block_rows<ST, R, EPI, false, B, true, kDeep>(P, P.blocks[q], P.blocks[q + 1], lane, s_tab, fpart, cpart, xs,
                                                    Q.col16);
     }
     workgroup_partials_n<R, EPI, kWaves>(P, lane, wid, fpart, cpart);
@@ -157,12 +190,7 @@ __global__ __launch_bounds__(kPanelThreads) __attribute__((amdgpu_waves_per_eu(8
         const int nu = (int)(pd.panel_u[pan + 1] - u0);
         const float* x = Bp.x[p];
         __syncthreads();                              // the previous part's gathers are done
-        for (int i = threadIdx.x; i < nu; i += kPanelThreads) {
-            const int64_t j = pd.ulist[u0 + i];
-            const float sc = SCALE_STAGE ? pd.scale[j] : 1.0f;
-#pragma unroll
-            for (int h = 0; h < R; ++h) xs[i * R + h] = x[j * nrhs + h0 + h] * sc;
-        }
+        stage_slice<R, SCALE_STAGE>(xs, pd.ulist + u0, nu, x + h0, nrhs, pd.scale);
         __syncthreads();
         SpmvParams P{};
         P.n_rows = pd.n_rows;
