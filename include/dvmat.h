@@ -145,9 +145,12 @@ typedef struct {
  * dose B = 2 at 4-byte and 4 at 2-byte values, price B = 1 and 2; panels:
  * dose B = 1 and 2, price B = 1), price rows in first-column order, layout
  * CSR with zero grids (a caller that knows the voxel and beamlet grids sets
- * layout 1, the grids and tiles), panel_cols 12288, part_entries 131072.  Environment variables DVMAT_DOSE_B, DVMAT_PRICE_B, DVMAT_INTERLEAVE,
- * DVMAT_BLOCK_NNZ, DVMAT_DOSE_ORDER, DVMAT_PRICE_ORDER, DVMAT_PANEL_COLS
- * override single fields.  DVMAT_E_ARG for an unknown storage. */
+ * layout 1, the grids and tiles), panel_cols 12288, part_entries 131072.
+ * Environment variables DVMAT_DOSE_B, DVMAT_PRICE_B, DVMAT_INTERLEAVE,
+ * DVMAT_BLOCK_NNZ, DVMAT_DOSE_ORDER, DVMAT_PRICE_ORDER, DVMAT_PANEL_COLS and
+ * DVMAT_PART_ENTRIES override single fields (DVMAT_SPMV_KIND and DVMAT_SPMV_WG
+ * the launch shape a new handle starts with).  DVMAT_E_ARG for an unknown
+ * storage. */
 dvmat_status dvmat_ddc_default_opts(int32_t storage, dvmat_build_opts* opts);
 
 /* Validate host COO (row = voxel, col = beamlet, val; length nnz; read during
