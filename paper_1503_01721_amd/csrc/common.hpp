@@ -29,8 +29,8 @@ constexpr int kBlockRowsMax = 64;
 // Plans per batched launch (their vector pointers travel as kernel arguments).
 constexpr int kMaxBatch = 64;
 
-// Launch shape of one SpMV orientation: block kernel (0 = row, 1 = stream)
-// and workgroup count.
+// Launch shape of one SpMV orientation: block kernel (Kind below) and
+// workgroup count.
 struct KernelCfg {
     int kind;
     int workgroups;
@@ -45,7 +45,7 @@ dvmat_status check_hip(hipError_t e, const char* what);
 
 inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
 
-// One CSR orientation inside the device workspace.
+// One orientation (CSR or panels) inside the device workspace.
 struct CsrDev {
     int64_t n_rows = 0;                // rows of the orientation (voxels or beamlets)
     int B = 1;                         // rows per block row

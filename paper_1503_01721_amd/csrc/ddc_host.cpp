@@ -1,11 +1,13 @@
-// Host side of the DDC handle: COO validation, the two CSR orientations
-// (counting sort by row, stable, multi-threaded), duplicate merging, row
-// padding, row blocks, 16-bit quantisation, and the upload into the caller's
+// Host side of the DDC handle: COO validation, the two orientations
+// (counting sort by row, stable, multi-threaded), duplicate merging, row order
+// (tiles of a row grid, or first column), block rows, row padding and entry
+// interleaving, work units, the panel layout (column lists with 16-bit local
+// indices, parts), 16-bit quantisation, and the upload into the caller's
 // device workspace.
 //
 // The paper converts each angle-group sub-matrix D_m to CSR of D_m^T at
-// initialisation (Sec. 2.2.2); here one GPU holds all of D, so both CSR(D)
-// and CSR(D^T) are built once from the host COO.
+// initialisation (Sec. 2.2.2); here one GPU holds all of D, so both
+// orientations of the whole matrix are built once from the host COO.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

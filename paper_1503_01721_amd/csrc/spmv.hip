@@ -10,14 +10,20 @@
 //
 // Work units: rows are grouped on the host into blocks of consecutive rows
 // with a bounded number of stored entries (and at most kBlockRowsMax rows).
-// One wave64 processes one block at a time.  Two block kernels:
-//  - "row": row by row; each lane streams 4 consecutive entries (16-byte
-//    non-temporal value and column loads, so the matrix stream does not evict
-//    the gathered vector from L2), gathers x[col], FP32 accumulation, a fixed
-//    butterfly reduces the wave, lane 0 finishes the row;
+// One wave64 processes one block at a time.  Three block kernels over CSR (the
+// panel layout has its own kernel, spmv_panel.hip, with the same arithmetic):
+//  - "row": block row by block row; each lane streams 4 consecutive block
+//    entries per step, two steps in flight (16-byte non-temporal value and
+//    column loads, so the matrix stream does not evict the gathered vector
+//    from L2), gathers x[col], FP32 accumulation, a fixed-order DPP reduction
+//    across the wave; small blocks leave each row's sums in the lane of that
+//    row and every lane finishes its own row;
 //  - "stream": the block's entries as one contiguous range, 256 per step with
 //    the next step's loads in flight, a segmented reduction across the wave,
-//    per-row sums in LDS, lane i finishes row i.
+//    per-row sums in LDS, lane i finishes row i;
+//  - "pipe": the row kernel's arithmetic with the loads of the next step
+//    (possibly the next block row's first) issued before the current step's
+//    gathers.
 // The grid is a multiple of the 8 XCDs; workgroup w runs on XCD w % 8 and each
 // XCD owns a contiguous range of blocks, so the waves sharing one L2 touch
 // neighbouring rows.  Every reduction has a fixed order: results are bitwise

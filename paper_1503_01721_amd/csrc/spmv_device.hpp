@@ -237,8 +237,10 @@ __device__ __forceinline__ void fma4_blocked(float (&acc)[B][NRHS], const SpmvPa
 
 // Kernel body "row": block rows in order; per block row each lane streams 4
 // consecutive block entries per step (16-byte column load, B 16-byte value
-// loads at FP32), two steps in flight; the wave's butterfly reduces each of
-// the B rows, lane 0 finishes them.  The row pointers and epilogue inputs of
+// loads at FP32), two steps in flight; the wave reduction (wave_sum) sums each
+// of the B rows; for B x NRHS <= 4 the sums stay in the lane of their block
+// row and every lane finishes its own rows after the unit, else lane 0
+// finishes each block row.  The row pointers and epilogue inputs of
 // every block row of the unit are loaded up front, lane i for block row i, so
 // the short block rows of the dose do not each wait for them in turn.
 // LDSG: gather from a panel's slice of the vector in LDS (xsrc) through the

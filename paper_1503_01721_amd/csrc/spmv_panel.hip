@@ -6,7 +6,8 @@
 // stored column indices are positions in that list (16 bits).  A workgroup
 // takes one part of a panel at a time (a run of its work units, so that large
 // panels are shared out): it copies the panel's slice of the input vector
-// into LDS (one coalesced pass over the sorted list), then its eight waves run
+// into LDS (the sorted list read coalesced, several entries in flight per
+// thread), then its eight waves run
 // the block-row arithmetic of the CSR row kernel with gathers served by LDS.
 // The gathers thus leave the L1/L2 request path, which bounds the CSR kernels:
 // there a gathered value costs a cache-line request of its own, here a staged
@@ -32,7 +33,9 @@ struct PanelParams {
     int64_t n_parts;
 };
 
-// Eight waves share one LDS slice, so the slice does not cap occupancy.
+// Eight waves share one LDS slice.  Slices up to 36 KB (the dose of the
+// full-scale single-arc workload has 9,012 columns) let four workgroups fill
+// a CU's 160 KB of LDS and all of its 32 wave slots.
 constexpr int kPanelThreads = 512;
 
 // Copy a panel's slice of the input into LDS: xs[i*R + h] = x[list[i]*ldx + h]
