@@ -44,15 +44,15 @@ constexpr int kPanelThreads = 512;
 // columns costs a few dependent round trips to memory instead of one per 512
 // columns.  Indexes past the list's end are clamped to its last entry (loads
 // stay in bounds, their values are not written).
-template <int R, bool SCALE>
+template <int R, bool SCALE, int NT = kPanelThreads>
 __device__ __forceinline__ void stage_slice(float* xs, const int32_t* __restrict__ list, int nu,
                                             const float* __restrict__ x, int64_t ldx,
                                             const float* __restrict__ scale) {
     constexpr int kDepth = R <= 2 ? 8 : 4;
-    for (int i0 = threadIdx.x; i0 < nu; i0 += kDepth * kPanelThreads) {
+    for (int i0 = threadIdx.x; i0 < nu; i0 += kDepth * NT) {
         int32_t j[kDepth];
 #pragma unroll
-        for (int u = 0; u < kDepth; ++u) j[u] = list[min(i0 + u * kPanelThreads, nu - 1)];
+        for (int u = 0; u < kDepth; ++u) j[u] = list[min(i0 + u * NT, nu - 1)];
         float v[kDepth][R];
 #pragma unroll
         for (int u = 0; u < kDepth; ++u) {
@@ -62,7 +62,7 @@ __device__ __forceinline__ void stage_slice(float* xs, const int32_t* __restrict
         }
 #pragma unroll
         for (int u = 0; u < kDepth; ++u) {
-            const int i = i0 + u * kPanelThreads;
+            const int i = i0 + u * NT;
             if (i < nu) {
 #pragma unroll
                 for (int h = 0; h < R; ++h) xs[i * R + h] = v[u][h];
@@ -170,11 +170,19 @@ dvmat_status launch_panel(const KernelCfg& cfg, int storage, const CsrDev& c, co
 //
 // The parts of all plans form one work list; a workgroup's cursor over the
 // plans only moves forward.  The dose of 16-bit storage multiplies the staged
-// slice by the per-beamlet scale (the values hold D_ij / s_j).
+// slice by the per-beamlet scale (the values hold D_ij / s_j).  Several
+// right-hand sides make the slice large (4 right-hand sides of a 3,584-column
+// panel: 56 KB), so the workgroup has sixteen waves: two workgroups fill a
+// CU's 32 wave slots within its 160 KB of LDS (with eight waves they filled
+// half; the batched dose ran 11 % slower).  Slices of all 8 right-hand sides
+// in one pass (112 KB, one workgroup per CU) timed the same as two passes.
+constexpr int kBatchPanelThreads = 1024;
+constexpr size_t kBatchLdsBytes = 64 * 1024;
+
 template <int ST, int R, int EPI, int B, bool SCALE_STAGE>
-__global__ __launch_bounds__(kPanelThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void spmv_batch_panel_kernel(
+__global__ __launch_bounds__(kBatchPanelThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void spmv_batch_panel_kernel(
     BatchParams Bp, int h0, int nrhs) {
-    constexpr int kWaves = kPanelThreads / kWaveSize;
+    constexpr int kWaves = kBatchPanelThreads / kWaveSize;
     static_assert(EPI == EPI_PLAIN || EPI == EPI_SCALE, "the batched launch has no objective epilogue");
     extern __shared__ float xs[];
     const int lane = threadIdx.x & (kWaveSize - 1);
@@ -193,7 +201,7 @@ __global__ __launch_bounds__(kPanelThreads) __attribute__((amdgpu_waves_per_eu(8
         const int nu = (int)(pd.panel_u[pan + 1] - u0);
         const float* x = Bp.x[p];
         __syncthreads();                              // the previous part's gathers are done
-        stage_slice<R, SCALE_STAGE>(xs, pd.ulist + u0, nu, x + h0, nrhs, pd.scale);
+        stage_slice<R, SCALE_STAGE, kBatchPanelThreads>(xs, pd.ulist + u0, nu, x + h0, nrhs, pd.scale);
         __syncthreads();
         SpmvParams P{};
         P.n_rows = pd.n_rows;
@@ -212,12 +220,17 @@ __global__ __launch_bounds__(kPanelThreads) __attribute__((amdgpu_waves_per_eu(8
     }
 }
 
+template <int ST, int R, int EPI, int B, bool SCALE_STAGE>
+static void launch_batch_one(int nwg, size_t lds, const BatchParams& Bp, int h0, int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL((spmv_batch_panel_kernel<ST, R, EPI, B, SCALE_STAGE>), dim3(nwg), dim3(kBatchPanelThreads),
+                       lds, s, Bp, h0, nrhs);
+}
+
 template <int ST, int R, int EPI, bool SCALE_STAGE>
 static void launch_batch_chunk(int B, int nwg, size_t lds, const BatchParams& Bp, int h0, int nrhs, hipStream_t s) {
-    dim3 grid(nwg), block(kPanelThreads);
-    if (B == 4) hipLaunchKernelGGL((spmv_batch_panel_kernel<ST, R, EPI, 4, SCALE_STAGE>), grid, block, lds, s, Bp, h0, nrhs);
-    else if (B == 2) hipLaunchKernelGGL((spmv_batch_panel_kernel<ST, R, EPI, 2, SCALE_STAGE>), grid, block, lds, s, Bp, h0, nrhs);
-    else hipLaunchKernelGGL((spmv_batch_panel_kernel<ST, R, EPI, 1, SCALE_STAGE>), grid, block, lds, s, Bp, h0, nrhs);
+    if (B == 4) launch_batch_one<ST, R, EPI, 4, SCALE_STAGE>(nwg, lds, Bp, h0, nrhs, s);
+    else if (B == 2) launch_batch_one<ST, R, EPI, 2, SCALE_STAGE>(nwg, lds, Bp, h0, nrhs, s);
+    else launch_batch_one<ST, R, EPI, 1, SCALE_STAGE>(nwg, lds, Bp, h0, nrhs, s);
 }
 
 template <int ST, int EPI, bool SCALE_STAGE>
@@ -233,11 +246,11 @@ dvmat_status launch_batch_panel(int storage, int B, int epi_scale, bool scale_st
     const int nwg = (int)std::max<int64_t>(1, std::min<int64_t>(std::max(1, workgroups), Bp.total_blocks));
     if (Bp.total_blocks == 0) return DVMAT_OK;
     const size_t per_rhs = (size_t)std::max<int64_t>(max_panel_cols, 1) * sizeof(float);
-    if (per_rhs > kPanelLdsBytes)
+    if (per_rhs > kBatchLdsBytes)
         return set_error(DVMAT_E_SHAPE, "panel of %lld columns exceeds the LDS slice", (long long)max_panel_cols);
     for (int h0 = 0; h0 < nrhs;) {
         int R = 8;
-        while (R > 1 && (R > nrhs - h0 || per_rhs * R > kPanelLdsBytes)) R >>= 1;
+        while (R > 1 && (R > nrhs - h0 || per_rhs * R > kBatchLdsBytes)) R >>= 1;
         const size_t lds = per_rhs * R;
 #define DVMAT_BATCH_ST(STT)                                                                          \
         if (epi_scale) launch_batch_r<STT, EPI_SCALE, false>(R, B, nwg, lds, Bp, h0, nrhs, s);       \
