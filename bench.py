@@ -77,10 +77,17 @@ def cpu_baseline(d, plan, bytes_dose_plain, bytes_price):
     oprod.price(d["row"], d["col"], d["val"], g, plan.n_bl)
     t2 = time.perf_counter()
     gbs = (bytes_dose_plain + bytes_price) / (t2 - t0) / 1e9
+    model = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next(line.split(":", 1)[1].strip() for line in fh if line.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    affinity = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     return {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": (f"one FP64 dose and one FP64 price product over the whole {plan.name} matrix "
-                       f"(NumPy bincount over COO; dose {t1 - t0:.2f} s, price {t2 - t1:.2f} s); "
-                       f"host {platform.processor() or platform.machine()}, os.cpu_count()={os.cpu_count()}"),
+                       f"(NumPy bincount over COO, single-threaded; dose {t1 - t0:.2f} s, price {t2 - t1:.2f} s); "
+                       f"host {model}, os.cpu_count()={os.cpu_count()}, affinity {affinity} CPUs"),
             "seconds": round(t2 - t0, 3)}
 
 
@@ -260,6 +267,79 @@ def bench_autograd(args):
     }), flush=True)
 
 
+def bench_shard(args):
+    """One GPU's share of a split by voxel rows: the z-slab of the two-arc
+    workload that a GPU of --shards would hold (the central slab, the heaviest:
+    the beamlet grids cover the middle of the cube), with its dose (objective
+    epilogue) and its partial price timed at that real shape.  The exchange the
+    split needs (the price summed over the GPUs, n_bl floats) is not run here."""
+    import torch
+    from paper_1503_01721_amd import dvmat, synth
+    workload = args.workload if args.workload != "cp180_bl40x40_vox128" else "cp360_bl60x60_vox160"
+    storage = args.storage if "--storage" in sys.argv else "f16"
+    plan = synth.PLANS[workload]
+    N, G = plan.n_grid, args.shards
+    if G < 1 or N % G:
+        raise SystemExit(f"--shards must divide the {N} voxel slices")
+    s = G // 2 - 1 if G > 1 else 0
+    z0, z1 = s * N // G, (s + 1) * N // G
+    t = time.perf_counter()
+    d = synth.generate_ddc(plan, z_slab=(z0, z1))
+    d["row"] -= z0 * N * N                                   # slab-local voxel rows
+    sid, table = synth.structures(plan)
+    sid = sid[z0 * N * N:z1 * N * N]
+    n_vox = (z1 - z0) * N * N
+    t_gen = time.perf_counter() - t
+    log(f"generated slab {s} of {G} (slices {z0}..{z1 - 1}) of {plan.name}: nnz={len(d['val'])} in {t_gen:.1f} s")
+    t = time.perf_counter()
+    layout = {} if args.layout == "csr" else {"dose_grid": (N, N, z1 - z0), "price_grid": plan.grids["price_grid"]}
+    ddc = dvmat.DDC(d["row"], d["col"], d["val"], n_vox, plan.n_bl, storage=storage, **layout)
+    del d
+    obj = dvmat.Objective(sid, table)
+    t_build = time.perf_counter() - t
+    if not args.no_autotune:
+        ddc.autotune(reps=3)
+    x, g = synth.bench_vectors(plan.n_bl, n_vox, 1004)
+    x = torch.from_numpy(x).cuda()
+    g0 = torch.from_numpy(g).cuda()
+    z = torch.empty(n_vox, device="cuda")
+    gz = torch.empty(n_vox, device="cuda")
+    F = torch.empty(1, device="cuda")
+    p = torch.empty(plan.n_bl, device="cuda")
+    for _ in range(max(args.warmup, 1)):
+        ddc.dose_(x, z, obj, gz, F)
+        ddc.price_(g0, p)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    for _ in range(args.steps):
+        ddc.dose_(x, z, obj, gz, F)
+    ev[1].record()
+    for _ in range(args.steps):
+        ddc.price_(g0, p)
+    ev[2].record()
+    torch.cuda.synchronize()
+    td = ev[0].elapsed_time(ev[1]) / args.steps
+    tp = ev[1].elapsed_time(ev[2]) / args.steps
+    b = algorithmic_bytes(ddc.info)
+    gbs = (b["dose"] + b["price"]) / ((td + tp) * 1e-3) / 1e9
+    allreduce_us = 2.0 * (G - 1) / G * 4 * plan.n_bl / 153e9 * 1e6
+    log(f"slab dose {td:.3f} ms, partial price {tp:.3f} ms ({gbs:.0f} GB/s); "
+        f"ring all-reduce of the price over {G} GPUs at 153 GB/s per link: ~{allreduce_us:.0f} us (estimate)")
+    print(json.dumps({
+        "metric": "effective HBM GB/s of one GPU's share (voxel-row split) of D.x + D^T.g",
+        "value": round(gbs, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(td + tp, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": storage, "data": "synthetic",
+        "config": {"workload": f"{plan.name}, voxel slab {s} of {G} (slices {z0}..{z1 - 1})", "n_vox": n_vox,
+                   "n_beamlets": plan.n_bl, "nnz": int(ddc.info.nnz), "storage": storage,
+                   "dose_ms": round(td, 4), "price_ms": round(tp, 4),
+                   "pct_hbm_peak": round(100.0 * gbs / HBM_PEAK_GBS, 2),
+                   "price_allreduce_us_estimate": round(allreduce_us, 1),
+                   "generate_s": round(t_gen, 1), "build_upload_s": round(t_build, 1)},
+    }), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -274,10 +354,12 @@ def main():
                     help="fix the dose launch (e.g. row:1024) instead of autotuning it")
     ap.add_argument("--price-kernel", default=None, metavar="KIND:WG",
                     help="fix the price launch (e.g. row:8192) instead of autotuning it")
-    ap.add_argument("--mode", default="colgen", choices=["colgen", "batched", "autograd"],
+    ap.add_argument("--mode", default="colgen", choices=["colgen", "batched", "autograd", "shard"],
                     help="colgen: column-generation iterations (default); batched: many plans x 8 "
                          "right-hand sides in one launch vs one plan at a time; autograd: F(D B y) "
-                         "forward + backward on the two-arc workload")
+                         "forward + backward on the two-arc workload; shard: one GPU's voxel slab of "
+                         "the two-arc workload (--shards)")
+    ap.add_argument("--shards", type=int, default=8, help="GPUs of the voxel-row split in --mode shard")
     ap.add_argument("--plans", type=int, default=48, help="plans in --mode batched")
     ap.add_argument("--panel-cols", type=int, default=3584,
                     help="column budget of the dose panels in --mode batched (3584: 4 right-hand sides per launch)")
@@ -307,6 +389,8 @@ def main():
         return bench_batched(args)
     if args.mode == "autograd":
         return bench_autograd(args)
+    if args.mode == "shard":
+        return bench_shard(args)
 
     plan = synth.PLANS[args.workload]
     if args.warmup + args.steps > plan.n_cp:

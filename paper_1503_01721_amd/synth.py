@@ -178,8 +178,9 @@ def _v_factors(plan: Plan, v_r):
     return np.exp(-(dz * dz) / (2.0 * SIGMA_MM ** 2))     # [n_rows, N]
 
 
-def generate_cp(plan: Plan, a: int, xy=None):
-    """All entries of control point a, sorted by beamlet then voxel index.
+def generate_cp(plan: Plan, a: int, xy=None, z_slab: Optional[Tuple[int, int]] = None):
+    """All entries of control point a, sorted by beamlet then voxel index;
+    with z_slab = (z0, z1) only the voxels of slices z0 <= iz < z1.
 
     Returns (row_vox int32, col_bl int32, val float32)."""
     px, py, pidx = xy if xy is not None else body_xy(plan)
@@ -187,6 +188,9 @@ def generate_cp(plan: Plan, a: int, xy=None):
     u_c, v_r = beamlet_offsets(plan)
     fu = _angle_factors(plan, a, px, py, u_c)             # [C, P]
     fv = _v_factors(plan, v_r)                            # [R, N]
+    if z_slab is not None:
+        fv[:, :z_slab[0]] = 0.0
+        fv[:, z_slab[1]:] = 0.0
     # Only points/slices that can pass the cut (the other factor is <= 1).
     # Padded per-column point lists keep the (r, c, iz, p) order of np.nonzero.
     keep_u = fu >= CUTOFF
@@ -226,8 +230,11 @@ def _threads() -> int:
     return max(1, min(n, 16))
 
 
-def generate_ddc(plan: Plan, cps: Optional[List[int]] = None, threads: Optional[int] = None):
+def generate_ddc(plan: Plan, cps: Optional[List[int]] = None, threads: Optional[int] = None,
+                 z_slab: Optional[Tuple[int, int]] = None):
     """COO of D (voxels x beamlets), sorted by (beamlet, voxel); unique pairs.
+    z_slab = (z0, z1): only the rows of voxel slices z0 <= iz < z1 (global
+    voxel indices), the share of one GPU in a split by voxel rows.
 
     Control points are generated on a thread pool (NumPy releases the GIL in
     its array loops); the result does not depend on the thread count.
@@ -237,9 +244,9 @@ def generate_ddc(plan: Plan, cps: Optional[List[int]] = None, threads: Optional[
     nt = threads or _threads()
     if nt > 1 and len(cps) > 1:
         with ThreadPoolExecutor(nt) as ex:
-            parts = list(ex.map(lambda a: generate_cp(plan, a, xy), cps))
+            parts = list(ex.map(lambda a: generate_cp(plan, a, xy, z_slab), cps))
     else:
-        parts = [generate_cp(plan, a, xy) for a in cps]
+        parts = [generate_cp(plan, a, xy, z_slab) for a in cps]
     nnz = sum(len(p[0]) for p in parts)
     row = np.empty(nnz, np.int32)
     col = np.empty(nnz, np.int32)

@@ -950,3 +950,30 @@ def test_column_generation_with_machine_matches_oracle(dv):
         assert np.all(y >= lo_k * (1 - 1e-6)) and np.all(y <= hi_k * (1 + 1e-6))
         lo_hit |= bool(np.any(np.abs(y - lo_k) <= 1e-6 * lo_k))
     assert bound_hit and lo_hit
+
+
+# ---------------------------------------------------------------- one GPU's share of a voxel-row split
+
+def test_voxel_slabs_compose_the_whole_products(dv, plan1):
+    """A split by voxel rows (z-slabs, in the panel layout with the slab's own
+    grid): each slab's dose is the full dose on its rows, and the slabs'
+    partial prices sum to the full price, the exchange the split needs."""
+    d, sid, table, ddc, obj = plan1
+    N, G = PLAN1.n_grid, 4
+    x, g = synth.bench_vectors(PLAN1.n_bl, PLAN1.n_vox, 61)
+    z_ref = oprod.dose(d["row"], d["col"], d["val"], x, PLAN1.n_vox)
+    p_ref = oprod.price(d["row"], d["col"], d["val"], g, PLAN1.n_bl)
+    p_sum = np.zeros(PLAN1.n_bl)
+    for s in range(G):
+        z0, z1 = s * N // G, (s + 1) * N // G
+        sl = synth.generate_ddc(PLAN1, z_slab=(z0, z1))
+        rows = sl["row"] - z0 * N * N
+        n = (z1 - z0) * N * N
+        part = dv.DDC(rows, sl["col"], sl["val"], n, PLAN1.n_bl, dose_grid=(N, N, z1 - z0),
+                      price_grid=PLAN1.grids["price_grid"])
+        assert part.info.dose_layout == 1
+        z = part.dose(cuda(x)).cpu().numpy()
+        assert np.abs(z - z_ref[z0 * N * N:z1 * N * N]).max() <= TOL * z_ref.max(), s
+        p_sum += part.price(cuda(g[z0 * N * N:z1 * N * N])).cpu().numpy()
+    scale = oprod.price(d["row"], d["col"], d["val"], np.abs(g), PLAN1.n_bl).max()
+    assert np.abs(p_sum - p_ref).max() <= TOL * scale

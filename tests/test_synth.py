@@ -68,3 +68,16 @@ def test_random_apertures_and_boxes():
     assert np.all(L >= 0) and np.all(R <= plan.n_cols) and np.all(L < R)
     lo, hi = synth.random_boxes(8, 5)
     assert np.all(lo >= 0) and np.all(hi > lo)
+
+
+def test_z_slab_is_the_full_matrix_restricted_to_the_slab():
+    """The share of one GPU in a split by voxel rows: generating only slices
+    z0 <= iz < z1 gives exactly the full matrix's entries in those rows."""
+    plan = synth.PLANS["cp20_bl20x20_vox32"]
+    full = synth.generate_ddc(plan)
+    N = plan.n_grid
+    for z0, z1 in ((8, 12), (0, 4), (28, 32)):
+        sl = synth.generate_ddc(plan, z_slab=(z0, z1))
+        keep = (full["row"] >= z0 * N * N) & (full["row"] < z1 * N * N)
+        for k in ("row", "col", "val"):
+            assert np.array_equal(sl[k], full[k][keep]), (z0, k)
