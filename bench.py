@@ -269,20 +269,29 @@ def bench_autograd(args):
 
 def bench_shard(args):
     """One GPU's share of a split by voxel rows: the z-slab of the two-arc
-    workload that a GPU of --shards would hold (the central slab, the heaviest:
-    the beamlet grids cover the middle of the cube), with its dose (objective
-    epilogue) and its partial price timed at that real shape.  The exchange the
-    split needs (the price summed over the GPUs, n_bl floats) is not run here."""
+    workload that a GPU of --shards would hold (slabs cut for equal entry
+    counts, or equal thickness with --slabs equal; the heaviest slab is timed),
+    with its dose (objective epilogue) and its partial price timed at that real
+    shape.  The exchange the split needs (the price summed over the GPUs, n_bl
+    floats) is not run here."""
+    import numpy as np
     import torch
     from paper_1503_01721_amd import dvmat, synth
     workload = args.workload if args.workload != "cp180_bl40x40_vox128" else "cp360_bl60x60_vox160"
     storage = args.storage if "--storage" in sys.argv else "f16"
     plan = synth.PLANS[workload]
     N, G = plan.n_grid, args.shards
-    if G < 1 or N % G:
-        raise SystemExit(f"--shards must divide the {N} voxel slices")
-    s = G // 2 - 1 if G > 1 else 0
-    z0, z1 = s * N // G, (s + 1) * N // G
+    if G < 1 or G > N:
+        raise SystemExit(f"--shards must be between 1 and the {N} voxel slices")
+    counts = synth.slice_counts(plan)
+    if args.slabs == "balanced":
+        slabs = synth.balanced_slabs(plan, G, counts)
+    else:
+        slabs = [(k * N // G, (k + 1) * N // G) for k in range(G)]
+    share = [int(counts[a:b].sum()) for a, b in slabs]
+    s = int(np.argmax(share))                                # the heaviest slab sets the pace
+    z0, z1 = slabs[s]
+    log(f"{args.slabs} slabs {slabs}; entries per slab {share}")
     t = time.perf_counter()
     d = synth.generate_ddc(plan, z_slab=(z0, z1))
     d["row"] -= z0 * N * N                                   # slab-local voxel rows
@@ -331,7 +340,8 @@ def bench_shard(args):
         "value": round(gbs, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(td + tp, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": storage, "data": "synthetic",
-        "config": {"workload": f"{plan.name}, voxel slab {s} of {G} (slices {z0}..{z1 - 1})", "n_vox": n_vox,
+        "config": {"workload": f"{plan.name}, voxel slab {s} of {G} (slices {z0}..{z1 - 1}, {args.slabs} slabs)",
+                   "n_vox": n_vox, "nnz_total": int(counts.sum()),
                    "n_beamlets": plan.n_bl, "nnz": int(ddc.info.nnz), "storage": storage,
                    "dose_ms": round(td, 4), "price_ms": round(tp, 4),
                    "pct_hbm_peak": round(100.0 * gbs / HBM_PEAK_GBS, 2),
@@ -360,6 +370,8 @@ def main():
                          "forward + backward on the two-arc workload; shard: one GPU's voxel slab of "
                          "the two-arc workload (--shards)")
     ap.add_argument("--shards", type=int, default=8, help="GPUs of the voxel-row split in --mode shard")
+    ap.add_argument("--slabs", default="balanced", choices=["balanced", "equal"],
+                    help="voxel slabs of --mode shard: equal entry counts (default) or equal thickness")
     ap.add_argument("--plans", type=int, default=48, help="plans in --mode batched")
     ap.add_argument("--panel-cols", type=int, default=3584,
                     help="column budget of the dose panels in --mode batched (3584: 4 right-hand sides per launch)")

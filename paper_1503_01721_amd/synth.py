@@ -264,6 +264,40 @@ def generate_ddc(plan: Plan, cps: Optional[List[int]] = None, threads: Optional[
     return dict(row=row, col=col, val=val)
 
 
+def slice_counts(plan: Plan, threads: Optional[int] = None) -> np.ndarray:
+    """Approximate number of stored entries in each voxel slice iz (int64[N]),
+    without generating them: an entry is kept where f_v[r, iz] * f_u[c, p] >=
+    CUTOFF, counted per (r, iz) by a search in the sorted f_u of each control
+    point (threshold CUTOFF / f_v; rounding can move an entry at the edge).
+    Used to cut balanced voxel slabs."""
+    xy = body_xy(plan)
+    px, py, _ = xy
+    u_c, v_r = beamlet_offsets(plan)
+    fv = _v_factors(plan, v_r)                                        # [R, N]
+    with np.errstate(divide="ignore", over="ignore"):
+        thr = np.where(fv > 0, CUTOFF / fv, np.inf)
+
+    def one(a):
+        fs = np.sort(_angle_factors(plan, a, px, py, u_c).ravel())
+        return (len(fs) - np.searchsorted(fs, thr, side="left")).sum(axis=0)
+
+    nt = threads or _threads()
+    with ThreadPoolExecutor(nt) as ex:
+        return np.sum(list(ex.map(one, range(plan.n_cp))), axis=0).astype(np.int64)
+
+
+def balanced_slabs(plan: Plan, G: int, counts: Optional[np.ndarray] = None) -> List[Tuple[int, int]]:
+    """G contiguous voxel-slice ranges with about equal entry counts."""
+    c = slice_counts(plan) if counts is None else counts
+    cum = np.concatenate([[0], np.cumsum(c)])
+    cuts = [0]
+    for k in range(1, G):
+        z = int(np.searchsorted(cum, cum[-1] * k / G))
+        cuts.append(min(max(z, cuts[-1] + 1), plan.n_grid - (G - k)))
+    cuts.append(plan.n_grid)
+    return [(cuts[k], cuts[k + 1]) for k in range(G)]
+
+
 def ddc_entries(plan: Plan, vox: np.ndarray, bl: np.ndarray) -> np.ndarray:
     """D_ij (float32, 0 where dropped) for explicit (voxel, beamlet) pairs.
 

@@ -890,7 +890,8 @@ def test_bb_set_boxes_moves_rates_into_the_boxes(dv):
     assert np.array_equal(y, np.array(exp, np.float32))
 
 
-def test_column_generation_with_machine_matches_oracle(dv):
+@pytest.mark.parametrize("form,interdigitated", [("D", False), ("DA", True)])
+def test_column_generation_with_machine_matches_oracle(dv, form, interdigitated):
     """The machine model in the GPU loop on the eight-point plan, checked per
     iteration against the oracle from the same state: prices, the selection's
     optimality within the leaf windows the machine implies, the boxes of
@@ -906,7 +907,7 @@ def test_column_generation_with_machine_matches_oracle(dv):
     om = omach.Machine(*vals)
     travel = omach.leaf_travel(om, n_cols)
     cg = ColumnGeneration(ddc, obj, n_cp, n_rows, n_cols, bb_steps=50, eps_f=0.0, eps_step=0.0,
-                          machine=dv.Machine(*vals))
+                          machine=dv.Machine(*vals), form=form, interdigitated=interdigitated)
     assert cg.leaf_travel == travel == 2
     cg.start()
     apset = obb.ApertureSet(n_cp, n_rows, n_cols)
@@ -924,11 +925,13 @@ def test_column_generation_with_machine_matches_oracle(dv):
         rec = cg.iteration()
         if rec is None:
             break
-        sel = ocg.select_aperture(p_ref, n_cp, n_rows, n_cols, occupied, L_all, R_all, False, travel)
+        sel = ocg.select_aperture(p_ref, n_cp, n_rows, n_cols, occupied, L_all, R_all, interdigitated, travel)
         L = cg.sel.L.cpu().numpy()[rec.cp]
         R = cg.sel.R.cpu().numpy()[rec.cp]
         w = oap.leaf_windows(n_cp, n_rows, n_cols, occupied, L_all, R_all, travel)
         assert all(oap.allowed((L[r], R[r]), w[rec.cp, r]) for r in range(n_rows))
+        if interdigitated:
+            assert all(oap.compatible((L[r], R[r]), (L[r + 1], R[r + 1])) for r in range(n_rows - 1))
         P = p_ref.reshape(n_cp, n_rows, n_cols)[rec.cp]
         chosen = sum(P[r, L[r]:R[r]].sum() for r in range(n_rows))
         tol = 1e-4 * scale * n_rows * n_cols

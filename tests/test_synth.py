@@ -81,3 +81,17 @@ def test_z_slab_is_the_full_matrix_restricted_to_the_slab():
         keep = (full["row"] >= z0 * N * N) & (full["row"] < z1 * N * N)
         for k in ("row", "col", "val"):
             assert np.array_equal(sl[k], full[k][keep]), (z0, k)
+
+
+def test_slice_counts_and_balanced_slabs():
+    plan = synth.PLANS["cp20_bl20x20_vox32"]
+    d = synth.generate_ddc(plan)
+    N = plan.n_grid
+    c = synth.slice_counts(plan)
+    assert np.array_equal(c, np.bincount(d["row"] // (N * N), minlength=N))
+    for G in (1, 3, 4, 7):
+        slabs = synth.balanced_slabs(plan, G, c)
+        assert slabs[0][0] == 0 and slabs[-1][1] == N and all(a < b for a, b in slabs)
+        assert all(slabs[k][1] == slabs[k + 1][0] for k in range(G - 1))
+        share = [c[a:b].sum() for a, b in slabs]
+        assert max(share) <= c.sum() / G + c.max()             # within one slice of the ideal
