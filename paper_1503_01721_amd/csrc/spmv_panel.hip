@@ -34,7 +34,7 @@ struct PanelParams {
 };
 
 // Eight waves share one LDS slice.  Slices up to 36 KB (the dose of the
-// full-scale single-arc workload has 9,012 columns) let four workgroups fill
+// full-scale single-arc workload has 9,114 columns) let four workgroups fill
 // a CU's 160 KB of LDS and all of its 32 wave slots.
 constexpr int kPanelThreads = 512;
 

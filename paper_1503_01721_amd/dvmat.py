@@ -63,9 +63,10 @@ class BuildOpts(ctypes.Structure):
                 ("panel_cols", ctypes.c_int32), ("part_entries", ctypes.c_int32)]
 
 
-# Panel tiles used when the grids are known: 16x8x8 voxels (dose); 4 beamlet
+# Panel tiles used when the grids are known: 32x16x2 voxels (dose: rows of 32
+# voxels make whole 128-byte lines of the dose output); 4 beamlet
 # columns x 2 MLC rows x 8 control points (price).
-DOSE_TILE = (16, 8, 8)
+DOSE_TILE = (32, 16, 2)
 PRICE_TILE = (4, 2, 8)
 LAYOUTS = {"csr": 0, "panel": 1}
 
