@@ -63,10 +63,13 @@ class BuildOpts(ctypes.Structure):
                 ("panel_cols", ctypes.c_int32), ("part_entries", ctypes.c_int32)]
 
 
-# Panel tiles used when the grids are known: 32x16x2 voxels (dose: rows of 32
-# voxels make whole 128-byte lines of the dose output); 4 beamlet
-# columns x 2 MLC rows x 8 control points (price).
+# Panel tiles used when the grids are known: 32x16x2 voxels for the dose at
+# FP32 (rows of 32 voxels make whole 128-byte lines of the dose output),
+# 16x8x8 at 16-bit storage (measured faster there, with two rows per block
+# row, and for the batched launch's narrow panels); 4 beamlet columns x 2 MLC
+# rows x 8 control points for the price.
 DOSE_TILE = (32, 16, 2)
+DOSE_TILE_16BIT = (16, 8, 8)
 PRICE_TILE = (4, 2, 8)
 LAYOUTS = {"csr": 0, "panel": 1}
 
@@ -223,8 +226,9 @@ class DDC:
 
         dose_grid / price_grid: the voxel grid (nx, ny, nz) and the beamlet grid
         (columns, MLC rows, control points), fastest axis first.  With a grid
-        the orientation defaults to the panel layout (tiles DOSE_TILE /
-        PRICE_TILE); without one, to CSR.  *_layout: "csr" or "panel"."""
+        the orientation defaults to the panel layout (tiles DOSE_TILE, or
+        DOSE_TILE_16BIT at 16-bit storage, and PRICE_TILE); without one, to
+        CSR.  *_layout: "csr" or "panel"."""
         row = np.ascontiguousarray(row, dtype=np.int32)
         col = np.ascontiguousarray(col, dtype=np.int32)
         val = np.ascontiguousarray(val, dtype=np.float32)
@@ -240,7 +244,8 @@ class DDC:
                         ("panel_cols", panel_cols), ("part_entries", part_entries)):
             if v is not None:
                 setattr(opts, name, int(v))
-        for side, grid, lay, tile, dflt in (("dose", dose_grid, dose_layout, dose_tile, DOSE_TILE),
+        dose_dflt = DOSE_TILE if storage == "f32" else DOSE_TILE_16BIT
+        for side, grid, lay, tile, dflt in (("dose", dose_grid, dose_layout, dose_tile, dose_dflt),
                                             ("price", price_grid, price_layout, price_tile, PRICE_TILE)):
             if lay is None:
                 lay = "panel" if grid is not None else "csr"
@@ -254,6 +259,7 @@ class DDC:
                                        col.ctypes.data_as(_P) if len(val) else None,
                                        val.ctypes.data_as(_P) if len(val) else None,
                                        STORAGE[storage], ctypes.byref(opts), ctypes.byref(h)))
+        self._destroy = lib.dvmat_ddc_destroy     # bound now: module globals may be gone at exit
         self._h = h
         info = DdcInfo()
         _check(lib.dvmat_ddc_info(h, ctypes.byref(info)))
@@ -268,8 +274,8 @@ class DDC:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib.dvmat_ddc_destroy(h)
+        if h and getattr(self, "_destroy", None) is not None:
+            self._destroy(h)
             self._h = None
 
     # -- products -----------------------------------------------------------
@@ -363,6 +369,7 @@ class Objective:
         h = _P()
         _check(lib.dvmat_obj_create(self.n_vox, table.shape[0], _ptr(self.sid), table.ctypes.data_as(_P),
                                     _ptr(self.workspace), self.workspace.numel(), _stream(), ctypes.byref(h)))
+        self._destroy = lib.dvmat_obj_destroy     # bound now: module globals may be gone at exit
         self._h = h
 
     @property
@@ -371,8 +378,8 @@ class Objective:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib.dvmat_obj_destroy(h)
+        if h and getattr(self, "_destroy", None) is not None:
+            self._destroy(h)
             self._h = None
 
     def __call__(self, z, with_grad=True):
@@ -487,6 +494,7 @@ class BB:
         h = _P()
         _check(lib.dvmat_bb_create(self.geom, max_apertures, self.params, _ptr(self.workspace),
                                    self.workspace.numel(), _stream(), ctypes.byref(h)))
+        self._destroy = lib.dvmat_bb_destroy     # bound now: module globals may be gone at exit
         self._h = h
         self.flags = torch.zeros(1, dtype=torch.int32, device=self.device)
 
@@ -509,8 +517,8 @@ class BB:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib.dvmat_bb_destroy(h)
+        if h and getattr(self, "_destroy", None) is not None:
+            self._destroy(h)
             self._h = None
 
     def add_aperture(self, cp, L_row, R_row, lo=0.0, hi=float("inf"), y0=None, stream=None):
@@ -577,12 +585,13 @@ class DAColumns:
         h = _P()
         _check(lib.dvmat_da_create(self.n_vox, int(max_apertures), _ptr(self.workspace), self.workspace.numel(),
                                    ctypes.byref(h)))
+        self._destroy = lib.dvmat_da_destroy     # bound now: module globals may be gone at exit
         self._h = h
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib.dvmat_da_destroy(h)
+        if h and getattr(self, "_destroy", None) is not None:
+            self._destroy(h)
             self._h = None
 
     @property
@@ -663,12 +672,13 @@ class Batch:
         h = _P()
         _check(lib.dvmat_batch_create(arr, n, _ptr(self.workspace), self.workspace.numel(), _stream(),
                                       ctypes.byref(h)))
+        self._destroy = lib.dvmat_batch_destroy     # bound now: module globals may be gone at exit
         self._h = h
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib.dvmat_batch_destroy(h)
+        if h and getattr(self, "_destroy", None) is not None:
+            self._destroy(h)
             self._h = None
 
     def _ptrs(self, ts, sizes, name):
