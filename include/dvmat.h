@@ -428,7 +428,9 @@ dvmat_status dvmat_bb_step(dvmat_bb bb, const float* p, const float* F, const do
 dvmat_status dvmat_bb_state(dvmat_bb bb, const float** y, const float** gt);
 /* As dvmat_bb_direction and dvmat_bb_step, but with the gradient in the
  * aperture domain supplied by the caller: G device float[count] = dF/dy_k
- * (e.g. from automatic differentiation of F(D B y)); nothing is gathered. */
+ * (e.g. from automatic differentiation of F(D B y)); nothing is gathered.
+ * x_next of dvmat_bb_step_g may be NULL: no beamlet fluence is written (the
+ * DA form forms the dose from its aperture columns, not from x). */
 dvmat_status dvmat_bb_direction_g(dvmat_bb bb, const float* G, float* x_dir, dvmat_stream stream);
 dvmat_status dvmat_bb_step_g(dvmat_bb bb, const float* G, const float* F, const double* curv,
                              float* x_next, uint32_t* flags, dvmat_stream stream);

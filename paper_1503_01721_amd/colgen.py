@@ -121,8 +121,10 @@ class ColumnGeneration:
         self.bb.direction_g_(G, self.x_dir)
         self.da.curvature_(self.obj, gt_ptr, self.z, self.curv)
         for _ in range(steps):
-            self.bb.step_g_(G, self.F, self.curv, self.x)
+            # no beamlet fluence per step: the dose comes from the m columns
+            self.bb.step_g_(G, self.F, self.curv, None)
             self.da.eval_(self.obj, y_ptr, G, z=self.z, g=self.g, F=self.F)
+        self.bb.expand_(self.x)                       # the fluence of the final rates
         self.ddc.price_(self.g, self.p)
 
     def _append_da_column(self, cp):

@@ -464,7 +464,7 @@ static dvmat_status bb_direction_impl(dvmat_bb b, const float* p, const float* G
 
 static dvmat_status bb_step_impl(dvmat_bb b, const float* p, const float* G_ext, const float* F, const double* curv,
                                  float* x_next, uint32_t* flags, dvmat_stream stream, const char* fn) {
-    if (!b || !(p || G_ext) || !F || !x_next) return set_error(DVMAT_E_ARG, "%s: NULL argument", fn);
+    if (!b || !(p || G_ext) || !F || (!x_next && !G_ext)) return set_error(DVMAT_E_ARG, "%s: NULL argument", fn);
     if (b->m == 0) return set_error(DVMAT_E_STATE, "%s: no apertures", fn);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const dvmat_geom& g = b->geom;
@@ -472,8 +472,9 @@ static dvmat_status bb_step_impl(dvmat_bb b, const float* p, const float* G_ext,
     if (!G_ext) hipLaunchKernelGGL(bb_gather_kernel, dim3(b->m), dim3(256), 0, s, b->dev, g.n_rows, g.n_cols, p);
     hipLaunchKernelGGL(bb_update_kernel, dim3(1), dim3(256), 0, s, b->dev, b->m, (int)MODE_STEP, F, curv, flags,
                        b->params, G_ext);
-    hipLaunchKernelGGL(bb_expand_kernel, dim3(grid_for(n_bl)), dim3(256), 0, s, b->dev, g.n_rows, g.n_cols, n_bl,
-                       (const float*)b->dev.y, x_next);
+    if (x_next)
+        hipLaunchKernelGGL(bb_expand_kernel, dim3(grid_for(n_bl)), dim3(256), 0, s, b->dev, g.n_rows, g.n_cols, n_bl,
+                           (const float*)b->dev.y, x_next);
     return check_hip(hipGetLastError(), fn);
 }
 }  // namespace dvmat

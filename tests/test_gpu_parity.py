@@ -980,3 +980,4 @@ def test_voxel_slabs_compose_the_whole_products(dv, plan1):
         p_sum += part.price(cuda(g[z0 * N * N:z1 * N * N])).cpu().numpy()
     scale = oprod.price(d["row"], d["col"], d["val"], np.abs(g), PLAN1.n_bl).max()
     assert np.abs(p_sum - p_ref).max() <= TOL * scale
+
