@@ -15,13 +15,15 @@ pytestmark = pytest.mark.gpu
 PLAN = synth.PLANS["cp64_bl12x12_vox40"]
 
 
-@pytest.fixture(scope="module")
-def setup():
+@pytest.fixture(scope="module", params=["csr", "panel"])
+def setup(request):
     assert torch.cuda.is_available()
     from paper_1503_01721_amd import dvmat
     d = synth.generate_ddc(PLAN)
     sid, table = synth.structures(PLAN)
-    ddc = dvmat.DDC(d["row"], d["col"], d["val"], PLAN.n_vox, PLAN.n_bl, storage="f16")
+    layout = PLAN.grids if request.param == "panel" else {}
+    ddc = dvmat.DDC(d["row"], d["col"], d["val"], PLAN.n_vox, PLAN.n_bl, storage="f16", **layout)
+    assert ddc.info.dose_layout == (request.param == "panel")
     obj = dvmat.Objective(sid, table)
     cps, L, R = synth.random_apertures(PLAN, 64, 2004)
     aps = dvmat.Apertures(PLAN.n_cp, PLAN.n_rows, PLAN.n_cols, cps, L, R)
