@@ -404,8 +404,9 @@ dvmat_status dvmat_bb_occupancy(dvmat_bb bb, const uint8_t** d_occupied);
  * y0 (clamped to the box).  DVMAT_E_STATE if cp is occupied or the set is full. */
 dvmat_status dvmat_bb_add_aperture(dvmat_bb bb, int32_t cp, const int32_t* d_L, const int32_t* d_R,
                                    float lo, float hi, float y0, dvmat_stream stream);
-/* Replace the box of every aperture by that of its control point: lo_cp,
- * hi_cp device float[n_cp] (e.g. from dvmat_machine_boxes); each rate is
+/* Replace the box of every aperture (the rate bounds of Eq. 6) by that of its
+ * control point: lo_cp, hi_cp device float[n_cp] (e.g. from
+ * dvmat_machine_boxes, which moves them as apertures are added); each rate is
  * clipped into its new box (into hi_cp where lo_cp > hi_cp).  Values are not
  * checked on the host: NaN boxes are the caller's error. */
 dvmat_status dvmat_bb_set_boxes(dvmat_bb bb, const float* lo_cp, const float* hi_cp, dvmat_stream stream);
