@@ -14,6 +14,12 @@ resident in HBM), `ms_per_step` the time per column-generation iteration.
 Progress goes to stderr.
 
     python bench.py [--steps K] [--warmup W] [--storage f32|f16|bf16]
+
+Other modes, each printing its own JSON line: --form DA (the paper's DA form
+of the master problem), --mode batched (many plans x 8 right-hand sides in
+one captured launch against one plan at a time), --mode autograd (F(D B y)
+and dF/dy by automatic differentiation on the two-arc workload), --mode shard
+(one GPU's voxel slab of the two-arc workload at its real shape).
 """
 from __future__ import annotations
 
