@@ -8,10 +8,13 @@ aperture, then a 50-iteration Barzilai-Borwein master-problem solve, each
 iteration a dose product with the fused objective and a price product over
 the whole DDC matrix, plus one curvature product for the first step length.
 
-Output: one JSON line on stdout.  `value` is the effective HBM bandwidth of
-the whole timed job (algorithmic bytes of every product / wall time, inputs
-resident in HBM), `ms_per_step` the time per column-generation iteration.
-Progress goes to stderr.
+Output: one JSON line on stdout.  `value` is the HBM bandwidth of the whole
+timed job (algorithmic bytes of every product / wall time, inputs resident in
+HBM), `ms_per_step` the time per column-generation iteration.  Algorithmic
+bytes count the matrix with the index width of its own layout (2-byte
+panel-local columns, 4-byte CSR columns, one index per B rows of a block row);
+`csr_equivalent_gbs` is the same time over the bytes of FP32/16-bit values
+with int32 CSR indices, the usual "effective" figure.  Progress goes to stderr.
 
     python bench.py [--steps K] [--warmup W] [--storage f32|f16|bf16]
 
@@ -39,14 +42,31 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(info, nrhs=1):
-    """Bytes each product must move: matrix once, row pointers, each vector once."""
+def index_bytes(info, orientation):
+    """Index bytes per stored non-zero of one orientation as built: 2 for the
+    panel layout's panel-local uint16 columns, 4 for CSR's int32 columns, shared
+    by the B rows of a block row (one index per stored position serves B rows).
+    Padding zeros of block rows and the panels' column lists are format
+    overhead and not counted."""
+    layout = info.dose_layout if orientation == "dose" else info.price_layout
+    B = max(1, info.dose_block_rows if orientation == "dose" else info.price_block_rows)
+    return (2.0 if layout == 1 else 4.0) / B
+
+
+def algorithmic_bytes(info, nrhs=1, csr_equivalent=False):
+    """Bytes each product must move: the matrix once (values plus the layout's
+    own index bytes, or 4-byte indices for the CSR-equivalent figure), row
+    pointers, each vector once, the objective's per-voxel inputs and outputs,
+    the per-beamlet scale at 16-bit storage."""
     n_vox, n_bl, nnz = info.n_vox, info.n_bl, info.nnz
-    mat = nnz * (info.value_bytes + 4)
+    ib_d = 4.0 if csr_equivalent else index_bytes(info, "dose")
+    ib_p = 4.0 if csr_equivalent else index_bytes(info, "price")
+    mat_d = int(round(nnz * (info.value_bytes + ib_d)))
+    mat_p = int(round(nnz * (info.value_bytes + ib_p)))
     scale = 4 * n_bl if info.value_bytes == 2 else 0
-    dose_obj = mat + 8 * (n_vox + 1) + 4 * nrhs * (n_bl + n_vox) + n_vox * (1 + 4 * nrhs) + scale
-    price = mat + 8 * (n_bl + 1) + 4 * nrhs * (n_vox + n_bl) + scale
-    curv = mat + 8 * (n_vox + 1) + 4 * n_bl + n_vox * (4 + 1) + scale
+    dose_obj = mat_d + 8 * (n_vox + 1) + 4 * nrhs * (n_bl + n_vox) + n_vox * (1 + 4 * nrhs) + scale
+    price = mat_p + 8 * (n_bl + 1) + 4 * nrhs * (n_vox + n_bl) + scale
+    curv = mat_d + 8 * (n_vox + 1) + 4 * n_bl + n_vox * (4 + 1) + scale
     return dict(dose=dose_obj, price=price, curv=curv)
 
 
@@ -110,13 +130,22 @@ def copy_calibration():
                       "launches": 5}), flush=True)
 
 
-def plain_bytes(info, nrhs):
+def plain_bytes(info, nrhs, csr_equivalent=False):
     """Algorithmic bytes of a plain dose and a plain price product with nrhs vectors."""
     n_vox, n_bl, nnz = info.n_vox, info.n_bl, info.nnz
-    mat = nnz * (info.value_bytes + 4)
+    ib_d = 4.0 if csr_equivalent else index_bytes(info, "dose")
+    ib_p = 4.0 if csr_equivalent else index_bytes(info, "price")
     scale = 4 * n_bl if info.value_bytes == 2 else 0
-    return (mat + 8 * (n_vox + 1) + 4 * nrhs * (n_bl + n_vox) + scale,
-            mat + 8 * (n_bl + 1) + 4 * nrhs * (n_vox + n_bl) + scale)
+    return (int(round(nnz * (info.value_bytes + ib_d))) + 8 * (n_vox + 1) + 4 * nrhs * (n_bl + n_vox) + scale,
+            int(round(nnz * (info.value_bytes + ib_p))) + 8 * (n_bl + 1) + 4 * nrhs * (n_vox + n_bl) + scale)
+
+
+def check_peak(name, gbs):
+    """A rate above the HBM peak means the byte count is wrong, not a fast kernel."""
+    if gbs > HBM_PEAK_GBS:
+        log(f"WARNING: {name} at {gbs:.0f} GB/s exceeds the {HBM_PEAK_GBS:.0f} GB/s HBM peak: "
+            "its algorithmic bytes overcount what it moves")
+    return gbs <= HBM_PEAK_GBS
 
 
 def bench_batched(args):
@@ -157,6 +186,7 @@ def bench_batched(args):
         log(f"autotuned: batch {binfo}")
     binfo = batch.info()
     total = sum(sum(plain_bytes(x.info, nrhs)) for x in ddcs)
+    total_csr = sum(sum(plain_bytes(x.info, nrhs, csr_equivalent=True)) for x in ddcs)
     # batched: one captured graph holding the two launches
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
@@ -191,6 +221,7 @@ def bench_batched(args):
     torch.cuda.synchronize()
     t_seq = (time.perf_counter() - t0) / args.steps
     gbs_b, gbs_s = total / t_batched / 1e9, total / t_seq / 1e9
+    check_peak("batched step", gbs_b)
     log(f"batched {t_batched * 1e3:.2f} ms ({gbs_b:.0f} GB/s) vs one-plan-at-a-time {t_seq * 1e3:.2f} ms "
         f"({gbs_s:.0f} GB/s)")
     print(json.dumps({
@@ -202,6 +233,7 @@ def bench_batched(args):
                    "layout": args.layout if args.layout == "csr" else "panel (dose), csr (price)",
                    "panel_cols": args.panel_cols,
                    "storage": storage, "nrhs": nrhs, "algorithmic_bytes_per_step": int(total),
+                   "csr_equivalent_gbs": round(total_csr / t_batched / 1e9, 2),
                    "one_plan_at_a_time_gbs": round(gbs_s, 2), "one_plan_at_a_time_ms": round(t_seq * 1e3, 3),
                    "speedup_vs_one_plan_at_a_time": round(t_seq / t_batched, 3),
                    "pct_hbm_peak": round(100.0 * gbs_b / HBM_PEAK_GBS, 2), "batch_launch": binfo,
@@ -261,6 +293,8 @@ def bench_autograd(args):
     bd, bp = plain_bytes(ddc.info, 1)
     extra = plan.n_vox * (4 + 1 + 4) + 4 * plan.n_bl            # objective pass, fluence expansion
     gbs = (bd + bp + extra) / dt / 1e9
+    check_peak("autograd step", gbs)
+    gbs_csr = (sum(plain_bytes(ddc.info, 1, csr_equivalent=True)) + extra) / dt / 1e9
     log(f"F = {float(F):.6g}; forward+backward {dt * 1e3:.3f} ms ({gbs:.0f} GB/s)")
     print(json.dumps({
         "metric": "effective HBM GB/s of one autograd evaluation of F(D B y) and dF/dy",
@@ -269,6 +303,7 @@ def bench_autograd(args):
         "dtype": storage, "data": "synthetic",
         "config": {"workload": plan.name, "n_vox": plan.n_vox, "n_beamlets": plan.n_bl, "nnz": int(ddc.info.nnz),
                    "apertures": 64, "storage": storage, "pct_hbm_peak": round(100.0 * gbs / HBM_PEAK_GBS, 2),
+                   "csr_equivalent_gbs": round(gbs_csr, 2),
                    "generate_s": round(t_gen, 1), "build_upload_s": round(t_build, 1)},
     }), flush=True)
 
@@ -340,6 +375,9 @@ def bench_shard(args):
     tp = ev[1].elapsed_time(ev[2]) / args.steps
     b = algorithmic_bytes(ddc.info)
     gbs = (b["dose"] + b["price"]) / ((td + tp) * 1e-3) / 1e9
+    check_peak("slab dose + price", gbs)
+    bc = algorithmic_bytes(ddc.info, csr_equivalent=True)
+    gbs_csr = (bc["dose"] + bc["price"]) / ((td + tp) * 1e-3) / 1e9
     allreduce_us = 2.0 * (G - 1) / G * 4 * plan.n_bl / 153e9 * 1e6
     log(f"slab dose {td:.3f} ms, partial price {tp:.3f} ms ({gbs:.0f} GB/s); "
         f"ring all-reduce of the price over {G} GPUs at 153 GB/s per link: ~{allreduce_us:.0f} us (estimate)")
@@ -351,7 +389,7 @@ def bench_shard(args):
         "config": {"workload": f"{plan.name}, voxel slab {s} of {G} (slices {z0}..{z1 - 1}, {args.slabs} slabs)",
                    "n_vox": n_vox, "nnz_total": int(counts.sum()),
                    "n_beamlets": plan.n_bl, "nnz": int(ddc.info.nnz), "storage": storage,
-                   "dose_ms": round(td, 4), "price_ms": round(tp, 4),
+                   "dose_ms": round(td, 4), "price_ms": round(tp, 4), "csr_equivalent_gbs": round(gbs_csr, 2),
                    "pct_hbm_peak": round(100.0 * gbs / HBM_PEAK_GBS, 2),
                    "price_allreduce_us_estimate": round(allreduce_us, 1),
                    "generate_s": round(t_gen, 1), "build_upload_s": round(t_build, 1)},
@@ -465,13 +503,18 @@ def main():
     log(f"timed {args.steps} iterations in {wall:.3f} s; last {cg.records[-1]}")
 
     ab = algorithmic_bytes(info)
-    if args.form == "D":
-        per_iter = args.bb_steps * (ab["dose"] + ab["price"]) + ab["curv"]
-    else:
+    abc = algorithmic_bytes(info, csr_equivalent=True)
+
+    def iteration_bytes(b):
+        if args.form == "D":
+            return args.bb_steps * (b["dose"] + b["price"]) + b["curv"]
         # one price product and one dose product (the new aperture's column) per
         # iteration; the BB iterations read the DA columns, not the matrix
-        per_iter = ab["price"] + ab["dose"]
+        return b["price"] + b["dose"]
+    per_iter = iteration_bytes(ab)
     value = args.steps * per_iter / wall / 1e9
+    value_csr = args.steps * iteration_bytes(abc) / wall / 1e9
+    check_peak("whole job", value)
     if not cg.events:
         cg.events = []
     if not cg.events:
@@ -497,6 +540,8 @@ def main():
     dom = "price" if mean_price >= mean_dose else "dose"
     dom_ms = mean_price if dom == "price" else mean_dose
     achieved = ab[dom] / (dom_ms * 1e-3) / 1e9
+    check_peak("dose kernel", ab["dose"] / mean_dose / 1e6)
+    check_peak("price kernel", ab["price"] / mean_price / 1e6)
     kfn = "spmv_panel_kernel" if args.layout == "panel" else "spmv_kernel"
     kname = (f"{kfn} (price, D^T in the {args.layout} layout)" if dom == "price"
              else f"{kfn} (dose, D in the {args.layout} layout, objective epilogue)")
@@ -524,7 +569,10 @@ def main():
             "master_problem_form": args.form,
             "products_per_iteration": 2 * args.bb_steps + 1 if args.form == "D" else 2,
             "algorithmic_bytes_per_iteration": per_iter,
+            "index_bytes_per_nnz": {"dose": index_bytes(info, "dose"), "price": index_bytes(info, "price")},
             "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
+            "csr_equivalent_gbs": round(value_csr, 2),
+            "dose_gbs": round(ab["dose"] / mean_dose / 1e6, 1), "price_gbs": round(ab["price"] / mean_price / 1e6, 1),
             "mean_dose_call_ms": round(mean_dose, 4), "mean_price_call_ms": round(mean_price, 4),
             "generate_s": round(t_gen, 2), "build_upload_s": round(t_build, 2),
             "layout": args.layout,
@@ -538,6 +586,7 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
             "algorithmic_bytes_per_launch": ab[dom], "mean_launch_ms": round(dom_ms, 4),
+            "csr_equivalent_gbs": round(abc[dom] / (dom_ms * 1e-3) / 1e9, 1),
         },
     }
     if not args.no_cpu_baseline:

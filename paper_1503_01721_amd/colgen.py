@@ -180,6 +180,13 @@ class ColumnGeneration:
             self.bb.set_boxes(self.boxes[1], self.boxes[2])
         if self.form == "DA":
             self._append_da_column(best)
+        elif self.lo > 0.0 or self.machine is not None:
+            # the new rate starts at lo, and new boxes may have moved every
+            # rate: dose, objective and price at the solve's starting point
+            # (with lo = 0 and fixed boxes the fluence is unchanged)
+            self.bb.expand_(self.x)
+            self.ddc.dose_(self.x, self.z, self.obj, self.g, self.F)
+            self.ddc.price_(self.g, self.p)
         self.master_problem()
         rec = IterationRecord(self.iterations, best, best_price, float(self.F.item()), int(self.bb.flags.item()))
         self.records.append(rec)

@@ -259,13 +259,16 @@ __global__ __launch_bounds__(256) void select_interdig_kernel(int n_rows, int n,
         }
         __syncthreads();
     }
+    // state = the final row's best state, or -1 when no aperture fits the
+    // leaf windows; every wave tests it, not rv[0], which the first wave to
+    // reach the backtracking below may already be overwriting
     __shared__ int state;
     if (tid == 0) {
         cp_price[k] = rv[0];
-        state = ri[0];
+        state = rv[0] < INFINITY ? ri[0] : -1;
     }
     __syncthreads();
-    if (!(rv[0] < INFINITY)) {                       // no aperture fits the leaf windows
+    if (state < 0) {                                 // no aperture fits the leaf windows
         for (int r = tid; r < n_rows; r += blockDim.x) {
             L[(int64_t)k * n_rows + r] = 0;
             R[(int64_t)k * n_rows + r] = 0;

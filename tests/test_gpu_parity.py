@@ -16,6 +16,7 @@ import torch
 from oracle import aperture as oap
 from oracle import bb as obb
 from oracle import colgen as ocg
+from oracle import machine as omach
 from oracle import objective as oobj
 from oracle import products as oprod
 from paper_1503_01721_amd import synth
@@ -471,6 +472,140 @@ def test_bb_box_bounds_and_stop_rule(dv, plan1):
             assert np.array_equal(gpu["y"][t], gpu["y"][s0])
 
 
+def _first_stop(flags):
+    """(call index, stop bits) of the first step call that reported a stop."""
+    for i, f in enumerate(flags):
+        if f & obb.STOP_MASK:
+            return i, f & obb.STOP_MASK
+    return None, 0
+
+
+@pytest.mark.parametrize("rule", ["rel_f", "small_step"])
+def test_bb_stop_iteration_and_flag_match_oracle(dv, plan1, rule):
+    """The live stopping tests (Sec. 2.1) stop the GPU solve at the same
+    iteration, with the same flag, as the oracle.  The threshold is placed by
+    the oracle's unstopped run between the ratio at the first qualifying
+    iteration t* and the smallest ratio before it, at least a factor 4 from
+    both, so FP32 rounding of F and y cannot move the decision."""
+    d, sid, table, ddc, obj = plan1
+    m = 5
+    lo, hi = synth.random_boxes(m, 43)
+    cps, L, R = synth.random_apertures(PLAN1, m, 44)
+    apset = obb.ApertureSet(PLAN1.n_cp, PLAN1.n_rows, PLAN1.n_cols)
+    for k in range(m):
+        apset.add(cps[k], L[k], R[k])
+    apply, adjoint = obb.d_form_ops(d["row"], d["col"], d["val"], PLAN1.n_vox, PLAN1.n_bl, apset)
+    y0 = lo.astype(np.float64)
+    free = obb.solve(apply, adjoint, sid, table, y0, lo, hi, obb.BBParams(30, 0.0, 0.0), record=True)
+    if rule == "rel_f":
+        Fh = free["hist"]["F"]
+        r = {t: abs(Fh[t - 5] - Fh[t]) / abs(Fh[t]) for t in range(5, 30)}
+    else:
+        ys = free["hist"]["y"]
+        r = {t: np.abs(ys[t] - ys[t - 1]).max() / max(1.0, np.abs(ys[t]).max()) for t in range(1, 30)}
+    t0 = min(r)
+    t_star = next(t for t in sorted(r) if t > t0 and r[t] < r[t0] / 16 and r[t] < min(r[u] for u in r if u < t) / 16)
+    eps = float(np.sqrt(r[t_star] * min(r[u] for u in r if u < t_star)))
+    params = (eps, 0.0) if rule == "rel_f" else (0.0, eps)
+    ref = obb.solve(apply, adjoint, sid, table, y0, lo, hi, obb.BBParams(30, *params))
+    flag = obb.FLAG_REL_F if rule == "rel_f" else obb.FLAG_SMALL_STEP
+    assert ref["iters"] == t_star and ref["flags"] & obb.STOP_MASK == flag
+    bb, _ = _device_apertures(dv, PLAN1, m, 44, lo, hi, max_iter=30, eps_f=params[0], eps_step=params[1])
+    gpu = _gpu_mp(dv, ddc, obj, bb, t_star + 3, PLAN1.n_vox, PLAN1.n_bl)
+    at, bits = _first_stop(gpu["flags"])
+    assert (at, bits) == (t_star, flag), (at, bits, t_star, flag)
+    yr = ref["y"]
+    assert np.allclose(gpu["y"][-1], yr, rtol=1e-4, atol=1e-4 * np.abs(yr).max())
+
+
+def test_bb_closed_aperture_converges_at_t0(dv, plan1):
+    """A fully closed aperture delivers no fluence: G = 0, the solve stops at
+    its first iteration with the converged flag and the rate untouched."""
+    d, sid, table, ddc, obj = plan1
+    bb = dv.BB(PLAN1.n_cp, PLAN1.n_rows, PLAN1.n_cols, 1, max_iter=50, eps_f=1e-5, eps_step=1e-7)
+    zero = cuda(np.zeros(PLAN1.n_rows, np.int32))
+    bb.add_aperture(3, zero, zero, 0.0, float("inf"), 0.3)
+    gpu = _gpu_mp(dv, ddc, obj, bb, 3, PLAN1.n_vox, PLAN1.n_bl)
+    assert _first_stop(gpu["flags"]) == (0, obb.FLAG_CONVERGED)
+    assert all(y.tolist() == [np.float32(0.3)] for y in gpu["y"])
+
+
+def test_bb_nonpositive_curvature_reuses_alpha_on_device(dv):
+    """The fallback branch (<s,q> <= 0: keep the previous step length) on the
+    device, driven through dvmat_bb_step_g by the prescribed gradient map of
+    the oracle pin: G(y) = (8 (y0 - 70), -2 (y1 - 70)), y = (60, 200), Cauchy
+    step 74000/186400 with the weights (4, 1); every later step reuses it."""
+    bb = dv.BB(2, 1, 1, 2, max_iter=3, eps_f=0.0, eps_step=0.0)
+    one = cuda(np.ones(1, np.int32))
+    zero = cuda(np.zeros(1, np.int32))
+    bb.add_aperture(0, zero, one, 0.0, float("inf"), 60.0)
+    bb.add_aperture(1, zero, one, 0.0, float("inf"), 200.0)
+
+    def G(y):
+        return np.array([8.0 * (y[0] - 70.0), -2.0 * (y[1] - 70.0)])
+
+    def F(y):
+        return 4.0 * (y[0] - 70.0) ** 2 + (y[1] - 70.0) ** 2
+
+    x_dir = torch.empty(2, device="cuda")
+    y = np.array([60.0, 200.0])
+    bb.begin()
+    bb.direction_g_(cuda(G(y).astype(np.float32)), x_dir)
+    g0 = G(y)
+    curv = cuda(np.array([4.0 * g0[0] ** 2 + g0[1] ** 2]))
+    a0 = 74000.0 / 186400.0
+    y_ref = y.copy()
+    for t in range(3):
+        bb.step_g_(cuda(G(y).astype(np.float32)), cuda(np.array([F(y)], np.float32)), curv, None)
+        y = bb.y().cpu().numpy().astype(np.float64)
+        y_ref = y_ref - a0 * G(y_ref)
+        assert np.allclose(y, y_ref, rtol=2e-6), (t, y, y_ref)
+    flags = int(bb.flags.cpu()[0])
+    assert flags & obb.FLAG_FALLBACK and flags & obb.STOP_MASK == obb.FLAG_MAX_ITER
+
+
+def test_machine_model_first_step_starts_from_clipped_rates(dv):
+    """With the machine model the new boxes move the rates before the solve
+    (lo > 0 and every box recomputed): the first BB step must use the
+    gradient, F and curvature at those clipped rates.  One BB step per
+    iteration, compared with the oracle's step from the same start."""
+    from paper_1503_01721_amd.colgen import ColumnGeneration
+    d = synth.generate_ddc(SMALL)
+    sid, table = synth.structures(SMALL)
+    ddc = dv.DDC(d["row"], d["col"], d["val"], SMALL.n_vox, SMALL.n_bl)
+    obj = dv.Objective(sid, table)
+    n_cp, n_rows, n_cols = SMALL.n_cp, SMALL.n_rows, SMALL.n_cols
+    vals = (1.0, 1.0, 4.0, 0.5, 2.0, 50.0, 2.0)
+    om = omach.Machine(*vals)
+    cg = ColumnGeneration(ddc, obj, n_cp, n_rows, n_cols, bb_steps=1, eps_f=0.0, eps_step=0.0,
+                          machine=dv.Machine(*vals))
+    cg.start()
+    apset = obb.ApertureSet(n_cp, n_rows, n_cols)
+    occupied = np.zeros(n_cp, bool)
+    L_all = np.zeros((n_cp, n_rows), np.int32)
+    R_all = np.zeros((n_cp, n_rows), np.int32)
+    y = np.zeros(0)
+    moved = False
+    for it in range(4):
+        rec = cg.iteration()
+        assert rec is not None
+        L = cg.sel.L.cpu().numpy()[rec.cp]
+        R = cg.sel.R.cpu().numpy()[rec.cp]
+        occupied[rec.cp] = True
+        L_all[rec.cp], R_all[rec.cp] = L, R
+        apset.add(rec.cp, L, R)
+        _, lo_ref, hi_ref = omach.boxes(om, occupied, L_all, R_all)
+        lo_k, hi_k = lo_ref[apset.cps], hi_ref[apset.cps]
+        y0 = np.clip(np.append(y, 0.0), lo_k, hi_k)
+        moved |= bool(np.any(y0[:-1] != y))
+        apply, adjoint = obb.d_form_ops(d["row"], d["col"], d["val"], SMALL.n_vox, SMALL.n_bl, apset)
+        ref = obb.solve(apply, adjoint, sid, table, y0, lo_k, hi_k, obb.BBParams(1, 0.0, 0.0), record=True)
+        y = cg.bb.y().cpu().numpy().astype(np.float64)
+        assert np.allclose(y, ref["y"], rtol=1e-4, atol=1e-4 * np.abs(ref["y"]).max()), (it, y, ref["y"])
+        assert rec.F == pytest.approx(ref["F"], rel=1e-4), it
+    assert moved                                   # the clipping did move an earlier rate
+
+
 @pytest.mark.parametrize("form,interdigitated,travel", [("D", False, None), ("DA", False, None),
                                                         ("D", True, None), ("D", False, 2), ("DA", True, 3)])
 def test_column_generation_matches_oracle(dv, plan1, form, interdigitated, travel):
@@ -826,7 +961,6 @@ def test_da_columns_and_eval(dv, plan1):
 
 # ---------------------------------------------------------------- machine constraints (Eq. 2 -> Eq. 6 boxes)
 
-from oracle import machine as omach  # noqa: E402
 
 
 MACHINES = [

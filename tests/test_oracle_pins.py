@@ -426,6 +426,132 @@ def test_bb_bound_rules_eq9_eq10():
     assert Gt.tolist() == [0.0, 0.0, 4.0, 0.0, 1.0]
 
 
+# ---------------------------------------------------------------- BB stopping rules and fallback (Sec. 2.1; Eqs. 7-8)
+#
+# Each case below is worked out by hand; the expected stop iteration, flag,
+# step lengths and rates are written out, not recomputed by the solver's own
+# formulas.  Readings: stop tests in the order relative-F, small step, zero
+# masked gradient; a threshold of 0 switches its test off.
+
+def _identity_ops(n):
+    """apply = identity (one voxel per aperture, DA = I), adjoint = identity."""
+    return (lambda y: np.asarray(y, np.float64).copy()), (lambda gF: np.asarray(gF, np.float64).copy())
+
+
+def test_bb_cauchy_step_lands_on_minimiser_converged_at_t1():
+    """One aperture, one PTV voxel (T = 70, w+ = w- = 1), DA = [1], y0 = 0.
+    F(y) = (y - 70)^2, G = 2(y - 70) = -140 at y0 (not masked: G < 0 at lo).
+    Cauchy step: <G,G> / (2 w d^2) with d = DA G = -140: 140^2/(2*140^2) = 1/2.
+    y1 = 0 + 70 = 70 exactly, G1 = 0: the masked gradient vanishes at t = 1."""
+    apply, adjoint = _identity_ops(1)
+    sid = np.array([0])
+    table = np.array([[70.0, 1.0, 1.0]])
+    res = bb.solve(apply, adjoint, sid, table, [0.0], [0.0], [np.inf], bb.BBParams(50, 1e-5, 1e-7), record=True)
+    assert res["flags"] == bb.FLAG_CONVERGED
+    assert res["iters"] == 1
+    assert res["hist"]["alpha"] == [0.5]
+    assert res["y"].tolist() == [70.0] and res["F"] == 0.0
+    # step test first: with eps_step = 1 the step of 70 is <= 1 * max(1, |y_1| = 70)
+    # (|y_0| = 0 would give 70 > 1: the test uses the new rates)
+    res = bb.solve(apply, adjoint, sid, table, [0.0], [0.0], [np.inf], bb.BBParams(50, 0.0, 1.0))
+    assert res["flags"] == bb.FLAG_SMALL_STEP and res["iters"] == 1
+
+
+def test_bb_zero_gradient_converged_at_t0(tiny):
+    """A fully closed aperture (L = R = 0 on every row) delivers no fluence:
+    its column of DA is zero, G = 0 at the start, and the solve stops at
+    t = 0 with the rates untouched and no step taken (D-form on real D)."""
+    d, sid, table = tiny
+    apset = bb.ApertureSet(TINY.n_cp, TINY.n_rows, TINY.n_cols)
+    apset.add(1, np.zeros(TINY.n_rows, np.int32), np.zeros(TINY.n_rows, np.int32))
+    apply, adjoint = bb.d_form_ops(d["row"], d["col"], d["val"], TINY.n_vox, TINY.n_bl, apset)
+    res = bb.solve(apply, adjoint, sid, table, [0.3], [0.0], [np.inf], bb.BBParams(50, 1e-5, 1e-7), record=True)
+    assert res["flags"] == bb.FLAG_CONVERGED and res["iters"] == 0
+    assert res["y"].tolist() == [0.3] and res["hist"]["alpha"] == []
+
+
+def test_bb_relative_f_fires_at_exactly_t5():
+    """Rates move but F stays put: apply maps every y to the same dose (a
+    zero column), while adjoint reports a constant non-zero gradient (a
+    prescribed map, not the adjoint of apply).  F_t = F_0 for all t, so
+    |F_{t-5} - F_t| = 0 <= eps_f |F_t| holds first at t = 5 (the test needs
+    five earlier values), whatever eps_f > 0; with eps_f = 0 it never fires."""
+    sid = np.array([0])
+    table = np.array([[70.0, 1.0, 1.0]])
+    apply = lambda y: np.zeros(1)                  # noqa: E731
+    adjoint = lambda gF: np.array([-1.0])          # noqa: E731
+    for eps_f in (1e-12, 1e-5, 0.5):
+        res = bb.solve(apply, adjoint, sid, table, [0.0], [0.0], [np.inf], bb.BBParams(50, eps_f, 0.0), record=True)
+        assert res["iters"] == 5 and res["flags"] & bb.STOP_MASK == bb.FLAG_REL_F, eps_f
+        assert len(res["hist"]["alpha"]) == 5
+        assert res["F"] == 4900.0
+    res = bb.solve(apply, adjoint, sid, table, [0.0], [0.0], [np.inf], bb.BBParams(9, 0.0, 0.0))
+    assert res["iters"] == 9 and res["flags"] & bb.STOP_MASK == bb.FLAG_MAX_ITER
+
+
+def test_bb_nonpositive_curvature_reuses_previous_alpha():
+    """<s,q> <= 0 keeps the previous step length (reading of Eqs. 7-8 when the
+    curvature estimate is not positive).  For the convex objective of Eq. (1)
+    with the bound rules this cannot happen (<s,q> >= <s, G_t - G_{t-1}> >= 0:
+    the masked components only add non-negative terms), so the branch is
+    driven by a prescribed gradient map that is not the adjoint of apply.
+
+    Two voxels, apply = identity, T = 70, w+ = w- = 4 on voxel 0 and 1 on
+    voxel 1, so dF/dz = (8 (z0 - 70), 2 (z1 - 70)); adjoint flips the sign of
+    the second component: G(y) = (8 (y0 - 70), -2 (y1 - 70)).
+    t = 0: y = (60, 200), G = (-80, -260), nothing masked.  Cauchy step with
+    d = G and the weights at z = y (4, 1): (6400 + 67600) / (2 (4*6400 + 67600))
+    = 74000 / 186400.  t = 1: s = -a0 G0, q = G1 - G0 = (8 s0, -2 s1), so
+    <s,q> = 8 s0^2 - 2 s1^2 = a0^2 (8*6400 - 2*67600) < 0: the length stays a0.
+    t = 2: likewise (s = -a0 G1, <s,q> = a0^2 (8 G1_0^2 - 2 G1_1^2) < 0 since
+    |G1_1| > 2 |G1_0|).  A fresh Cauchy step at y1 or |BB1| would differ."""
+    sid = np.array([0, 1])
+    table = np.array([[70.0, 4.0, 4.0], [70.0, 1.0, 1.0]])
+    apply = lambda y: np.asarray(y, np.float64).copy()                       # noqa: E731
+    adjoint = lambda gF: np.array([gF[0], -gF[1]], np.float64)               # noqa: E731
+    res = bb.solve(apply, adjoint, sid, table, [60.0, 200.0], [0.0, 0.0], [np.inf, np.inf],
+                   bb.BBParams(3, 0.0, 0.0), record=True)
+    a0 = 74000.0 / 186400.0
+    assert res["hist"]["alpha"][0] == pytest.approx(a0, rel=1e-15)
+    assert res["hist"]["alpha"][1] == res["hist"]["alpha"][0]
+    assert res["hist"]["alpha"][2] == res["hist"]["alpha"][0]
+    assert res["flags"] == bb.FLAG_FALLBACK | bb.FLAG_MAX_ITER and res["iters"] == 3
+
+    def G(y):
+        return np.array([8.0 * (y[0] - 70.0), -2.0 * (y[1] - 70.0)])
+    y = np.array([60.0, 200.0])
+    for t in range(3):
+        y = y - a0 * G(y)                        # no bound active: y0 stays near 70, y1 grows
+        assert np.allclose(res["hist"]["y"][t + 1] if t + 1 < 3 else res["y"], y, rtol=1e-13), t
+    # the alternatives the reading rules out
+    y1 = res["hist"]["y"][1]
+    g1 = G(y1)
+    cauchy1 = (g1 @ g1) / (2.0 * (4.0 * g1[0] ** 2 + g1[1] ** 2))
+    s, q = y1 - np.array([60.0, 200.0]), g1 - G(np.array([60.0, 200.0]))
+    assert abs(cauchy1 - a0) > 1e-3 and abs(abs((s @ s) / (s @ q)) - a0) > 1e-3
+
+
+def test_bb_stop_at_first_iteration_meeting_rel_f(small):
+    """On a real D-form problem the solve stops at the first t >= 5 whose F
+    history meets the five-back test, and returns that iterate (hist of the
+    unstopped run, chosen threshold between two observed ratios)."""
+    d, sid, table = small
+    apset = _ptv_apertures(SMALL, 4, 17)
+    apply, adjoint = bb.d_form_ops(d["row"], d["col"], d["val"], SMALL.n_vox, SMALL.n_bl, apset)
+    free = bb.solve(apply, adjoint, sid, table, np.zeros(4), np.zeros(4), np.full(4, np.inf),
+                    bb.BBParams(40, 0.0, 0.0), record=True)
+    Fh = free["hist"]["F"]
+    r = [abs(Fh[t - 5] - Fh[t]) / abs(Fh[t]) for t in range(5, 40)]
+    # a threshold between the smallest ratio before t* and the ratio at t*
+    t_star = next(t for t in range(6, 40) if r[t - 5] < 0.5 * min(r[:t - 5]))
+    eps = math.sqrt(r[t_star - 5] * min(r[:t_star - 5]))
+    res = bb.solve(apply, adjoint, sid, table, np.zeros(4), np.zeros(4), np.full(4, np.inf),
+                   bb.BBParams(40, eps, 0.0), record=True)
+    assert res["iters"] == t_star and res["flags"] & bb.STOP_MASK == bb.FLAG_REL_F
+    assert np.array_equal(res["y"], free["hist"]["y"][t_star])
+    assert res["F"] == Fh[t_star]
+
+
 # ---------------------------------------------------------------- column generation
 
 def test_column_generation_decreases_objective(tiny):
