@@ -159,8 +159,9 @@ def body_xy(plan: Plan) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
     return xx.ravel()[idx], yy.ravel()[idx], idx.astype(np.int64)
 
 
-def _angle_factors(plan: Plan, a: int, px, py, u_c):
-    """f_u[c, p] for every beamlet column c and body cross-section point p."""
+def _angle_factors(plan: Plan, a: int, px, py, u_c, with_lateral: bool = False):
+    """f_u[c, p] for every beamlet column c and body cross-section point p
+    (and, with_lateral, the squared distance along u to the beamlet axis)."""
     th = cp_angle(plan, a)
     s, co = math.sin(th), math.cos(th)
     t = px * s - py * co
@@ -169,7 +170,8 @@ def _angle_factors(plan: Plan, a: int, px, py, u_c):
     entry = np.sqrt(np.maximum(R * R - u_c * u_c, 0.0))
     depth = np.maximum(0.0, t[None, :] + entry[:, None])
     lat = pu[None, :] - u_c[:, None]
-    return np.exp(-MU_PER_MM * depth) * np.exp(-(lat * lat) / (2.0 * SIGMA_MM ** 2))
+    fu = np.exp(-MU_PER_MM * depth) * np.exp(-(lat * lat) / (2.0 * SIGMA_MM ** 2))
+    return (fu, lat * lat) if with_lateral else fu
 
 
 def _v_factors(plan: Plan, v_r):
@@ -178,33 +180,44 @@ def _v_factors(plan: Plan, v_r):
     return np.exp(-(dz * dz) / (2.0 * SIGMA_MM ** 2))     # [n_rows, N]
 
 
-def generate_cp(plan: Plan, a: int, xy=None, z_slab: Optional[Tuple[int, int]] = None):
+def generate_cp(plan: Plan, a: int, xy=None, z_slab: Optional[Tuple[int, int]] = None,
+                cutoff: float = CUTOFF, cone_mm: Optional[float] = None):
     """All entries of control point a, sorted by beamlet then voxel index;
     with z_slab = (z0, z1) only the voxels of slices z0 <= iz < z1.
+    cutoff: entries below it are dropped; cone_mm: entries of voxels farther
+    than this from the beamlet's central axis are dropped too (the truncation
+    by a cone about each beamlet axis of Sec. 2.4; the beams here are
+    parallel, so the cone is a cylinder of that radius).
 
     Returns (row_vox int32, col_bl int32, val float32)."""
     px, py, pidx = xy if xy is not None else body_xy(plan)
     N = plan.n_grid
     u_c, v_r = beamlet_offsets(plan)
-    fu = _angle_factors(plan, a, px, py, u_c)             # [C, P]
+    fu, lat2_u = _angle_factors(plan, a, px, py, u_c, with_lateral=True)   # [C, P]
     fv = _v_factors(plan, v_r)                            # [R, N]
+    lat2_v = (axis_centres(N, plan.vox_mm)[None, :] - v_r[:, None]) ** 2
     if z_slab is not None:
         fv[:, :z_slab[0]] = 0.0
         fv[:, z_slab[1]:] = 0.0
-    # Only points/slices that can pass the cut (the other factor is <= 1).
+    r2max = np.inf if cone_mm is None else float(cone_mm) ** 2
+    # Only points/slices that can pass the cut (the other factor is <= 1,
+    # the other squared distance >= 0).
     # Padded per-column point lists keep the (r, c, iz, p) order of np.nonzero.
-    keep_u = fu >= CUTOFF
+    keep_u = (fu >= cutoff) & (lat2_u <= r2max)
     cnt_u = keep_u.sum(axis=1)
     Pm = max(int(cnt_u.max()), 1)
     order_u = np.argsort(~keep_u, axis=1, kind="stable")[:, :Pm]   # kept first, raster order
     fu_pad = np.take_along_axis(fu, order_u, axis=1)
     fu_pad[np.arange(Pm)[None, :] >= cnt_u[:, None]] = 0.0
-    keep_v = fv >= CUTOFF
+    keep_v = (fv >= cutoff) & (lat2_v <= r2max)
     cnt_v = keep_v.sum(axis=1)
     Km = max(int(cnt_v.max()), 1)
     order_v = np.argsort(~keep_v, axis=1, kind="stable")[:, :Km]
     fv_pad = np.take_along_axis(fv, order_v, axis=1)
     fv_pad[np.arange(Km)[None, :] >= cnt_v[:, None]] = 0.0
+    if cone_mm is not None:
+        l2u_pad = np.take_along_axis(lat2_u, order_u, axis=1)
+        l2v_pad = np.take_along_axis(lat2_v, order_v, axis=1)
     rows_out, cols_out, vals_out = [], [], []
     # chunk over leaf rows to bound memory
     R, C = plan.n_rows, plan.n_cols
@@ -212,7 +225,10 @@ def generate_cp(plan: Plan, a: int, xy=None, z_slab: Optional[Tuple[int, int]] =
     for r0 in range(0, R, chunk):
         r1 = min(R, r0 + chunk)
         prod = fv_pad[r0:r1, None, :, None] * fu_pad[None, :, None, :]   # [r, c, k, p]
-        rr, cc, kk, pp = np.nonzero(prod >= CUTOFF)
+        keep = prod >= cutoff
+        if cone_mm is not None:
+            keep &= (l2v_pad[r0:r1, None, :, None] + l2u_pad[None, :, None, :]) <= r2max
+        rr, cc, kk, pp = np.nonzero(keep)
         vals = prod[rr, cc, kk, pp]
         iz = order_v[rr + r0, kk]
         p = order_u[cc, pp]
@@ -231,10 +247,14 @@ def _threads() -> int:
 
 
 def generate_ddc(plan: Plan, cps: Optional[List[int]] = None, threads: Optional[int] = None,
-                 z_slab: Optional[Tuple[int, int]] = None):
+                 z_slab: Optional[Tuple[int, int]] = None, cutoff: float = CUTOFF,
+                 cone_mm: Optional[float] = None):
     """COO of D (voxels x beamlets), sorted by (beamlet, voxel); unique pairs.
     z_slab = (z0, z1): only the rows of voxel slices z0 <= iz < z1 (global
     voxel indices), the share of one GPU in a split by voxel rows.
+    cutoff, cone_mm: the truncation (generate_cp); the defaults give the
+    complete matrix, and any truncation keeps a subset of its entries with
+    the same values.
 
     Control points are generated on a thread pool (NumPy releases the GIL in
     its array loops); the result does not depend on the thread count.
@@ -244,9 +264,9 @@ def generate_ddc(plan: Plan, cps: Optional[List[int]] = None, threads: Optional[
     nt = threads or _threads()
     if nt > 1 and len(cps) > 1:
         with ThreadPoolExecutor(nt) as ex:
-            parts = list(ex.map(lambda a: generate_cp(plan, a, xy, z_slab), cps))
+            parts = list(ex.map(lambda a: generate_cp(plan, a, xy, z_slab, cutoff, cone_mm), cps))
     else:
-        parts = [generate_cp(plan, a, xy, z_slab) for a in cps]
+        parts = [generate_cp(plan, a, xy, z_slab, cutoff, cone_mm) for a in cps]
     nnz = sum(len(p[0]) for p in parts)
     row = np.empty(nnz, np.int32)
     col = np.empty(nnz, np.int32)
@@ -298,7 +318,8 @@ def balanced_slabs(plan: Plan, G: int, counts: Optional[np.ndarray] = None) -> L
     return [(cuts[k], cuts[k + 1]) for k in range(G)]
 
 
-def ddc_entries(plan: Plan, vox: np.ndarray, bl: np.ndarray) -> np.ndarray:
+def ddc_entries(plan: Plan, vox: np.ndarray, bl: np.ndarray, cutoff: float = CUTOFF,
+                cone_mm: Optional[float] = None) -> np.ndarray:
     """D_ij (float32, 0 where dropped) for explicit (voxel, beamlet) pairs.
 
     Same definition as generate_ddc, evaluated pointwise; used to sample rows
@@ -326,7 +347,9 @@ def ddc_entries(plan: Plan, vox: np.ndarray, bl: np.ndarray) -> np.ndarray:
     fv = np.exp(-((pz - v_r) ** 2) / (2.0 * SIGMA_MM ** 2))
     d = fu * fv
     inside = (px * px + py * py) <= R * R
-    keep = inside & (d >= CUTOFF)
+    keep = inside & (d >= cutoff)
+    if cone_mm is not None:
+        keep &= ((pu - u_c) ** 2 + (pz - v_r) ** 2) <= float(cone_mm) ** 2
     return np.where(keep, d, 0.0).astype(np.float32)
 
 

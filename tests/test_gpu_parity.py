@@ -480,23 +480,27 @@ def _first_stop(flags):
     return None, 0
 
 
-@pytest.mark.parametrize("rule", ["rel_f", "small_step"])
-def test_bb_stop_iteration_and_flag_match_oracle(dv, plan1, rule):
+@pytest.mark.parametrize("rule,m,seed", [("rel_f", 5, 44), ("small_step", 2, 47)])
+def test_bb_stop_iteration_and_flag_match_oracle(dv, plan1, rule, m, seed):
     """The live stopping tests (Sec. 2.1) stop the GPU solve at the same
     iteration, with the same flag, as the oracle.  The threshold is placed by
     the oracle's unstopped run between the ratio at the first qualifying
     iteration t* and the smallest ratio before it, at least a factor 4 from
-    both, so FP32 rounding of F and y cannot move the decision."""
+    both, so FP32 rounding of F and y cannot move the decision.  Rates start
+    at random lower bounds with no upper bound, so the solve runs its 30 steps
+    without converging onto the box (aperture sets chosen so t* comes early,
+    while the FP32 and FP64 trajectories still agree closely)."""
     d, sid, table, ddc, obj = plan1
-    m = 5
-    lo, hi = synth.random_boxes(m, 43)
-    cps, L, R = synth.random_apertures(PLAN1, m, 44)
+    lo, _ = synth.random_boxes(m, 43)
+    hi = np.full(m, np.inf, np.float32)
+    cps, L, R = synth.random_apertures(PLAN1, m, seed)
     apset = obb.ApertureSet(PLAN1.n_cp, PLAN1.n_rows, PLAN1.n_cols)
     for k in range(m):
         apset.add(cps[k], L[k], R[k])
     apply, adjoint = obb.d_form_ops(d["row"], d["col"], d["val"], PLAN1.n_vox, PLAN1.n_bl, apset)
     y0 = lo.astype(np.float64)
     free = obb.solve(apply, adjoint, sid, table, y0, lo, hi, obb.BBParams(30, 0.0, 0.0), record=True)
+    assert free["iters"] == 30
     if rule == "rel_f":
         Fh = free["hist"]["F"]
         r = {t: abs(Fh[t - 5] - Fh[t]) / abs(Fh[t]) for t in range(5, 30)}
@@ -510,7 +514,7 @@ def test_bb_stop_iteration_and_flag_match_oracle(dv, plan1, rule):
     ref = obb.solve(apply, adjoint, sid, table, y0, lo, hi, obb.BBParams(30, *params))
     flag = obb.FLAG_REL_F if rule == "rel_f" else obb.FLAG_SMALL_STEP
     assert ref["iters"] == t_star and ref["flags"] & obb.STOP_MASK == flag
-    bb, _ = _device_apertures(dv, PLAN1, m, 44, lo, hi, max_iter=30, eps_f=params[0], eps_step=params[1])
+    bb, _ = _device_apertures(dv, PLAN1, m, seed, lo, hi, max_iter=30, eps_f=params[0], eps_step=params[1])
     gpu = _gpu_mp(dv, ddc, obj, bb, t_star + 3, PLAN1.n_vox, PLAN1.n_bl)
     at, bits = _first_stop(gpu["flags"])
     assert (at, bits) == (t_star, flag), (at, bits, t_star, flag)
@@ -575,7 +579,10 @@ def test_machine_model_first_step_starts_from_clipped_rates(dv):
     ddc = dv.DDC(d["row"], d["col"], d["val"], SMALL.n_vox, SMALL.n_bl)
     obj = dv.Objective(sid, table)
     n_cp, n_rows, n_cols = SMALL.n_cp, SMALL.n_rows, SMALL.n_cols
-    vals = (1.0, 1.0, 4.0, 0.5, 2.0, 50.0, 2.0)
+    # a high minimum dose rate: the lower bounds (rate_min / S^U_k) climb past
+    # earlier rates when new neighbours slow the gantry (the fourth aperture
+    # lifts the third's bound from 5 to 20 on this plan)
+    vals = (1.0, 1.0, 4.0, 0.5, 20.0, 50.0, 2.0)
     om = omach.Machine(*vals)
     cg = ColumnGeneration(ddc, obj, n_cp, n_rows, n_cols, bb_steps=1, eps_f=0.0, eps_step=0.0,
                           machine=dv.Machine(*vals))

@@ -837,3 +837,40 @@ def test_column_generation_with_machine_model(small):
         y = res["y"]
         assert np.all(y >= lo[cps] - 1e-12) and np.all(y <= hi[cps] + 1e-12)
         assert np.any(np.abs(y - lo[cps]) <= 1e-12)                      # so does a lower rate bound
+
+
+# ---------------------------------------------------------------- truncation (Sec. 2.4, S1)
+
+def test_truncated_dose_is_the_complete_dose_less_the_dropped_entries(small):
+    """Truncating D (Sec. 2.4 S1) keeps a subset of its non-negative entries,
+    so for any fluence x >= 0 the truncated dose is at most the complete dose
+    in every voxel, short by exactly the dose of the dropped entries; the
+    plan optimised on the truncated matrix therefore delivers at least its
+    optimised dose everywhere (Sec. 3: the actual dose of Plan-S1 is higher)."""
+    d, sid, table = small
+    tr = synth.generate_ddc(SMALL, cone_mm=4.5)
+    key_full = d["col"].astype(np.int64) * SMALL.n_vox + d["row"]
+    key_tr = tr["col"].astype(np.int64) * SMALL.n_vox + tr["row"]
+    kept = np.isin(key_full, key_tr)
+    assert kept.sum() == len(key_tr) and 0 < kept.sum() < len(key_full)
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0.0, 1.0, SMALL.n_bl)
+    z_full = products.dose(d["row"], d["col"], d["val"], x, SMALL.n_vox)
+    z_tr = products.dose(tr["row"], tr["col"], tr["val"], x, SMALL.n_vox)
+    drop = ~kept
+    z_drop = products.dose(d["row"][drop], d["col"][drop], d["val"][drop], x, SMALL.n_vox)
+    assert np.all(z_tr <= z_full * (1 + 1e-12))
+    assert np.abs(z_full - z_tr - z_drop).max() <= 1e-12 * z_full.max()
+    assert z_drop[sid == synth.S_PTV0].min() > 0.0          # every target voxel loses some dose
+    # a plan optimised on the truncated matrix, re-evaluated on the complete one
+    res = colgen.run(tr["row"], tr["col"], tr["val"], SMALL.n_vox, SMALL.n_cp, SMALL.n_rows, SMALL.n_cols, sid,
+                     table, max_cg=4, params=bb.BBParams(max_iter=30, eps_f=0.0, eps_step=0.0))
+    apset = bb.ApertureSet(SMALL.n_cp, SMALL.n_rows, SMALL.n_cols)
+    for cp, L, R in res["apertures"]:
+        apset.add(cp, L, R)
+    xs = apset.expand(res["y"])
+    z_opt = products.dose(tr["row"], tr["col"], tr["val"], xs, SMALL.n_vox)
+    z_act = products.dose(d["row"], d["col"], d["val"], xs, SMALL.n_vox)
+    assert np.allclose(z_opt, res["z"], rtol=1e-12, atol=1e-12 * z_opt.max())
+    ptv = sid == synth.S_PTV0
+    assert np.all(z_act >= z_opt * (1 - 1e-12)) and z_act[ptv].mean() > z_opt[ptv].mean()

@@ -95,3 +95,58 @@ def test_slice_counts_and_balanced_slabs():
         assert all(slabs[k][1] == slabs[k + 1][0] for k in range(G - 1))
         share = [c[a:b].sum() for a, b in slabs]
         assert max(share) <= c.sum() / G + c.max()             # within one slice of the ideal
+
+
+def _lateral_mm(plan, vox, bl):
+    """Distance from voxel centres to beamlet central axes, computed here
+    from the geometry (beam direction (sin, -cos, 0), u = (cos, sin, 0),
+    v = z), independently of the generator's factorisation."""
+    N, h = plan.n_grid, plan.vox_mm
+    ix, iy, iz = vox % N, (vox // N) % N, vox // (N * N)
+    P = np.stack([(ix - (N - 1) / 2) * h, (iy - (N - 1) / 2) * h, (iz - (N - 1) / 2) * h], axis=1)
+    c, r, a = bl % plan.n_cols, (bl // plan.n_cols) % plan.n_rows, bl // (plan.n_cols * plan.n_rows)
+    th = 2 * np.pi * a / plan.n_cp
+    axis_point = np.stack([((c - (plan.n_cols - 1) / 2) * plan.bl_mm) * np.cos(th),
+                           ((c - (plan.n_cols - 1) / 2) * plan.bl_mm) * np.sin(th),
+                           (r - (plan.n_rows - 1) / 2) * plan.bl_mm], axis=1)
+    d = np.stack([np.sin(th), -np.cos(th), np.zeros_like(th)], axis=1)
+    w = P - axis_point
+    along = (w * d).sum(axis=1)
+    return np.linalg.norm(w - along[:, None] * d, axis=1)
+
+
+@pytest.mark.parametrize("cone", [4.5, 6.0, 7.5])
+def test_cone_truncation_keeps_the_complete_entries_within_the_cone(cone):
+    """Sec. 2.4 S1: the truncated matrix holds exactly the complete matrix's
+    entries of voxels within the cone radius of the beamlet axis, with the
+    same values; the pointwise form agrees."""
+    plan = synth.PLANS["cp20_bl20x20_vox32"]
+    full = synth.generate_ddc(plan)
+    tr = synth.generate_ddc(plan, cone_mm=cone)
+    dist = _lateral_mm(plan, full["row"].astype(np.int64), full["col"].astype(np.int64))
+    inside = dist <= cone
+    # margin: entries within 1e-9 mm of the cone surface could round either way
+    assert not np.any(np.abs(dist - cone) < 1e-9)
+    for k in ("row", "col", "val"):
+        assert np.array_equal(tr[k], full[k][inside]), k
+    assert 0 < len(tr["val"]) < len(full["val"])
+    assert np.array_equal(synth.ddc_entries(plan, tr["row"], tr["col"], cone_mm=cone), tr["val"])
+    out = ~inside
+    assert not np.any(synth.ddc_entries(plan, full["row"][out], full["col"][out], cone_mm=cone))
+
+
+def test_cone_wider_than_the_cutoff_reach_changes_nothing():
+    """At depth 0 the 1e-3 cut-off reaches sqrt(2 sigma^2 ln 1000) = 11.15 mm
+    from the axis: a cone of 11.2 mm drops nothing, and a higher value
+    cut-off drops exactly the entries below it."""
+    plan = synth.PLANS["cp20_bl20x20_vox32"]
+    full = synth.generate_ddc(plan)
+    assert np.sqrt(2 * synth.SIGMA_MM ** 2 * np.log(1e3)) == pytest.approx(11.15, abs=0.01)
+    wide = synth.generate_ddc(plan, cone_mm=11.2)
+    for k in ("row", "col", "val"):
+        assert np.array_equal(wide[k], full[k])
+    hi = synth.generate_ddc(plan, cutoff=1e-2)
+    keep = full["val"] >= np.float32(1e-2)
+    # stored values are float32 roundings of the float64 entries tested against the cut
+    assert abs(len(hi["val"]) - int(keep.sum())) <= 8
+    assert hi["val"].min() >= np.float32(1e-2) * (1 - 1e-6)
