@@ -316,6 +316,25 @@ dvmat_status dvmat_aperture_select_interdigitated(dvmat_geom geom, const float* 
                                                   float* cp_price,
                                                   int32_t* best, float* best_price,
                                                   void* d_workspace, size_t bytes, dvmat_stream stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * selection as dvmat_aperture_select_interdigitated, same arguments and
+ * results bit for bit, without the workspace.  The per-row state values live
+ * in a library-owned static device array of 32 MiB (DVMAT_SELECT_SCRATCH_BYTES)
+ * that each GPU the library runs on holds until the process ends; its device
+ * address is looked up on the first call on each device (the device current
+ * on the calling thread, which must be the stream's).  No call allocates.
+ * DVMAT_E_NOMEM when dvmat_aperture_select_ws_size exceeds the array (e.g. the
+ * 180 x 40 x 40 geometry needs 24.8 MB; 96 columns allow 1,764 rows in all);
+ * DVMAT_E_SHAPE / DVMAT_E_ARG as the workspace form.  Every call on one GPU
+ * shares the array, which keeps the last call's values: each call writes
+ * every value it reads, but calls that overlap in time on one GPU (other
+ * streams, other threads) race on it; serialise them. */
+#define DVMAT_SELECT_SCRATCH_BYTES (32u << 20)
+dvmat_status dvmat_aperture_select_interdigitated_noalloc(dvmat_geom geom, const float* p, const uint8_t* occupied,
+                                                          const int32_t* leaf_window, int32_t* L, int32_t* R,
+                                                          float* cp_price, int32_t* best, float* best_price,
+                                                          dvmat_stream stream);
 
 /* ------------------------------------------------------------------------
  * Machine constraints of Eq. (2) and the rate boxes they give the master

@@ -17,8 +17,18 @@
 #include "common.hpp"
 
 #include <cmath>
+#include <mutex>
 
 namespace dvmat {
+
+// Library-owned scratch for the interdigitated selection's per-row dynamic-
+// programming values when the caller cannot pass a workspace.  Each GPU the
+// library runs on holds its own copy until the process ends.  In host code
+// the name stands for a host-side shadow, not the device address: kernels get
+// the address that hipGetSymbolAddress returns for the current device.
+constexpr size_t kSelectScratchBytes = DVMAT_SELECT_SCRATCH_BYTES;
+static_assert(kSelectScratchBytes % 256 == 0, "scratch size");
+static __device__ __align__(256) float scratch[kSelectScratchBytes / sizeof(float)];
 
 // Leaf window of one row: (Lmin, Lmax, Rmin, Rmax), clamped to [0, n]; the
 // full window when none is given.
@@ -365,6 +375,62 @@ extern "C" dvmat_status dvmat_aperture_select_interdigitated(dvmat_geom geom, co
                        occupied, leaf_window, L, R, cp_price, static_cast<float*>(d_workspace));
     hipLaunchKernelGGL(select_best_kernel, dim3(1), dim3(256), 0, s, geom.n_cp, cp_price, best, best_price);
     return check_hip(hipGetLastError(), "dvmat_aperture_select_interdigitated launch");
+}
+
+namespace dvmat {
+
+constexpr int kMaxScratchDevices = 64;
+
+// Device address of the scratch array on the current device, looked up once
+// per device (with that device current) and kept.
+static dvmat_status scratch_address(float** out, const char* fn) {
+    static std::mutex mu;
+    static float* addr[kMaxScratchDevices] = {};
+    int dev = -1;
+    dvmat_status st = check_hip(hipGetDevice(&dev), fn);
+    if (st) return st;
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return set_error(DVMAT_E_ARG, "%s: device %d beyond the %d supported", fn, dev, kMaxScratchDevices);
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        st = check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), fn);
+        if (st) return st;
+        if (!p) return set_error(DVMAT_E_HIP, "%s: no device address for the scratch array", fn);
+        addr[dev] = static_cast<float*>(p);
+    }
+    *out = addr[dev];
+    return DVMAT_OK;
+}
+
+}  // namespace dvmat
+
+extern "C" dvmat_status dvmat_aperture_select_interdigitated_noalloc(dvmat_geom geom, const float* p,
+                                                                     const uint8_t* occupied,
+                                                                     const int32_t* leaf_window, int32_t* L,
+                                                                     int32_t* R, float* cp_price, int32_t* best,
+                                                                     float* best_price, dvmat_stream stream) {
+    const char* fn = "dvmat_aperture_select_interdigitated_noalloc";
+    size_t need = 0;
+    dvmat_status st = dvmat_aperture_select_ws_size(geom, &need);
+    if (st) return st;
+    if (!p || !L || !R || !cp_price || !best || !best_price) return set_error(DVMAT_E_ARG, "%s: NULL argument", fn);
+    if (need > kSelectScratchBytes)
+        return set_error(DVMAT_E_NOMEM, "%s: geometry %d x %d x %d needs %zu bytes of scratch, the limit is %zu", fn,
+                         geom.n_cp, geom.n_rows, geom.n_cols, need, kSelectScratchBytes);
+    float* hist = nullptr;
+    st = scratch_address(&hist, fn);
+    if (st) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int W = geom.n_cols + 1;
+    const int S = W * (W + 1) / 2;
+    const size_t lds = ((size_t)W * W + S + W) * sizeof(float);
+    // every value a call reads from the scratch is written earlier in the same
+    // call (row r's values before row r+1 and the backtracking read them)
+    hipLaunchKernelGGL(select_interdig_kernel, dim3(geom.n_cp), dim3(256), lds, s, geom.n_rows, geom.n_cols, p,
+                       occupied, leaf_window, L, R, cp_price, hist);
+    hipLaunchKernelGGL(select_best_kernel, dim3(1), dim3(256), 0, s, geom.n_cp, cp_price, best, best_price);
+    return check_hip(hipGetLastError(), "dvmat_aperture_select_interdigitated_noalloc launch");
 }
 
 extern "C" dvmat_status dvmat_leaf_windows(dvmat_geom geom, const uint8_t* occupied, const int32_t* L,

@@ -129,6 +129,7 @@ _SIGNATURES = {
     "dvmat_machine_boxes": (_I32, [Geom, ctypes.POINTER(Machine), _P, _P, _P, _P, _P, _P, _P]),
     "dvmat_bb_set_boxes": (_I32, [_P, _P, _P, _P]),
     "dvmat_aperture_select_interdigitated": (_I32, [Geom, _P, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "dvmat_aperture_select_interdigitated_noalloc": (_I32, [Geom, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "dvmat_bb_workspace_size": (_I32, [Geom, _I32, ctypes.POINTER(_SZ)]),
     "dvmat_bb_create": (_I32, [Geom, _I32, BBParams, _P, _SZ, _P, ctypes.POINTER(_P)]),
     "dvmat_bb_destroy": (None, [_P]),

@@ -190,3 +190,17 @@ def test_machine_leaf_travel_and_argument_checks(dv):
     assert dv.lib.dvmat_machine_boxes(dv.Geom(8193, 3, 5), ctypes.byref(good), None, None, None, None, None, None,
                                       None) == -2
     assert dv.lib.dvmat_bb_set_boxes(None, None, None, None) == -1
+
+
+def test_select_noalloc_rejects_before_touching_a_device(dv):
+    """The no-allocation selection checks its arguments and the scratch limit
+    on the host before it looks up the device array or enqueues anything."""
+    f = dv.lib.dvmat_aperture_select_interdigitated_noalloc
+    dummy = ctypes.c_void_p(256)          # never dereferenced: the call returns first
+    args = [dummy] * 5 + [None]          # L, R, cp_price, best, best_price; null stream
+    # 96 columns: 4,753 states x 4 bytes per row; 1,765 rows exceed 32 MiB
+    assert f(dv.Geom(1765, 1, 96), dummy, None, None, *args) == -4
+    assert b"limit" in dv.lib.dvmat_last_error()
+    assert f(dv.Geom(1, 1, 97), dummy, None, None, *args) == -2      # DP limited to 96 columns
+    assert f(dv.Geom(0, 1, 8), dummy, None, None, *args) == -2
+    assert f(dv.Geom(4, 2, 8), None, None, None, *args) == -1        # p is NULL
