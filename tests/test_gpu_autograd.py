@@ -71,7 +71,9 @@ def test_gradient_matches_oracle_and_finite_differences(setup):
     h = 1e-3
     G_fd = np.array([(oobj.objective(z + h * DA[k], sid, table) - oobj.objective(z - h * DA[k], sid, table)) / (2 * h)
                      for k in range(64)])
-    assert np.abs(G - G_fd).max() <= 1e-3 * np.abs(G_fd).max()
+    # on this case the central differences of the FP64 objective match its exact
+    # gradient to about 2e-12 (h = 1e-3), so the bound is the exact gradient's
+    assert np.abs(G - G_fd).max() <= 1e-4 * np.abs(G_fd).max()
 
 
 def test_dose_fn_backward_is_price(setup):
