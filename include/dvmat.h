@@ -536,6 +536,17 @@ dvmat_status dvmat_da_append(dvmat_da da, dvmat_ddc ddc, const float* x_ind, dvm
  * and dF/dz; G: device float[count] = dF/dy; F (nullable): device float[1]. */
 dvmat_status dvmat_da_eval(dvmat_da da, dvmat_obj obj, const float* y, float* z, float* g, float* G,
                            float* F, dvmat_stream stream);
+/* One Barzilai-Borwein iteration of the DA-form master problem in one launch
+ * (the four steps of Sec. 2.2.2 on the aperture columns; Eqs. 7-10): G = dF/dy
+ * and F at the current rates of bb (as dvmat_da_eval, without z and dF/dz),
+ * then the step of dvmat_bb_step_g(bb, G, F, curv, NULL, flags), taken by the
+ * launch's last workgroup.  The result equals those two calls bit for bit.
+ * bb holds the apertures of the da columns, in the same order (DVMAT_E_STATE
+ * if the counts differ).  G: device float[>= count] and F: device float[1]
+ * receive the values at the rates before the step; curv, flags as
+ * dvmat_bb_step_g.  Calls on one da handle must not overlap in time. */
+dvmat_status dvmat_da_bb_step(dvmat_da da, dvmat_bb bb, dvmat_obj obj, float* G, float* F, const double* curv,
+                              uint32_t* flags, dvmat_stream stream);
 /* curv = sum_i w_i(z_ref) (sum_k DA_k dir_k)_i^2 (weights as dvmat_dose_curvature);
  * dir: device float[count]; curv: device double[1]. */
 dvmat_status dvmat_da_curvature(dvmat_da da, dvmat_obj obj, const float* dir, const float* z_ref,

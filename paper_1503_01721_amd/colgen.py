@@ -21,14 +21,23 @@ leaf_travel beamlets of its position there.  A machine model (Eq. 2: gantry
 speed and dose-rate ranges, speed change, leaf speed) sets that travel and,
 after each new aperture, every aperture's rate box (Eq. 6).
 
-Per iteration the host reads back one small record (chosen control point,
-its price, the solve's flags and F); all other data stays on the device.
+Per iteration the host reads back one small record, in one copy: the chosen
+control point and its price, with F and the flags of the latest solve; all
+other data stays on the device.  With sync=False an iteration's own F and
+flags arrive with the next iteration's read-back (or finish()), so the loop
+waits on the device once per iteration.  With graph=True the master problem's
+launches are captured once in a HIP graph (per step count) and replayed in
+every later iteration: the library keeps the aperture count on the device and
+sizes every grid for the largest set, so the captured launches stay valid as
+apertures are added.
 """
 from __future__ import annotations
 
 import dataclasses
-from typing import List, Optional
+import math
+from typing import Dict, List, Optional
 
+import numpy as np
 import torch
 
 from . import dvmat
@@ -50,7 +59,7 @@ class ColumnGeneration:
                  max_apertures: Optional[int] = None, bb_steps: int = 50, eps_f: float = 1e-5,
                  eps_step: float = 1e-7, lo: float = 0.0, hi: float = float("inf"), form: str = "D",
                  interdigitated: bool = False, leaf_travel: Optional[int] = None,
-                 machine: Optional[dvmat.Machine] = None):
+                 machine: Optional[dvmat.Machine] = None, graph: bool = False):
         if form not in ("D", "DA"):
             raise ValueError("form must be 'D' or 'DA'")
         self.form = form
@@ -64,7 +73,15 @@ class ColumnGeneration:
         self.lo, self.hi = lo, hi
         self.bb = dvmat.BB(n_cp, n_rows, n_cols, self.max_apertures, max_iter=bb_steps, eps_f=eps_f,
                            eps_step=eps_step, device=dev)
-        self.sel = dvmat.ApertureSelector(n_cp, n_rows, n_cols, device=dev, interdigitated=interdigitated)
+        # [chosen control point, its price, F, flags]: written in place by the
+        # selection, the dose's objective epilogue and the BB step, read back
+        # in one copy per iteration
+        self.status = torch.zeros(4, dtype=torch.int32, device=dev)
+        self.host_status = torch.zeros(4, dtype=torch.int32, pin_memory=True)
+        self._host = self.host_status.numpy()
+        self.bb.flags = self.status[3:4]
+        self.sel = dvmat.ApertureSelector(n_cp, n_rows, n_cols, device=dev, interdigitated=interdigitated,
+                                          best=self.status[0:1], best_price=self.status[1:2].view(torch.float32))
         self.machine = machine
         if machine is not None:
             t = dvmat.machine_leaf_travel(machine, n_cols)
@@ -82,7 +99,7 @@ class ColumnGeneration:
         self.p = torch.empty(ddc.n_bl, **f32)
         self.z = torch.empty(ddc.n_vox, **f32)
         self.g = torch.empty(ddc.n_vox, **f32)
-        self.F = torch.empty(1, **f32)
+        self.F = self.status[2:3].view(torch.float32)
         self.curv = torch.empty(1, dtype=torch.float64, device=dev)
         if form == "DA":
             self.da = dvmat.DAColumns(ddc.n_vox, self.max_apertures, device=dev)
@@ -97,6 +114,9 @@ class ColumnGeneration:
         self.events: Optional[list] = None
         self.iterations = 0
         self.done = False
+        self.graph = graph
+        self._graphs: Dict[int, torch.cuda.CUDAGraph] = {}
+        self._pending: Optional[IterationRecord] = None
 
     def start(self):
         """z = 0 (no apertures): F, dF/dz and the first prices."""
@@ -113,16 +133,20 @@ class ColumnGeneration:
         return self.sel(self.p, self.bb.occupied_ptr, windows=self.windows)
 
     def _master_problem_da(self, steps):
-        m = self.bb.count
-        G = self.G[:m]
+        # the whole G buffer: the kernels read the aperture count on the device
+        G = self.G
         y_ptr, gt_ptr = self.bb.state_ptrs()
         self.bb.begin()
         self.da.eval_(self.obj, y_ptr, G, z=self.z, g=self.g, F=self.F)
         self.bb.direction_g_(G, self.x_dir)
         self.da.curvature_(self.obj, gt_ptr, self.z, self.curv)
-        for _ in range(steps):
-            # no beamlet fluence per step: the dose comes from the m columns
+        if steps > 0:
+            # no beamlet fluence per step: the dose comes from the m columns.
+            # Step t uses G, F at y_t: the first from the evaluation above, the
+            # next ones from the fused launch (evaluation, then the step)
             self.bb.step_g_(G, self.F, self.curv, None)
+            for _ in range(steps - 1):
+                self.da.bb_step_(self.bb, self.obj, G, self.F, self.curv)
             self.da.eval_(self.obj, y_ptr, G, z=self.z, g=self.g, F=self.F)
         self.bb.expand_(self.x)                       # the fluence of the final rates
         self.ddc.price_(self.g, self.p)
@@ -140,6 +164,20 @@ class ColumnGeneration:
         """BB solve over the current aperture set: begin, the first step
         length's curvature product, then `steps` x (step, dose+objective, price)."""
         steps = self.bb_steps if steps is None else steps
+        if self.graph:
+            if self.events is not None:
+                raise ValueError("per-launch events cannot be recorded inside a captured graph")
+            g = self._graphs.get(steps)
+            if g is None:
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g):
+                    self._master_problem_body(steps)
+                self._graphs[steps] = g
+            g.replay()
+            return
+        self._master_problem_body(steps)
+
+    def _master_problem_body(self, steps):
         if self.form == "DA":
             return self._master_problem_da(steps)
         self.bb.begin()
@@ -160,12 +198,33 @@ class ColumnGeneration:
                 e[2].record()
                 ev.append(e)
 
-    def iteration(self) -> Optional[IterationRecord]:
-        """One column-generation iteration; None when no improving aperture is left."""
+    def _read_status(self):
+        """The one device-to-host copy of an iteration: (best control point,
+        its price, F and flags of the latest solve)."""
+        self.host_status.copy_(self.status, non_blocking=True)
+        torch.cuda.current_stream().synchronize()
+        h = self._host
+        return int(h[0]), float(h[1:2].view(np.float32)[0]), float(h[2:3].view(np.float32)[0]), int(h[3])
+
+    def _complete(self, F, flags):
+        if self._pending is not None:
+            self._pending.F, self._pending.flags = F, flags
+            self._pending = None
+
+    def finish(self):
+        """Fill in F and flags of the last iteration run with sync=False."""
+        if self._pending is not None:
+            _, _, F, flags = self._read_status()
+            self._complete(F, flags)
+
+    def iteration(self, sync: bool = True) -> Optional[IterationRecord]:
+        """One column-generation iteration; None when no improving aperture is left.
+        sync=False leaves the record's F and flags to the next read-back."""
         if self.done:
             return None
         self.select()
-        best, best_price = int(self.sel.best.item()), float(self.sel.best_price.item())
+        best, best_price, F_prev, flags_prev = self._read_status()
+        self._complete(F_prev, flags_prev)
         if best < 0 or self.bb.count >= self.max_apertures:
             self.done = True
             return None
@@ -188,14 +247,19 @@ class ColumnGeneration:
             self.ddc.dose_(self.x, self.z, self.obj, self.g, self.F)
             self.ddc.price_(self.g, self.p)
         self.master_problem()
-        rec = IterationRecord(self.iterations, best, best_price, float(self.F.item()), int(self.bb.flags.item()))
+        rec = IterationRecord(self.iterations, best, best_price, math.nan, 0)
+        self._pending = rec
+        if sync:
+            _, _, F, flags = self._read_status()
+            self._complete(F, flags)
         self.records.append(rec)
         self.iterations += 1
         return rec
 
-    def run(self, max_iterations: int) -> List[IterationRecord]:
+    def run(self, max_iterations: int, sync: bool = True) -> List[IterationRecord]:
         self.start()
         for _ in range(max_iterations):
-            if self.iteration() is None:
+            if self.iteration(sync=sync) is None:
                 break
+        self.finish()
         return self.records

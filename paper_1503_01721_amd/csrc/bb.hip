@@ -7,52 +7,15 @@
 // launches: gather G_k = sum_{j in A_k} p_j (one workgroup per aperture, fixed
 // reduction order), the update (one workgroup: bound rules, FP64 inner
 // products, step length, stopping tests, clipped step), and the expansion of
-// the rates to the beamlet fluence x = B y (one thread per beamlet).
-#include "common.hpp"
+// the rates to the beamlet fluence x = B y (one thread per beamlet).  The
+// aperture count lives on the device as well and every kernel reads it there,
+// with grids sized for the largest set: the launches of a solve do not change
+// as apertures are added, so a captured graph of them replays for every
+// column-generation iteration.
+#include "bb_device.hpp"
 
 #include <cmath>
 #include <new>
-
-namespace dvmat {
-
-constexpr uint32_t kStopMask = DVMAT_BB_REL_F | DVMAT_BB_SMALL_STEP | DVMAT_BB_MAX_ITER | DVMAT_BB_CONVERGED |
-                               DVMAT_BB_NONFINITE;
-constexpr int kFHist = 8;
-
-struct BBState {
-    int32_t t;         // iteration counter of the current solve
-    uint32_t flags;
-    float alpha;       // last step length
-    float pad;
-    float F_hist[kFHist];
-};
-
-struct BBDev {
-    BBState* state;
-    int32_t* cp;       // [max_ap]
-    int32_t* L;        // [max_ap * n_rows]
-    int32_t* R;
-    float* lo;         // [max_ap]
-    float* hi;
-    float* y;
-    float* y_prev;
-    float* G;
-    float* Gt;
-    float* Gt_prev;
-    int32_t* cp_slot;  // [n_cp] aperture index or -1
-    uint8_t* occ;      // [n_cp] 1 where a control point holds an aperture
-};
-
-}  // namespace dvmat
-
-struct dvmat_bb_s {
-    dvmat_geom geom{};
-    int32_t max_ap = 0;
-    int32_t m = 0;
-    dvmat_bb_params params{};
-    std::vector<uint8_t> occupied;   // host mirror of control-point occupancy
-    dvmat::BBDev dev{};
-};
 
 namespace dvmat {
 
@@ -85,6 +48,7 @@ __global__ void bb_init_kernel(BBDev B, int n_cp) {
         B.state->t = 0;
         B.state->flags = 0;
         B.state->alpha = 0.0f;
+        B.state->m = 0;
         for (int i = 0; i < kFHist; ++i) B.state->F_hist[i] = 0.0f;
     }
 }
@@ -96,6 +60,7 @@ __global__ void bb_add_kernel(BBDev B, int slot, int cp, int n_rows, const int32
         B.R[(int64_t)slot * n_rows + r] = dR[r];
     }
     if (threadIdx.x == 0) {
+        B.state->m = slot + 1;
         B.cp[slot] = cp;
         B.cp_slot[cp] = slot;
         B.occ[cp] = 1;
@@ -111,7 +76,8 @@ __global__ void bb_add_kernel(BBDev B, int slot, int cp, int n_rows, const int32
 }
 
 // Boxes from per-control-point arrays; each rate clipped into its new box.
-__global__ void bb_set_boxes_kernel(BBDev B, int m, const float* __restrict__ lo_cp, const float* __restrict__ hi_cp) {
+__global__ void bb_set_boxes_kernel(BBDev B, const float* __restrict__ lo_cp, const float* __restrict__ hi_cp) {
+    const int m = B.state->m;
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < m; k += gridDim.x * blockDim.x) {
         const int c = B.cp[k];
         const float lo = lo_cp[c], hi = hi_cp[c];
@@ -134,6 +100,7 @@ __global__ void bb_begin_kernel(BBDev B) {
 __global__ __launch_bounds__(256) void bb_gather_kernel(BBDev B, int n_rows, int n_cols, const float* __restrict__ p) {
     __shared__ float s[256];
     const int k = blockIdx.x;
+    if (k >= B.state->m) return;                      // grid sized for the largest set
     const int cp = B.cp[k];
     const int64_t base = (int64_t)cp * n_rows * n_cols;
     const int per_cp = n_rows * n_cols;
@@ -151,127 +118,11 @@ __global__ __launch_bounds__(256) void bb_gather_kernel(BBDev B, int n_rows, int
     if (threadIdx.x == 0) B.G[k] = s[0];
 }
 
-enum { MODE_DIRECTION = 0, MODE_STEP = 1 };
-
 // Bound rules, step length, stopping tests and the clipped step (one workgroup).
-__global__ __launch_bounds__(256) void bb_update_kernel(BBDev B, int m, int mode, const float* Fp, const double* curv,
+__global__ __launch_bounds__(256) void bb_update_kernel(BBDev B, int mode, const float* Fp, const double* curv,
                                                         uint32_t* flags_out, dvmat_bb_params prm,
                                                         const float* __restrict__ G_ext) {
-    __shared__ double r_ss[256], r_sq[256], r_qq[256], r_gg[256];
-    __shared__ float r_ds[256], r_y[256], r_g[256];
-    __shared__ int r_nz[256];
-    __shared__ float s_alpha;
-    __shared__ uint32_t s_stop;
-    const int tid = threadIdx.x;
-    const int t = B.state->t;
-    uint32_t flags = B.state->flags;
-    if (mode == MODE_STEP && (flags & kStopMask)) {   // solve already stopped: rates stay
-        if (tid == 0 && flags_out) *flags_out = flags;
-        return;
-    }
-    // Eqs. (9)-(10) on G = dF/dy (the paper's g_A = -G)
-    double ss = 0.0, sq = 0.0, qq = 0.0, gg = 0.0;
-    float ds = 0.0f, ymax = 0.0f, gmax = 0.0f;
-    int nz = 0;
-    for (int k = tid; k < m; k += 256) {
-        const float lo = B.lo[k], hi = B.hi[k];
-        const float y = fminf(fmaxf(B.y[k], lo), hi);
-        const float G = G_ext ? G_ext[k] : B.G[k];
-        float gt = G;
-        if (y <= lo && G > 0.0f) gt = 0.0f;
-        if (y >= hi && G < 0.0f) gt = 0.0f;
-        B.y[k] = y;
-        B.Gt[k] = gt;
-        if (mode == MODE_STEP) {
-            nz += gt != 0.0f;
-            gg += (double)gt * (double)gt;
-            ymax = fmaxf(ymax, fabsf(y));
-            gmax = fmaxf(gmax, fabsf(gt));
-            if (t >= 1) {
-                const double s = (double)y - (double)B.y_prev[k];
-                const double q = (double)gt - (double)B.Gt_prev[k];
-                ss += s * s;
-                sq += s * q;
-                qq += q * q;
-                ds = fmaxf(ds, fabsf(y - B.y_prev[k]));
-            }
-        }
-    }
-    if (mode == MODE_DIRECTION) return;
-    r_ss[tid] = ss; r_sq[tid] = sq; r_qq[tid] = qq; r_gg[tid] = gg;
-    r_ds[tid] = ds; r_y[tid] = ymax; r_g[tid] = gmax; r_nz[tid] = nz;
-    __syncthreads();
-    for (int o = 128; o >= 1; o >>= 1) {
-        if (tid < o) {
-            r_ss[tid] += r_ss[tid + o];
-            r_sq[tid] += r_sq[tid + o];
-            r_qq[tid] += r_qq[tid + o];
-            r_gg[tid] += r_gg[tid + o];
-            r_ds[tid] = fmaxf(r_ds[tid], r_ds[tid + o]);
-            r_y[tid] = fmaxf(r_y[tid], r_y[tid + o]);
-            r_g[tid] = fmaxf(r_g[tid], r_g[tid + o]);
-            r_nz[tid] += r_nz[tid + o];
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        const float F = *Fp;
-        B.state->F_hist[t % kFHist] = F;
-        uint32_t stop = 0;
-        if (!isfinite(F)) {
-            stop = DVMAT_BB_NONFINITE;
-        } else if (prm.eps_f > 0.0f && t >= 5 &&
-                   fabs((double)B.state->F_hist[(t - 5) % kFHist] - (double)F) <= (double)prm.eps_f * fabs((double)F)) {
-            stop = DVMAT_BB_REL_F;
-        } else if (prm.eps_step > 0.0f && t >= 1 && r_ds[0] <= prm.eps_step * fmaxf(1.0f, r_y[0])) {
-            stop = DVMAT_BB_SMALL_STEP;
-        } else if (r_nz[0] == 0) {
-            stop = DVMAT_BB_CONVERGED;
-        }
-        float alpha = B.state->alpha;
-        if (!stop) {
-            if (t == 0) {
-                const double den = curv ? 2.0 * (*curv) : 0.0;
-                if (den > 0.0 && isfinite(den)) {
-                    alpha = (float)(r_gg[0] / den);
-                } else {
-                    alpha = (r_y[0] > 0.0f ? r_y[0] : 1.0f) / r_g[0];
-                    flags |= DVMAT_BB_FALLBACK;
-                }
-            } else {
-                const double sqv = r_sq[0];
-                const double cand = (t & 1) ? r_ss[0] / sqv : sqv / r_qq[0];
-                if (sqv > 0.0 && isfinite(cand) && cand > 0.0) alpha = (float)cand;
-                else flags |= DVMAT_BB_FALLBACK;
-            }
-            if (!isfinite(alpha)) stop = DVMAT_BB_NONFINITE;
-        }
-        flags |= stop;
-        s_alpha = alpha;
-        s_stop = stop;
-        B.state->alpha = alpha;
-    }
-    __syncthreads();
-    const uint32_t stop = s_stop;
-    const float alpha = s_alpha;
-    if (!stop) {
-        for (int k = tid; k < m; k += 256) {
-            const float y = B.y[k];
-            const float gt = B.Gt[k];
-            B.y_prev[k] = y;
-            B.Gt_prev[k] = gt;
-            const double yn = (double)y - (double)alpha * (double)gt;
-            B.y[k] = fminf(fmaxf((float)yn, B.lo[k]), B.hi[k]);
-        }
-    }
-    if (tid == 0) {
-        if (!stop) {
-            if (t + 1 >= prm.max_iter) flags |= DVMAT_BB_MAX_ITER;
-            B.state->t = t + 1;
-        }
-        B.state->flags = flags;
-        if (flags_out) *flags_out = flags;
-    }
+    bb_update_block(B, mode, Fp, curv, flags_out, prm, G_ext);
 }
 
 // x_j = src_k for beamlet j in aperture k, else 0.
@@ -289,7 +140,8 @@ __global__ __launch_bounds__(256) void bb_expand_kernel(BBDev B, int n_rows, int
     }
 }
 
-__global__ void bb_copy_y_kernel(BBDev B, int m, float* y) {
+__global__ void bb_copy_y_kernel(BBDev B, float* y) {
+    const int m = B.state->m;
     for (int k = threadIdx.x; k < m; k += blockDim.x) y[k] = B.y[k];
 }
 
@@ -433,8 +285,8 @@ dvmat_status dvmat_bb_add_aperture(dvmat_bb b, int32_t cp, const int32_t* dL, co
 dvmat_status dvmat_bb_set_boxes(dvmat_bb b, const float* lo_cp, const float* hi_cp, dvmat_stream stream) {
     if (!b || !lo_cp || !hi_cp) return set_error(DVMAT_E_ARG, "dvmat_bb_set_boxes: NULL argument");
     if (b->m == 0) return DVMAT_OK;
-    hipLaunchKernelGGL(bb_set_boxes_kernel, dim3((unsigned)((b->m + 255) / 256)), dim3(256), 0,
-                       reinterpret_cast<hipStream_t>(stream), b->dev, b->m, lo_cp, hi_cp);
+    hipLaunchKernelGGL(bb_set_boxes_kernel, dim3((unsigned)((b->max_ap + 255) / 256)), dim3(256), 0,
+                       reinterpret_cast<hipStream_t>(stream), b->dev, lo_cp, hi_cp);
     return check_hip(hipGetLastError(), "dvmat_bb_set_boxes launch");
 }
 
@@ -454,8 +306,8 @@ static dvmat_status bb_direction_impl(dvmat_bb b, const float* p, const float* G
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const dvmat_geom& g = b->geom;
     const int64_t n_bl = (int64_t)g.n_cp * g.n_rows * g.n_cols;
-    if (!G_ext) hipLaunchKernelGGL(bb_gather_kernel, dim3(b->m), dim3(256), 0, s, b->dev, g.n_rows, g.n_cols, p);
-    hipLaunchKernelGGL(bb_update_kernel, dim3(1), dim3(256), 0, s, b->dev, b->m, (int)MODE_DIRECTION,
+    if (!G_ext) hipLaunchKernelGGL(bb_gather_kernel, dim3(b->max_ap), dim3(256), 0, s, b->dev, g.n_rows, g.n_cols, p);
+    hipLaunchKernelGGL(bb_update_kernel, dim3(1), dim3(256), 0, s, b->dev, (int)MODE_DIRECTION,
                        (const float*)nullptr, (const double*)nullptr, (uint32_t*)nullptr, b->params, G_ext);
     hipLaunchKernelGGL(bb_expand_kernel, dim3(grid_for(n_bl)), dim3(256), 0, s, b->dev, g.n_rows, g.n_cols, n_bl,
                        (const float*)b->dev.Gt, x_dir);
@@ -469,8 +321,8 @@ static dvmat_status bb_step_impl(dvmat_bb b, const float* p, const float* G_ext,
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const dvmat_geom& g = b->geom;
     const int64_t n_bl = (int64_t)g.n_cp * g.n_rows * g.n_cols;
-    if (!G_ext) hipLaunchKernelGGL(bb_gather_kernel, dim3(b->m), dim3(256), 0, s, b->dev, g.n_rows, g.n_cols, p);
-    hipLaunchKernelGGL(bb_update_kernel, dim3(1), dim3(256), 0, s, b->dev, b->m, (int)MODE_STEP, F, curv, flags,
+    if (!G_ext) hipLaunchKernelGGL(bb_gather_kernel, dim3(b->max_ap), dim3(256), 0, s, b->dev, g.n_rows, g.n_cols, p);
+    hipLaunchKernelGGL(bb_update_kernel, dim3(1), dim3(256), 0, s, b->dev, (int)MODE_STEP, F, curv, flags,
                        b->params, G_ext);
     if (x_next)
         hipLaunchKernelGGL(bb_expand_kernel, dim3(grid_for(n_bl)), dim3(256), 0, s, b->dev, g.n_rows, g.n_cols, n_bl,
@@ -538,7 +390,7 @@ dvmat_status dvmat_aperture_gather(dvmat_geom geom, int32_t m, const int32_t* cp
 dvmat_status dvmat_bb_get_y(dvmat_bb b, float* y, dvmat_stream stream) {
     if (!b || !y) return set_error(DVMAT_E_ARG, "dvmat_bb_get_y: NULL argument");
     if (b->m == 0) return DVMAT_OK;
-    hipLaunchKernelGGL(bb_copy_y_kernel, dim3(1), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), b->dev, b->m, y);
+    hipLaunchKernelGGL(bb_copy_y_kernel, dim3(1), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), b->dev, y);
     return check_hip(hipGetLastError(), "dvmat_bb_get_y launch");
 }
 

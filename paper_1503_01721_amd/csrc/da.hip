@@ -12,7 +12,10 @@
 // chunk of voxels, forms z and dF/dz for it (columns streamed from HBM), keeps
 // dF/dz in LDS, then re-reads its chunk of every column (now in L2) to form
 // its share of each G_k; per-workgroup shares are summed in a fixed order.
-#include "common.hpp"
+// The column count is kept on the device too and the kernels read it there
+// (grids do not depend on it), so a captured graph of a solve replays as
+// columns are appended.
+#include "bb_device.hpp"
 
 #include <cmath>
 #include <new>
@@ -34,6 +37,8 @@ struct dvmat_da_s {
     float* partial = nullptr;    // [max_ap + 1][n_chunks]: G shares, then F shares
     double* partial_d = nullptr; // [n_chunks]
     float* gbuf = nullptr;       // [n_vox] dF/dz when the caller does not keep it
+    int32_t* d_m = nullptr;      // device copy of m, set by dvmat_da_append
+    uint32_t* arrived = nullptr; // workgroups done with a fused step (0 between launches)
 };
 
 namespace dvmat {
@@ -47,6 +52,8 @@ static size_t da_layout(int64_t n_vox, int32_t max_ap, dvmat_da_s* d, char* base
     p = take((size_t)(max_ap + 1) * chunks * 4);    if (d) d->partial = reinterpret_cast<float*>(p);
     p = take((size_t)chunks * 8);                   if (d) d->partial_d = reinterpret_cast<double*>(p);
     p = take((size_t)n_vox * 4);                    if (d) d->gbuf = reinterpret_cast<float*>(p);
+    p = take(sizeof(int32_t));                      if (d) d->d_m = reinterpret_cast<int32_t*>(p);
+    p = take(sizeof(uint32_t));                     if (d) d->arrived = reinterpret_cast<uint32_t*>(p);
     if (d) d->n_chunks = (int32_t)chunks;
     return off;
 }
@@ -62,11 +69,17 @@ __device__ __forceinline__ float block_sum(float v, float* red) {
     return s;
 }
 
-__global__ __launch_bounds__(kDaThreads) void da_eval_kernel(const float* __restrict__ cols, int64_t n_vox, int m,
-                                                             const float* __restrict__ y, const uint8_t* __restrict__ sid,
-                                                             const float* __restrict__ table, float* __restrict__ z,
-                                                             float* __restrict__ g, float* __restrict__ partial,
-                                                             int n_chunks) {
+__global__ void da_set_count_kernel(int32_t* d_m, int m, uint32_t* arrived) {
+    *d_m = m;
+    *arrived = 0u;
+}
+
+// One workgroup's chunk of the evaluation: z and dF/dz of its voxels (stored
+// where z, g are given), its shares of every G_k and of F into partial.
+__device__ __forceinline__ void da_eval_chunk(const float* __restrict__ cols, int64_t n_vox, int m,
+                                              const float* __restrict__ y, const uint8_t* __restrict__ sid,
+                                              const float* __restrict__ table, float* __restrict__ z,
+                                              float* __restrict__ g, float* __restrict__ partial, int n_chunks) {
     __shared__ float sy[1024];
     __shared__ float sg[kDaChunk];
     __shared__ float red[kDaThreads / 64];
@@ -87,7 +100,7 @@ __global__ __launch_bounds__(kDaThreads) void da_eval_kernel(const float* __rest
             gi = 2.0f * wo * over - 2.0f * wu * under;
             fpart += wo * over * over + wu * under * under;
             if (z) z[i] = zi;
-            g[i] = gi;
+            if (g) g[i] = gi;
         }
         sg[li] = gi;
     }
@@ -106,9 +119,19 @@ __global__ __launch_bounds__(kDaThreads) void da_eval_kernel(const float* __rest
     if (threadIdx.x == 0) partial[(int64_t)m * n_chunks + blockIdx.x] = fs;
 }
 
-// G[k] = sum of the chunk shares (k < m), F = sum of the F shares; fixed order, FP64.
-__global__ __launch_bounds__(256) void da_finalize_kernel(const float* __restrict__ partial, int m, int n_chunks,
-                                                          float* __restrict__ G, float* __restrict__ F) {
+__global__ __launch_bounds__(kDaThreads) void da_eval_kernel(const float* __restrict__ cols, int64_t n_vox,
+                                                             const int32_t* __restrict__ d_m,
+                                                             const float* __restrict__ y, const uint8_t* __restrict__ sid,
+                                                             const float* __restrict__ table, float* __restrict__ z,
+                                                             float* __restrict__ g, float* __restrict__ partial,
+                                                             int n_chunks) {
+    da_eval_chunk(cols, n_vox, *d_m, y, sid, table, z, g, partial, n_chunks);
+}
+
+// G[k] = sum of the chunk shares (k < m), F = sum of the F shares; fixed order,
+// FP64; one workgroup of 256 threads.
+__device__ __forceinline__ void da_finalize_block(const float* __restrict__ partial, int m, int n_chunks,
+                                                  float* __restrict__ G, float* __restrict__ F) {
     __shared__ double s[256];
     for (int k = 0; k <= m; ++k) {
         double a = 0.0;
@@ -127,7 +150,44 @@ __global__ __launch_bounds__(256) void da_finalize_kernel(const float* __restric
     }
 }
 
-__global__ __launch_bounds__(kDaThreads) void da_curv_kernel(const float* __restrict__ cols, int64_t n_vox, int m,
+__global__ __launch_bounds__(256) void da_finalize_kernel(const float* __restrict__ partial,
+                                                          const int32_t* __restrict__ d_m, int n_chunks,
+                                                          float* __restrict__ G, float* __restrict__ F) {
+    da_finalize_block(partial, *d_m, n_chunks, G, F);
+}
+
+// One BB iteration of the DA form in one launch: every workgroup evaluates its
+// chunk at the current rates (no z or dF/dz stored); the last workgroup to
+// finish (a device-scope counter; the acquire/release pair makes the other
+// workgroups' shares visible to it) sums the shares in the fixed order of
+// da_finalize_kernel and takes the BB step of bb_update_kernel, so the result
+// equals the three separate launches bit for bit.  It resets the counter for
+// the next launch.
+__global__ __launch_bounds__(kDaThreads) void da_bb_step_kernel(const float* __restrict__ cols, int64_t n_vox,
+                                                                const int32_t* __restrict__ d_m,
+                                                                const uint8_t* __restrict__ sid,
+                                                                const float* __restrict__ table,
+                                                                float* __restrict__ partial, int n_chunks,
+                                                                uint32_t* arrived, float* __restrict__ G,
+                                                                float* __restrict__ F, BBDev B, dvmat_bb_params prm,
+                                                                const double* curv, uint32_t* flags_out) {
+    __shared__ int s_last;
+    const int m = *d_m;
+    da_eval_chunk(cols, n_vox, m, B.y, sid, table, nullptr, nullptr, partial, n_chunks);
+    if (threadIdx.x == 0) {
+        const uint32_t before = __hip_atomic_fetch_add(arrived, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = before == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (threadIdx.x == 0) __hip_atomic_store(arrived, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    da_finalize_block(partial, m, n_chunks, G, F);
+    bb_update_block(B, MODE_STEP, F, curv, flags_out, prm, G);
+}
+
+__global__ __launch_bounds__(kDaThreads) void da_curv_kernel(const float* __restrict__ cols, int64_t n_vox,
+                                                             const int32_t* __restrict__ d_m,
                                                              const float* __restrict__ dirv,
                                                              const uint8_t* __restrict__ sid,
                                                              const float* __restrict__ table,
@@ -135,6 +195,7 @@ __global__ __launch_bounds__(kDaThreads) void da_curv_kernel(const float* __rest
                                                              double* __restrict__ partial_d) {
     __shared__ float sd[1024];
     __shared__ double red[kDaThreads / 64];
+    const int m = *d_m;
     const int64_t c0 = (int64_t)blockIdx.x * kDaChunk;
     for (int k = threadIdx.x; k < m; k += kDaThreads) sd[k] = dirv[k];
     __syncthreads();
@@ -220,6 +281,9 @@ dvmat_status dvmat_da_append(dvmat_da d, dvmat_ddc ddc, const float* x_ind, dvma
     if (info.n_vox != d->n_vox) return set_error(DVMAT_E_SHAPE, "dvmat_da_append: voxel count mismatch");
     st = dvmat_dose(ddc, x_ind, 1, d->cols + (int64_t)d->m * d->n_vox, nullptr, nullptr, nullptr, stream);
     if (st) return st;
+    hipLaunchKernelGGL(da_set_count_kernel, dim3(1), dim3(1), 0, reinterpret_cast<hipStream_t>(stream), d->d_m,
+                       d->m + 1, d->arrived);
+    if ((st = check_hip(hipGetLastError(), "dvmat_da_append launch"))) return st;
     d->m++;
     return DVMAT_OK;
 }
@@ -230,10 +294,23 @@ dvmat_status dvmat_da_eval(dvmat_da d, dvmat_obj obj, const float* y, float* z, 
     if (obj->n_vox != d->n_vox) return set_error(DVMAT_E_SHAPE, "dvmat_da_eval: voxel count mismatch");
     if (d->m == 0) return set_error(DVMAT_E_STATE, "dvmat_da_eval: no columns");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(da_eval_kernel, dim3(d->n_chunks), dim3(kDaThreads), 0, s, d->cols, d->n_vox, d->m, y,
+    hipLaunchKernelGGL(da_eval_kernel, dim3(d->n_chunks), dim3(kDaThreads), 0, s, d->cols, d->n_vox, d->d_m, y,
                        obj->sid, obj->table, z, g ? g : d->gbuf, d->partial, d->n_chunks);
-    hipLaunchKernelGGL(da_finalize_kernel, dim3(1), dim3(256), 0, s, d->partial, d->m, d->n_chunks, G, F);
+    hipLaunchKernelGGL(da_finalize_kernel, dim3(1), dim3(256), 0, s, d->partial, d->d_m, d->n_chunks, G, F);
     return check_hip(hipGetLastError(), "dvmat_da_eval launch");
+}
+
+dvmat_status dvmat_da_bb_step(dvmat_da d, dvmat_bb bb, dvmat_obj obj, float* G, float* F, const double* curv,
+                              uint32_t* flags, dvmat_stream stream) {
+    if (!d || !bb || !obj || !G || !F) return set_error(DVMAT_E_ARG, "dvmat_da_bb_step: NULL argument");
+    if (obj->n_vox != d->n_vox) return set_error(DVMAT_E_SHAPE, "dvmat_da_bb_step: voxel count mismatch");
+    if (d->m == 0) return set_error(DVMAT_E_STATE, "dvmat_da_bb_step: no columns");
+    if (bb->m != d->m)
+        return set_error(DVMAT_E_STATE, "dvmat_da_bb_step: %d apertures but %d columns", bb->m, d->m);
+    hipLaunchKernelGGL(da_bb_step_kernel, dim3(d->n_chunks), dim3(kDaThreads), 0, reinterpret_cast<hipStream_t>(stream),
+                       d->cols, d->n_vox, d->d_m, obj->sid, obj->table, d->partial, d->n_chunks, d->arrived, G, F,
+                       bb->dev, bb->params, curv, flags);
+    return check_hip(hipGetLastError(), "dvmat_da_bb_step launch");
 }
 
 dvmat_status dvmat_da_curvature(dvmat_da d, dvmat_obj obj, const float* dir, const float* z_ref, double* curv,
@@ -242,7 +319,7 @@ dvmat_status dvmat_da_curvature(dvmat_da d, dvmat_obj obj, const float* dir, con
     if (obj->n_vox != d->n_vox) return set_error(DVMAT_E_SHAPE, "dvmat_da_curvature: voxel count mismatch");
     if (d->m == 0) return set_error(DVMAT_E_STATE, "dvmat_da_curvature: no columns");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(da_curv_kernel, dim3(d->n_chunks), dim3(kDaThreads), 0, s, d->cols, d->n_vox, d->m, dir,
+    hipLaunchKernelGGL(da_curv_kernel, dim3(d->n_chunks), dim3(kDaThreads), 0, s, d->cols, d->n_vox, d->d_m, dir,
                        obj->sid, obj->table, z_ref, d->partial_d);
     hipLaunchKernelGGL(da_finalize_d_kernel, dim3(1), dim3(256), 0, s, d->partial_d, d->n_chunks, curv);
     return check_hip(hipGetLastError(), "dvmat_da_curvature launch");

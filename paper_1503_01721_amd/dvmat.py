@@ -149,6 +149,7 @@ _SIGNATURES = {
     "dvmat_da_append": (_I32, [_P, _P, _P, _P]),
     "dvmat_da_eval": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "dvmat_da_curvature": (_I32, [_P, _P, _P, _P, _P, _P]),
+    "dvmat_da_bb_step": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "dvmat_da_column": (_I32, [_P, _I32, ctypes.POINTER(_P)]),
     "dvmat_aperture_expand": (_I32, [Geom, _I32, _P, _P, _P, _P, _P, _P]),
     "dvmat_aperture_gather": (_I32, [Geom, _I32, _P, _P, _P, _P, _P, _P]),
@@ -397,7 +398,9 @@ class ApertureSelector:
     """Aperture selection over control points (preallocated outputs); with
     interdigitated=True the leaf rows obey the interdigitation constraint."""
 
-    def __init__(self, n_cp, n_rows, n_cols, device="cuda", interdigitated=False):
+    def __init__(self, n_cp, n_rows, n_cols, device="cuda", interdigitated=False, best=None, best_price=None):
+        """best, best_price: optional 1-element device tensors (int32, float32)
+        that receive the choice, e.g. views into a caller's status record."""
         self.geom = Geom(n_cp, n_rows, n_cols)
         dev = torch.device(device)
         self.interdigitated = interdigitated
@@ -409,8 +412,10 @@ class ApertureSelector:
         self.L = torch.empty((n_cp, n_rows), dtype=torch.int32, device=dev)
         self.R = torch.empty((n_cp, n_rows), dtype=torch.int32, device=dev)
         self.cp_price = torch.empty(n_cp, dtype=torch.float32, device=dev)
-        self.best = torch.empty(1, dtype=torch.int32, device=dev)
-        self.best_price = torch.empty(1, dtype=torch.float32, device=dev)
+        self.best = torch.empty(1, dtype=torch.int32, device=dev) if best is None else best
+        self.best_price = torch.empty(1, dtype=torch.float32, device=dev) if best_price is None else best_price
+        _need(self.best, 1, torch.int32, name="best")
+        _need(self.best_price, 1, name="best_price")
 
     def __call__(self, p, occupied=None, stream=None, windows=None):
         """windows: device int32 [n_cp, n_rows, 4] leaf windows (Lmin, Lmax, Rmin, Rmax) or None."""
@@ -500,6 +505,10 @@ class BB:
         self.flags = torch.zeros(1, dtype=torch.int32, device=self.device)
 
     @property
+    def handle(self):
+        return self._h
+
+    @property
     def count(self):
         return lib.dvmat_bb_count(self._h)
 
@@ -552,12 +561,12 @@ class BB:
                                  _stream(stream)))
 
     def direction_g_(self, G, x_dir, stream=None):
-        _need(G, self.count, name="G")
+        _need(G, self.count, name="G", at_least=True)
         _need(x_dir, self.n_bl, name="x_dir")
         _check(lib.dvmat_bb_direction_g(self._h, _ptr(G), _ptr(x_dir), _stream(stream)))
 
     def step_g_(self, G, F, curv, x_next, stream=None):
-        _need(G, self.count, name="G")
+        _need(G, self.count, name="G", at_least=True)
         _need(F, 1, name="F", at_least=True)
         _need(curv, 1, torch.float64, name="curv", at_least=True)
         _need(x_next, self.n_bl, name="x_next")
@@ -607,12 +616,21 @@ class DAColumns:
         """y, G: device pointers (c_void_p) or tensors of count floats."""
         yp = y if isinstance(y, ctypes.c_void_p) else _ptr(y)
         if not isinstance(y, ctypes.c_void_p):
-            _need(y, self.count, name="y")
-        _need(G, self.count, name="G")
+            _need(y, self.count, name="y", at_least=True)
+        _need(G, self.count, name="G", at_least=True)
         _need(z, self.n_vox, name="z")
         _need(g, self.n_vox, name="g")
         _need(F, 1, name="F", at_least=True)
         _check(lib.dvmat_da_eval(self._h, obj.handle, yp, _ptr(z), _ptr(g), _ptr(G), _ptr(F), _stream(stream)))
+
+    def bb_step_(self, bb, obj, G, F, curv, stream=None):
+        """One BB iteration on the columns in one launch (dvmat_da_bb_step):
+        G, F at bb's current rates, then its step; flags go to bb.flags."""
+        _need(G, self.count, name="G", at_least=True)
+        _need(F, 1, name="F", at_least=True)
+        _need(curv, 1, torch.float64, name="curv", at_least=True)
+        _check(lib.dvmat_da_bb_step(self._h, bb.handle, obj.handle, _ptr(G), _ptr(F), _ptr(curv), _ptr(bb.flags),
+                                    _stream(stream)))
 
     def curvature_(self, obj, direction, z_ref, curv, stream=None):
         dp = direction if isinstance(direction, ctypes.c_void_p) else _ptr(direction)

@@ -673,6 +673,34 @@ def test_column_generation_matches_oracle(dv, plan1, form, interdigitated, trave
         y = cg.bb.y().cpu().numpy().astype(np.float64)
 
 
+@pytest.mark.parametrize("form", ["D", "DA"])
+def test_captured_master_problem_replays_match_eager(dv, plan1, form):
+    """The master problem captured once in a HIP graph and replayed in every
+    later iteration (the aperture set grows between replays: the library reads
+    its size on the device) gives bit for bit the eager run's iterates, with
+    the selection, new apertures, DA columns and read-backs run eagerly
+    between the replays; the graph run reads back once per iteration."""
+    from paper_1503_01721_amd.colgen import ColumnGeneration
+    d, sid, table, ddc, obj = plan1
+    n_cp, n_rows, n_cols = PLAN1.n_cp, PLAN1.n_rows, PLAN1.n_cols
+    eager = ColumnGeneration(ddc, obj, n_cp, n_rows, n_cols, bb_steps=20, form=form)
+    graph = ColumnGeneration(ddc, obj, n_cp, n_rows, n_cols, bb_steps=20, form=form, graph=True)
+    eager.start()
+    graph.start()
+    for it in range(6):
+        a = eager.iteration()
+        b = graph.iteration(sync=False)
+        assert a is not None and b is not None
+        assert (a.cp, a.best_price) == (b.cp, b.best_price), it
+        ya, yb = eager.bb.y().cpu().numpy(), graph.bb.y().cpu().numpy()
+        assert np.array_equal(ya, yb), (it, ya, yb)
+    graph.finish()
+    assert len(graph._graphs) == 1
+    for a, b in zip(eager.records, graph.records):
+        assert (a.cp, a.best_price, a.F, a.flags) == (b.cp, b.best_price, b.F, b.flags)
+    assert np.array_equal(eager.p.cpu().numpy(), graph.p.cpu().numpy())
+
+
 # ---------------------------------------------------------------- precision forms
 
 def _bf16_round(a):
@@ -964,6 +992,63 @@ def test_da_columns_and_eval(dv, plan1):
     da.curvature_(obj, torch.tensor(dirv, device="cuda"), z, curv)
     c_ref = oobj.curvature(DA @ dirv.astype(np.float64), z.cpu().numpy().astype(np.float64), sid, table)
     assert abs(float(curv.cpu()[0]) - c_ref) <= 3e-5 * c_ref
+
+
+def test_fused_da_step_equals_evaluation_then_step(dv, plan1):
+    """dvmat_da_bb_step (evaluation and BB step in one launch, the last
+    workgroup summing the shares and stepping) gives the separate
+    dvmat_da_eval + dvmat_bb_step_g sequence bit for bit, step after step,
+    including after the solve stops (finite boxes bind) and when a later
+    aperture joins both sets."""
+    d, sid, table, ddc, obj = plan1
+    m = 5
+    cps, L, R = synth.random_apertures(PLAN1, m + 1, 58)
+    lo, hi = synth.random_boxes(m + 1, 59)
+    hi = hi * 60.0
+    runs = []
+    for fused in (False, True):
+        bb = dv.BB(PLAN1.n_cp, PLAN1.n_rows, PLAN1.n_cols, m + 1, max_iter=12, eps_f=1e-5, eps_step=1e-7)
+        da = dv.DAColumns(PLAN1.n_vox, m + 1)
+        G = torch.zeros(m + 1, device="cuda")
+        F = torch.zeros(1, device="cuda")
+        curv = torch.empty(1, dtype=torch.float64, device="cuda")
+        z = torch.empty(PLAN1.n_vox, device="cuda")
+        xd = torch.empty(PLAN1.n_bl, device="cuda")
+        trace = []
+
+        def add(k):
+            Ld, Rd = cuda(L[k]), cuda(R[k])
+            bb.add_aperture(int(cps[k]), Ld, Rd, float(lo[k]), float(hi[k]))
+            one = dv.Apertures(PLAN1.n_cp, PLAN1.n_rows, PLAN1.n_cols, cps[k:k + 1], L[k:k + 1], R[k:k + 1])
+            x_ind = torch.empty(PLAN1.n_bl, device="cuda")
+            one.expand_(torch.ones(1, device="cuda"), x_ind)
+            da.append_(ddc, x_ind)
+
+        for k in range(m):
+            add(k)
+        for solve in range(2):
+            y_ptr, gt_ptr = bb.state_ptrs()
+            bb.begin()
+            da.eval_(obj, y_ptr, G, z=z, F=F)
+            bb.direction_g_(G, xd)
+            da.curvature_(obj, gt_ptr, z, curv)
+            bb.step_g_(G, F, curv, None)
+            for t in range(14):
+                if fused:
+                    da.bb_step_(bb, obj, G, F, curv)
+                else:
+                    da.eval_(obj, y_ptr, G, F=F)
+                    bb.step_g_(G, F, curv, None)
+                trace.append((bb.y().cpu().numpy().copy(), G.cpu().numpy().copy(), F.cpu().numpy().copy(),
+                              int(bb.flags.cpu()[0])))
+            if solve == 0:
+                add(m)
+        runs.append(trace)
+    assert any(f & obb.STOP_MASK for *_, f in runs[0])
+    for t, (a, b) in enumerate(zip(*runs)):
+        for u, v in zip(a[:3], b[:3]):
+            assert np.array_equal(u, v), t
+        assert a[3] == b[3], t
 
 
 # ---------------------------------------------------------------- machine constraints (Eq. 2 -> Eq. 6 boxes)
