@@ -528,6 +528,17 @@ dvmat_status dvmat_da_create(int64_t n_vox, int32_t max_apertures, void* d_works
                              dvmat_da* out);
 void dvmat_da_destroy(dvmat_da da);
 int32_t dvmat_da_count(dvmat_da da);
+/* Keep only the rows of the objective's support in the columns: the voxels
+ * whose structure has a non-zero weight (w+ or w-), the only ones F and
+ * G = dF/dy depend on (dF/dz is zero elsewhere).  Call before the first
+ * dvmat_da_append (DVMAT_E_STATE after); obj must have n_vox voxels.  Once
+ * restricted, dvmat_da_eval writes z and dF/dz only at support voxels, leaving
+ * the caller's other entries unchanged (dF/dz is zero there; the dose there is
+ * not formed), and dvmat_da_column returns columns of *n_rows entries in the
+ * support's voxel order.  *n_rows (nullable) receives the support's size
+ * (n_vox if no voxel is weighted: nothing is restricted).  Set-up work: one
+ * workgroup scans the voxels, then the call synchronises the stream. */
+dvmat_status dvmat_da_set_support(dvmat_da da, dvmat_obj obj, int64_t* n_rows, dvmat_stream stream);
 /* Append DA = D x_ind for the next aperture: x_ind device float[n_bl], the
  * aperture's indicator fluence (e.g. dvmat_aperture_expand with rate 1).
  * DVMAT_E_STATE when max_apertures columns exist. */
@@ -551,7 +562,7 @@ dvmat_status dvmat_da_bb_step(dvmat_da da, dvmat_bb bb, dvmat_obj obj, float* G,
  * dir: device float[count]; curv: device double[1]. */
 dvmat_status dvmat_da_curvature(dvmat_da da, dvmat_obj obj, const float* dir, const float* z_ref,
                                 double* curv, dvmat_stream stream);
-/* Device pointer of column k (float[n_vox]). */
+/* Device pointer of column k (float[n_vox], or float[n_rows] of the support). */
 dvmat_status dvmat_da_column(dvmat_da da, int32_t k, const float** col);
 
 #ifdef __cplusplus

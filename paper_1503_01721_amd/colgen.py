@@ -102,7 +102,10 @@ class ColumnGeneration:
         self.F = self.status[2:3].view(torch.float32)
         self.curv = torch.empty(1, dtype=torch.float64, device=dev)
         if form == "DA":
-            self.da = dvmat.DAColumns(ddc.n_vox, self.max_apertures, device=dev)
+            # columns over the objective's support only; z and dF/dz elsewhere
+            # stay as start() leaves them (zero dose, zero gradient there when
+            # the matrix has no entries outside the structures)
+            self.da = dvmat.DAColumns(ddc.n_vox, self.max_apertures, device=dev, obj=obj)
             self.G = torch.empty(self.max_apertures, dtype=torch.float32, device=dev)
             self.one = torch.ones(1, dtype=torch.float32, device=dev)
             self.cp_dev = torch.empty(1, dtype=torch.int32, device=dev)

@@ -10,30 +10,46 @@
 //
 // dvmat_da_eval is one pass over the columns: a workgroup owns a contiguous
 // chunk of voxels, forms z and dF/dz for it (columns streamed from HBM), keeps
-// dF/dz in LDS, then re-reads its chunk of every column (now in L2) to form
-// its share of each G_k; per-workgroup shares are summed in a fixed order.
+// dF/dz in registers, then re-reads its chunk of every column (now in L2) to
+// form its share of each G_k (wave sums, no barrier per column);
+// per-workgroup shares are summed in a fixed order.
 // The column count is kept on the device too and the kernels read it there
 // (grids do not depend on it), so a captured graph of a solve replays as
 // columns are appended.
+//
+// Optionally (dvmat_da_set_support) the columns keep only the rows of the
+// objective's support, the voxels whose structure carries a weight: F and G
+// depend on nothing else (dF/dz is zero elsewhere), and outside the body,
+// over half of the full-scale cube, every column would hold zeros.
 #include "bb_device.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <new>
 
 namespace dvmat {
 
+// Four voxels per thread, 1024 per workgroup: eight workgroups per compute
+// unit, each thread with one load per voxel and column in flight.
 constexpr int kDaThreads = 256;
-constexpr int kDaPerThread = 16;
+constexpr int kDaWaves = kDaThreads / 64;
+constexpr int kDaPerThread = 4;
 constexpr int kDaChunk = kDaThreads * kDaPerThread;   // voxels per workgroup
 
 }  // namespace dvmat
 
 struct dvmat_da_s {
     int64_t n_vox = 0;
+    int64_t n_rows = 0;          // rows per column: n_vox, or the support's size
+    const int32_t* rows = nullptr;   // voxel of each row (support), or nullptr (identity)
+    const uint8_t* row_sid = nullptr;  // structure id of each row when restricted
+    int32_t* support = nullptr;  // [n_vox] workspace for the support's voxel list
+    uint8_t* csid = nullptr;     // [n_vox] workspace for its structure ids
+    int32_t* d_nsup = nullptr;   // device count of the support
     int32_t max_ap = 0;
     int32_t m = 0;
     int32_t n_chunks = 0;
-    float* cols = nullptr;       // [max_ap][n_vox]
+    float* cols = nullptr;       // [max_ap][n_rows]
     float* partial = nullptr;    // [max_ap + 1][n_chunks]: G shares, then F shares
     double* partial_d = nullptr; // [n_chunks]
     float* gbuf = nullptr;       // [n_vox] dF/dz when the caller does not keep it
@@ -54,20 +70,23 @@ static size_t da_layout(int64_t n_vox, int32_t max_ap, dvmat_da_s* d, char* base
     p = take((size_t)n_vox * 4);                    if (d) d->gbuf = reinterpret_cast<float*>(p);
     p = take(sizeof(int32_t));                      if (d) d->d_m = reinterpret_cast<int32_t*>(p);
     p = take(sizeof(uint32_t));                     if (d) d->arrived = reinterpret_cast<uint32_t*>(p);
+    p = take((size_t)n_vox * 4);                    if (d) d->support = reinterpret_cast<int32_t*>(p);
+    p = take((size_t)n_vox);                        if (d) d->csid = reinterpret_cast<uint8_t*>(p);
+    p = take(sizeof(int32_t));                      if (d) d->d_nsup = reinterpret_cast<int32_t*>(p);
     if (d) d->n_chunks = (int32_t)chunks;
     return off;
 }
 
-__device__ __forceinline__ float block_sum(float v, float* red) {
+// Sum over the 64 lanes of a wave in a fixed order, returned to every lane.
+template <typename T>
+__device__ __forceinline__ T wave_sum64(T v) {
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) red[wid] = v;
-    __syncthreads();
-    float s = 0.0f;
-    for (int w = 0; w < kDaThreads / 64; ++w) s += red[w];
-    return s;
+    return v;
 }
+
+// Dynamic LDS of the evaluation kernels: the rates (max_ap floats) and the
+// per-wave shares of every G_k and of F (kDaWaves x (max_ap + 1) floats).
+static size_t da_lds_bytes(int max_ap) { return ((size_t)max_ap + (size_t)kDaWaves * (max_ap + 1)) * sizeof(float); }
 
 __global__ void da_set_count_kernel(int32_t* d_m, int m, uint32_t* arrived) {
     *d_m = m;
@@ -76,78 +95,100 @@ __global__ void da_set_count_kernel(int32_t* d_m, int m, uint32_t* arrived) {
 
 // One workgroup's chunk of the evaluation: z and dF/dz of its voxels (stored
 // where z, g are given), its shares of every G_k and of F into partial.
-__device__ __forceinline__ void da_eval_chunk(const float* __restrict__ cols, int64_t n_vox, int m,
-                                              const float* __restrict__ y, const uint8_t* __restrict__ sid,
+// Rows are positions in the columns (n_rows of them); rows != nullptr maps a
+// row to its voxel for the stored z and dF/dz; rsid is the structure id of
+// each row.
+__device__ __forceinline__ void da_eval_chunk(const float* __restrict__ cols, int64_t n_rows, int m, int max_ap,
+                                              const float* __restrict__ y, const uint8_t* __restrict__ rsid,
+                                              const int32_t* __restrict__ rows,
                                               const float* __restrict__ table, float* __restrict__ z,
                                               float* __restrict__ g, float* __restrict__ partial, int n_chunks) {
-    __shared__ float sy[1024];
-    __shared__ float sg[kDaChunk];
-    __shared__ float red[kDaThreads / 64];
+    extern __shared__ float da_lds[];
+    float* sy = da_lds;                       // [max_ap]
+    float* wpart = da_lds + max_ap;           // [kDaWaves][max_ap + 1]
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int64_t c0 = (int64_t)blockIdx.x * kDaChunk;
     for (int k = threadIdx.x; k < m; k += kDaThreads) sy[k] = y[k];
     __syncthreads();
-    float fpart = 0.0f;
+    int64_t iv[kDaPerThread];
+    bool in[kDaPerThread];
+    float zi[kDaPerThread], gi[kDaPerThread];
+#pragma unroll
     for (int u = 0; u < kDaPerThread; ++u) {
-        const int li = u * kDaThreads + threadIdx.x;
-        const int64_t i = c0 + li;
-        float gi = 0.0f;
-        if (i < n_vox) {
-            float zi = 0.0f;
-            for (int k = 0; k < m; ++k) zi += cols[(int64_t)k * n_vox + i] * sy[k];
-            const int s = sid[i];
-            const float T = table[s * 4 + 0], wo = table[s * 4 + 1], wu = table[s * 4 + 2];
-            const float over = fmaxf(zi - T, 0.0f), under = fmaxf(T - zi, 0.0f);
-            gi = 2.0f * wo * over - 2.0f * wu * under;
-            fpart += wo * over * over + wu * under * under;
-            if (z) z[i] = zi;
-            if (g) g[i] = gi;
-        }
-        sg[li] = gi;
+        iv[u] = c0 + u * kDaThreads + threadIdx.x;
+        in[u] = iv[u] < n_rows;
+        zi[u] = 0.0f;
     }
-    // G_k shares: this chunk of every column (just streamed, so in L2)
+    // z_i = sum_k DA_k,i y_k in the order of k; the voxels of a thread load together
     for (int k = 0; k < m; ++k) {
-        float a = 0.0f;
-        for (int u = 0; u < kDaPerThread; ++u) {
-            const int li = u * kDaThreads + threadIdx.x;
-            const int64_t i = c0 + li;
-            if (i < n_vox) a += cols[(int64_t)k * n_vox + i] * sg[li];
-        }
-        const float s = block_sum(a, red);
-        if (threadIdx.x == 0) partial[(int64_t)k * n_chunks + blockIdx.x] = s;
+        const float yk = sy[k];
+        const float* ck = cols + (int64_t)k * n_rows;
+#pragma unroll
+        for (int u = 0; u < kDaPerThread; ++u)
+            if (in[u]) zi[u] += ck[iv[u]] * yk;
     }
-    const float fs = block_sum(fpart, red);
-    if (threadIdx.x == 0) partial[(int64_t)m * n_chunks + blockIdx.x] = fs;
+    float fpart = 0.0f;
+#pragma unroll
+    for (int u = 0; u < kDaPerThread; ++u) {
+        gi[u] = 0.0f;
+        if (in[u]) {
+            const int s = rsid[iv[u]];
+            const float T = table[s * 4 + 0], wo = table[s * 4 + 1], wu = table[s * 4 + 2];
+            const float over = fmaxf(zi[u] - T, 0.0f), under = fmaxf(T - zi[u], 0.0f);
+            gi[u] = 2.0f * wo * over - 2.0f * wu * under;
+            fpart += wo * over * over + wu * under * under;
+            const int64_t vox = rows ? (int64_t)rows[iv[u]] : iv[u];
+            if (z) z[vox] = zi[u];
+            if (g) g[vox] = gi[u];
+        }
+    }
+    // G_k shares: this chunk of every column (just streamed, so in L2), summed
+    // per wave, then over the waves in order
+    for (int k = 0; k < m; ++k) {
+        const float* ck = cols + (int64_t)k * n_rows;
+        float a = 0.0f;
+#pragma unroll
+        for (int u = 0; u < kDaPerThread; ++u)
+            if (in[u]) a += ck[iv[u]] * gi[u];
+        a = wave_sum64(a);
+        if (lane == 0) wpart[wid * (max_ap + 1) + k] = a;
+    }
+    fpart = wave_sum64(fpart);
+    if (lane == 0) wpart[wid * (max_ap + 1) + m] = fpart;
+    __syncthreads();
+    for (int k = threadIdx.x; k <= m; k += kDaThreads) {
+        float a = 0.0f;
+#pragma unroll
+        for (int w = 0; w < kDaWaves; ++w) a += wpart[w * (max_ap + 1) + k];
+        partial[(int64_t)k * n_chunks + blockIdx.x] = a;
+    }
 }
 
-__global__ __launch_bounds__(kDaThreads) void da_eval_kernel(const float* __restrict__ cols, int64_t n_vox,
+__global__ __launch_bounds__(kDaThreads) void da_eval_kernel(const float* __restrict__ cols, int64_t n_rows,
                                                              const int32_t* __restrict__ d_m,
-                                                             const float* __restrict__ y, const uint8_t* __restrict__ sid,
+                                                             const float* __restrict__ y, const uint8_t* __restrict__ rsid,
+                                                             const int32_t* __restrict__ rows,
                                                              const float* __restrict__ table, float* __restrict__ z,
                                                              float* __restrict__ g, float* __restrict__ partial,
-                                                             int n_chunks) {
-    da_eval_chunk(cols, n_vox, *d_m, y, sid, table, z, g, partial, n_chunks);
+                                                             int n_chunks, int max_ap) {
+    da_eval_chunk(cols, n_rows, *d_m, max_ap, y, rsid, rows, table, z, g, partial, n_chunks);
 }
 
 // G[k] = sum of the chunk shares (k < m), F = sum of the F shares; fixed order,
-// FP64; one workgroup of 256 threads.
+// FP64; one workgroup of 256 threads, one wave per share vector.
 __device__ __forceinline__ void da_finalize_block(const float* __restrict__ partial, int m, int n_chunks,
                                                   float* __restrict__ G, float* __restrict__ F) {
-    __shared__ double s[256];
-    for (int k = 0; k <= m; ++k) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int k = wid; k <= m; k += kDaWaves) {
         double a = 0.0;
-        for (int c = threadIdx.x; c < n_chunks; c += 256) a += (double)partial[(int64_t)k * n_chunks + c];
-        s[threadIdx.x] = a;
-        __syncthreads();
-        for (int o = 128; o >= 1; o >>= 1) {
-            if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
-            __syncthreads();
+        for (int c = lane; c < n_chunks; c += 64) a += (double)partial[(int64_t)k * n_chunks + c];
+        a = wave_sum64(a);
+        if (lane == 0) {
+            if (k < m) G[k] = (float)a;
+            else if (F) F[0] = (float)a;
         }
-        if (threadIdx.x == 0) {
-            if (k < m) G[k] = (float)s[0];
-            else if (F) F[0] = (float)s[0];
-        }
-        __syncthreads();
     }
+    __syncthreads();
 }
 
 __global__ __launch_bounds__(256) void da_finalize_kernel(const float* __restrict__ partial,
@@ -163,17 +204,17 @@ __global__ __launch_bounds__(256) void da_finalize_kernel(const float* __restric
 // da_finalize_kernel and takes the BB step of bb_update_kernel, so the result
 // equals the three separate launches bit for bit.  It resets the counter for
 // the next launch.
-__global__ __launch_bounds__(kDaThreads) void da_bb_step_kernel(const float* __restrict__ cols, int64_t n_vox,
+__global__ __launch_bounds__(kDaThreads) void da_bb_step_kernel(const float* __restrict__ cols, int64_t n_rows,
                                                                 const int32_t* __restrict__ d_m,
-                                                                const uint8_t* __restrict__ sid,
+                                                                const uint8_t* __restrict__ rsid,
                                                                 const float* __restrict__ table,
                                                                 float* __restrict__ partial, int n_chunks,
                                                                 uint32_t* arrived, float* __restrict__ G,
                                                                 float* __restrict__ F, BBDev B, dvmat_bb_params prm,
-                                                                const double* curv, uint32_t* flags_out) {
+                                                                const double* curv, uint32_t* flags_out, int max_ap) {
     __shared__ int s_last;
     const int m = *d_m;
-    da_eval_chunk(cols, n_vox, m, B.y, sid, table, nullptr, nullptr, partial, n_chunks);
+    da_eval_chunk(cols, n_rows, m, max_ap, B.y, rsid, nullptr, table, nullptr, nullptr, partial, n_chunks);
     if (threadIdx.x == 0) {
         const uint32_t before = __hip_atomic_fetch_add(arrived, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         s_last = before == gridDim.x - 1;
@@ -186,10 +227,11 @@ __global__ __launch_bounds__(kDaThreads) void da_bb_step_kernel(const float* __r
     bb_update_block(B, MODE_STEP, F, curv, flags_out, prm, G);
 }
 
-__global__ __launch_bounds__(kDaThreads) void da_curv_kernel(const float* __restrict__ cols, int64_t n_vox,
+__global__ __launch_bounds__(kDaThreads) void da_curv_kernel(const float* __restrict__ cols, int64_t n_rows,
                                                              const int32_t* __restrict__ d_m,
                                                              const float* __restrict__ dirv,
-                                                             const uint8_t* __restrict__ sid,
+                                                             const uint8_t* __restrict__ rsid,
+                                                             const int32_t* __restrict__ rows,
                                                              const float* __restrict__ table,
                                                              const float* __restrict__ zref,
                                                              double* __restrict__ partial_d) {
@@ -202,12 +244,12 @@ __global__ __launch_bounds__(kDaThreads) void da_curv_kernel(const float* __rest
     double a = 0.0;
     for (int u = 0; u < kDaPerThread; ++u) {
         const int64_t i = c0 + u * kDaThreads + threadIdx.x;
-        if (i >= n_vox) continue;
+        if (i >= n_rows) continue;
         float di = 0.0f;
-        for (int k = 0; k < m; ++k) di += cols[(int64_t)k * n_vox + i] * sd[k];
-        const int s = sid[i];
+        for (int k = 0; k < m; ++k) di += cols[(int64_t)k * n_rows + i] * sd[k];
+        const int s = rsid[i];
         const float T = table[s * 4 + 0];
-        const float zr = zref[i];
+        const float zr = zref[rows ? (int64_t)rows[i] : i];
         const float w = zr > T ? table[s * 4 + 1] : (zr < T ? table[s * 4 + 2] : 0.0f);
         a += (double)w * (double)di * (double)di;
     }
@@ -233,6 +275,53 @@ __global__ __launch_bounds__(256) void da_finalize_d_kernel(const double* __rest
         __syncthreads();
     }
     if (threadIdx.x == 0) *out = s[0];
+}
+
+// The objective's support in voxel order, in one workgroup: each round of
+// 1024 voxels flags the weighted ones, a wave ballot and a scan of the wave
+// counts place them after the previous rounds'.  One-time set-up work.
+__global__ __launch_bounds__(1024) void da_support_kernel(int64_t n_vox, const uint8_t* __restrict__ sid,
+                                                          const float* __restrict__ table, int32_t* __restrict__ out,
+                                                          uint8_t* __restrict__ out_sid, int32_t* __restrict__ count) {
+    __shared__ int wave_count[16];
+    __shared__ int base;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (threadIdx.x == 0) base = 0;
+    __syncthreads();
+    for (int64_t r0 = 0; r0 < n_vox; r0 += 1024) {
+        const int64_t i = r0 + threadIdx.x;
+        int s = 0;
+        bool w = false;
+        if (i < n_vox) {
+            s = sid[i];
+            w = table[s * 4 + 1] != 0.0f || table[s * 4 + 2] != 0.0f;
+        }
+        const uint64_t mask = __ballot(w);
+        const int before = __popcll(mask & ((uint64_t(1) << lane) - 1));
+        if (lane == 0) wave_count[wid] = __popcll(mask);
+        __syncthreads();
+        int off = base;
+        for (int q = 0; q < wid; ++q) off += wave_count[q];
+        if (w) {
+            out[off + before] = (int32_t)i;
+            out_sid[off + before] = (uint8_t)s;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int t = 0;
+            for (int q = 0; q < 16; ++q) t += wave_count[q];
+            base += t;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = base;
+}
+
+// col[r] = full[rows[r]]: a dense column cut to the support.
+__global__ __launch_bounds__(256) void da_gather_rows_kernel(int64_t n_rows, const int32_t* __restrict__ rows,
+                                                             const float* __restrict__ full, float* __restrict__ col) {
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n_rows; r += (int64_t)gridDim.x * 256)
+        col[r] = full[rows[r]];
 }
 
 }  // namespace dvmat
@@ -262,9 +351,33 @@ dvmat_status dvmat_da_create(int64_t n_vox, int32_t max_ap, void* ws, size_t byt
     dvmat_da_s* d = new (std::nothrow) dvmat_da_s();
     if (!d) return set_error(DVMAT_E_NOMEM, "dvmat_da_create: host allocation failed");
     d->n_vox = n_vox;
+    d->n_rows = n_vox;
     d->max_ap = max_ap;
     da_layout(n_vox, max_ap, d, static_cast<char*>(ws));
     *out = d;
+    return DVMAT_OK;
+}
+
+dvmat_status dvmat_da_set_support(dvmat_da d, dvmat_obj obj, int64_t* n_rows, dvmat_stream stream) {
+    if (!d || !obj) return set_error(DVMAT_E_ARG, "dvmat_da_set_support: NULL argument");
+    if (obj->n_vox != d->n_vox) return set_error(DVMAT_E_SHAPE, "dvmat_da_set_support: voxel count mismatch");
+    if (d->m != 0) return set_error(DVMAT_E_STATE, "dvmat_da_set_support: %d columns exist already", d->m);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(da_support_kernel, dim3(1), dim3(1024), 0, s, d->n_vox, obj->sid, (const float*)obj->table,
+                       d->support, d->csid, d->d_nsup);
+    dvmat_status st = check_hip(hipGetLastError(), "dvmat_da_set_support launch");
+    if (st) return st;
+    int32_t n = 0;
+    if ((st = check_hip(hipMemcpyAsync(&n, d->d_nsup, sizeof(n), hipMemcpyDeviceToHost, s), "dvmat_da_set_support copy")))
+        return st;
+    if ((st = check_hip(hipStreamSynchronize(s), "dvmat_da_set_support synchronize"))) return st;
+    if (n > 0) {                               // no weighted voxel at all: keep every row
+        d->n_rows = n;
+        d->rows = d->support;
+        d->row_sid = d->csid;
+        d->n_chunks = (int32_t)((d->n_rows + kDaChunk - 1) / kDaChunk);
+    }
+    if (n_rows) *n_rows = d->n_rows;
     return DVMAT_OK;
 }
 
@@ -279,8 +392,14 @@ dvmat_status dvmat_da_append(dvmat_da d, dvmat_ddc ddc, const float* x_ind, dvma
     dvmat_status st = dvmat_ddc_info(ddc, &info);
     if (st) return st;
     if (info.n_vox != d->n_vox) return set_error(DVMAT_E_SHAPE, "dvmat_da_append: voxel count mismatch");
-    st = dvmat_dose(ddc, x_ind, 1, d->cols + (int64_t)d->m * d->n_vox, nullptr, nullptr, nullptr, stream);
+    float* col = d->cols + (int64_t)d->m * d->n_rows;
+    st = dvmat_dose(ddc, x_ind, 1, d->rows ? d->gbuf : col, nullptr, nullptr, nullptr, stream);
     if (st) return st;
+    if (d->rows) {
+        const int64_t nb = std::min<int64_t>((d->n_rows + 255) / 256, 4096);
+        hipLaunchKernelGGL(da_gather_rows_kernel, dim3((unsigned)std::max<int64_t>(nb, 1)), dim3(256), 0,
+                           reinterpret_cast<hipStream_t>(stream), d->n_rows, d->rows, (const float*)d->gbuf, col);
+    }
     hipLaunchKernelGGL(da_set_count_kernel, dim3(1), dim3(1), 0, reinterpret_cast<hipStream_t>(stream), d->d_m,
                        d->m + 1, d->arrived);
     if ((st = check_hip(hipGetLastError(), "dvmat_da_append launch"))) return st;
@@ -294,8 +413,9 @@ dvmat_status dvmat_da_eval(dvmat_da d, dvmat_obj obj, const float* y, float* z, 
     if (obj->n_vox != d->n_vox) return set_error(DVMAT_E_SHAPE, "dvmat_da_eval: voxel count mismatch");
     if (d->m == 0) return set_error(DVMAT_E_STATE, "dvmat_da_eval: no columns");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(da_eval_kernel, dim3(d->n_chunks), dim3(kDaThreads), 0, s, d->cols, d->n_vox, d->d_m, y,
-                       obj->sid, obj->table, z, g ? g : d->gbuf, d->partial, d->n_chunks);
+    hipLaunchKernelGGL(da_eval_kernel, dim3(d->n_chunks), dim3(kDaThreads), da_lds_bytes(d->max_ap), s, d->cols,
+                       d->n_rows, d->d_m, y, d->rows ? d->row_sid : obj->sid, d->rows, obj->table, z,
+                       g ? g : d->gbuf, d->partial, d->n_chunks, d->max_ap);
     hipLaunchKernelGGL(da_finalize_kernel, dim3(1), dim3(256), 0, s, d->partial, d->d_m, d->n_chunks, G, F);
     return check_hip(hipGetLastError(), "dvmat_da_eval launch");
 }
@@ -307,9 +427,10 @@ dvmat_status dvmat_da_bb_step(dvmat_da d, dvmat_bb bb, dvmat_obj obj, float* G, 
     if (d->m == 0) return set_error(DVMAT_E_STATE, "dvmat_da_bb_step: no columns");
     if (bb->m != d->m)
         return set_error(DVMAT_E_STATE, "dvmat_da_bb_step: %d apertures but %d columns", bb->m, d->m);
-    hipLaunchKernelGGL(da_bb_step_kernel, dim3(d->n_chunks), dim3(kDaThreads), 0, reinterpret_cast<hipStream_t>(stream),
-                       d->cols, d->n_vox, d->d_m, obj->sid, obj->table, d->partial, d->n_chunks, d->arrived, G, F,
-                       bb->dev, bb->params, curv, flags);
+    hipLaunchKernelGGL(da_bb_step_kernel, dim3(d->n_chunks), dim3(kDaThreads), da_lds_bytes(d->max_ap),
+                       reinterpret_cast<hipStream_t>(stream), d->cols, d->n_rows, d->d_m,
+                       d->rows ? d->row_sid : obj->sid, obj->table, d->partial, d->n_chunks, d->arrived, G, F,
+                       bb->dev, bb->params, curv, flags, d->max_ap);
     return check_hip(hipGetLastError(), "dvmat_da_bb_step launch");
 }
 
@@ -319,8 +440,8 @@ dvmat_status dvmat_da_curvature(dvmat_da d, dvmat_obj obj, const float* dir, con
     if (obj->n_vox != d->n_vox) return set_error(DVMAT_E_SHAPE, "dvmat_da_curvature: voxel count mismatch");
     if (d->m == 0) return set_error(DVMAT_E_STATE, "dvmat_da_curvature: no columns");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(da_curv_kernel, dim3(d->n_chunks), dim3(kDaThreads), 0, s, d->cols, d->n_vox, d->d_m, dir,
-                       obj->sid, obj->table, z_ref, d->partial_d);
+    hipLaunchKernelGGL(da_curv_kernel, dim3(d->n_chunks), dim3(kDaThreads), 0, s, d->cols, d->n_rows, d->d_m, dir,
+                       d->rows ? d->row_sid : obj->sid, d->rows, obj->table, z_ref, d->partial_d);
     hipLaunchKernelGGL(da_finalize_d_kernel, dim3(1), dim3(256), 0, s, d->partial_d, d->n_chunks, curv);
     return check_hip(hipGetLastError(), "dvmat_da_curvature launch");
 }
@@ -328,7 +449,7 @@ dvmat_status dvmat_da_curvature(dvmat_da d, dvmat_obj obj, const float* dir, con
 dvmat_status dvmat_da_column(dvmat_da d, int32_t k, const float** col) {
     if (!d || !col) return set_error(DVMAT_E_ARG, "dvmat_da_column: NULL argument");
     if (k < 0 || k >= d->m) return set_error(DVMAT_E_ARG, "dvmat_da_column: column %d of %d", k, d->m);
-    *col = d->cols + (int64_t)k * d->n_vox;
+    *col = d->cols + (int64_t)k * d->n_rows;
     return DVMAT_OK;
 }
 

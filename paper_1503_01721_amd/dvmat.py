@@ -150,6 +150,7 @@ _SIGNATURES = {
     "dvmat_da_eval": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "dvmat_da_curvature": (_I32, [_P, _P, _P, _P, _P, _P]),
     "dvmat_da_bb_step": (_I32, [_P, _P, _P, _P, _P, _P, _P, _P]),
+    "dvmat_da_set_support": (_I32, [_P, _P, ctypes.POINTER(_I64), _P]),
     "dvmat_da_column": (_I32, [_P, _I32, ctypes.POINTER(_P)]),
     "dvmat_aperture_expand": (_I32, [Geom, _I32, _P, _P, _P, _P, _P, _P]),
     "dvmat_aperture_gather": (_I32, [Geom, _I32, _P, _P, _P, _P, _P, _P]),
@@ -584,9 +585,11 @@ class BB:
 
 
 class DAColumns:
-    """Dense aperture dose vectors DA_k (Eq. 5) for the DA-form master problem."""
+    """Dense aperture dose vectors DA_k (Eq. 5) for the DA-form master problem.
+    With obj, the columns keep only the rows of the objective's support
+    (dvmat_da_set_support): eval then writes z and dF/dz at those voxels only."""
 
-    def __init__(self, n_vox, max_apertures, device="cuda"):
+    def __init__(self, n_vox, max_apertures, device="cuda", obj=None):
         self.n_vox = int(n_vox)
         nbytes = _SZ()
         _check(lib.dvmat_da_workspace_size(self.n_vox, int(max_apertures), ctypes.byref(nbytes)))
@@ -597,6 +600,13 @@ class DAColumns:
                                    ctypes.byref(h)))
         self._destroy = lib.dvmat_da_destroy     # bound now: module globals may be gone at exit
         self._h = h
+        self.n_rows = self.n_vox
+        if obj is not None:
+            if obj.n_vox != self.n_vox:
+                raise ValueError("objective and columns differ in voxel count")
+            n = _I64()
+            _check(lib.dvmat_da_set_support(h, obj.handle, ctypes.byref(n), _stream()))
+            self.n_rows = n.value
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -947,13 +947,20 @@ def test_panel_layout_kind_checks_and_batch(dv, plan1):
     assert info.dose_kernel == 3 and info.price_kernel == 3 and info.dose_tuned_ms > 0
 
 
-def test_da_columns_and_eval(dv, plan1):
+@pytest.mark.parametrize("support", [False, True])
+def test_da_columns_and_eval(dv, plan1, support):
     """DA-form pieces: the columns equal Eq. (5) and one evaluation gives the
-    oracle's z = sum_k DA_k y_k, F and G_k = <DA_k, dF/dz>."""
+    oracle's z = sum_k DA_k y_k, F and G_k = <DA_k, dF/dz>; with the columns
+    cut to the objective's support, the same at the support's voxels, and the
+    caller's other entries untouched."""
     d, sid, table, ddc, obj = plan1
     m = 6
     cps, L, R = synth.random_apertures(PLAN1, m, 55)
-    da = dv.DAColumns(PLAN1.n_vox, 8)
+    da = dv.DAColumns(PLAN1.n_vox, 8, obj=obj if support else None)
+    weighted = (table[sid][:, 1] != 0) | (table[sid][:, 2] != 0)
+    if support:
+        assert da.n_rows == int(weighted.sum()) < PLAN1.n_vox
+    on = weighted if support else np.ones(PLAN1.n_vox, bool)
     apset = obb.ApertureSet(PLAN1.n_cp, PLAN1.n_rows, PLAN1.n_cols)
     for k in range(m):
         one = dv.Apertures(PLAN1.n_cp, PLAN1.n_rows, PLAN1.n_cols, cps[k:k + 1], L[k:k + 1], R[k:k + 1])
@@ -965,21 +972,25 @@ def test_da_columns_and_eval(dv, plan1):
     DA = np.stack([oprod.aperture_ddc(d["row"], d["col"], d["val"], apset.owner == k, PLAN1.n_vox)
                    for k in range(m)], axis=1)
     # each column (Eq. 5), read back through an evaluation at a unit rate vector
-    z1 = torch.empty(PLAN1.n_vox, device="cuda")
+    z1 = torch.full((PLAN1.n_vox,), -7.0, device="cuda")
     Gk = torch.empty(m, device="cuda")
     for k in range(m):
         e = torch.zeros(m, device="cuda")
         e[k] = 1.0
         da.eval_(obj, e, Gk, z=z1)
-        assert np.abs(z1.cpu().numpy() - DA[:, k]).max() <= TOL * DA[:, k].max()
+        zk = z1.cpu().numpy()
+        assert np.abs(zk[on] - DA[on, k]).max() <= TOL * DA[:, k].max()
+        assert np.all(zk[~on] == -7.0)
     # evaluate at random rates
     y = np.random.default_rng(56).uniform(0.5, 4.0, m).astype(np.float32)
     G = torch.empty(m, device="cuda")
-    z = torch.empty(PLAN1.n_vox, device="cuda")
-    g = torch.empty(PLAN1.n_vox, device="cuda")
+    z = torch.zeros(PLAN1.n_vox, device="cuda")
+    g = torch.zeros(PLAN1.n_vox, device="cuda")
     F = torch.empty(1, device="cuda")
     da.eval_(obj, torch.tensor(y, device="cuda"), G, z=z, g=g, F=F)
     z_ref = DA @ y.astype(np.float64)
+    if support:                                   # the generator leaves no dose outside the body
+        assert np.all(z_ref[~on] == 0.0)
     assert np.abs(z.cpu().numpy() - z_ref).max() <= TOL * z_ref.max()
     F_ref = oobj.objective(z_ref, sid, table)
     assert abs(float(F.cpu()[0]) - F_ref) <= 1e-5 * F_ref
@@ -994,7 +1005,8 @@ def test_da_columns_and_eval(dv, plan1):
     assert abs(float(curv.cpu()[0]) - c_ref) <= 3e-5 * c_ref
 
 
-def test_fused_da_step_equals_evaluation_then_step(dv, plan1):
+@pytest.mark.parametrize("support", [False, True])
+def test_fused_da_step_equals_evaluation_then_step(dv, plan1, support):
     """dvmat_da_bb_step (evaluation and BB step in one launch, the last
     workgroup summing the shares and stepping) gives the separate
     dvmat_da_eval + dvmat_bb_step_g sequence bit for bit, step after step,
@@ -1008,7 +1020,7 @@ def test_fused_da_step_equals_evaluation_then_step(dv, plan1):
     runs = []
     for fused in (False, True):
         bb = dv.BB(PLAN1.n_cp, PLAN1.n_rows, PLAN1.n_cols, m + 1, max_iter=12, eps_f=1e-5, eps_step=1e-7)
-        da = dv.DAColumns(PLAN1.n_vox, m + 1)
+        da = dv.DAColumns(PLAN1.n_vox, m + 1, obj=obj if support else None)
         G = torch.zeros(m + 1, device="cuda")
         F = torch.zeros(1, device="cuda")
         curv = torch.empty(1, dtype=torch.float64, device="cuda")
