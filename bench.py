@@ -167,8 +167,10 @@ def bench_batched(args):
         # multi-vector panels pay where a slice serves many rows: the dose (a
         # voxel tile touches few beamlets); a beamlet row alone touches ~2000
         # voxels, so the price stays in CSR
-        layout = {} if args.layout == "csr" else dict(dose_block_rows=1, panel_cols=args.panel_cols,
-                                                       price_layout="csr", **p.grids)
+        layout = {} if args.layout == "csr" else dict(dose_block_rows=args.batch_dose_b, panel_cols=args.panel_cols,
+                                                       price_layout=args.batch_price_layout, **p.grids)
+        if args.batch_price_b:
+            layout["price_block_rows"] = args.batch_price_b
         ddcs.append(dvmat.DDC(d["row"], d["col"], d["val"], p.n_vox, p.n_bl, storage=storage, **layout))
         t_build += time.perf_counter() - t
         del d
@@ -232,7 +234,8 @@ def bench_batched(args):
         "ms_per_step": round(t_batched * 1e3, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": storage, "data": "synthetic",
         "config": {"workload": f"{len(plans)} uneven plans x {nrhs} right-hand sides", "nnz_total": int(nnz),
-                   "layout": args.layout if args.layout == "csr" else "panel (dose), csr (price)",
+                   "layout": args.layout if args.layout == "csr" else f"panel (dose), {args.batch_price_layout} (price)",
+                   "dose_block_rows": args.batch_dose_b,
                    "panel_cols": args.panel_cols,
                    "storage": storage, "nrhs": nrhs, "algorithmic_bytes_per_step": int(total),
                    "csr_equivalent_gbs": round(total_csr / t_batched / 1e9, 2),
@@ -519,6 +522,11 @@ def main():
     ap.add_argument("--slabs", default="balanced", choices=["balanced", "equal"],
                     help="voxel slabs of --mode shard: equal entry counts (default) or equal thickness")
     ap.add_argument("--plans", type=int, default=48, help="plans in --mode batched")
+    ap.add_argument("--batch-price-layout", default="csr", choices=["csr", "panel"],
+                    help="layout of the price orientation in --mode batched")
+    ap.add_argument("--batch-dose-b", type=int, default=1, help="rows per block row of the dose in --mode batched")
+    ap.add_argument("--batch-price-b", type=int, default=0,
+                    help="rows per block row of the price in --mode batched (0: the library's default)")
     ap.add_argument("--panel-cols", type=int, default=3584,
                     help="column budget of the dose panels in --mode batched (3584: 4 right-hand sides per launch)")
     ap.add_argument("--form", default="D", choices=["D", "DA"],
@@ -527,6 +535,9 @@ def main():
     ap.add_argument("--layout", default="panel", choices=["panel", "csr"],
                     help="device layout of both orientations: panels (vector slices staged in LDS, "
                          "default) or CSR (gathers from global memory)")
+    ap.add_argument("--tune", action="store_true",
+                    help="time the candidate layouts first and cache the fastest (DVMAT_TUNE_CACHE)")
+    ap.add_argument("--no-tuned-layout", action="store_true", help="ignore the tuner cache: library defaults")
     ap.add_argument("--no-graph", action="store_true",
                     help="DA form: launch the master problem's kernels one by one instead of replaying a captured graph")
     ap.add_argument("--copy-calibration", action="store_true", help=argparse.SUPPRESS)
@@ -542,7 +553,7 @@ def main():
         copy_calibration()
         return
 
-    from paper_1503_01721_amd import dvmat, synth
+    from paper_1503_01721_amd import dvmat, synth, tuner
     from paper_1503_01721_amd.colgen import ColumnGeneration
 
     if args.mode == "batched":
@@ -564,10 +575,27 @@ def main():
     t_gen = time.perf_counter() - t
     log(f"generated nnz={len(d['val'])} in {t_gen:.1f} s")
 
-    t = time.perf_counter()
-    layout = {} if args.layout == "csr" else plan.grids
-    ddc = dvmat.DDC(d["row"], d["col"], d["val"], plan.n_vox, plan.n_bl, storage=args.storage, **layout)
     obj = dvmat.Objective(sid, table)
+    layout = {} if args.layout == "csr" else dict(plan.grids)
+    layout_source = "csr" if args.layout == "csr" else "defaults"
+    if args.layout == "panel":
+        # the layout knobs (tiles, block rows, panel budget, part size) come from
+        # the tuner: its cache, or a tuning run now with --tune
+        sig = tuner.signature(plan.n_vox, plan.n_bl, len(d["val"]), args.storage, plan.grids, 1)
+        tuned = None
+        if args.tune:
+            tuned = tuner.tune(d["row"], d["col"], d["val"], plan.n_vox, plan.n_bl, args.storage, plan.grids, obj,
+                               log=log)
+        elif not args.no_tuned_layout:
+            tuned = tuner.layout_for(sig)
+        if tuned:
+            layout.update(tuned)
+            layout_source = "tuner"
+            log(f"layout from the tuner ({tuner.cache_path()}): {tuned}")
+        else:
+            log(f"no tuned layout for {sig}: library defaults")
+    t = time.perf_counter()
+    ddc = dvmat.DDC(d["row"], d["col"], d["val"], plan.n_vox, plan.n_bl, storage=args.storage, **layout)
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t
     info = ddc.info
@@ -575,7 +603,7 @@ def main():
     fixed = {"dose": args.dose_kernel, "price": args.price_kernel}
     if not args.no_autotune and not any(fixed.values()):
         t = time.perf_counter()
-        info = ddc.autotune(reps=5)
+        info = ddc.autotune(reps=5, obj=obj)
         log(f"autotuned in {time.perf_counter() - t:.1f} s: dose kernel {('row', 'stream', 'pipe', 'panel')[info.dose_kernel]} "
             f"x {info.dose_workgroups} wg ({info.dose_tuned_ms:.3f} ms), price kernel "
             f"{('row', 'stream', 'pipe', 'panel')[info.price_kernel]} x {info.price_workgroups} wg ({info.price_tuned_ms:.3f} ms)")
@@ -680,13 +708,15 @@ def main():
             "master_problem_form": args.form, "master_problem_graph": graph,
             "products_per_iteration": 2 * args.bb_steps + 1 if args.form == "D" else 2,
             "algorithmic_bytes_per_iteration": per_iter,
+            "algorithmic_bytes_per_launch": {"dose": ab["dose"], "price": ab["price"], "curvature": ab["curv"]},
             "index_bytes_per_nnz": {"dose": index_bytes(info, "dose"), "price": index_bytes(info, "price")},
             "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
             "csr_equivalent_gbs": round(value_csr, 2),
             "dose_gbs": round(ab["dose"] / mean_dose / 1e6, 1), "price_gbs": round(ab["price"] / mean_price / 1e6, 1),
             "mean_dose_call_ms": round(mean_dose, 4), "mean_price_call_ms": round(mean_price, 4),
             "generate_s": round(t_gen, 2), "build_upload_s": round(t_build, 2),
-            "layout": args.layout,
+            "layout": args.layout, "layout_source": layout_source,
+            "layout_options": {k: v for k, v in layout.items() if k not in ("dose_grid", "price_grid")},
             "dose_panels": int(info.dose_panels), "price_panels": int(info.price_panels),
             "dose_launch": {"kernel": ("row", "stream", "pipe", "panel")[info.dose_kernel], "workgroups": info.dose_workgroups},
             "price_launch": {"kernel": ("row", "stream", "pipe", "panel")[info.price_kernel], "workgroups": info.price_workgroups},

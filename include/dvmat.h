@@ -243,6 +243,13 @@ dvmat_status dvmat_price(dvmat_ddc ddc, const float* g, int32_t nrhs, float* p,
  * every shape (each shape's reductions have a fixed order). */
 dvmat_status dvmat_ddc_autotune(dvmat_ddc ddc, const float* x, float* z, const float* g, float* p,
                                 int32_t reps, dvmat_stream stream);
+/* As dvmat_ddc_autotune, with the products timed as the column-generation
+ * loop runs them: the dose with obj's objective epilogue (writing z, g = dF/dz
+ * and F) and the price of that g, nrhs right-hand sides.  x: device
+ * float[n_bl][nrhs]; z, g: float[n_vox][nrhs]; F: float[nrhs]; p:
+ * float[n_bl][nrhs] (z, g, F, p are overwritten). */
+dvmat_status dvmat_ddc_autotune_obj(dvmat_ddc ddc, dvmat_obj obj, const float* x, int32_t nrhs, float* z, float* g,
+                                    float* F, float* p, int32_t reps, dvmat_stream stream);
 /* Set the launch shape by hand: orientation 0 = dose, 1 = price; kind 0 =
  * row (one block row at a time), 1 = stream (a unit's entries as one range;
  * one row per block row only), 2 = pipe (row, with the next step's loads

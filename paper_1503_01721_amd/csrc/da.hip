@@ -35,6 +35,8 @@ constexpr int kDaThreads = 256;
 constexpr int kDaWaves = kDaThreads / 64;
 constexpr int kDaPerThread = 4;
 constexpr int kDaChunk = kDaThreads * kDaPerThread;   // voxels per workgroup
+constexpr int kDaGroup = 8;                            // columns whose loads go out together
+static_assert(kDaWaves == 4, "the share sums combine four waves");
 
 }  // namespace dvmat
 
@@ -119,8 +121,23 @@ __device__ __forceinline__ void da_eval_chunk(const float* __restrict__ cols, in
         in[u] = iv[u] < n_rows;
         zi[u] = 0.0f;
     }
-    // z_i = sum_k DA_k,i y_k in the order of k; the voxels of a thread load together
-    for (int k = 0; k < m; ++k) {
+    // z_i = sum_k DA_k,i y_k in the order of k; the loads of kDaGroup columns
+    // for all the thread's voxels are in flight together
+    int k = 0;
+    for (; k + kDaGroup <= m; k += kDaGroup) {
+        float c[kDaGroup][kDaPerThread];
+#pragma unroll
+        for (int j = 0; j < kDaGroup; ++j)
+#pragma unroll
+            for (int u = 0; u < kDaPerThread; ++u) c[j][u] = in[u] ? cols[(int64_t)(k + j) * n_rows + iv[u]] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < kDaGroup; ++j) {
+            const float yk = sy[k + j];
+#pragma unroll
+            for (int u = 0; u < kDaPerThread; ++u) zi[u] += c[j][u] * yk;
+        }
+    }
+    for (; k < m; ++k) {
         const float yk = sy[k];
         const float* ck = cols + (int64_t)k * n_rows;
 #pragma unroll
@@ -143,8 +160,24 @@ __device__ __forceinline__ void da_eval_chunk(const float* __restrict__ cols, in
         }
     }
     // G_k shares: this chunk of every column (just streamed, so in L2), summed
-    // per wave, then over the waves in order
-    for (int k = 0; k < m; ++k) {
+    // per wave, then over the waves in order; kDaGroup columns' loads at a time
+    for (k = 0; k + kDaGroup <= m; k += kDaGroup) {
+        float c[kDaGroup][kDaPerThread];
+#pragma unroll
+        for (int j = 0; j < kDaGroup; ++j)
+#pragma unroll
+            for (int u = 0; u < kDaPerThread; ++u) c[j][u] = in[u] ? cols[(int64_t)(k + j) * n_rows + iv[u]] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < kDaGroup; ++j) {
+            float a = 0.0f;
+#pragma unroll
+            for (int u = 0; u < kDaPerThread; ++u)
+                if (in[u]) a += c[j][u] * gi[u];
+            a = wave_sum64(a);
+            if (lane == 0) wpart[wid * (max_ap + 1) + k + j] = a;
+        }
+    }
+    for (; k < m; ++k) {
         const float* ck = cols + (int64_t)k * n_rows;
         float a = 0.0f;
 #pragma unroll
@@ -175,20 +208,49 @@ __global__ __launch_bounds__(kDaThreads) void da_eval_kernel(const float* __rest
 }
 
 // G[k] = sum of the chunk shares (k < m), F = sum of the F shares; fixed order,
-// FP64; one workgroup of 256 threads, one wave per share vector.
+// FP64; one workgroup of 256 threads takes kFinGroup share vectors at a time
+// with four chunks per thread per pass (16 loads in flight; the register
+// budget of the fused step, 64, bounds it), wave sums, then the four waves in
+// order.
+constexpr int kFinGroup = 4;
+
 __device__ __forceinline__ void da_finalize_block(const float* __restrict__ partial, int m, int n_chunks,
                                                   float* __restrict__ G, float* __restrict__ F) {
+    __shared__ double fin[kDaWaves][kFinGroup];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int k = wid; k <= m; k += kDaWaves) {
-        double a = 0.0;
-        for (int c = lane; c < n_chunks; c += 64) a += (double)partial[(int64_t)k * n_chunks + c];
-        a = wave_sum64(a);
-        if (lane == 0) {
-            if (k < m) G[k] = (float)a;
-            else if (F) F[0] = (float)a;
+    for (int k0 = 0; k0 <= m; k0 += kFinGroup) {
+        double a[kFinGroup];
+#pragma unroll
+        for (int j = 0; j < kFinGroup; ++j) a[j] = 0.0;
+        for (int c0 = threadIdx.x; c0 < n_chunks; c0 += 4 * kDaThreads) {
+            float v[4][kFinGroup];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int c = c0 + q * kDaThreads;
+#pragma unroll
+                for (int j = 0; j < kFinGroup; ++j)
+                    v[q][j] = (c < n_chunks && k0 + j <= m) ? partial[(int64_t)(k0 + j) * n_chunks + c] : 0.0f;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int j = 0; j < kFinGroup; ++j) a[j] += (double)v[q][j];
         }
+#pragma unroll
+        for (int j = 0; j < kFinGroup; ++j) a[j] = wave_sum64(a[j]);
+        if (lane == 0) {
+#pragma unroll
+            for (int j = 0; j < kFinGroup; ++j) fin[wid][j] = a[j];
+        }
+        __syncthreads();
+        const int kk = k0 + (int)threadIdx.x;
+        if ((int)threadIdx.x < kFinGroup && kk <= m) {
+            const double t = (fin[0][threadIdx.x] + fin[1][threadIdx.x]) + (fin[2][threadIdx.x] + fin[3][threadIdx.x]);
+            if (kk < m) G[kk] = (float)t;
+            else if (F) F[0] = (float)t;
+        }
+        __syncthreads();
     }
-    __syncthreads();
 }
 
 __global__ __launch_bounds__(256) void da_finalize_kernel(const float* __restrict__ partial,

@@ -290,7 +290,8 @@ static SpmvParams orientation_params(const CsrDev& c) {
 template <int EPI>
 static dvmat_status run_orientation(const dvmat_ddc_s* d, const CsrDev& c, const KernelCfg& cfg, SpmvParams P,
                                     const float* x, int nrhs, hipStream_t s, int* nwg) {
-    if (c.layout == 1) return launch_panel<EPI>(cfg, d->storage, c, P, x, nrhs, s, nwg);
+    // the price's long beamlet rows gain 2 % from XCD-contiguous parts; the dose lost 2 % with them
+    if (c.layout == 1) return launch_panel<EPI>(cfg, d->storage, c, P, x, nrhs, s, nwg, &c == &d->price);
     P.x = x;
     *nwg = clamp_workgroups(cfg.workgroups, P.n_blocks);
     if constexpr (EPI == EPI_CURV) launch_curv(cfg, d->storage, c.B, P, s);
@@ -313,6 +314,23 @@ static dvmat_status dose_plain(dvmat_ddc_s* d, const KernelCfg& cfg, const float
     P.y = z;
     int nwg = 0;
     return run_orientation<EPI_PLAIN>(d, d->dose, cfg, P, xin, nrhs, s, &nwg);
+}
+
+// Dose with the objective epilogue: z, dF/dz (g, nullable) and F (nullable).
+static dvmat_status dose_obj(dvmat_ddc_s* d, const KernelCfg& cfg, const float* x, int nrhs, float* z,
+                             const dvmat_obj_s* obj, float* g, float* F, hipStream_t s) {
+    const float* xin = dose_input(d, x, nrhs, s);
+    SpmvParams P = orientation_params(d->dose);
+    P.y = z;
+    P.sid = obj->sid;
+    P.table = obj->table;
+    P.g = g;
+    P.partial = obj->partial;
+    int nwg = 0;
+    dvmat_status st = run_orientation<EPI_OBJ>(d, d->dose, cfg, P, xin, nrhs, s, &nwg);
+    if (st) return st;
+    if (F) hipLaunchKernelGGL(finalize_f_kernel, dim3(1), dim3(256), 0, s, obj->partial, nwg, nrhs, F);
+    return check_hip(hipGetLastError(), "dose launch");
 }
 
 static dvmat_status price_any(dvmat_ddc_s* d, const KernelCfg& cfg, const float* g, int nrhs, float* p, hipStream_t s) {
@@ -521,18 +539,7 @@ dvmat_status dvmat_dose(dvmat_ddc d, const float* x, int32_t nrhs, float* z, dvm
                          (long long)obj->n_vox, (long long)d->n_vox);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (!obj) return dose_plain(d, d->dose_cfg, x, nrhs, z, s);
-    const float* xin = dose_input(d, x, nrhs, s);
-    SpmvParams P = orientation_params(d->dose);
-    P.y = z;
-    P.sid = obj->sid;
-    P.table = obj->table;
-    P.g = g;
-    P.partial = obj->partial;
-    int nwg = 0;
-    dvmat_status st2 = run_orientation<EPI_OBJ>(d, d->dose, d->dose_cfg, P, xin, nrhs, s, &nwg);
-    if (st2) return st2;
-    if (F) hipLaunchKernelGGL(finalize_f_kernel, dim3(1), dim3(256), 0, s, obj->partial, nwg, nrhs, F);
-    return check_hip(hipGetLastError(), "dvmat_dose launch");
+    return dose_obj(d, d->dose_cfg, x, nrhs, z, obj, g, F, s);
 }
 
 dvmat_status dvmat_price(dvmat_ddc d, const float* g, int32_t nrhs, float* p, dvmat_stream stream) {
@@ -580,6 +587,31 @@ dvmat_status dvmat_ddc_autotune(dvmat_ddc d, const float* x, float* z, const flo
     d->dose_tuned_ms = ms;
     st = tune([&](const KernelCfg& c) { return price_any(d, c, g, 1, p, s); }, reps, s, &best, &ms, d->price.B, true,
               d->price.layout == 1);
+    if (st) return st;
+    d->price_cfg = best;
+    d->price_tuned_ms = ms;
+    return DVMAT_OK;
+}
+
+dvmat_status dvmat_ddc_autotune_obj(dvmat_ddc d, dvmat_obj obj, const float* x, int32_t nrhs, float* z, float* g,
+                                    float* F, float* p, int32_t reps, dvmat_stream stream) {
+    dvmat_status st = check_ddc(d, "dvmat_ddc_autotune_obj");
+    if (st) return st;
+    if (!obj || !x || !z || !g || !F || !p) return set_error(DVMAT_E_ARG, "dvmat_ddc_autotune_obj: NULL argument");
+    if (obj->n_vox != d->n_vox) return set_error(DVMAT_E_SHAPE, "dvmat_ddc_autotune_obj: voxel count mismatch");
+    if (nrhs < 1 || nrhs > kMaxRhs) return set_error(DVMAT_E_ARG, "dvmat_ddc_autotune_obj: nrhs=%d not in 1..8", nrhs);
+    if (reps < 1) return set_error(DVMAT_E_ARG, "dvmat_ddc_autotune_obj: reps < 1");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    KernelCfg best{};
+    float ms = 0.0f;
+    st = tune([&](const KernelCfg& c) { return dose_obj(d, c, x, nrhs, z, obj, g, F, s); }, reps, s, &best, &ms,
+              d->dose.B, true, d->dose.layout == 1);
+    if (st) return st;
+    d->dose_cfg = best;
+    d->dose_tuned_ms = ms;
+    // the price of the gradient the dose just wrote, as the loop runs it
+    st = tune([&](const KernelCfg& c) { return price_any(d, c, g, nrhs, p, s); }, reps, s, &best, &ms, d->price.B,
+              true, d->price.layout == 1);
     if (st) return st;
     d->price_cfg = best;
     d->price_tuned_ms = ms;

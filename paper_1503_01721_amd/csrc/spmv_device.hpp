@@ -262,6 +262,9 @@ __device__ __forceinline__ void block_rows(const SpmvParams& P, int r0, int r1, 
     const int64_t base = P.rowptr[r0];
     const int64_t last = P.rowptr[r1];
     const int rel = (int)(P.rowptr[r0 + li] - base);
+    // end of each lane's block row (the next row's start; the unit's end for the last)
+    const int rel_dn = __shfl_down(rel, 1);
+    const int rel_end = lane + 1 < nbr ? rel_dn : (int)(last - base);
     // epilogue inputs: structure ids packed one byte per row, or floats; the
     // natural index of the block row's first row when its rows run consecutively
     int sid4 = 0;
@@ -282,9 +285,9 @@ __device__ __forceinline__ void block_rows(const SpmvParams& P, int r0, int r1, 
     for (int q = 0; q < (kLaneEpilogue ? B : 1); ++q)
 #pragma unroll
         for (int h = 0; h < (kLaneEpilogue ? NRHS : 1); ++h) mine[q][h] = 0.0f;
-    for (int i = 0; i < nbr; ++i) {
+    auto row = [&](int i) {
         const int64_t e0 = base + __builtin_amdgcn_readlane(rel, i);
-        const int64_t e1 = i + 1 < nbr ? base + __builtin_amdgcn_readlane(rel, i + 1) : last;
+        const int64_t e1 = base + __builtin_amdgcn_readlane(rel_end, i);
         float acc[B][NRHS];
 #pragma unroll
         for (int q = 0; q < B; ++q)
@@ -368,6 +371,18 @@ __device__ __forceinline__ void block_rows(const SpmvParams& P, int r0, int r1, 
                 }
             }
         }
+    };
+    if constexpr (kLaneEpilogue) {
+        // empty block rows (voxels no beamlet reaches) take no pass: their
+        // lanes keep zero sums, and the epilogue below writes them
+        uint64_t todo = __ballot(lane < nbr && rel_end > rel);
+        while (todo) {
+            const int i = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(todo));
+            todo &= todo - 1;
+            row(i);
+        }
+    } else {
+        for (int i = 0; i < nbr; ++i) row(i);
     }
     if constexpr (kLaneEpilogue) {
         // every lane finishes its own block row: coalesced stores, parallel epilogue
@@ -647,7 +662,7 @@ dvmat_status launch_batch_panel(int storage, int B, int epi_scale, bool scale_st
 // number of workgroups launched is returned in nwg (for the partial sums).
 template <int EPI>
 dvmat_status launch_panel(const KernelCfg& cfg, int storage, const CsrDev& c, const SpmvParams& P, const float* x,
-                          int nrhs, hipStream_t s, int* nwg);
+                          int nrhs, hipStream_t s, int* nwg, bool xcd_runs);
 
 // Wave position: workgroup w on XCD w % 8; the XCD's waves share its block range.
 struct WaveSlot {

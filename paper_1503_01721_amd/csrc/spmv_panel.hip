@@ -31,6 +31,7 @@ struct PanelParams {
     const int32_t* part_units;
     const int32_t* part_panel;
     int64_t n_parts;
+    int xcd_runs;               // 1: each XCD takes a contiguous eighth of the parts
 };
 
 // Eight waves share one LDS slice.  Slices up to 36 KB (the dose of the
@@ -90,7 +91,14 @@ __global__ __launch_bounds__(kPanelThreads) __attribute__((amdgpu_waves_per_eu(8
 #pragma unroll
     for (int h = 0; h < R; ++h) fpart[h] = 0.0f;
     double cpart = 0.0;
-    for (int64_t t = blockIdx.x; t < Q.n_parts; t += gridDim.x) {
+    // with xcd_runs, workgroup b (dispatched to XCD b % 8) walks that XCD's
+    // contiguous eighth of the parts: neighbouring panels share input columns
+    // in its L2
+    const int xcd = Q.xcd_runs ? (int)(blockIdx.x % kNumXcd) : 0;
+    const int64_t stride = Q.xcd_runs ? gridDim.x / kNumXcd : gridDim.x;
+    const int64_t t_end = Q.xcd_runs ? Q.n_parts * (xcd + 1) / kNumXcd : Q.n_parts;
+    const int64_t t_begin = Q.xcd_runs ? Q.n_parts * xcd / kNumXcd + blockIdx.x / kNumXcd : blockIdx.x;
+    for (int64_t t = t_begin; t < t_end; t += stride) {
         const int p = Q.part_panel[t];
         const int64_t u0 = Q.panel_u[p];
         const int nu = (int)(Q.panel_u[p + 1] - u0);
@@ -132,9 +140,11 @@ static void launch_chunk_r(int R, int B, int nwg, size_t lds, const SpmvParams& 
 
 template <int EPI>
 dvmat_status launch_panel(const KernelCfg& cfg, int storage, const CsrDev& c, const SpmvParams& P0, const float* x,
-                          int nrhs, hipStream_t s, int* nwg_out) {
+                          int nrhs, hipStream_t s, int* nwg_out, bool xcd_runs) {
     const int64_t want = std::max(1, cfg.workgroups);
-    const int nwg = (int)std::max<int64_t>(1, std::min<int64_t>(want, c.n_parts));
+    // XCD-contiguous parts need a grid of whole XCD rounds
+    const int nwg = xcd_runs ? (int)std::max<int64_t>(kNumXcd, std::min<int64_t>(want, c.n_parts) / kNumXcd * kNumXcd)
+                             : (int)std::max<int64_t>(1, std::min<int64_t>(want, c.n_parts));
     *nwg_out = nwg;
     if (c.n_parts == 0) return DVMAT_OK;
     const size_t per_rhs = (size_t)std::max<int64_t>(c.max_panel_cols, 1) * sizeof(float);
@@ -148,6 +158,7 @@ dvmat_status launch_panel(const KernelCfg& cfg, int storage, const CsrDev& c, co
     Q.part_units = c.part_units;
     Q.part_panel = c.part_panel;
     Q.n_parts = c.n_parts;
+    Q.xcd_runs = xcd_runs ? 1 : 0;
     for (int h0 = 0; h0 < nrhs;) {
         int R = 8;
         while (R > 1 && (R > nrhs - h0 || per_rhs * R > kPanelLdsBytes)) R >>= 1;
@@ -270,12 +281,12 @@ dvmat_status launch_batch_panel(int storage, int B, int epi_scale, bool scale_st
 }
 
 template dvmat_status launch_panel<EPI_PLAIN>(const KernelCfg&, int, const CsrDev&, const SpmvParams&, const float*,
-                                              int, hipStream_t, int*);
+                                              int, hipStream_t, int*, bool);
 template dvmat_status launch_panel<EPI_OBJ>(const KernelCfg&, int, const CsrDev&, const SpmvParams&, const float*, int,
-                                            hipStream_t, int*);
+                                            hipStream_t, int*, bool);
 template dvmat_status launch_panel<EPI_CURV>(const KernelCfg&, int, const CsrDev&, const SpmvParams&, const float*,
-                                             int, hipStream_t, int*);
+                                             int, hipStream_t, int*, bool);
 template dvmat_status launch_panel<EPI_SCALE>(const KernelCfg&, int, const CsrDev&, const SpmvParams&, const float*,
-                                              int, hipStream_t, int*);
+                                              int, hipStream_t, int*, bool);
 
 }  // namespace dvmat

@@ -112,6 +112,7 @@ _SIGNATURES = {
     "dvmat_price": (_I32, [_P, _P, _I32, _P, _P]),
     "dvmat_dose_curvature": (_I32, [_P, _P, _P, _P, _P, _P, _P]),
     "dvmat_ddc_autotune": (_I32, [_P, _P, _P, _P, _P, _I32, _P]),
+    "dvmat_ddc_autotune_obj": (_I32, [_P, _P, _P, _I32, _P, _P, _P, _P, _I32, _P]),
     "dvmat_ddc_set_kernel": (_I32, [_P, _I32, _I32, _I32]),
     "dvmat_batch_workspace_size": (_I32, [_I32, ctypes.POINTER(_SZ)]),
     "dvmat_batch_create": (_I32, [ctypes.POINTER(_P), _I32, _P, _SZ, _P, ctypes.POINTER(_P)]),
@@ -325,9 +326,24 @@ class DDC:
         _check(lib.dvmat_ddc_info(self._h, ctypes.byref(self.info)))
         return self.info
 
-    def autotune(self, reps=5, seed=0):
-        """Pick the fastest launch shape per orientation (times every candidate)."""
+    def autotune(self, reps=5, seed=0, obj=None, nrhs=1):
+        """Pick the fastest launch shape per orientation (times every candidate);
+        with obj, the dose is timed with its objective epilogue and the price
+        on the gradient it writes, nrhs right-hand sides."""
         gen = torch.Generator(device=self.device).manual_seed(seed)
+        if obj is not None:
+            if obj.n_vox != self.n_vox:
+                raise ValueError("objective and matrix differ in voxel count")
+            shape_x = (self.n_bl,) if nrhs == 1 else (self.n_bl, nrhs)
+            shape_z = (self.n_vox,) if nrhs == 1 else (self.n_vox, nrhs)
+            x = torch.rand(shape_x, device=self.device, generator=gen)
+            z = torch.empty(shape_z, device=self.device)
+            g = torch.empty(shape_z, device=self.device)
+            F = torch.empty(nrhs, device=self.device)
+            p = torch.empty(shape_x, device=self.device)
+            _check(lib.dvmat_ddc_autotune_obj(self._h, obj.handle, _ptr(x), int(nrhs), _ptr(z), _ptr(g), _ptr(F),
+                                              _ptr(p), int(reps), _stream()))
+            return self.refresh_info()
         x = torch.rand(self.n_bl, device=self.device, generator=gen)
         g = torch.randn(self.n_vox, device=self.device, generator=gen)
         z = torch.empty(self.n_vox, device=self.device)

@@ -97,7 +97,8 @@ def main():
                  f"WRITE_SIZE {cw:.1f} KiB -> write scale {ws:.3f}",
                  f"# FETCH_SIZE {fetch:.1f} KiB (mean of {n_f} launches), WRITE_SIZE {write:.1f} KiB (mean of {n_w})",
                  f"# read {rb / 1e9:.4f} GB + written {wb / 1e9:.4f} GB per launch; algorithmic "
-                 f"{a.algorithmic / 1e9:.4f} GB ({(rb + wb) / a.algorithmic:.3f} of it)",
+                 f"{a.algorithmic / 1e9:.4f} GB (the layout's own index width; traffic "
+                 f"{(rb + wb) / a.algorithmic:.3f} x the algorithmic bytes)",
                  f"products_source_sha256_16 = {products_source_sha()}",
                  f"hbm_read_bytes_per_launch = {rb:.0f}",
                  f"hbm_write_bytes_per_launch = {wb:.0f}",
