@@ -123,26 +123,22 @@ __device__ __forceinline__ void da_eval_chunk(const float* __restrict__ cols, in
     }
     // z_i = sum_k DA_k,i y_k in the order of k; the loads of kDaGroup columns
     // for all the thread's voxels are in flight together
-    int k = 0;
-    for (; k + kDaGroup <= m; k += kDaGroup) {
+    // (a last, partial group loads and adds only its columns below m)
+    for (int k = 0; k < m; k += kDaGroup) {
         float c[kDaGroup][kDaPerThread];
 #pragma unroll
         for (int j = 0; j < kDaGroup; ++j)
 #pragma unroll
-            for (int u = 0; u < kDaPerThread; ++u) c[j][u] = in[u] ? cols[(int64_t)(k + j) * n_rows + iv[u]] : 0.0f;
+            for (int u = 0; u < kDaPerThread; ++u)
+                c[j][u] = (in[u] && k + j < m) ? cols[(int64_t)(k + j) * n_rows + iv[u]] : 0.0f;
 #pragma unroll
         for (int j = 0; j < kDaGroup; ++j) {
-            const float yk = sy[k + j];
+            if (k + j < m) {
+                const float yk = sy[k + j];
 #pragma unroll
-            for (int u = 0; u < kDaPerThread; ++u) zi[u] += c[j][u] * yk;
+                for (int u = 0; u < kDaPerThread; ++u) zi[u] += c[j][u] * yk;
+            }
         }
-    }
-    for (; k < m; ++k) {
-        const float yk = sy[k];
-        const float* ck = cols + (int64_t)k * n_rows;
-#pragma unroll
-        for (int u = 0; u < kDaPerThread; ++u)
-            if (in[u]) zi[u] += ck[iv[u]] * yk;
     }
     float fpart = 0.0f;
 #pragma unroll
@@ -161,30 +157,24 @@ __device__ __forceinline__ void da_eval_chunk(const float* __restrict__ cols, in
     }
     // G_k shares: this chunk of every column (just streamed, so in L2), summed
     // per wave, then over the waves in order; kDaGroup columns' loads at a time
-    for (k = 0; k + kDaGroup <= m; k += kDaGroup) {
+    for (int k = 0; k < m; k += kDaGroup) {
         float c[kDaGroup][kDaPerThread];
 #pragma unroll
         for (int j = 0; j < kDaGroup; ++j)
 #pragma unroll
-            for (int u = 0; u < kDaPerThread; ++u) c[j][u] = in[u] ? cols[(int64_t)(k + j) * n_rows + iv[u]] : 0.0f;
+            for (int u = 0; u < kDaPerThread; ++u)
+                c[j][u] = (in[u] && k + j < m) ? cols[(int64_t)(k + j) * n_rows + iv[u]] : 0.0f;
 #pragma unroll
         for (int j = 0; j < kDaGroup; ++j) {
-            float a = 0.0f;
+            if (k + j < m) {
+                float a = 0.0f;
 #pragma unroll
-            for (int u = 0; u < kDaPerThread; ++u)
-                if (in[u]) a += c[j][u] * gi[u];
-            a = wave_sum64(a);
-            if (lane == 0) wpart[wid * (max_ap + 1) + k + j] = a;
+                for (int u = 0; u < kDaPerThread; ++u)
+                    if (in[u]) a += c[j][u] * gi[u];
+                a = wave_sum64(a);
+                if (lane == 0) wpart[wid * (max_ap + 1) + k + j] = a;
+            }
         }
-    }
-    for (; k < m; ++k) {
-        const float* ck = cols + (int64_t)k * n_rows;
-        float a = 0.0f;
-#pragma unroll
-        for (int u = 0; u < kDaPerThread; ++u)
-            if (in[u]) a += ck[iv[u]] * gi[u];
-        a = wave_sum64(a);
-        if (lane == 0) wpart[wid * (max_ap + 1) + k] = a;
     }
     fpart = wave_sum64(fpart);
     if (lane == 0) wpart[wid * (max_ap + 1) + m] = fpart;
