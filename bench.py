@@ -52,7 +52,22 @@ def index_bytes(info, orientation):
     overhead and not counted."""
     layout = info.dose_layout if orientation == "dose" else info.price_layout
     B = max(1, info.dose_block_rows if orientation == "dose" else info.price_block_rows)
-    return (2.0 if layout == 1 else 4.0) / B
+    return (2.0 if layout >= 1 else 4.0) / B
+
+
+LAYOUT_NAMES = {0: "csr", 1: "panel", 2: "sliced"}
+KERNEL_NAMES = {0: "spmv_kernel", 1: "spmv_panel_kernel", 2: "spmv_slice_kernel"}
+
+
+def grid_layout(args, grids):
+    """Build options of --layout: CSR, or the grids with the library's default
+    grid layout (sliced panels), or panels / sliced panels forced."""
+    if args.layout == "csr":
+        return {}
+    out = dict(grids)
+    if args.layout in ("panel", "sliced"):
+        out.update(dose_layout=args.layout, price_layout=args.layout)
+    return out
 
 
 def algorithmic_bytes(info, nrhs=1, csr_equivalent=False):
@@ -168,7 +183,8 @@ def bench_batched(args):
         # voxel tile touches few beamlets); a beamlet row alone touches ~2000
         # voxels, so the price stays in CSR
         layout = {} if args.layout == "csr" else dict(dose_block_rows=args.batch_dose_b, panel_cols=args.panel_cols,
-                                                       price_layout=args.batch_price_layout, **p.grids)
+                                                       dose_layout="panel", price_layout=args.batch_price_layout,
+                                                       **p.grids)
         if args.batch_price_b:
             layout["price_block_rows"] = args.batch_price_b
         ddcs.append(dvmat.DDC(d["row"], d["col"], d["val"], p.n_vox, p.n_bl, storage=storage, **layout))
@@ -262,7 +278,7 @@ def bench_autograd(args):
     t_gen = time.perf_counter() - t
     log(f"generated {plan.name}: nnz={len(d['val'])} in {t_gen:.1f} s")
     t = time.perf_counter()
-    layout = {} if args.layout == "csr" else plan.grids
+    layout = grid_layout(args, plan.grids)
     ddc = dvmat.DDC(d["row"], d["col"], d["val"], plan.n_vox, plan.n_bl, storage=storage, **layout)
     del d
     obj = dvmat.Objective(sid, table)
@@ -347,7 +363,7 @@ def bench_shard(args):
     t_gen = time.perf_counter() - t
     log(f"generated slab {s} of {G} (slices {z0}..{z1 - 1}) of {plan.name}: nnz={len(d['val'])} in {t_gen:.1f} s")
     t = time.perf_counter()
-    layout = {} if args.layout == "csr" else {"dose_grid": (N, N, z1 - z0), "price_grid": plan.grids["price_grid"]}
+    layout = grid_layout(args, {"dose_grid": (N, N, z1 - z0), "price_grid": plan.grids["price_grid"]})
     # a thin slab leaves each beamlet row a few hundred entries: two rows per
     # block row halve the reductions (partial price 0.560 against 0.666 ms)
     ddc = dvmat.DDC(d["row"], d["col"], d["val"], n_vox, plan.n_bl, storage=storage, price_block_rows=2, **layout)
@@ -442,7 +458,7 @@ def bench_truncation(args):
     sid_dev = torch.from_numpy(sid).cuda()
     ptv_ids = [k for k in range(synth.S_PTV0, len(table))]
     obj = dvmat.Objective(sid, table)
-    layout = {} if args.layout == "csr" else plan.grids
+    layout = grid_layout(args, plan.grids)
     iters = args.warmup + args.steps
     rows, full_ddc, ref_nnz = [], None, None
     for cone in cones:
@@ -532,9 +548,10 @@ def main():
     ap.add_argument("--form", default="D", choices=["D", "DA"],
                     help="master problem over the whole matrix (D, default: every BB iteration runs "
                          "a dose and a price product) or over the aperture dose vectors (DA)")
-    ap.add_argument("--layout", default="panel", choices=["panel", "csr"],
-                    help="device layout of both orientations: panels (vector slices staged in LDS, "
-                         "default) or CSR (gathers from global memory)")
+    ap.add_argument("--layout", default="grid", choices=["grid", "sliced", "panel", "csr"],
+                    help="device layout of both orientations: grid (default: the tuner's cached choice of "
+                         "panel layouts, else the library's default, sliced panels), sliced or panel forced "
+                         "(vector slices staged in LDS), or CSR (gathers from global memory)")
     ap.add_argument("--tune", action="store_true",
                     help="time the candidate layouts first and cache the fastest (DVMAT_TUNE_CACHE)")
     ap.add_argument("--no-tuned-layout", action="store_true", help="ignore the tuner cache: library defaults")
@@ -576,9 +593,9 @@ def main():
     log(f"generated nnz={len(d['val'])} in {t_gen:.1f} s")
 
     obj = dvmat.Objective(sid, table)
-    layout = {} if args.layout == "csr" else dict(plan.grids)
-    layout_source = "csr" if args.layout == "csr" else "defaults"
-    if args.layout == "panel":
+    layout = grid_layout(args, plan.grids)
+    layout_source = "csr" if args.layout == "csr" else "defaults" if args.layout == "grid" else "forced"
+    if args.layout == "grid":
         # the layout knobs (tiles, block rows, panel budget, part size) come from
         # the tuner: its cache, or a tuning run now with --tune
         sig = tuner.signature(plan.n_vox, plan.n_bl, len(d["val"]), args.storage, plan.grids, 1)
@@ -681,10 +698,11 @@ def main():
     achieved = ab[dom] / (dom_ms * 1e-3) / 1e9
     check_peak("dose kernel", ab["dose"] / mean_dose / 1e6)
     check_peak("price kernel", ab["price"] / mean_price / 1e6)
-    kfn = "spmv_panel_kernel" if args.layout == "panel" else "spmv_kernel"
-    kname = (f"{kfn} (price, D^T in the {args.layout} layout)" if dom == "price"
-             else f"{kfn} (dose, D in the {args.layout} layout, objective epilogue)")
-    traffic = read_traffic(dom, plan.name, args.storage, args.layout)
+    dom_layout = info.price_layout if dom == "price" else info.dose_layout
+    kfn = KERNEL_NAMES[dom_layout]
+    kname = (f"{kfn} (price, D^T in the {LAYOUT_NAMES[dom_layout]} layout)" if dom == "price"
+             else f"{kfn} (dose, D in the {LAYOUT_NAMES[dom_layout]} layout, objective epilogue)")
+    traffic = read_traffic(dom, plan.name, args.storage, LAYOUT_NAMES[dom_layout])
     log(f"mean dose call {mean_dose:.3f} ms ({ab['dose'] / mean_dose / 1e6:.0f} GB/s), "
         f"mean price call {mean_price:.3f} ms ({ab['price'] / mean_price / 1e6:.0f} GB/s)")
 
@@ -715,7 +733,8 @@ def main():
             "dose_gbs": round(ab["dose"] / mean_dose / 1e6, 1), "price_gbs": round(ab["price"] / mean_price / 1e6, 1),
             "mean_dose_call_ms": round(mean_dose, 4), "mean_price_call_ms": round(mean_price, 4),
             "generate_s": round(t_gen, 2), "build_upload_s": round(t_build, 2),
-            "layout": args.layout, "layout_source": layout_source,
+            "layout": {"dose": LAYOUT_NAMES[info.dose_layout], "price": LAYOUT_NAMES[info.price_layout]},
+            "layout_source": layout_source,
             "layout_options": {k: v for k, v in layout.items() if k not in ("dose_grid", "price_grid")},
             "dose_panels": int(info.dose_panels), "price_panels": int(info.price_panels),
             "dose_launch": {"kernel": ("row", "stream", "pipe", "panel")[info.dose_kernel], "workgroups": info.dose_workgroups},

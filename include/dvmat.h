@@ -85,11 +85,12 @@ typedef struct {
     float dose_tuned_ms, price_tuned_ms;    /* autotuner's best times (0 before tuning) */
     int32_t dose_block_rows, price_block_rows;  /* rows sharing one column index (build option) */
     int32_t dose_row_order, price_row_order;    /* row order of the layout (build option) */
-    int32_t dose_layout, price_layout;          /* 0 = CSR, 1 = panels (as built)           */
-    int64_t dose_panels, price_panels;          /* panels (layout 1), else 0                */
+    int32_t dose_layout, price_layout;          /* 0 = CSR, 1 = panels, 2 = sliced panels (as built) */
+    int64_t dose_panels, price_panels;          /* panels (layouts 1 and 2), else 0         */
     int64_t dose_panel_cols, price_panel_cols;  /* largest column list of a panel           */
     int64_t dose_panel_cols_total, price_panel_cols_total; /* sum of the panels' column lists */
     int64_t dose_panel_parts, price_panel_parts;  /* workgroup tasks: runs of a panel's units */
+    int32_t dose_slice_lanes, price_slice_lanes;  /* lanes per row of the sliced layout, else 0 */
 } dvmat_ddc_info_t;
 
 /* Build options of the device layout.  block_rows B in {1, 2, 4} (0: the
@@ -125,7 +126,20 @@ typedef struct {
  * orientation is built as CSR (dvmat_ddc_info reports the layout built).
  * part_entries: a workgroup takes one part of a panel at a time, a run of
  * the panel's work units holding up to this many stored values (each part
- * stages the whole panel slice), so large panels are shared out. */
+ * stages the whole panel slice), so large panels are shared out.
+ *
+ * layout 2 = sliced panels: the panels of layout 1 (one row per block row),
+ * each cut into parts of whole lines of rows (a line: the first extent of the
+ * tile, or one row without a grid) holding up to part_entries stored values;
+ * the rows of each part are sorted by length, longest first, and cut into
+ * slices of 64 / W rows (W = dose_slice_lanes or price_slice_lanes); a wave
+ * streams a slice with W lanes per row, all rows advancing together, four entries per lane and
+ * step, so short rows pay neither a reduction over the whole wave nor a
+ * partial step each.  Rows shorter than their slice's longest are padded
+ * with zeros to its step count.  Rows without entries form slices of up to
+ * 64 rows with no steps.  A slice is the work unit (n_blocks counts slices).
+ * W in {4, 8, 16} (0: the fastest measured, 8 but 4 for the dose at 16-bit
+ * storage); layout 2 needs block_rows 1 (0 resolves to 1). */
 typedef struct {
     int32_t dose_block_rows;
     int32_t price_block_rows;
@@ -138,6 +152,7 @@ typedef struct {
     int32_t dose_tile[3], price_tile[3];
     int32_t panel_cols;
     int32_t part_entries;
+    int32_t dose_slice_lanes, price_slice_lanes;
 } dvmat_build_opts;
 
 /* Fill opts with the defaults for a storage type (DVMAT_F32/F16/BF16): block
@@ -179,8 +194,10 @@ dvmat_status dvmat_ddc_info(dvmat_ddc ddc, dvmat_ddc_info_t* info);
  * rows), 4 = row at each stored position (int32; empty for natural order),
  * 5 = panel column lists (int32), 6 = panel offsets into them (int64), 7 =
  * first work unit of each panel (int32), 8 = first work unit of each part
- * (int32), 9 = panel of each part (int32).  *size receives the array's byte
- * size; dst (host, may be NULL to query) must hold cap >= *size bytes. */
+ * (int32), 9 = panel of each part (int32).  Sliced panels (layout 2): 0 =
+ * first entry of each slice (int64), 3 = first row position of each slice,
+ * 7 and 8 count slices.  *size receives the array's byte size; dst (host, may
+ * be NULL to query) must hold cap >= *size bytes. */
 dvmat_status dvmat_ddc_layout_array(dvmat_ddc ddc, int32_t orientation, int32_t which, void* dst, size_t cap,
                                     size_t* size);
 /* Copy the staged matrices into the caller's device workspace (>= info.
@@ -472,7 +489,8 @@ dvmat_status dvmat_bb_get_y(dvmat_bb bb, float* y, dvmat_stream stream);
  * very different sizes share the GPU without a launch per plan.  (The paper
  * suggests lending idle GPUs to another plan, Sec. 4; here the plans share
  * one GPU.)  All plans must be bound and share a storage type, the block
- * rows and, per orientation, the layout; n <= 64.  With panels the work list
+ * rows and, per orientation, the layout (CSR or panels; sliced panels are
+ * refused with DVMAT_E_ARG); n <= 64.  With panels the work list
  * is the plans' panel parts, each staging its panel's slice of the input
  * vectors in LDS; right-hand sides beyond what LDS holds go in chunks, one
  * launch each (plans built with panel_cols <= 3584 take 4 right-hand sides per

@@ -28,6 +28,8 @@ constexpr int kMaxRhs = 8;
 constexpr int kBlockRowsMax = 64;
 // Plans per batched launch (their vector pointers travel as kernel arguments).
 constexpr int kMaxBatch = 64;
+// Sliced panels: lanes per row (a slice holds 64 / W rows).
+inline bool slice_lanes_ok(int w) { return w == 4 || w == 8 || w == 16; }
 
 // Launch shape of one SpMV orientation: block kernel (Kind below) and
 // workgroup count.
@@ -69,6 +71,8 @@ struct CsrDev {
     int64_t n_parts = 0;
     const int32_t* part_units = nullptr;   // [n_parts + 1] first work unit of each part
     const int32_t* part_panel = nullptr;   // [n_parts] panel of each part
+    // sliced panels (layout 2): rowptr and blocks index slices, W lanes per row
+    int slice_lanes = 0;
 };
 
 // Host staging of one orientation before bind.
@@ -90,6 +94,8 @@ struct CsrHost {
     std::vector<int32_t> panel_units;
     std::vector<int32_t> part_units, part_panel;
     int64_t max_panel_cols = 0;
+    int slice_lanes = 0;
+    int slice_entries = 0;
 };
 
 }  // namespace dvmat

@@ -94,6 +94,8 @@ static uint16_t float_to_bf16_bits(float f) {
 struct OrientOpts {
     int layout = 0;
     int row_order = 0;
+    int slice_lanes = 4;
+    int slice_entries = 4;   // entries per lane and step: 16 bytes of values
     int32_t grid[3] = {0, 0, 0};
     int32_t tile[3] = {0, 0, 0};
 };
@@ -216,7 +218,7 @@ static dvmat_status order_rows(const SortedRows& sr, int64_t n_rows, int B, cons
     tile_of_pos.clear();
     const int64_t g0 = oo.grid[0], g1 = oo.grid[1], g2 = oo.grid[2];
     try {
-        if (oo.layout == 1 && (g0 | g1 | g2) != 0) {
+        if (oo.layout >= 1 && (g0 | g1 | g2) != 0) {
             if (g0 < 1 || g1 < 1 || g2 < 1 || g0 * g1 * g2 != n_rows)
                 return set_error(DVMAT_E_ARG, "row grid %lld x %lld x %lld does not match %lld rows", (long long)g0,
                                  (long long)g1, (long long)g2, (long long)n_rows);
@@ -274,7 +276,7 @@ static void cut_units(const CsrHost& out, int64_t b0, int64_t b1, int64_t unit_c
 // DVMAT_E_SHAPE (no error text) when a single block row has more than cap
 // columns: the caller then keeps the CSR layout.
 static dvmat_status build_panels(CsrHost& out, int64_t n_cols, const std::vector<int32_t>& tile_of_pos, int64_t cap,
-                                 int64_t unit_cap, int64_t part_cap) {
+                                 int64_t unit_cap, int64_t part_cap, std::vector<int64_t>& pstart) {
     const int64_t n_br = out.n_brows;
     const int B = out.B;
     auto tile_of_br = [&](int64_t br) -> int64_t { return tile_of_pos.empty() ? 0 : tile_of_pos[br * B]; };
@@ -337,7 +339,7 @@ static dvmat_status build_panels(CsrHost& out, int64_t n_cols, const std::vector
     seens.clear();
     phase("panel cuts");
     if (too_wide.load()) return DVMAT_E_SHAPE;
-    std::vector<int64_t> pstart;
+    pstart.clear();
     for (auto& v : cuts)
         for (int64_t x : v) pstart.push_back(x);
     pstart.push_back(n_br);
@@ -413,6 +415,153 @@ static dvmat_status build_panels(CsrHost& out, int64_t n_cols, const std::vector
     }
     out.layout = 1;
     phase("panel units");
+    return DVMAT_OK;
+}
+
+// Sliced panels (layout 2), from the panel layout with one row per block row
+// and no chunk interleave.  Each panel's rows, in their tile order, are first
+// cut into parts: runs of whole lines of line_rows rows holding up to
+// part_cap entries (a part is a workgroup's task, and the rows of one output
+// line then share a workgroup, so its stores meet in one L2).  Inside each
+// part the rows are sorted by length, longest first (stable), and cut into
+// slices of C = 64 / W rows; a wave runs a slice with W lanes per row, all
+// rows advancing together.  A slice of n_r
+// rows and S steps stores, for step t, row i and lane w of that row, four
+// entries at slice offset ((t*n_r + i)*W + w)*4 + q, q = 0..3: the row's sorted
+// entry 4Wt + qW + w, or a zero with local column 0 past the row's end.  One
+// 16-byte load per lane and step thus streams the slice, and each gather
+// instruction of a row's W lanes covers W consecutive sorted columns.  Rows
+// without entries close each part in slices of up to 64 rows and no steps.
+// Afterwards rowptr holds each slice's first entry (int64, n_slices + 1),
+// blocks each slice's first row position, perm the natural row of each
+// position, panel_units each panel's first slice, part_units each part's
+// first slice.  len_of_pos: entries of the row at each old position (before
+// the padding to a multiple of 4).
+static dvmat_status build_slices(CsrHost& out, std::vector<float>& fvalb, const std::vector<int64_t>& pstart,
+                                 const std::vector<int64_t>& len_of_pos, int W, int E, int64_t part_cap,
+                                 int64_t line_rows) {
+    const int C = kWaveSize / W;
+    const int64_t n_pan = (int64_t)pstart.size() - 1;
+    line_rows = std::max<int64_t>(line_rows, 1);
+    // per panel: rows in slice order, the slices' row counts and steps, and
+    // the first slice of each part (relative to the panel)
+    std::vector<std::vector<int64_t>> order(n_pan);
+    std::vector<std::vector<int32_t>> nrs(n_pan);
+    std::vector<std::vector<int64_t>> steps(n_pan);
+    std::vector<std::vector<int32_t>> part_first(n_pan);
+    parallel_for(n_pan, [&](int64_t a, int64_t b, int) {
+        for (int64_t p = a; p < b; ++p) {
+            std::vector<int64_t>& o = order[p];
+            o.resize(pstart[p + 1] - pstart[p]);
+            std::iota(o.begin(), o.end(), pstart[p]);
+            // parts: runs of whole lines up to part_cap entries (a line wider
+            // than the budget is a part of its own)
+            std::vector<size_t> cut{0};
+            int64_t acc = 0;
+            for (size_t l0 = 0; l0 < o.size(); l0 += line_rows) {
+                const size_t l1 = std::min(o.size(), l0 + (size_t)line_rows);
+                int64_t le = 0;
+                for (size_t r = l0; r < l1; ++r) le += len_of_pos[o[r]];
+                if (l0 > cut.back() && acc + le > part_cap) {
+                    cut.push_back(l0);
+                    acc = 0;
+                }
+                acc += le;
+            }
+            cut.push_back(o.size());
+            for (size_t g = 0; g + 1 < cut.size(); ++g) {
+                std::stable_sort(o.begin() + cut[g], o.begin() + cut[g + 1],
+                                 [&](int64_t x, int64_t y) { return len_of_pos[x] > len_of_pos[y]; });
+                part_first[p].push_back((int32_t)nrs[p].size());
+                size_t i = cut[g];
+                while (i < cut[g + 1]) {
+                    const int64_t lmax = len_of_pos[o[i]];
+                    const int cap_rows = lmax > 0 ? C : kWaveSize;
+                    size_t j = i;
+                    while (j < cut[g + 1] && (int64_t)(j - i) < cap_rows && (len_of_pos[o[j]] > 0) == (lmax > 0)) ++j;
+                    nrs[p].push_back((int32_t)(j - i));
+                    steps[p].push_back(((lmax + E - 1) / E + W - 1) / W);
+                    i = j;
+                }
+            }
+        }
+    });
+    // slice offsets
+    std::vector<int64_t> first_slice(n_pan + 1, 0);
+    for (int64_t p = 0; p < n_pan; ++p) first_slice[p + 1] = first_slice[p] + (int64_t)nrs[p].size();
+    const int64_t n_sl = first_slice[n_pan];
+    if (n_sl >= (int64_t(1) << 31)) return set_error(DVMAT_E_SHAPE, "too many slices");
+    std::vector<int64_t> rowptr(n_sl + 1, 0);
+    std::vector<int32_t> blocks(n_sl + 1, 0);
+    {
+        int64_t q = 0, e = 0, pos = 0;
+        for (int64_t p = 0; p < n_pan; ++p)
+            for (size_t k = 0; k < nrs[p].size(); ++k, ++q) {
+                rowptr[q] = e;
+                blocks[q] = (int32_t)pos;
+                e += steps[p][k] * nrs[p][k] * W * E;
+                pos += nrs[p][k];
+            }
+        rowptr[n_sl] = e;
+        blocks[n_sl] = (int32_t)pos;
+    }
+    const int64_t ne = rowptr[n_sl];
+    std::vector<uint16_t> col16(ne, 0);
+    std::vector<int32_t> col(ne, 0);
+    std::vector<float> val(ne, 0.0f);
+    std::vector<int32_t> perm(out.n_rows);
+    parallel_for(n_pan, [&](int64_t a, int64_t b, int) {
+        for (int64_t p = a; p < b; ++p) {
+            int64_t q = first_slice[p];
+            size_t r = 0;
+            for (size_t k = 0; k < nrs[p].size(); ++k, ++q) {
+                const int nr = nrs[p][k];
+                const int64_t S = steps[p][k];
+                for (int i = 0; i < nr; ++i, ++r) {
+                    const int64_t op = order[p][r];
+                    perm[blocks[q] + i] = out.perm.empty() ? (int32_t)op : out.perm[op];
+                    const int64_t s0 = out.rowptr[op], L = len_of_pos[op];
+                    const int32_t c0 = L > 0 ? out.col[s0] : 0;
+                    for (int64_t t = 0; t < S; ++t)
+                        for (int w = 0; w < W; ++w)
+                            for (int qq = 0; qq < E; ++qq) {
+                                const int64_t sidx = E * W * t + qq * W + w;
+                                const int64_t dst = rowptr[q] + ((t * nr + i) * W + w) * E + qq;
+                                if (sidx < L) {
+                                    col16[dst] = out.col16[s0 + sidx];
+                                    col[dst] = out.col[s0 + sidx];
+                                    val[dst] = fvalb[s0 + sidx];
+                                } else {
+                                    col[dst] = c0;      // a valid beamlet for the 16-bit scale; the value is zero
+                                }
+                            }
+                }
+            }
+        }
+    });
+    // parts as cut above (a panel without rows is one empty part)
+    out.part_units.assign(1, 0);
+    out.part_panel.clear();
+    for (int64_t p = 0; p < n_pan; ++p) {
+        for (size_t g = 1; g < part_first[p].size(); ++g) {
+            out.part_units.push_back((int32_t)(first_slice[p] + part_first[p][g]));
+            out.part_panel.push_back((int32_t)p);
+        }
+        out.part_units.push_back((int32_t)first_slice[p + 1]);
+        out.part_panel.push_back((int32_t)p);
+    }
+    out.panel_units.assign(first_slice.begin(), first_slice.end());
+    out.rowptr.swap(rowptr);
+    out.blocks.swap(blocks);
+    out.col16.swap(col16);
+    out.col.swap(col);
+    fvalb.swap(val);
+    out.perm.swap(perm);
+    out.perm_runs = 0;
+    out.slice_lanes = W;
+    out.slice_entries = E;
+    out.layout = 2;
+    phase("slices");
     return DVMAT_OK;
 }
 
@@ -492,7 +641,7 @@ static dvmat_status build_blocked(const SortedRows& sr, int64_t n_rows, int64_t 
                 }
                 const int32_t last = u > 0 ? c[u - 1] : 0;
                 for (int64_t k = u; k < e0 - s0; ++k) c[k] = last;      // padding: valid column, zero values
-                if (!interleave) continue;
+                if (!interleave || oo.layout == 2) continue;
                 const int64_t len = e0 - s0;
                 for (int64_t base = 0; base < len; base += 256) {
                     const int64_t n = std::min<int64_t>(256, len - base);
@@ -510,11 +659,22 @@ static dvmat_status build_blocked(const SortedRows& sr, int64_t n_rows, int64_t 
         phase("block rows");
         out.blocks.clear();
         out.blocks.push_back(0);
-        bool csr = oo.layout != 1;
+        bool csr = oo.layout == 0;
         if (!csr) {
-            const dvmat_status sp = build_panels(out, n_cols, tile_of_pos, panel_cols, unit_cap, part_cap);
+            std::vector<int64_t> pstart;
+            const dvmat_status sp = build_panels(out, n_cols, tile_of_pos, panel_cols, unit_cap, part_cap, pstart);
             if (sp == DVMAT_E_SHAPE) csr = true;             // a block row wider than the panel budget
             else if (sp) return sp;
+            if (!csr && oo.layout == 2) {
+                std::vector<int64_t> len_of_pos(n_rows);
+                for (int64_t p = 0; p < n_rows; ++p) len_of_pos[p] = sr.len[row_at(p)];
+                // an output line: the first extent of a tile (rows of a tile run
+                // in natural order, fastest axis first)
+                const int64_t line = (oo.grid[0] | oo.grid[1] | oo.grid[2]) != 0 ? oo.tile[0] : 1;
+                const dvmat_status ss =
+                    build_slices(out, fvalb, pstart, len_of_pos, oo.slice_lanes, oo.slice_entries, part_cap, line);
+                if (ss) return ss;
+            }
         }
         if (csr) {
             out.layout = 0;
@@ -537,7 +697,7 @@ static dvmat_status build_blocked(const SortedRows& sr, int64_t n_rows, int64_t 
 // the panel layout drops them afterwards.
 static void encode_values(CsrHost& h, const std::vector<float>& fvalb, int32_t storage,
                           const std::vector<float>& scale, bool beamlet_is_row) {
-    const int64_t ne = h.rowptr.empty() ? 0 : h.rowptr[h.n_brows];
+    const int64_t ne = h.rowptr.empty() ? 0 : h.rowptr.back();
     const int B = h.B;
     if (storage == DVMAT_F32) {
         h.val.resize(ne * B * 4);
@@ -546,6 +706,23 @@ static void encode_values(CsrHost& h, const std::vector<float>& fvalb, int32_t s
     }
     h.val.resize(ne * B * 2);
     uint16_t* q = reinterpret_cast<uint16_t*>(h.val.data());
+    auto enc = [&](float x) { return storage == DVMAT_F16 ? float_to_half_bits(x) : float_to_bf16_bits(x); };
+    if (h.layout == 2) {
+        // slices: entry k of slice u with n_r rows belongs to row (k / E / W) % n_r of the slice
+        const int W = h.slice_lanes, E = h.slice_entries;
+        const int64_t n_sl = (int64_t)h.blocks.size() - 1;
+        parallel_for(n_sl, [&](int64_t a, int64_t b, int) {
+            for (int64_t u = a; u < b; ++u) {
+                const int64_t nr = h.blocks[u + 1] - h.blocks[u];
+                for (int64_t k = h.rowptr[u]; k < h.rowptr[u + 1]; ++k) {
+                    const int64_t i = ((k - h.rowptr[u]) / E / W) % nr;
+                    const float s = scale[beamlet_is_row ? h.perm[h.blocks[u] + i] : h.col[k]];
+                    q[k] = enc(fvalb[k] / s);
+                }
+            }
+        });
+        return;
+    }
     parallel_for(h.n_brows, [&](int64_t a, int64_t b, int) {
         for (int64_t br = a; br < b; ++br)
             for (int64_t k = h.rowptr[br]; k < h.rowptr[br + 1]; ++k)
@@ -554,7 +731,7 @@ static void encode_values(CsrHost& h, const std::vector<float>& fvalb, int32_t s
                     const int64_t r = h.perm.empty() ? pos : h.perm[pos];
                     const float s = scale[beamlet_is_row ? r : h.col[k]];
                     const float x = fvalb[k * B + bb] / s;
-                    q[k * B + bb] = storage == DVMAT_F16 ? float_to_half_bits(x) : float_to_bf16_bits(x);
+                    q[k * B + bb] = enc(x);
                 }
     });
 }
@@ -588,6 +765,8 @@ dvmat_status dvmat_ddc_default_opts(int32_t storage, dvmat_build_opts* opts) {
     }
     opts->panel_cols = 12288;
     opts->part_entries = 131072;
+    opts->dose_slice_lanes = 0;
+    opts->price_slice_lanes = 0;
     if (const char* e = std::getenv("DVMAT_PANEL_COLS")) opts->panel_cols = std::atoi(e);
     if (const char* e = std::getenv("DVMAT_PART_ENTRIES")) opts->part_entries = std::atoi(e);
     if (const char* e = std::getenv("DVMAT_DOSE_ORDER")) opts->dose_row_order = std::atoi(e);
@@ -621,20 +800,30 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
     // smaller block rows win (dose B = 1 at 4-byte, 2 at 2-byte values).
     {
         const bool f32 = storage == DVMAT_F32;
-        if (o.dose_block_rows == 0) o.dose_block_rows = o.dose_layout == 1 ? (f32 ? 1 : 2) : (f32 ? 2 : 4);
-        if (o.price_block_rows == 0) o.price_block_rows = o.price_layout == 1 ? 1 : (f32 ? 1 : 2);
+        if (o.dose_block_rows == 0)
+            o.dose_block_rows = o.dose_layout == 2 ? 1 : o.dose_layout == 1 ? (f32 ? 1 : 2) : (f32 ? 2 : 4);
+        if (o.price_block_rows == 0) o.price_block_rows = o.price_layout >= 1 ? 1 : (f32 ? 1 : 2);
+        // sliced panels: 8 lanes per row, but 4 for the dose's 16-bit rows
+        // (eight entries per lane and step there)
+        if (o.dose_slice_lanes == 0) o.dose_slice_lanes = f32 ? 8 : 4;
+        if (o.price_slice_lanes == 0) o.price_slice_lanes = 8;
         // work units: on panels the gathers are cheap and each unit's start
         // (bounds, row pointers, epilogue inputs) is the cost to amortise
-        if (o.unit_entries == 0) o.unit_entries = (o.dose_layout == 1 || o.price_layout == 1) ? 8192 : 2048;
+        if (o.unit_entries == 0) o.unit_entries = (o.dose_layout >= 1 || o.price_layout >= 1) ? 8192 : 2048;
     }
     auto okB = [](int b) { return b == 1 || b == 2 || b == 4; };
     if (!okB(o.dose_block_rows) || !okB(o.price_block_rows) || (o.interleave != 0 && o.interleave != 1) ||
         o.unit_entries < 4 || o.unit_entries > (1 << 24) || (o.dose_row_order != 0 && o.dose_row_order != 1) ||
-        (o.price_row_order != 0 && o.price_row_order != 1) || (o.dose_layout != 0 && o.dose_layout != 1) ||
-        (o.price_layout != 0 && o.price_layout != 1) || o.panel_cols < 1 || o.panel_cols > 65536 ||
-        o.part_entries < 1)
-        return set_error(DVMAT_E_ARG, "dvmat_ddc_create: bad build options (block rows %d/%d, interleave %d, unit %d)",
-                         o.dose_block_rows, o.price_block_rows, o.interleave, o.unit_entries);
+        (o.price_row_order != 0 && o.price_row_order != 1) || o.dose_layout < 0 || o.dose_layout > 2 ||
+        o.price_layout < 0 || o.price_layout > 2 || o.panel_cols < 1 || o.panel_cols > 65536 ||
+        o.part_entries < 1 || !slice_lanes_ok(o.dose_slice_lanes) || !slice_lanes_ok(o.price_slice_lanes) ||
+        (o.dose_layout == 2 && o.dose_block_rows != 1) ||
+        (o.price_layout == 2 && o.price_block_rows != 1))
+        return set_error(DVMAT_E_ARG,
+                         "dvmat_ddc_create: bad build options (block rows %d/%d, interleave %d, unit %d, layouts %d/%d, "
+                         "slice lanes %d/%d)",
+                         o.dose_block_rows, o.price_block_rows, o.interleave, o.unit_entries, o.dose_layout,
+                         o.price_layout, o.dose_slice_lanes, o.price_slice_lanes);
     *out = nullptr;
     if (n_vox < 1 || n_vox >= (int64_t(1) << 31) || n_bl < 1 || n_bl >= (int64_t(1) << 31))
         return set_error(DVMAT_E_ARG, "dvmat_ddc_create: n_vox=%lld n_bl=%lld must be in [1, 2^31)",
@@ -682,8 +871,12 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
     OrientOpts dose_oo, price_oo;
     dose_oo.layout = o.dose_layout;
     dose_oo.row_order = o.dose_row_order;
+    dose_oo.slice_lanes = o.dose_slice_lanes;
+    dose_oo.slice_entries = storage == DVMAT_F32 ? 4 : 8;
     price_oo.layout = o.price_layout;
     price_oo.row_order = o.price_row_order;
+    price_oo.slice_lanes = o.price_slice_lanes;
+    price_oo.slice_entries = storage == DVMAT_F32 ? 4 : 8;
     for (int i = 0; i < 3; ++i) {
         dose_oo.grid[i] = o.dose_grid[i];
         dose_oo.tile[i] = o.dose_tile[i];
@@ -729,7 +922,7 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
         std::vector<float>().swap(sr.val);
         encode_values(d->host_dose, fvalb, storage, d->host_scale, false);
         phase("encode dose values");
-        if (d->host_dose.layout == 1) std::vector<int32_t>().swap(d->host_dose.col);
+        if (d->host_dose.layout >= 1) std::vector<int32_t>().swap(d->host_dose.col);
     }
     {
         // price orientation: rows = beamlets, columns = voxels
@@ -746,7 +939,7 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
         std::vector<float>().swap(sr.val);
         encode_values(d->host_price, fvalb, storage, d->host_scale, true);
         phase("encode price values");
-        if (d->host_price.layout == 1) std::vector<int32_t>().swap(d->host_price.col);
+        if (d->host_price.layout >= 1) std::vector<int32_t>().swap(d->host_price.col);
     }
 
     // device workspace layout
@@ -755,7 +948,7 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
     const CsrHost& hd = d->host_dose;
     const CsrHost& hp = d->host_price;
     d->off_dose_rowptr = take(hd.rowptr.size() * 8);
-    d->off_dose_col = take(hd.layout == 1 ? hd.col16.size() * 2 : hd.col.size() * 4);
+    d->off_dose_col = take(hd.layout >= 1 ? hd.col16.size() * 2 : hd.col.size() * 4);
     d->off_dose_val = take(hd.val.size());
     d->off_dose_blocks = take(hd.blocks.size() * 4);
     d->off_dose_perm = take(hd.perm.size() * 4);
@@ -765,7 +958,7 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
     d->off_dose_part_units = take(hd.part_units.size() * 4);
     d->off_dose_part_panel = take(hd.part_panel.size() * 4);
     d->off_price_rowptr = take(hp.rowptr.size() * 8);
-    d->off_price_col = take(hp.layout == 1 ? hp.col16.size() * 2 : hp.col.size() * 4);
+    d->off_price_col = take(hp.layout >= 1 ? hp.col16.size() * 2 : hp.col.size() * 4);
     d->off_price_val = take(hp.val.size());
     d->off_price_blocks = take(hp.blocks.size() * 4);
     d->off_price_perm = take(hp.perm.size() * 4);
@@ -781,23 +974,25 @@ dvmat_status dvmat_ddc_create_ex(int64_t n_vox, int64_t n_bl, int64_t nnz, const
     d->ws_bytes = std::max<size_t>(off, kAlign);
     d->dose.n_rows = n_vox;
     d->dose.B = hd.B;
-    d->dose.nnz_pad = (int64_t)(hd.layout == 1 ? hd.col16.size() : hd.col.size()) * hd.B;
+    d->dose.nnz_pad = (int64_t)(hd.layout >= 1 ? hd.col16.size() : hd.col.size()) * hd.B;
     d->dose.layout = hd.layout;
-    d->dose.n_panels = hd.layout == 1 ? (int64_t)hd.panel_u.size() - 1 : 0;
+    d->dose.slice_lanes = hd.slice_lanes;
+    d->dose.n_panels = hd.layout >= 1 ? (int64_t)hd.panel_u.size() - 1 : 0;
     d->dose.max_panel_cols = hd.max_panel_cols;
-    d->dose.n_parts = hd.layout == 1 ? (int64_t)hd.part_panel.size() : 0;
+    d->dose.n_parts = hd.layout >= 1 ? (int64_t)hd.part_panel.size() : 0;
     d->dose_panel_cols_total = hd.ulist.size();
     d->dose.n_blocks = (int64_t)hd.blocks.size() - 1;
     d->dose.nonempty = hd.nonempty;
     d->price.n_rows = n_bl;
     d->price.B = hp.B;
-    d->price.nnz_pad = (int64_t)(hp.layout == 1 ? hp.col16.size() : hp.col.size()) * hp.B;
+    d->price.nnz_pad = (int64_t)(hp.layout >= 1 ? hp.col16.size() : hp.col.size()) * hp.B;
     d->price.layout = hp.layout;
-    d->price.n_panels = hp.layout == 1 ? (int64_t)hp.panel_u.size() - 1 : 0;
-    if (hd.layout == 1) d->dose_cfg.kind = KIND_PANEL;
-    if (hp.layout == 1) d->price_cfg.kind = KIND_PANEL;
+    d->price.slice_lanes = hp.slice_lanes;
+    d->price.n_panels = hp.layout >= 1 ? (int64_t)hp.panel_u.size() - 1 : 0;
+    if (hd.layout >= 1) d->dose_cfg.kind = KIND_PANEL;
+    if (hp.layout >= 1) d->price_cfg.kind = KIND_PANEL;
     d->price.max_panel_cols = hp.max_panel_cols;
-    d->price.n_parts = hp.layout == 1 ? (int64_t)hp.part_panel.size() : 0;
+    d->price.n_parts = hp.layout >= 1 ? (int64_t)hp.part_panel.size() : 0;
     d->price_panel_cols_total = hp.ulist.size();
     d->price.n_blocks = (int64_t)hp.blocks.size() - 1;
     d->price.nonempty = hp.nonempty;
@@ -839,6 +1034,8 @@ dvmat_status dvmat_ddc_info(dvmat_ddc d, dvmat_ddc_info_t* info) {
     info->dose_panel_parts = d->dose.n_parts;
     info->price_panel_parts = d->price.n_parts;
     info->price_panel_cols_total = d->price_panel_cols_total;
+    info->dose_slice_lanes = d->dose.layout == 2 ? d->dose.slice_lanes : 0;
+    info->price_slice_lanes = d->price.layout == 2 ? d->price.slice_lanes : 0;
     return DVMAT_OK;
 }
 
@@ -859,7 +1056,7 @@ dvmat_status dvmat_ddc_bind(dvmat_ddc d, void* ws, size_t bytes, dvmat_stream st
     const CsrHost& hp = d->host_price;
     dvmat_status st = DVMAT_OK;
     if ((st = up(d->off_dose_rowptr, hd.rowptr.data(), hd.rowptr.size() * 8))) return st;
-    if (hd.layout == 1) {
+    if (hd.layout >= 1) {
         if ((st = up(d->off_dose_col, hd.col16.data(), hd.col16.size() * 2))) return st;
         if ((st = up(d->off_dose_ulist, hd.ulist.data(), hd.ulist.size() * 4))) return st;
         if ((st = up(d->off_dose_panel_u, hd.panel_u.data(), hd.panel_u.size() * 8))) return st;
@@ -873,7 +1070,7 @@ dvmat_status dvmat_ddc_bind(dvmat_ddc d, void* ws, size_t bytes, dvmat_stream st
     if ((st = up(d->off_dose_blocks, hd.blocks.data(), hd.blocks.size() * 4))) return st;
     if ((st = up(d->off_dose_perm, hd.perm.data(), hd.perm.size() * 4))) return st;
     if ((st = up(d->off_price_rowptr, hp.rowptr.data(), hp.rowptr.size() * 8))) return st;
-    if (hp.layout == 1) {
+    if (hp.layout >= 1) {
         if ((st = up(d->off_price_col, hp.col16.data(), hp.col16.size() * 2))) return st;
         if ((st = up(d->off_price_ulist, hp.ulist.data(), hp.ulist.size() * 4))) return st;
         if ((st = up(d->off_price_panel_u, hp.panel_u.data(), hp.panel_u.size() * 8))) return st;
@@ -890,8 +1087,8 @@ dvmat_status dvmat_ddc_bind(dvmat_ddc d, void* ws, size_t bytes, dvmat_stream st
         if ((st = up(d->off_scale, d->host_scale.data(), d->host_scale.size() * 4))) return st;
     if ((st = check_hip(hipStreamSynchronize(s), "dvmat_ddc_bind: synchronize"))) return st;
     d->dose.rowptr = reinterpret_cast<const int64_t*>(base + d->off_dose_rowptr);
-    d->dose.col = hd.layout == 1 ? nullptr : reinterpret_cast<const int32_t*>(base + d->off_dose_col);
-    if (hd.layout == 1) {
+    d->dose.col = hd.layout >= 1 ? nullptr : reinterpret_cast<const int32_t*>(base + d->off_dose_col);
+    if (hd.layout >= 1) {
         d->dose.col16 = reinterpret_cast<const uint16_t*>(base + d->off_dose_col);
         d->dose.ulist = reinterpret_cast<const int32_t*>(base + d->off_dose_ulist);
         d->dose.panel_u = reinterpret_cast<const int64_t*>(base + d->off_dose_panel_u);
@@ -904,8 +1101,8 @@ dvmat_status dvmat_ddc_bind(dvmat_ddc d, void* ws, size_t bytes, dvmat_stream st
     d->dose.perm = hd.perm.empty() ? nullptr : reinterpret_cast<const int32_t*>(base + d->off_dose_perm);
     d->dose.perm_runs = hd.perm_runs;
     d->price.rowptr = reinterpret_cast<const int64_t*>(base + d->off_price_rowptr);
-    d->price.col = hp.layout == 1 ? nullptr : reinterpret_cast<const int32_t*>(base + d->off_price_col);
-    if (hp.layout == 1) {
+    d->price.col = hp.layout >= 1 ? nullptr : reinterpret_cast<const int32_t*>(base + d->off_price_col);
+    if (hp.layout >= 1) {
         d->price.col16 = reinterpret_cast<const uint16_t*>(base + d->off_price_col);
         d->price.ulist = reinterpret_cast<const int32_t*>(base + d->off_price_ulist);
         d->price.panel_u = reinterpret_cast<const int64_t*>(base + d->off_price_panel_u);
@@ -940,7 +1137,7 @@ dvmat_status dvmat_ddc_layout_array(dvmat_ddc d, int32_t orientation, int32_t wh
     switch (which) {
         case 0: src = h.rowptr.data(); n = h.rowptr.size() * 8; break;
         case 1:
-            if (h.layout == 1) { src = h.col16.data(); n = h.col16.size() * 2; }
+            if (h.layout >= 1) { src = h.col16.data(); n = h.col16.size() * 2; }
             else { src = h.col.data(); n = h.col.size() * 4; }
             break;
         case 2: src = h.val.data(); n = h.val.size(); break;

@@ -291,7 +291,7 @@ template <int EPI>
 static dvmat_status run_orientation(const dvmat_ddc_s* d, const CsrDev& c, const KernelCfg& cfg, SpmvParams P,
                                     const float* x, int nrhs, hipStream_t s, int* nwg) {
     // the price's long beamlet rows gain 2 % from XCD-contiguous parts; the dose lost 2 % with them
-    if (c.layout == 1) return launch_panel<EPI>(cfg, d->storage, c, P, x, nrhs, s, nwg, &c == &d->price);
+    if (c.layout >= 1) return launch_panel<EPI>(cfg, d->storage, c, P, x, nrhs, s, nwg, &c == &d->price);
     P.x = x;
     *nwg = clamp_workgroups(cfg.workgroups, P.n_blocks);
     if constexpr (EPI == EPI_CURV) launch_curv(cfg, d->storage, c.B, P, s);
@@ -581,12 +581,12 @@ dvmat_status dvmat_ddc_autotune(dvmat_ddc d, const float* x, float* z, const flo
     KernelCfg best{};
     float ms = 0.0f;
     st = tune([&](const KernelCfg& c) { return dose_plain(d, c, x, 1, z, s); }, reps, s, &best, &ms, d->dose.B, true,
-              d->dose.layout == 1);
+              d->dose.layout >= 1);
     if (st) return st;
     d->dose_cfg = best;
     d->dose_tuned_ms = ms;
     st = tune([&](const KernelCfg& c) { return price_any(d, c, g, 1, p, s); }, reps, s, &best, &ms, d->price.B, true,
-              d->price.layout == 1);
+              d->price.layout >= 1);
     if (st) return st;
     d->price_cfg = best;
     d->price_tuned_ms = ms;
@@ -605,13 +605,13 @@ dvmat_status dvmat_ddc_autotune_obj(dvmat_ddc d, dvmat_obj obj, const float* x, 
     KernelCfg best{};
     float ms = 0.0f;
     st = tune([&](const KernelCfg& c) { return dose_obj(d, c, x, nrhs, z, obj, g, F, s); }, reps, s, &best, &ms,
-              d->dose.B, true, d->dose.layout == 1);
+              d->dose.B, true, d->dose.layout >= 1);
     if (st) return st;
     d->dose_cfg = best;
     d->dose_tuned_ms = ms;
     // the price of the gradient the dose just wrote, as the loop runs it
     st = tune([&](const KernelCfg& c) { return price_any(d, c, g, nrhs, p, s); }, reps, s, &best, &ms, d->price.B,
-              true, d->price.layout == 1);
+              true, d->price.layout >= 1);
     if (st) return st;
     d->price_cfg = best;
     d->price_tuned_ms = ms;
@@ -629,7 +629,7 @@ dvmat_status dvmat_ddc_set_kernel(dvmat_ddc d, int32_t orientation, int32_t kind
         return set_error(DVMAT_E_ARG, "dvmat_ddc_set_kernel: orientation %d", orientation);
     if (kind == KIND_STREAM && (orientation == 0 ? d->dose.B : d->price.B) != 1)
         return set_error(DVMAT_E_ARG, "dvmat_ddc_set_kernel: the stream kernel needs one row per block row");
-    if ((kind == KIND_PANEL) != ((orientation == 0 ? d->dose.layout : d->price.layout) == 1))
+    if ((kind == KIND_PANEL) != ((orientation == 0 ? d->dose.layout : d->price.layout) >= 1))
         return set_error(DVMAT_E_ARG, "dvmat_ddc_set_kernel: kind 3 (panel) goes with the panel layout and only there");
     if (orientation == 0) d->dose_cfg = c;
     else d->price_cfg = c;
@@ -666,6 +666,9 @@ dvmat_status dvmat_batch_create(const dvmat_ddc* ddcs, int32_t n, void* ws, size
             return set_error(DVMAT_E_ARG, "dvmat_batch_create: plan %d has a different block-row layout", i);
         if (d->dose.layout != ddcs[0]->dose.layout || d->price.layout != ddcs[0]->price.layout)
             return set_error(DVMAT_E_ARG, "dvmat_batch_create: plan %d has a different layout (CSR / panels)", i);
+        if (d->dose.layout == 2 || d->price.layout == 2)
+            return set_error(DVMAT_E_ARG, "dvmat_batch_create: plan %d uses sliced panels; the batched launch takes "
+                             "CSR or panels", i);
         auto plan = [](const CsrDev& c, const float* scale, int64_t base) {
             PlanDev q{};
             q.rowptr = c.rowptr;

@@ -19,6 +19,7 @@
 #include "spmv_device.hpp"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace dvmat {
 
@@ -113,14 +114,264 @@ __global__ __launch_bounds__(kPanelThreads) __attribute__((amdgpu_waves_per_eu(8
     workgroup_partials_n<R, EPI, kWaves>(P, lane, wid, fpart, cpart);
 }
 
+// ---- sliced panels (layout 2) ------------------------------------------------
+//
+// A slice holds up to 64 / W rows of one panel, sorted by length; the wave's
+// lanes i*W .. i*W + W-1 share row i and all rows advance together, four
+// entries per lane and step (one 16-byte value load at FP32, one 8-byte index
+// load), four steps in flight.  The step count is the slice's (uniform), so
+// the loop has no per-lane exit and no partial step per row; the W lanes of a
+// row are summed by DPP permutes at the end (two to four per slice instead of
+// a whole-wave reduction per row).  Lanes past the slice's rows re-read an
+// active lane's entries (same cache lines, no extra traffic) and store
+// nothing.  Rows without entries come in slices with no steps: one lane per
+// row writes its epilogue from zero sums.
+
+// Sum over the W lanes of each row group, every lane of the group receiving it.
+template <int W>
+__device__ __forceinline__ float group_sum(float v) {
+    static_assert(W == 1 || W == 2 || W == 4 || W == 8 || W == 16, "lanes per row");
+    if constexpr (W >= 2) v = dpp_step<0xB1>(v);    // quad_perm [1,0,3,2]
+    if constexpr (W >= 4) v = dpp_step<0x4E>(v);    // quad_perm [2,3,0,1]
+    if constexpr (W >= 8) v = dpp_step<0x141>(v);   // row_half_mirror
+    if constexpr (W >= 16) v = dpp_step<0x140>(v);  // row_mirror
+    return v;
+}
+
+// A slice's first row position, row count, first entry and stored entries.
+struct SliceDesc {
+    int p0, nr, len;
+    int64_t base;
+};
+
+__device__ __forceinline__ int64_t readlane64(int64_t v, int j) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, j);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), j);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// The epilogue inputs of a row whose natural index is known.
+template <int EPI>
+__device__ __forceinline__ EpiRow epi_load_nat(const SpmvParams& P, int64_t n) {
+    EpiRow e{0, 0.0f, 1.0f};
+    if constexpr (EPI == EPI_OBJ || EPI == EPI_CURV) e.sid = P.sid[n];
+    if constexpr (EPI == EPI_CURV) e.zr = P.zref[n];
+    if constexpr (EPI == EPI_SCALE) e.rs = P.row_scale[n];
+    return e;
+}
+
+// Entries per lane and step: 16 bytes of values (4 at FP32, 8 at 16 bits).
+template <int ST>
+constexpr int slice_entries() { return ST == DVMAT_F32 ? 4 : 8; }
+
+// One lane's entries of one step as loaded: 16 bytes of values (4 FP32 or 8
+// 16-bit codes) and their panel-local columns (8 or 16 bytes); unpacked only
+// when the products are formed, so that four steps in flight fit the
+// registers.
+typedef unsigned int u32x2v __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
+
+template <int ST>
+struct SliceStep {
+    u32x4v v;
+    typename std::conditional<ST == DVMAT_F32, u32x2v, u32x4v>::type c;
+};
+
+template <int ST>
+__device__ __forceinline__ void slice_step_loads(const SpmvParams& P, const uint16_t* col16, int64_t k,
+                                                 SliceStep<ST>& s) {
+    constexpr int E = slice_entries<ST>();
+    s.v = __builtin_nontemporal_load(reinterpret_cast<const u32x4v*>(P.val) + k / E);
+    s.c = __builtin_nontemporal_load(reinterpret_cast<const decltype(s.c)*>(col16) + k / E);
+}
+
+template <int ST>
+__device__ __forceinline__ void slice_step_zero(SliceStep<ST>& s) {
+    s.v = u32x4v{0u, 0u, 0u, 0u};
+}
+
+__device__ __forceinline__ i32x4 unpack_cols(unsigned a, unsigned b) {
+    return i32x4{(int)(a & 0xffffu), (int)(a >> 16), (int)(b & 0xffffu), (int)(b >> 16)};
+}
+
+template <int ST>
+__device__ __forceinline__ f32x4 unpack_vals(unsigned a, unsigned b) {
+    if constexpr (ST == DVMAT_F16) {
+        typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+        const f16x2 x = __builtin_bit_cast(f16x2, a), y = __builtin_bit_cast(f16x2, b);
+        return f32x4{(float)x.x, (float)x.y, (float)y.x, (float)y.y};
+    } else {
+        return f32x4{__uint_as_float(a << 16), __uint_as_float(a & 0xffff0000u), __uint_as_float(b << 16),
+                     __uint_as_float(b & 0xffff0000u)};
+    }
+}
+
+template <int ST, int R>
+__device__ __forceinline__ void slice_step_fma(float (&acc)[1][R], const SpmvParams& P, const float* xs,
+                                               const SliceStep<ST>& s) {
+    if constexpr (ST == DVMAT_F32) {
+        const f32x4 V[1] = {__builtin_bit_cast(f32x4, s.v)};
+        fma4_blocked<R, 1, false>(acc, P, xs, V, unpack_cols(s.c.x, s.c.y));
+    } else {
+        const f32x4 V0[1] = {unpack_vals<ST>(s.v.x, s.v.y)};
+        const f32x4 V1[1] = {unpack_vals<ST>(s.v.z, s.v.w)};
+        fma4_blocked<R, 1, false>(acc, P, xs, V0, unpack_cols(s.c.x, s.c.y));
+        fma4_blocked<R, 1, false>(acc, P, xs, V1, unpack_cols(s.c.z, s.c.w));
+    }
+}
+
+template <int ST, int R, int EPI, int W>
+__device__ __forceinline__ void slice_rows(const SpmvParams& P, const SliceDesc& d, int lane, const f32x4* tab,
+                                           float (&fpart)[R], double& cpart, const float* xs,
+                                           const uint16_t* col16) {
+    // sliced panels always carry the row permutation (rows sorted by length)
+    if (d.len == 0) {
+        if (lane < d.nr) {
+            const int64_t n = P.perm[d.p0 + lane];
+            const EpiRow e = epi_load_nat<EPI>(P, n);
+            float acc[R];
+#pragma unroll
+            for (int h = 0; h < R; ++h) acc[h] = 0.0f;
+            row_epilogue<R, EPI>(P, n, e, tab, acc, fpart, cpart);
+        }
+        return;
+    }
+    const int i = lane / W;
+    const bool act = i < d.nr;
+    const int64_t nat = P.perm[d.p0 + (act ? i : 0)];
+    constexpr int E = slice_entries<ST>();
+    const int stride = d.nr * W * E;                   // entries per step
+    const int S = d.len / stride;                      // >= 1
+    const int64_t k0 = d.base + E * (act ? lane : lane % (d.nr * W));
+    float acc[1][R];
+#pragma unroll
+    for (int h = 0; h < R; ++h) acc[0][h] = 0.0f;
+    // steps in flight: four for one right-hand side, two where four would
+    // not fit the registers (several right-hand sides, the curvature,
+    // bfloat16's unpacking)
+    constexpr int D = (R == 1 && EPI != EPI_CURV && ST != DVMAT_BF16) ? 4 : 2;
+    // the first D steps without branches: steps past the slice's end re-read
+    // its last step (lines already on their way) and count zero
+    {
+        SliceStep<ST> st[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) slice_step_loads<ST>(P, col16, k0 + (int64_t)min(j, S - 1) * stride, st[j]);
+#pragma unroll
+        for (int j = 1; j < D; ++j)
+            if (j >= S) slice_step_zero<ST>(st[j]);
+#pragma unroll
+        for (int j = 0; j < D; ++j) slice_step_fma<ST, R>(acc, P, xs, st[j]);
+    }
+    // the epilogue inputs: the natural row arrived with the first steps, and
+    // this load's latency hides behind the next steps'
+    const EpiRow e = epi_load_nat<EPI>(P, nat);
+    int64_t k = k0 + (int64_t)D * stride;
+    int t = D;
+    for (; t + D <= S; t += D) {
+        SliceStep<ST> st[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) slice_step_loads<ST>(P, col16, k + j * stride, st[j]);
+#pragma unroll
+        for (int j = 0; j < D; ++j) slice_step_fma<ST, R>(acc, P, xs, st[j]);
+        k += (int64_t)D * stride;
+    }
+    if (t < S) {
+        // the last steps (fewer than D), loads issued together
+        const int rem = S - t;
+        SliceStep<ST> st[D - 1];
+        slice_step_loads<ST>(P, col16, k, st[0]);
+#pragma unroll
+        for (int j = 1; j < D - 1; ++j)
+            if (rem > j) slice_step_loads<ST>(P, col16, k + j * stride, st[j]);
+        slice_step_fma<ST, R>(acc, P, xs, st[0]);
+#pragma unroll
+        for (int j = 1; j < D - 1; ++j)
+            if (rem > j) slice_step_fma<ST, R>(acc, P, xs, st[j]);
+    }
+    float sum[R];
+#pragma unroll
+    for (int h = 0; h < R; ++h) sum[h] = group_sum<W>(acc[0][h]);
+    if (act && lane % W == 0) row_epilogue<R, EPI>(P, nat, e, tab, sum, fpart, cpart);
+}
+
+// Parts of sliced panels: the staging of the panel kernel, then the part's
+// slices in a fixed order: a part's slices are sorted longest first, and wave w
+// takes slice w of each round of eight, in reverse order every second round,
+// so that each wave's share of a part comes out about even.  The descriptors
+// of a wave's next 64 slices are read one per lane (during the staging for
+// the first 64), so a slice starts without a round trip for them.
+template <int ST, int R, int EPI, int W>
+__global__ __launch_bounds__(kPanelThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void spmv_slice_kernel(
+    SpmvParams P, PanelParams Q) {
+    constexpr int kWaves = kPanelThreads / kWaveSize;
+    extern __shared__ float xs[];
+    __shared__ f32x4 s_tab[(EPI == EPI_OBJ || EPI == EPI_CURV) ? 256 : 1];
+    if constexpr (EPI == EPI_OBJ || EPI == EPI_CURV) {
+        if (threadIdx.x < 256) s_tab[threadIdx.x] = reinterpret_cast<const f32x4*>(P.table)[threadIdx.x];
+    }
+    const int lane = threadIdx.x & (kWaveSize - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWaveSize);
+    float fpart[R];
+#pragma unroll
+    for (int h = 0; h < R; ++h) fpart[h] = 0.0f;
+    double cpart = 0.0;
+    for (int64_t t = blockIdx.x; t < Q.n_parts; t += gridDim.x) {
+        const int p = Q.part_panel[t];
+        const int64_t u0 = Q.panel_u[p];
+        const int nu = (int)(Q.panel_u[p + 1] - u0);
+        const int q0 = Q.part_units[t], q1 = Q.part_units[t + 1];
+        auto slice_of = [&](int r) { return q0 + r * kWaves + ((r & 1) ? kWaves - 1 - wid : wid); };
+        int dp0 = 0, dp1 = 0;
+        int64_t db0 = 0, db1 = 0;
+        auto lane_desc = [&](int rb) {
+            const int qj = slice_of(rb + lane);
+            dp0 = dp1 = 0;
+            db0 = db1 = 0;
+            if (qj < q1) {
+                dp0 = P.blocks[qj];
+                dp1 = P.blocks[qj + 1];
+                db0 = P.rowptr[qj];
+                db1 = P.rowptr[qj + 1];
+            }
+        };
+        __syncthreads();                              // the previous panel's gathers are done
+        lane_desc(0);
+        // a part of rows without entries (outside the body) needs no slice
+        if (P.rowptr[q1] > P.rowptr[q0]) stage_slice<R, false>(xs, Q.ulist + u0, nu, Q.x, Q.ldx, nullptr);
+        __syncthreads();
+        for (int rb = 0; slice_of(rb) < q1; rb += kWaveSize) {
+            if (rb > 0) lane_desc(rb);
+            for (int j = 0; j < kWaveSize && slice_of(rb + j) < q1; ++j) {
+                SliceDesc d;
+                d.p0 = __builtin_amdgcn_readlane(dp0, j);
+                d.nr = __builtin_amdgcn_readlane(dp1, j) - d.p0;
+                const int64_t b0 = readlane64(db0, j);
+                d.base = b0;
+                d.len = (int)(readlane64(db1, j) - b0);
+                slice_rows<ST, R, EPI, W>(P, d, lane, s_tab, fpart, cpart, xs, Q.col16);
+            }
+        }
+    }
+    workgroup_partials_n<R, EPI, kWaves>(P, lane, wid, fpart, cpart);
+}
+
 // Largest LDS slice a launch uses; with the objective table (4 KB) and the
 // partial sums the workgroup stays within 64 KB.
 constexpr size_t kPanelLdsBytes = 56 * 1024;
 
 template <int ST, int R, int EPI>
+static void launch_slice_chunk(int W, int nwg, size_t lds, const SpmvParams& P, const PanelParams& Q, hipStream_t s) {
+    dim3 grid(nwg), block(kPanelThreads);
+    if (W == 16) hipLaunchKernelGGL((spmv_slice_kernel<ST, R, EPI, 16>), grid, block, lds, s, P, Q);
+    else if (W == 8) hipLaunchKernelGGL((spmv_slice_kernel<ST, R, EPI, 8>), grid, block, lds, s, P, Q);
+    else hipLaunchKernelGGL((spmv_slice_kernel<ST, R, EPI, 4>), grid, block, lds, s, P, Q);
+}
+
+template <int ST, int R, int EPI>
 static void launch_chunk(int B, int nwg, size_t lds, const SpmvParams& P, const PanelParams& Q, hipStream_t s) {
     dim3 grid(nwg), block(kPanelThreads);
-    if (B == 4) hipLaunchKernelGGL((spmv_panel_kernel<ST, R, EPI, 4>), grid, block, lds, s, P, Q);
+    if (B < 0) launch_slice_chunk<ST, R, EPI>(-B, nwg, lds, P, Q, s);
+    else if (B == 4) hipLaunchKernelGGL((spmv_panel_kernel<ST, R, EPI, 4>), grid, block, lds, s, P, Q);
     else if (B == 2) hipLaunchKernelGGL((spmv_panel_kernel<ST, R, EPI, 2>), grid, block, lds, s, P, Q);
     else hipLaunchKernelGGL((spmv_panel_kernel<ST, R, EPI, 1>), grid, block, lds, s, P, Q);
 }
@@ -169,9 +420,11 @@ dvmat_status launch_panel(const KernelCfg& cfg, int storage, const CsrDev& c, co
         if (P.partial) P.partial += h0;
         Q.x = x + h0;
         const size_t lds = per_rhs * R;
-        if (storage == DVMAT_F32) launch_chunk_r<DVMAT_F32, EPI>(R, c.B, nwg, lds, P, Q, s);
-        else if (storage == DVMAT_F16) launch_chunk_r<DVMAT_F16, EPI>(R, c.B, nwg, lds, P, Q, s);
-        else launch_chunk_r<DVMAT_BF16, EPI>(R, c.B, nwg, lds, P, Q, s);
+        // sliced panels pass their lanes per row as a negative block-row count
+        const int Bk = c.layout == 2 ? -c.slice_lanes : c.B;
+        if (storage == DVMAT_F32) launch_chunk_r<DVMAT_F32, EPI>(R, Bk, nwg, lds, P, Q, s);
+        else if (storage == DVMAT_F16) launch_chunk_r<DVMAT_F16, EPI>(R, Bk, nwg, lds, P, Q, s);
+        else launch_chunk_r<DVMAT_BF16, EPI>(R, Bk, nwg, lds, P, Q, s);
         h0 += R;
     }
     return check_hip(hipGetLastError(), "panel launch");

@@ -50,7 +50,8 @@ class DdcInfo(ctypes.Structure):
                 ("dose_panels", ctypes.c_int64), ("price_panels", ctypes.c_int64),
                 ("dose_panel_cols", ctypes.c_int64), ("price_panel_cols", ctypes.c_int64),
                 ("dose_panel_cols_total", ctypes.c_int64), ("price_panel_cols_total", ctypes.c_int64),
-                ("dose_panel_parts", ctypes.c_int64), ("price_panel_parts", ctypes.c_int64)]
+                ("dose_panel_parts", ctypes.c_int64), ("price_panel_parts", ctypes.c_int64),
+                ("dose_slice_lanes", ctypes.c_int32), ("price_slice_lanes", ctypes.c_int32)]
 
 
 class BuildOpts(ctypes.Structure):
@@ -60,7 +61,8 @@ class BuildOpts(ctypes.Structure):
                 ("dose_layout", ctypes.c_int32), ("price_layout", ctypes.c_int32),
                 ("dose_grid", ctypes.c_int32 * 3), ("price_grid", ctypes.c_int32 * 3),
                 ("dose_tile", ctypes.c_int32 * 3), ("price_tile", ctypes.c_int32 * 3),
-                ("panel_cols", ctypes.c_int32), ("part_entries", ctypes.c_int32)]
+                ("panel_cols", ctypes.c_int32), ("part_entries", ctypes.c_int32),
+                ("dose_slice_lanes", ctypes.c_int32), ("price_slice_lanes", ctypes.c_int32)]
 
 
 # Panel tiles used when the grids are known: 32x16x2 voxels for the dose at
@@ -71,7 +73,7 @@ class BuildOpts(ctypes.Structure):
 DOSE_TILE = (32, 16, 2)
 DOSE_TILE_16BIT = (16, 8, 8)
 PRICE_TILE = (4, 2, 8)
-LAYOUTS = {"csr": 0, "panel": 1}
+LAYOUTS = {"csr": 0, "panel": 1, "sliced": 2}
 
 
 class Geom(ctypes.Structure):
@@ -225,14 +227,16 @@ class DDC:
                  dose_block_rows=None, price_block_rows=None, interleave=None, unit_entries=None,
                  dose_row_order=None, price_row_order=None, dose_grid=None, price_grid=None,
                  dose_layout=None, price_layout=None, dose_tile=None, price_tile=None, panel_cols=None,
-                 part_entries=None):
+                 part_entries=None, slice_lanes=None, dose_slice_lanes=None, price_slice_lanes=None):
         """COO (row = voxel, col = beamlet) to the device layouts.
 
         dose_grid / price_grid: the voxel grid (nx, ny, nz) and the beamlet grid
         (columns, MLC rows, control points), fastest axis first.  With a grid
-        the orientation defaults to the panel layout (tiles DOSE_TILE, or
-        DOSE_TILE_16BIT at 16-bit storage, and PRICE_TILE); without one, to
-        CSR.  *_layout: "csr" or "panel"."""
+        the orientation defaults to the sliced panel layout, the fastest
+        measured (tiles DOSE_TILE, or DOSE_TILE_16BIT at 16-bit storage, and
+        PRICE_TILE); without one, to CSR.  *_layout: "csr", "panel" or "sliced" (panels whose rows, sorted
+        by length, run in slices of 64 / W rows with W lanes per row: W from
+        dose_slice_lanes / price_slice_lanes, or slice_lanes for both)."""
         row = np.ascontiguousarray(row, dtype=np.int32)
         col = np.ascontiguousarray(col, dtype=np.int32)
         val = np.ascontiguousarray(val, dtype=np.float32)
@@ -245,14 +249,16 @@ class DDC:
         for name, v in (("dose_block_rows", dose_block_rows), ("price_block_rows", price_block_rows),
                         ("interleave", interleave), ("unit_entries", unit_entries),
                         ("dose_row_order", dose_row_order), ("price_row_order", price_row_order),
-                        ("panel_cols", panel_cols), ("part_entries", part_entries)):
+                        ("panel_cols", panel_cols), ("part_entries", part_entries),
+                        ("dose_slice_lanes", dose_slice_lanes if dose_slice_lanes is not None else slice_lanes),
+                        ("price_slice_lanes", price_slice_lanes if price_slice_lanes is not None else slice_lanes)):
             if v is not None:
                 setattr(opts, name, int(v))
         dose_dflt = DOSE_TILE if storage == "f32" else DOSE_TILE_16BIT
         for side, grid, lay, tile, dflt in (("dose", dose_grid, dose_layout, dose_tile, dose_dflt),
                                             ("price", price_grid, price_layout, price_tile, PRICE_TILE)):
             if lay is None:
-                lay = "panel" if grid is not None else "csr"
+                lay = "sliced" if grid is not None else "csr"
             setattr(opts, side + "_layout", LAYOUTS[lay])
             if grid is not None:
                 getattr(opts, side + "_grid")[:] = [int(v) for v in grid]

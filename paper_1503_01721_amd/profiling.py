@@ -4,12 +4,16 @@
     python -m paper_1503_01721_amd.profiling traffic --fetch DIR --write DIR --copy-fetch DIR \\
         --copy-write DIR --kernel PATTERN --orientation dose|price --algorithmic BYTES \\
         --workload W --storage S --layout L --command CMD --out FILE
+    python -m paper_1503_01721_amd.profiling counters --dir DIR [--dir DIR ...] --kernel PATTERN \\
+        [--kernel PATTERN ...] --title T --command CMD --out FILE
 
 `trace` turns a `--kernel-trace --stats` directory into a table of kernels
 (calls, average/min/max duration).  `traffic` turns two `--pmc FETCH_SIZE`
 and `--pmc WRITE_SIZE` runs of the benchmark, plus the same counters over a
 plain 1 GiB device copy, into HBM bytes per launch of one kernel: the
-counters' KiB are scaled by what they read for the copy of known size.  The
+counters' KiB are scaled by what they read for the copy of known size.
+`counters` tabulates the mean of every counter of one or more `--pmc` runs per
+launch of each named kernel.  The
 traffic file carries the hash of the product kernels' sources; bench.py
 reports its figure only while the sources are unchanged.
 """
@@ -74,8 +78,30 @@ def main():
         f.add_argument("--" + k, required=True)
     f.add_argument("--algorithmic", type=float, required=True)
     f.add_argument("--copy-bytes", type=float, default=float(1 << 30))
+    c = sub.add_parser("counters")
+    c.add_argument("--dir", action="append", required=True)
+    c.add_argument("--kernel", action="append", required=True)
+    c.add_argument("--title", required=True)
+    c.add_argument("--command", action="append", required=True)
+    c.add_argument("--note", action="append", default=[])
+    c.add_argument("--out", required=True)
     a = ap.parse_args()
-    if a.what == "trace":
+    if a.what == "counters":
+        lines = [f"# rocprofv3 counters, mean per launch: {a.title}", "#",
+                 "# commands (from /tmp with TMPDIR=/tmp, one run per counter set):",
+                 *[f"#   rocprofv3 --pmc {cmd}" for cmd in a.command], *[f"# {n}" for n in a.note], "#"]
+        for k in a.kernel:
+            lines.append(f"kernel: {k}")
+            for d in a.dir:
+                names = sorted({r["Counter_Name"] for r in csv.DictReader(
+                    open(_one(os.path.join(d, "**", "*counter_collection.csv"))))})
+                for n in names:
+                    try:
+                        v, cnt = counter_mean(d, n, k)
+                    except SystemExit:
+                        continue
+                    lines.append(f"  {n:24s} {v:14.5g}  (mean of {cnt} launches)")
+    elif a.what == "trace":
         lines = [f"# rocprofv3 kernel trace: {a.title}", "#", "# command (from /tmp with TMPDIR=/tmp, library built in place):",
                  f"#   {a.command}", *[f"# {n}" for n in a.note], "#", *trace_table(a.dir)]
     else:

@@ -1,9 +1,10 @@
 """Layout autotuner for the DDC products.
 
-The device layout of each orientation has knobs that no formula settles: the
-voxel tile of the dose panels, the beamlet tile of the price panels, the rows
-per block row of each, the panel column budget and the part size that shares
-large panels between workgroups.  tune() builds the matrix once per candidate,
+The device layout of each orientation has knobs that no formula settles:
+panels or sliced panels, the voxel tile of the dose panels, the beamlet tile
+of the price panels, the rows per block row (panels) or lanes per row (sliced
+panels) of each, the panel column budget and the part size that shares large
+panels between workgroups.  tune() builds the matrix once per candidate,
 lets the library pick each orientation's launch shape (dvmat_ddc_autotune),
 then times the two products exactly as the column-generation loop runs them
 (the dose with the objective epilogue writing F and dF/dz, the price of that
@@ -34,17 +35,24 @@ DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_
 # Candidate knobs per storage type.  Dose tiles are voxel bricks (x, y, z);
 # 32-voxel rows write whole 128-byte lines of the dose output.  Price tiles are
 # (beamlet columns, MLC rows, control points).
+def _sl(side, tile, lanes):
+    return {side + "_layout": "sliced", side + "_tile": tile, side + "_slice_lanes": lanes, side + "_block_rows": 1}
+
+
+def _pn(side, tile, B):
+    return {side + "_layout": "panel", side + "_tile": tile, side + "_block_rows": B}
+
+
 DOSE_CANDIDATES = {
-    "f32": [dict(dose_tile=(32, 16, 2), dose_block_rows=1), dict(dose_tile=(16, 8, 8), dose_block_rows=1),
-            dict(dose_tile=(32, 8, 4), dose_block_rows=1), dict(dose_tile=(32, 16, 2), dose_block_rows=2),
-            dict(dose_tile=(32, 16, 4), dose_block_rows=1)],
-    "16bit": [dict(dose_tile=(16, 8, 8), dose_block_rows=2), dict(dose_tile=(32, 16, 2), dose_block_rows=2),
-              dict(dose_tile=(16, 8, 8), dose_block_rows=1), dict(dose_tile=(32, 8, 4), dose_block_rows=2)],
+    "f32": [_sl("dose", (32, 16, 2), 8), _sl("dose", (32, 16, 2), 4), _sl("dose", (32, 16, 4), 8),
+            _sl("dose", (16, 8, 8), 8), _pn("dose", (32, 16, 2), 1)],
+    "16bit": [_sl("dose", (16, 8, 8), 4), _sl("dose", (32, 16, 2), 4), _sl("dose", (16, 8, 8), 8),
+              _sl("dose", (32, 16, 4), 4), _pn("dose", (16, 8, 8), 2)],
 }
-PRICE_CANDIDATES = [dict(price_tile=(4, 2, 8), price_block_rows=1), dict(price_tile=(8, 2, 4), price_block_rows=1),
-                    dict(price_tile=(4, 4, 4), price_block_rows=1), dict(price_tile=(4, 2, 8), price_block_rows=2)]
-SHARED_CANDIDATES = [dict(panel_cols=12288, part_entries=131072), dict(panel_cols=8192, part_entries=131072),
-                     dict(panel_cols=12288, part_entries=262144)]
+PRICE_CANDIDATES = [_sl("price", (4, 2, 8), 8), _sl("price", (4, 2, 8), 16), _sl("price", (8, 2, 4), 8),
+                    _sl("price", (4, 4, 4), 4), _pn("price", (4, 2, 8), 1)]
+SHARED_CANDIDATES = [dict(panel_cols=8192, part_entries=131072), dict(panel_cols=12288, part_entries=131072),
+                     dict(panel_cols=8192, part_entries=196608)]
 
 
 def cache_path() -> str:

@@ -15,15 +15,16 @@ pytestmark = pytest.mark.gpu
 PLAN = synth.PLANS["cp64_bl12x12_vox40"]
 
 
-@pytest.fixture(scope="module", params=["csr", "panel"])
+@pytest.fixture(scope="module", params=["csr", "panel", "sliced"])
 def setup(request):
     assert torch.cuda.is_available()
     from paper_1503_01721_amd import dvmat
     d = synth.generate_ddc(PLAN)
     sid, table = synth.structures(PLAN)
-    layout = PLAN.grids if request.param == "panel" else {}
+    layout = {} if request.param == "csr" else dict(PLAN.grids, dose_layout=request.param,
+                                                            price_layout=request.param)
     ddc = dvmat.DDC(d["row"], d["col"], d["val"], PLAN.n_vox, PLAN.n_bl, storage="f16", **layout)
-    assert ddc.info.dose_layout == (request.param == "panel")
+    assert ddc.info.dose_layout == {"csr": 0, "panel": 1, "sliced": 2}[request.param]
     obj = dvmat.Objective(sid, table)
     cps, L, R = synth.random_apertures(PLAN, 64, 2004)
     aps = dvmat.Apertures(PLAN.n_cp, PLAN.n_rows, PLAN.n_cols, cps, L, R)

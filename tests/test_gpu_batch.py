@@ -122,7 +122,7 @@ def _panel_ddcs(storage, cap=3584):
         d = synth.generate_ddc(pl)
         out.append((pl.n_vox, pl.n_bl, d, dvmat.DDC(d["row"], d["col"], d["val"], pl.n_vox, pl.n_bl, storage=storage,
                                                      dose_block_rows=1, price_block_rows=1, panel_cols=cap,
-                                                     **pl.grids)))
+                                                     dose_layout="panel", price_layout="panel", **pl.grids)))
     d = synth.random_sparse(3001, 517, 0.02, 5, empty_rows=300, empty_cols=40)
     out.append((3001, 517, d, dvmat.DDC(d["row"], d["col"], d["val"], 3001, 517, storage=storage, dose_block_rows=1,
                                         price_block_rows=1, dose_layout="panel", price_layout="panel", panel_cols=cap)))

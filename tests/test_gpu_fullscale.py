@@ -1,8 +1,9 @@
 """Parity at full size, in the launch configuration the benchmark times.
 
 The full-scale single-arc workload (180 control points x 40x40 beamlets,
-128^3 voxels, ~5e8 non-zeros) is built in the panel layout the benchmark
-uses (and in the CSR layout) and autotuned exactly as bench.py does.  The FP64 oracle cannot run the whole
+128^3 voxels, ~5e8 non-zeros) is built in the layout the benchmark uses (the
+tuner's cached choice), in the panel and in the CSR layout, and autotuned
+exactly as bench.py does.  The FP64 oracle cannot run the whole
 products quickly, so it checks sampled outputs one by one: each sampled
 dose row and price row is formed from the generator's pointwise definition of
 D_ij (independent of the COO arrays and of the library), plus properties that
@@ -22,19 +23,28 @@ PLAN = synth.PLANS["cp180_bl40x40_vox128"]
 TOL = 1e-5
 
 
-@pytest.fixture(scope="module", params=["panel", "csr"])
+@pytest.fixture(scope="module", params=["bench", "panel", "csr"])
 def full(request):
     assert torch.cuda.is_available()
-    from paper_1503_01721_amd import dvmat
+    from paper_1503_01721_amd import dvmat, tuner
     d = synth.generate_ddc(PLAN)
     sid, table = synth.structures(PLAN)
-    layout = PLAN.grids if request.param == "panel" else {}
+    obj = dvmat.Objective(sid, table)
+    if request.param == "bench":
+        layout = dict(PLAN.grids, **(tuner.layout_for(tuner.signature(PLAN.n_vox, PLAN.n_bl, len(d["val"]), "f32",
+                                                                      PLAN.grids, 1)) or {}))
+    elif request.param == "panel":
+        layout = dict(PLAN.grids, dose_layout="panel", price_layout="panel")
+    else:
+        layout = {}
     ddc = dvmat.DDC(d["row"], d["col"], d["val"], PLAN.n_vox, PLAN.n_bl, **layout)
-    assert ddc.info.dose_layout == (request.param == "panel")
+    assert (ddc.info.dose_layout == 0) == (request.param == "csr")
     nnz = len(d["val"])
     del d
-    ddc.autotune(reps=3)
-    obj = dvmat.Objective(sid, table)
+    if request.param == "csr":
+        ddc.autotune(reps=3)
+    else:
+        ddc.autotune(reps=3, obj=obj)
     return dvmat, ddc, obj, sid, table, nnz
 
 

@@ -851,7 +851,8 @@ def test_panel_layout_plain_method_workload(dv, plan1, storage, B, panel_cols):
     d, sid, table, _, obj = plan1
     ddc = dv.DDC(d["row"], d["col"], d["val"], PLAN1.n_vox, PLAN1.n_bl, storage=storage,
                  dose_block_rows=B[0], price_block_rows=B[1], panel_cols=panel_cols,
-                 part_entries=131072 if panel_cols == 8192 else 20000, **PLAN1.grids)
+                 part_entries=131072 if panel_cols == 8192 else 20000, dose_layout="panel", price_layout="panel",
+                 **PLAN1.grids)
     info = ddc.info
     # beamlet rows here touch up to ~1300 voxels: a budget of 1000 keeps the
     # price matrix in CSR (and splits the dose tiles), 2500 splits the price tiles
@@ -935,7 +936,8 @@ def test_panel_layout_unstructured(dv, wg):
 
 def test_panel_layout_kind_checks_and_batch(dv, plan1):
     d, _, _, _, _ = plan1
-    ddc = dv.DDC(d["row"], d["col"], d["val"], PLAN1.n_vox, PLAN1.n_bl, **PLAN1.grids)
+    ddc = dv.DDC(d["row"], d["col"], d["val"], PLAN1.n_vox, PLAN1.n_bl, dose_layout="panel", price_layout="panel",
+                 **PLAN1.grids)
     with pytest.raises(dv.DvmatError):
         ddc.set_kernel("dose", "row", 1024)
     csr = dv.DDC(d["row"], d["col"], d["val"], PLAN1.n_vox, PLAN1.n_bl)
@@ -1196,9 +1198,9 @@ def test_column_generation_with_machine_matches_oracle(dv, form, interdigitated)
 # ---------------------------------------------------------------- one GPU's share of a voxel-row split
 
 def test_voxel_slabs_compose_the_whole_products(dv, plan1):
-    """A split by voxel rows (z-slabs, in the panel layout with the slab's own
-    grid): each slab's dose is the full dose on its rows, and the slabs'
-    partial prices sum to the full price, the exchange the split needs."""
+    """A split by voxel rows (z-slabs, in the default sliced layout with the
+    slab's own grid): each slab's dose is the full dose on its rows, and the
+    slabs' partial prices sum to the full price, the exchange the split needs."""
     d, sid, table, ddc, obj = plan1
     N, G = PLAN1.n_grid, 4
     x, g = synth.bench_vectors(PLAN1.n_bl, PLAN1.n_vox, 61)
@@ -1212,7 +1214,7 @@ def test_voxel_slabs_compose_the_whole_products(dv, plan1):
         n = (z1 - z0) * N * N
         part = dv.DDC(rows, sl["col"], sl["val"], n, PLAN1.n_bl, dose_grid=(N, N, z1 - z0),
                       price_grid=PLAN1.grids["price_grid"])
-        assert part.info.dose_layout == 1
+        assert part.info.dose_layout == 2
         z = part.dose(cuda(x)).cpu().numpy()
         assert np.abs(z - z_ref[z0 * N * N:z1 * N * N]).max() <= TOL * z_ref.max(), s
         p_sum += part.price(cuda(g[z0 * N * N:z1 * N * N])).cpu().numpy()

@@ -1,7 +1,7 @@
 """Error of the storage forms against the FP64 oracle at full size, per structure.
 
 The full-scale single-arc workload (180 control points x 40x40 beamlets, 128^3
-voxels, ~5e8 non-zeros) in the panel layout the benchmark times, with values
+voxels, ~5e8 non-zeros) in the sliced panel layout the benchmark times, with values
 stored as FP32, FP16 and BF16 (16-bit forms: per-beamlet FP32 scale, FP32
 accumulation).  Reference: COO products in FP64 over the whole matrix.
 Reported (run with -s): the largest dose error over the voxels of each
@@ -41,7 +41,7 @@ def test_fullscale_error_per_structure(reference, storage):
     from paper_1503_01721_amd import dvmat
     d, sid, x, g, z64, p64, pscale = reference
     ddc = dvmat.DDC(d["row"], d["col"], d["val"], PLAN.n_vox, PLAN.n_bl, storage=storage, **PLAN.grids)
-    assert ddc.info.dose_layout == 1 and ddc.info.price_layout == 1
+    assert ddc.info.dose_layout == 2 and ddc.info.price_layout == 2       # the default with grids: sliced panels
     z = ddc.dose(torch.from_numpy(x).cuda()).cpu().numpy().astype(np.float64)
     p = ddc.price(torch.from_numpy(g).cuda()).cpu().numpy().astype(np.float64)
     del ddc

@@ -1,8 +1,9 @@
 """Parity past 2^31 stored entries: the two-arc workload (360 control points x
 60x60 beamlets of 3.3 mm, 160^3 voxels of 2 mm, 4.35e9 non-zeros) in FP16
-storage and the panel layout, the differentiation form's configuration.
+storage and the default sliced panel layout, the differentiation form's
+configuration.
 
-Row pointers, panel offsets and work-unit starts beyond 2^31 are exercised by
+Slice offsets, panel offsets and slice starts beyond 2^31 are exercised by
 the rows and columns sampled at the end of each orientation.  The FP64 oracle
 cannot hold the products of a matrix this size quickly, so it checks sampled
 outputs one by one from the generator's pointwise definition of D_ij
@@ -78,7 +79,7 @@ def test_twoarc_layout_is_past_2_31(twoarc):
     dvmat, ddc, obj, sid, table, nnz, s = twoarc
     info = ddc.info
     assert info.nnz == nnz and nnz > 2 ** 31
-    assert info.dose_layout == 1 and info.price_layout == 1 and info.storage == dvmat.F16
+    assert info.dose_layout == 2 and info.price_layout == 2 and info.storage == dvmat.F16     # sliced panels
     assert info.nnz_pad_dose > 2 ** 31 and info.nnz_pad_price > 2 ** 31
 
 

@@ -45,10 +45,80 @@ def _create(dv, row, col, val, n_vox, n_bl, opts, storage=0):
     return h, info
 
 
+def _rebuild_sliced(dv, h, info, orient, n_rows, n_cols, scale=None):
+    """Dense matrix of a sliced-panel orientation (layout 2) from its arrays,
+    plus the invariants the slice kernel relies on."""
+    W = info.dose_slice_lanes if orient == 0 else info.price_slice_lanes
+    assert W in (4, 8, 16)
+    C = 64 // W
+    E = 16 // info.value_bytes                            # entries per lane and step
+    sptr = _array(dv, h, orient, 0, np.int64)
+    col16 = _array(dv, h, orient, 1, np.uint16)
+    vals = _array(dv, h, orient, 2, np.float32 if info.value_bytes == 4 else np.uint16)
+    first = _array(dv, h, orient, 3, np.int32)
+    perm = _array(dv, h, orient, 4, np.int32)
+    ulist = _array(dv, h, orient, 5, np.int32)
+    pu = _array(dv, h, orient, 6, np.int64)
+    pslices = _array(dv, h, orient, 7, np.int32)
+    parts = _array(dv, h, orient, 8, np.int32)
+    ppan = _array(dv, h, orient, 9, np.int32)
+    n_sl = len(sptr) - 1
+    assert len(first) == n_sl + 1 and first[0] == 0 and first[-1] == n_rows and np.all(np.diff(first) >= 1)
+    assert sptr[0] == 0 and np.all(np.diff(sptr) >= 0) and len(col16) == len(vals) == sptr[-1]
+    assert np.array_equal(np.sort(perm), np.arange(n_rows))
+    assert pslices[0] == 0 and pslices[-1] == n_sl and np.all(np.diff(pslices) >= 0)
+    assert parts[0] == 0 and parts[-1] == n_sl and np.all(np.diff(ppan) >= 0)
+    assert np.all(parts[:-1] >= pslices[ppan]) and np.all(parts[1:] <= pslices[ppan + 1])
+    D = np.zeros((n_rows, n_cols), np.float64)
+    lens = np.zeros(n_rows, np.int64)                     # stored non-zeros per row, for the order checks
+    part_start = set(parts[:-1].tolist())
+    for p in range(len(pu) - 1):
+        u = ulist[pu[p]:pu[p + 1]]
+        assert np.all(np.diff(u) > 0)
+        prev = None
+        for q in range(pslices[p], pslices[p + 1]):
+            if q in part_start:
+                prev = None                               # rows are sorted within each part
+            nr = first[q + 1] - first[q]
+            k0, k1 = sptr[q], sptr[q + 1]
+            if k1 == k0:
+                assert nr <= 64
+                continue
+            assert nr <= C and (k1 - k0) % (nr * W * E) == 0
+            S = (k1 - k0) // (nr * W * E)
+            k = np.arange(k1 - k0)
+            i = (k // E // W) % nr
+            t, w, qq = k // (E * W * nr), (k // E) % W, k % E
+            sidx = E * W * t + qq * W + w                 # sorted entry of the row held at k
+            rows = perm[first[q] + i]
+            loc = col16[k0:k1].astype(np.int64)
+            assert len(u) == 0 or np.all(loc < len(u))
+            v = vals[k0:k1]
+            if info.value_bytes == 2:                     # FP16 codes of D_ij / s_j (beamlet scale s_j)
+                v = v.view(np.float16).astype(np.float64) * scale[u[loc] if orient == 0 else rows]
+            np.add.at(D, (rows, u[loc] if len(u) else loc), v)
+            # a row's columns increase along its sorted entries
+            for r in range(nr):
+                m = (i == r) & (v != 0)
+                order = np.argsort(sidx[m])
+                assert np.all(np.diff(u[loc[m]][order]) > 0)
+                lens[perm[first[q] + r]] = m.sum()
+            # the step count is the longest row's
+            longest = max(lens[perm[first[q]:first[q + 1]]])
+            assert S == -(-(-(-longest // E)) // W)
+            # rows sorted by length, longest first, within the part
+            ls = lens[perm[first[q]:first[q + 1]]]
+            assert np.all(np.diff(ls) <= 0) and (prev is None or ls[0] <= prev)
+            prev = ls[-1]
+    return D, 2
+
+
 def _rebuild(dv, h, info, orient, n_rows, n_cols):
     """Dense matrix of one orientation from its layout arrays, plus invariants."""
     B = info.dose_block_rows if orient == 0 else info.price_block_rows
     layout = info.dose_layout if orient == 0 else info.price_layout
+    if layout == 2:
+        return _rebuild_sliced(dv, h, info, orient, n_rows, n_cols)
     rowptr = _array(dv, h, orient, 0, np.int64)
     vals = _array(dv, h, orient, 2, np.float32)
     units = _array(dv, h, orient, 3, np.int32)
@@ -108,7 +178,7 @@ def _dense(row, col, val, n_vox, n_bl):
 
 
 def _opts(dv, B=(1, 1), layout=(0, 0), grids=None, tiles=None, panel_cols=8192, order=(0, 0), interleave=1,
-          part_entries=131072, unit_entries=0):
+          part_entries=131072, unit_entries=0, slice_lanes=0):
     o = dv.BuildOpts()
     assert dv.lib.dvmat_ddc_default_opts(0, ctypes.byref(o)) == 0
     o.dose_block_rows, o.price_block_rows = B
@@ -118,6 +188,7 @@ def _opts(dv, B=(1, 1), layout=(0, 0), grids=None, tiles=None, panel_cols=8192, 
     o.panel_cols = panel_cols
     o.part_entries = part_entries
     o.unit_entries = unit_entries
+    o.dose_slice_lanes = o.price_slice_lanes = slice_lanes
     if grids is not None:
         o.dose_grid[:] = grids["dose_grid"]
         o.price_grid[:] = grids["price_grid"]
@@ -197,6 +268,59 @@ def test_unstructured_greedy_panels_and_fallback(dv):
     # a dense row wider than the budget keeps that orientation in CSR
     info, ld, lp = _check_both(dv, r, c, v, n_vox, n_bl, _opts(dv, (1, 1), (1, 1), panel_cols=500))
     assert ld == 0 and info.dose_panels == 0
+
+
+@pytest.mark.parametrize("W", [4, 8, 16])
+def test_sliced_panels_rebuild_the_matrix(dv, small, W):
+    row, col, val = small
+    info, ld, lp = _check_both(dv, row, col, val, PLAN.n_vox, PLAN.n_bl,
+                               _opts(dv, (1, 1), (2, 2), PLAN.grids, (dv.DOSE_TILE, dv.PRICE_TILE), slice_lanes=W,
+                                     part_entries=3000))
+    assert (ld, lp) == (2, 2) and info.dose_slice_lanes == W and info.price_slice_lanes == W
+    assert info.dose_panel_parts > info.dose_panels
+    # ragged tiles, a small budget, sliced dose with a panel-layout price
+    info, ld, lp = _check_both(dv, row, col, val, PLAN.n_vox, PLAN.n_bl,
+                               _opts(dv, (1, 2), (2, 1), PLAN.grids, ((6, 5, 3), (4, 4, 4)), panel_cols=2000,
+                                     slice_lanes=W))
+    assert (ld, lp) == (2, 1) and info.price_slice_lanes == 0
+
+
+@pytest.mark.parametrize("W", [4, 16])
+def test_sliced_panels_16bit_codes(dv, small, W):
+    """At 16-bit storage a lane's step holds 8 entries (16 bytes of codes);
+    every stored code is the FP16 rounding of D_ij / s_j."""
+    row, col, val = small
+    o = _opts(dv, (1, 1), (2, 2), PLAN.grids, (dv.DOSE_TILE, dv.PRICE_TILE), slice_lanes=W, part_entries=3000)
+    h, info = _create(dv, row, col, val, PLAN.n_vox, PLAN.n_bl, o, storage=1)
+    try:
+        assert (info.dose_layout, info.price_layout, info.value_bytes) == (2, 2, 2)
+        ref = _dense(row, col, val, PLAN.n_vox, PLAN.n_bl).astype(np.float32)
+        s = np.abs(ref).max(axis=0)
+        s[s == 0] = 1.0
+        q = (ref / s[None, :]).astype(np.float16).astype(np.float64) * s[None, :].astype(np.float64)
+        Dd, _ = _rebuild_sliced(dv, h, info, 0, PLAN.n_vox, PLAN.n_bl, scale=s.astype(np.float64))
+        Dp, _ = _rebuild_sliced(dv, h, info, 1, PLAN.n_bl, PLAN.n_vox, scale=s.astype(np.float64))
+        assert np.array_equal(Dd, q) and np.array_equal(Dp, q.T)
+    finally:
+        dv.lib.dvmat_ddc_destroy(h)
+
+
+def test_sliced_panels_unstructured_and_options(dv):
+    rng = np.random.default_rng(91)
+    n_vox, n_bl = 500, 600
+    mask = rng.random((n_vox, n_bl)) < 0.03
+    mask[50:60] = rng.random((10, n_bl)) < 0.8            # long rows
+    mask[200:290] = False                                 # more empty rows than one slice holds
+    r, c = np.nonzero(mask)
+    v = rng.uniform(0.001, 1, len(r)).astype(np.float32)
+    info, ld, lp = _check_both(dv, r, c, v, n_vox, n_bl, _opts(dv, (1, 1), (2, 2), panel_cols=1024, slice_lanes=8))
+    assert (ld, lp) == (2, 2)
+    # block rows other than 1 and unknown lane counts are refused
+    for o in (_opts(dv, (2, 1), (2, 0)), _opts(dv, (1, 1), (2, 0), slice_lanes=3)):
+        h = ctypes.c_void_p()
+        rr = np.ascontiguousarray(r, np.int32); cc = np.ascontiguousarray(c, np.int32)
+        assert dv.lib.dvmat_ddc_create_ex(n_vox, n_bl, len(v), rr.ctypes.data_as(P), cc.ctypes.data_as(P),
+                                          v.ctypes.data_as(P), 0, ctypes.byref(o), ctypes.byref(h)) == -1
 
 
 def test_grid_must_match_rows(dv, small):

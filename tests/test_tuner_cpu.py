@@ -24,7 +24,12 @@ def test_signature_and_cache_lookup(tmp_path, monkeypatch):
 def test_committed_cache_names_valid_options():
     """Every cached choice uses knobs the matrix build accepts."""
     from paper_1503_01721_amd import tuner
-    allowed = {"dose_tile", "price_tile", "dose_block_rows", "price_block_rows", "panel_cols", "part_entries"}
+    allowed = {"dose_tile", "price_tile", "dose_block_rows", "price_block_rows", "panel_cols", "part_entries",
+               "dose_layout", "price_layout", "dose_slice_lanes", "price_slice_lanes"}
     for sig, entry in tuner._load(tuner.DEFAULT_CACHE).items():
         assert set(entry["options"]) <= allowed, sig
         assert entry["options"].get("dose_block_rows", 1) in (1, 2, 4)
+        for side in ("dose", "price"):
+            if entry["options"].get(side + "_layout") == "sliced":
+                assert entry["options"].get(side + "_block_rows", 1) == 1
+                assert entry["options"].get(side + "_slice_lanes", 8) in (4, 8, 16)
