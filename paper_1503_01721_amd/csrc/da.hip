@@ -36,6 +36,7 @@ constexpr int kDaWaves = kDaThreads / 64;
 constexpr int kDaPerThread = 4;
 constexpr int kDaChunk = kDaThreads * kDaPerThread;   // voxels per workgroup
 constexpr int kDaGroup = 8;                            // columns whose loads go out together
+constexpr int kDaFanIn = 16;                           // chunk shares per group sum
 static_assert(kDaWaves == 4, "the share sums combine four waves");
 
 }  // namespace dvmat
@@ -53,10 +54,12 @@ struct dvmat_da_s {
     int32_t n_chunks = 0;
     float* cols = nullptr;       // [max_ap][n_rows]
     float* partial = nullptr;    // [max_ap + 1][n_chunks]: G shares, then F shares
+    double* gpart = nullptr;     // [max_ap + 1][n_groups]: group sums of the shares
     double* partial_d = nullptr; // [n_chunks]
     float* gbuf = nullptr;       // [n_vox] dF/dz when the caller does not keep it
     int32_t* d_m = nullptr;      // device copy of m, set by dvmat_da_append
-    uint32_t* arrived = nullptr; // workgroups done with a fused step (0 between launches)
+    uint32_t* arrived = nullptr; // [n_groups + 1]: workgroups of each group done, then groups done
+                                 // (0 between launches)
 };
 
 namespace dvmat {
@@ -67,11 +70,13 @@ static size_t da_layout(int64_t n_vox, int32_t max_ap, dvmat_da_s* d, char* base
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return base ? base + o : nullptr; };
     char* p;
     p = take((size_t)max_ap * n_vox * 4);           if (d) d->cols = reinterpret_cast<float*>(p);
+    const int64_t groups = (chunks + kDaFanIn - 1) / kDaFanIn;
     p = take((size_t)(max_ap + 1) * chunks * 4);    if (d) d->partial = reinterpret_cast<float*>(p);
+    p = take((size_t)(max_ap + 1) * groups * 8);    if (d) d->gpart = reinterpret_cast<double*>(p);
     p = take((size_t)chunks * 8);                   if (d) d->partial_d = reinterpret_cast<double*>(p);
     p = take((size_t)n_vox * 4);                    if (d) d->gbuf = reinterpret_cast<float*>(p);
     p = take(sizeof(int32_t));                      if (d) d->d_m = reinterpret_cast<int32_t*>(p);
-    p = take(sizeof(uint32_t));                     if (d) d->arrived = reinterpret_cast<uint32_t*>(p);
+    p = take((size_t)(groups + 1) * sizeof(uint32_t)); if (d) d->arrived = reinterpret_cast<uint32_t*>(p);
     p = take((size_t)n_vox * 4);                    if (d) d->support = reinterpret_cast<int32_t*>(p);
     p = take((size_t)n_vox);                        if (d) d->csid = reinterpret_cast<uint8_t*>(p);
     p = take(sizeof(int32_t));                      if (d) d->d_nsup = reinterpret_cast<int32_t*>(p);
@@ -90,9 +95,9 @@ __device__ __forceinline__ T wave_sum64(T v) {
 // per-wave shares of every G_k and of F (kDaWaves x (max_ap + 1) floats).
 static size_t da_lds_bytes(int max_ap) { return ((size_t)max_ap + (size_t)kDaWaves * (max_ap + 1)) * sizeof(float); }
 
-__global__ void da_set_count_kernel(int32_t* d_m, int m, uint32_t* arrived) {
-    *d_m = m;
-    *arrived = 0u;
+__global__ void da_set_count_kernel(int32_t* d_m, int m, uint32_t* arrived, int n_counters) {
+    if (threadIdx.x == 0) *d_m = m;
+    for (int i = threadIdx.x; i < n_counters; i += blockDim.x) arrived[i] = 0u;
 }
 
 // One workgroup's chunk of the evaluation: z and dF/dz of its voxels (stored
@@ -110,11 +115,10 @@ __device__ __forceinline__ void da_eval_chunk(const float* __restrict__ cols, in
     float* wpart = da_lds + max_ap;           // [kDaWaves][max_ap + 1]
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int64_t c0 = (int64_t)blockIdx.x * kDaChunk;
-    for (int k = threadIdx.x; k < m; k += kDaThreads) sy[k] = y[k];
-    __syncthreads();
     int64_t iv[kDaPerThread];
     bool in[kDaPerThread];
     float zi[kDaPerThread], gi[kDaPerThread];
+    int sid[kDaPerThread];
 #pragma unroll
     for (int u = 0; u < kDaPerThread; ++u) {
         iv[u] = c0 + u * kDaThreads + threadIdx.x;
@@ -122,15 +126,25 @@ __device__ __forceinline__ void da_eval_chunk(const float* __restrict__ cols, in
         zi[u] = 0.0f;
     }
     // z_i = sum_k DA_k,i y_k in the order of k; the loads of kDaGroup columns
-    // for all the thread's voxels are in flight together
-    // (a last, partial group loads and adds only its columns below m)
-    for (int k = 0; k < m; k += kDaGroup) {
-        float c[kDaGroup][kDaPerThread];
+    // for all the thread's voxels are in flight together (a last, partial
+    // group loads and adds only its columns below m).  The first group's
+    // loads, the structure ids and the rates go out together, before the
+    // barrier that publishes the rates in LDS.
+    float c[kDaGroup][kDaPerThread];
+    auto load_group = [&](int k) {
 #pragma unroll
         for (int j = 0; j < kDaGroup; ++j)
 #pragma unroll
             for (int u = 0; u < kDaPerThread; ++u)
                 c[j][u] = (in[u] && k + j < m) ? cols[(int64_t)(k + j) * n_rows + iv[u]] : 0.0f;
+    };
+    load_group(0);
+#pragma unroll
+    for (int u = 0; u < kDaPerThread; ++u) sid[u] = in[u] ? (int)rsid[iv[u]] : 0;
+    for (int k = threadIdx.x; k < m; k += kDaThreads) sy[k] = y[k];
+    __syncthreads();
+    for (int k = 0; k < m; k += kDaGroup) {
+        if (k > 0) load_group(k);
 #pragma unroll
         for (int j = 0; j < kDaGroup; ++j) {
             if (k + j < m) {
@@ -145,7 +159,7 @@ __device__ __forceinline__ void da_eval_chunk(const float* __restrict__ cols, in
     for (int u = 0; u < kDaPerThread; ++u) {
         gi[u] = 0.0f;
         if (in[u]) {
-            const int s = rsid[iv[u]];
+            const int s = sid[u];
             const float T = table[s * 4 + 0], wo = table[s * 4 + 1], wu = table[s * 4 + 2];
             const float over = fmaxf(zi[u] - T, 0.0f), under = fmaxf(T - zi[u], 0.0f);
             gi[u] = 2.0f * wo * over - 2.0f * wu * under;
@@ -187,95 +201,138 @@ __device__ __forceinline__ void da_eval_chunk(const float* __restrict__ cols, in
     }
 }
 
-__global__ __launch_bounds__(kDaThreads) void da_eval_kernel(const float* __restrict__ cols, int64_t n_rows,
-                                                             const int32_t* __restrict__ d_m,
-                                                             const float* __restrict__ y, const uint8_t* __restrict__ rsid,
-                                                             const int32_t* __restrict__ rows,
-                                                             const float* __restrict__ table, float* __restrict__ z,
-                                                             float* __restrict__ g, float* __restrict__ partial,
-                                                             int n_chunks, int max_ap) {
-    da_eval_chunk(cols, n_rows, *d_m, max_ap, y, rsid, rows, table, z, g, partial, n_chunks);
-}
 
-// G[k] = sum of the chunk shares (k < m), F = sum of the F shares; fixed order,
-// FP64; one workgroup of 256 threads takes kFinGroup share vectors at a time
-// with four chunks per thread per pass (16 loads in flight; the register
-// budget of the fused step, 64, bounds it), wave sums, then the four waves in
-// order.
-constexpr int kFinGroup = 4;
+// G[k] = sum of the chunk shares (k < m), F = sum of the F shares, in a fixed
+// order, FP64, as a two-level tree: the chunks form groups of kDaFanIn; the
+// last workgroup of a group to finish (a device-scope counter per group)
+// sums the group's shares in chunk order into gpart, and the last group to
+// finish (one more counter) sums the group sums in a fixed order into G and F.
+// Every evaluation (the separate one and the fused step) runs this same
+// tree, so their results agree bit for bit; each counter is reset by the
+// workgroup it elects.
 
-__device__ __forceinline__ void da_finalize_block(const float* __restrict__ partial, int m, int n_chunks,
-                                                  float* __restrict__ G, float* __restrict__ F) {
-    __shared__ double fin[kDaWaves][kFinGroup];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int k0 = 0; k0 <= m; k0 += kFinGroup) {
-        double a[kFinGroup];
+// Level 1: thread t takes share t % kDaFanIn of aperture t / kDaFanIn of the
+// current pass (32 apertures per pass, two loads per thread).
+__device__ __forceinline__ void da_group_sum(const float* __restrict__ partial, int m, int n_chunks, int grp,
+                                             int n_groups, double* __restrict__ gpart) {
+    __shared__ double s[2][kDaThreads];
+    constexpr int kPer = kDaThreads / kDaFanIn;          // apertures per half pass
+    const int c0 = grp * kDaFanIn;
+    const int nc = min(kDaFanIn, n_chunks - c0);
+    const int c = threadIdx.x % kDaFanIn, kk = threadIdx.x / kDaFanIn;
+    for (int kb = 0; kb <= m; kb += 2 * kPer) {
 #pragma unroll
-        for (int j = 0; j < kFinGroup; ++j) a[j] = 0.0;
-        for (int c0 = threadIdx.x; c0 < n_chunks; c0 += 4 * kDaThreads) {
-            float v[4][kFinGroup];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int c = c0 + q * kDaThreads;
-#pragma unroll
-                for (int j = 0; j < kFinGroup; ++j)
-                    v[q][j] = (c < n_chunks && k0 + j <= m) ? partial[(int64_t)(k0 + j) * n_chunks + c] : 0.0f;
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int j = 0; j < kFinGroup; ++j) a[j] += (double)v[q][j];
-        }
-#pragma unroll
-        for (int j = 0; j < kFinGroup; ++j) a[j] = wave_sum64(a[j]);
-        if (lane == 0) {
-#pragma unroll
-            for (int j = 0; j < kFinGroup; ++j) fin[wid][j] = a[j];
+        for (int h = 0; h < 2; ++h) {
+            const int k = kb + h * kPer + kk;
+            s[h][threadIdx.x] = (k <= m && c < nc) ? (double)partial[(int64_t)k * n_chunks + c0 + c] : 0.0;
         }
         __syncthreads();
-        const int kk = k0 + (int)threadIdx.x;
-        if ((int)threadIdx.x < kFinGroup && kk <= m) {
-            const double t = (fin[0][threadIdx.x] + fin[1][threadIdx.x]) + (fin[2][threadIdx.x] + fin[3][threadIdx.x]);
-            if (kk < m) G[kk] = (float)t;
+        if (c == 0) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int k = kb + h * kPer + kk;
+                if (k <= m) {
+                    double a = 0.0;
+                    for (int j = 0; j < nc; ++j) a += s[h][threadIdx.x + j];
+                    gpart[(int64_t)k * n_groups + grp] = a;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Level 2: strand t / 32 of aperture t % 32 sums the groups congruent to it
+// mod 8, in order; the eight strands are then added in order.
+__device__ __forceinline__ void da_total_sum(const double* __restrict__ gpart, int m, int n_groups,
+                                             float* __restrict__ G, float* __restrict__ F) {
+    constexpr int kStrands = kDaThreads / 32;
+    __shared__ double r[kStrands][32];
+    const int kk = threadIdx.x % 32, st = threadIdx.x / 32;
+    for (int kb = 0; kb <= m; kb += 32) {
+        const int k = kb + kk;
+        double a = 0.0;
+        if (k <= m) {
+#pragma unroll 8
+            for (int gi = st; gi < n_groups; gi += kStrands) a += gpart[(int64_t)k * n_groups + gi];
+        }
+        r[st][kk] = a;
+        __syncthreads();
+        if (threadIdx.x < 32 && k <= m) {
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < kStrands; ++q) t += r[q][kk];
+            if (k < m) G[k] = (float)t;
             else if (F) F[0] = (float)t;
         }
         __syncthreads();
     }
 }
 
-__global__ __launch_bounds__(256) void da_finalize_kernel(const float* __restrict__ partial,
-                                                          const int32_t* __restrict__ d_m, int n_chunks,
-                                                          float* __restrict__ G, float* __restrict__ F) {
-    da_finalize_block(partial, *d_m, n_chunks, G, F);
+// After a workgroup's shares are stored: the group and total elections and
+// the tree's sums.  Returns true in the one workgroup that wrote G and F.
+__device__ __forceinline__ bool da_reduce_shares(const float* __restrict__ partial, double* __restrict__ gpart,
+                                                 int m, int n_chunks, uint32_t* arrived, float* __restrict__ G,
+                                                 float* __restrict__ F) {
+    __shared__ int s_last;
+    const int n_groups = (n_chunks + kDaFanIn - 1) / kDaFanIn;
+    const int grp = (int)blockIdx.x / kDaFanIn;
+    const uint32_t in_group = (uint32_t)min(kDaFanIn, n_chunks - grp * kDaFanIn);
+    __syncthreads();                                   // every wave's shares are stored
+    if (threadIdx.x == 0) {
+        const uint32_t before = __hip_atomic_fetch_add(arrived + grp, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = before == in_group - 1;
+    }
+    __syncthreads();
+    if (!s_last) return false;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (threadIdx.x == 0) __hip_atomic_store(arrived + grp, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    da_group_sum(partial, m, n_chunks, grp, n_groups, gpart);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t before =
+            __hip_atomic_fetch_add(arrived + n_groups, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = before == (uint32_t)n_groups - 1;
+    }
+    __syncthreads();
+    if (!s_last) return false;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (threadIdx.x == 0) __hip_atomic_store(arrived + n_groups, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    da_total_sum(gpart, m, n_groups, G, F);
+    __syncthreads();
+    return true;
+}
+
+__global__ __launch_bounds__(kDaThreads) void da_eval_kernel(const float* __restrict__ cols, int64_t n_rows,
+                                                             const int32_t* __restrict__ d_m,
+                                                             const float* __restrict__ y, const uint8_t* __restrict__ rsid,
+                                                             const int32_t* __restrict__ rows,
+                                                             const float* __restrict__ table, float* __restrict__ z,
+                                                             float* __restrict__ g, float* __restrict__ partial,
+                                                             double* __restrict__ gpart, int n_chunks, int max_ap,
+                                                             uint32_t* arrived, float* __restrict__ G,
+                                                             float* __restrict__ F) {
+    const int m = *d_m;
+    da_eval_chunk(cols, n_rows, m, max_ap, y, rsid, rows, table, z, g, partial, n_chunks);
+    da_reduce_shares(partial, gpart, m, n_chunks, arrived, G, F);
 }
 
 // One BB iteration of the DA form in one launch: every workgroup evaluates its
-// chunk at the current rates (no z or dF/dz stored); the last workgroup to
-// finish (a device-scope counter; the acquire/release pair makes the other
-// workgroups' shares visible to it) sums the shares in the fixed order of
-// da_finalize_kernel and takes the BB step of bb_update_kernel, so the result
-// equals the three separate launches bit for bit.  It resets the counter for
-// the next launch.
+// chunk at the current rates (no z or dF/dz stored); the workgroup that the
+// share tree elects last also takes the BB step of bb_update_kernel, so the
+// result equals the separate evaluation + step launches bit for bit.
 __global__ __launch_bounds__(kDaThreads) void da_bb_step_kernel(const float* __restrict__ cols, int64_t n_rows,
                                                                 const int32_t* __restrict__ d_m,
                                                                 const uint8_t* __restrict__ rsid,
                                                                 const float* __restrict__ table,
-                                                                float* __restrict__ partial, int n_chunks,
+                                                                float* __restrict__ partial,
+                                                                double* __restrict__ gpart, int n_chunks,
                                                                 uint32_t* arrived, float* __restrict__ G,
                                                                 float* __restrict__ F, BBDev B, dvmat_bb_params prm,
                                                                 const double* curv, uint32_t* flags_out, int max_ap) {
-    __shared__ int s_last;
     const int m = *d_m;
     da_eval_chunk(cols, n_rows, m, max_ap, B.y, rsid, nullptr, table, nullptr, nullptr, partial, n_chunks);
-    if (threadIdx.x == 0) {
-        const uint32_t before = __hip_atomic_fetch_add(arrived, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = before == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (threadIdx.x == 0) __hip_atomic_store(arrived, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    da_finalize_block(partial, m, n_chunks, G, F);
+    if (!da_reduce_shares(partial, gpart, m, n_chunks, arrived, G, F)) return;
     bb_update_block(B, MODE_STEP, F, curv, flags_out, prm, G);
 }
 
@@ -452,8 +509,9 @@ dvmat_status dvmat_da_append(dvmat_da d, dvmat_ddc ddc, const float* x_ind, dvma
         hipLaunchKernelGGL(da_gather_rows_kernel, dim3((unsigned)std::max<int64_t>(nb, 1)), dim3(256), 0,
                            reinterpret_cast<hipStream_t>(stream), d->n_rows, d->rows, (const float*)d->gbuf, col);
     }
-    hipLaunchKernelGGL(da_set_count_kernel, dim3(1), dim3(1), 0, reinterpret_cast<hipStream_t>(stream), d->d_m,
-                       d->m + 1, d->arrived);
+    const int n_counters = (d->n_chunks + kDaFanIn - 1) / kDaFanIn + 1;
+    hipLaunchKernelGGL(da_set_count_kernel, dim3(1), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), d->d_m,
+                       d->m + 1, d->arrived, n_counters);
     if ((st = check_hip(hipGetLastError(), "dvmat_da_append launch"))) return st;
     d->m++;
     return DVMAT_OK;
@@ -467,8 +525,7 @@ dvmat_status dvmat_da_eval(dvmat_da d, dvmat_obj obj, const float* y, float* z, 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(da_eval_kernel, dim3(d->n_chunks), dim3(kDaThreads), da_lds_bytes(d->max_ap), s, d->cols,
                        d->n_rows, d->d_m, y, d->rows ? d->row_sid : obj->sid, d->rows, obj->table, z,
-                       g ? g : d->gbuf, d->partial, d->n_chunks, d->max_ap);
-    hipLaunchKernelGGL(da_finalize_kernel, dim3(1), dim3(256), 0, s, d->partial, d->d_m, d->n_chunks, G, F);
+                       g ? g : d->gbuf, d->partial, d->gpart, d->n_chunks, d->max_ap, d->arrived, G, F);
     return check_hip(hipGetLastError(), "dvmat_da_eval launch");
 }
 
@@ -481,8 +538,8 @@ dvmat_status dvmat_da_bb_step(dvmat_da d, dvmat_bb bb, dvmat_obj obj, float* G, 
         return set_error(DVMAT_E_STATE, "dvmat_da_bb_step: %d apertures but %d columns", bb->m, d->m);
     hipLaunchKernelGGL(da_bb_step_kernel, dim3(d->n_chunks), dim3(kDaThreads), da_lds_bytes(d->max_ap),
                        reinterpret_cast<hipStream_t>(stream), d->cols, d->n_rows, d->d_m,
-                       d->rows ? d->row_sid : obj->sid, obj->table, d->partial, d->n_chunks, d->arrived, G, F,
-                       bb->dev, bb->params, curv, flags, d->max_ap);
+                       d->rows ? d->row_sid : obj->sid, obj->table, d->partial, d->gpart, d->n_chunks, d->arrived,
+                       G, F, bb->dev, bb->params, curv, flags, d->max_ap);
     return check_hip(hipGetLastError(), "dvmat_da_bb_step launch");
 }
 

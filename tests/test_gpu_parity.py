@@ -1065,6 +1065,71 @@ def test_fused_da_step_equals_evaluation_then_step(dv, plan1, support):
         assert a[3] == b[3], t
 
 
+@pytest.mark.parametrize("support", [False, True])
+def test_da_many_apertures_share_tree(dv, support):
+    """64 apertures (every control point of a 64-angle plan): the shares of
+    G_k and F pass two levels of group sums over several passes of 32
+    apertures, and the share of F comes from the second wave; the evaluation
+    matches the oracle and the fused step matches evaluation + step bit for
+    bit."""
+    plan = synth.PLANS["cp64_bl12x12_vox40"]
+    d = synth.generate_ddc(plan)
+    sid, table = synth.structures(plan)
+    ddc = dv.DDC(d["row"], d["col"], d["val"], plan.n_vox, plan.n_bl, **plan.grids)
+    obj = dv.Objective(sid, table)
+    m = 64
+    cps, L, R = synth.random_apertures(plan, m, 71)
+    apset = obb.ApertureSet(plan.n_cp, plan.n_rows, plan.n_cols)
+    for k in range(m):
+        apset.add(cps[k], L[k], R[k])
+    DA = np.stack([oprod.aperture_ddc(d["row"], d["col"], d["val"], apset.owner == k, plan.n_vox)
+                   for k in range(m)], axis=1)
+    lo, hi = synth.random_boxes(m, 72)
+    runs = []
+    for fused in (False, True):
+        da = dv.DAColumns(plan.n_vox, m, obj=obj if support else None)
+        bb = dv.BB(plan.n_cp, plan.n_rows, plan.n_cols, m, max_iter=20, eps_f=0.0, eps_step=0.0)
+        for k in range(m):
+            one = dv.Apertures(plan.n_cp, plan.n_rows, plan.n_cols, cps[k:k + 1], L[k:k + 1], R[k:k + 1])
+            x_ind = torch.empty(plan.n_bl, device="cuda")
+            one.expand_(torch.ones(1, device="cuda"), x_ind)
+            da.append_(ddc, x_ind)
+            bb.add_aperture(int(cps[k]), cuda(L[k]), cuda(R[k]), float(lo[k]), float(hi[k] * 50.0))
+        y = np.random.default_rng(73).uniform(0.5, 4.0, m).astype(np.float32)
+        G = torch.empty(m, device="cuda")
+        F = torch.empty(1, device="cuda")
+        z = torch.zeros(plan.n_vox, device="cuda")
+        da.eval_(obj, torch.tensor(y, device="cuda"), G, z=z, F=F)
+        z_ref = DA @ y.astype(np.float64)
+        assert np.abs(z.cpu().numpy() - z_ref).max() <= TOL * z_ref.max()
+        F_ref = oobj.objective(z_ref, sid, table)
+        assert abs(float(F.cpu()[0]) - F_ref) <= 1e-5 * F_ref
+        gr = oobj.gradient(z_ref, sid, table)
+        G_ref = DA.T @ gr
+        assert np.all(np.abs(G.cpu().numpy() - G_ref) <= 1e-5 * (np.abs(DA).T @ np.abs(gr)).max())
+        # a few BB steps, fused or not
+        curv = torch.empty(1, dtype=torch.float64, device="cuda")
+        xd = torch.empty(plan.n_bl, device="cuda")
+        y_ptr, gt_ptr = bb.state_ptrs()
+        bb.begin()
+        da.eval_(obj, y_ptr, G, z=z, F=F)
+        bb.direction_g_(G, xd)
+        da.curvature_(obj, gt_ptr, z, curv)
+        bb.step_g_(G, F, curv, None)
+        trace = []
+        for t in range(4):
+            if fused:
+                da.bb_step_(bb, obj, G, F, curv)
+            else:
+                da.eval_(obj, y_ptr, G, F=F)
+                bb.step_g_(G, F, curv, None)
+            trace.append((bb.y().cpu().numpy().copy(), G.cpu().numpy().copy(), F.cpu().numpy().copy()))
+        runs.append(trace)
+    for t, (a, b) in enumerate(zip(*runs)):
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v), t
+
+
 # ---------------------------------------------------------------- machine constraints (Eq. 2 -> Eq. 6 boxes)
 
 
