@@ -182,10 +182,11 @@ def bench_batched(args):
         # multi-vector panels pay where a slice serves many rows: the dose (a
         # voxel tile touches few beamlets); a beamlet row alone touches ~2000
         # voxels, so the price stays in CSR
-        layout = {} if args.layout == "csr" else dict(dose_block_rows=args.batch_dose_b, panel_cols=args.panel_cols,
-                                                       dose_layout="panel", price_layout=args.batch_price_layout,
-                                                       **p.grids)
-        if args.batch_price_b:
+        layout = {} if args.layout == "csr" else dict(panel_cols=args.panel_cols, dose_layout=args.batch_dose_layout,
+                                                       price_layout=args.batch_price_layout, **p.grids)
+        if args.layout != "csr" and args.batch_dose_layout == "panel":
+            layout["dose_block_rows"] = args.batch_dose_b
+        if args.batch_price_b and args.batch_price_layout != "sliced":
             layout["price_block_rows"] = args.batch_price_b
         ddcs.append(dvmat.DDC(d["row"], d["col"], d["val"], p.n_vox, p.n_bl, storage=storage, **layout))
         t_build += time.perf_counter() - t
@@ -250,8 +251,9 @@ def bench_batched(args):
         "ms_per_step": round(t_batched * 1e3, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": storage, "data": "synthetic",
         "config": {"workload": f"{len(plans)} uneven plans x {nrhs} right-hand sides", "nnz_total": int(nnz),
-                   "layout": args.layout if args.layout == "csr" else f"panel (dose), {args.batch_price_layout} (price)",
-                   "dose_block_rows": args.batch_dose_b,
+                   "layout": args.layout if args.layout == "csr" else
+                   f"{args.batch_dose_layout} (dose), {args.batch_price_layout} (price)",
+                   "dose_block_rows": args.batch_dose_b if args.batch_dose_layout == "panel" else 1,
                    "panel_cols": args.panel_cols,
                    "storage": storage, "nrhs": nrhs, "algorithmic_bytes_per_step": int(total),
                    "csr_equivalent_gbs": round(total_csr / t_batched / 1e9, 2),
@@ -538,8 +540,10 @@ def main():
     ap.add_argument("--slabs", default="balanced", choices=["balanced", "equal"],
                     help="voxel slabs of --mode shard: equal entry counts (default) or equal thickness")
     ap.add_argument("--plans", type=int, default=48, help="plans in --mode batched")
-    ap.add_argument("--batch-price-layout", default="csr", choices=["csr", "panel"],
+    ap.add_argument("--batch-price-layout", default="csr", choices=["csr", "panel", "sliced"],
                     help="layout of the price orientation in --mode batched")
+    ap.add_argument("--batch-dose-layout", default="sliced", choices=["panel", "sliced"],
+                    help="layout of the dose orientation in --mode batched")
     ap.add_argument("--batch-dose-b", type=int, default=1, help="rows per block row of the dose in --mode batched")
     ap.add_argument("--batch-price-b", type=int, default=0,
                     help="rows per block row of the price in --mode batched (0: the library's default)")

@@ -489,12 +489,12 @@ dvmat_status dvmat_bb_get_y(dvmat_bb bb, float* y, dvmat_stream stream);
  * very different sizes share the GPU without a launch per plan.  (The paper
  * suggests lending idle GPUs to another plan, Sec. 4; here the plans share
  * one GPU.)  All plans must be bound and share a storage type, the block
- * rows and, per orientation, the layout (CSR or panels; sliced panels are
- * refused with DVMAT_E_ARG); n <= 64.  With panels the work list
+ * rows and, per orientation, the layout (and, for sliced panels, the lanes
+ * per row); n <= 64.  With panels the work list
  * is the plans' panel parts, each staging its panel's slice of the input
- * vectors in LDS; right-hand sides beyond what LDS holds go in chunks, one
- * launch each (plans built with panel_cols <= 3584 take 4 right-hand sides per
- * launch).
+ * vectors in LDS (a sliced plan's slices run as in the single-plan product);
+ * right-hand sides beyond what LDS holds go in chunks, one launch each (plans
+ * built with panel_cols <= 3584 take 4 right-hand sides per launch).
  * ---------------------------------------------------------------------- */
 typedef struct dvmat_batch_s* dvmat_batch;
 

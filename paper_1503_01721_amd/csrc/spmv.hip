@@ -354,6 +354,7 @@ struct dvmat_batch_s {
     dvmat::KernelCfg dose_cfg{}, price_cfg{};
     int dose_B = 1, price_B = 1;
     int dose_layout = 0, price_layout = 0;
+    int dose_W = 0, price_W = 0;                   // lanes per row of sliced panels
     int64_t dose_max_cols = 0, price_max_cols = 0; // largest panel column list over the plans
 };
 
@@ -411,8 +412,10 @@ static dvmat_status batch_call(dvmat_batch_s* bt, bool dose, const KernelCfg& cf
         B.x[i] = in[i];
         B.y[i] = out[i];
     }
-    if ((dose ? bt->dose_layout : bt->price_layout) == 1)
-        return launch_batch_panel(bt->storage, dose ? bt->dose_B : bt->price_B,
+    const int layout = dose ? bt->dose_layout : bt->price_layout;
+    const int Bk = layout == 2 ? -(dose ? bt->dose_W : bt->price_W) : (dose ? bt->dose_B : bt->price_B);
+    if (layout >= 1)
+        return launch_batch_panel(bt->storage, Bk,
                                   !dose && bt->storage != DVMAT_F32, dose && bt->storage != DVMAT_F32,
                                   dose ? bt->dose_max_cols : bt->price_max_cols, B, nrhs, cfg.workgroups, s);
     if (dose) launch_batch<true>(bt, cfg, B, nrhs, s);
@@ -666,9 +669,9 @@ dvmat_status dvmat_batch_create(const dvmat_ddc* ddcs, int32_t n, void* ws, size
             return set_error(DVMAT_E_ARG, "dvmat_batch_create: plan %d has a different block-row layout", i);
         if (d->dose.layout != ddcs[0]->dose.layout || d->price.layout != ddcs[0]->price.layout)
             return set_error(DVMAT_E_ARG, "dvmat_batch_create: plan %d has a different layout (CSR / panels)", i);
-        if (d->dose.layout == 2 || d->price.layout == 2)
-            return set_error(DVMAT_E_ARG, "dvmat_batch_create: plan %d uses sliced panels; the batched launch takes "
-                             "CSR or panels", i);
+        if ((d->dose.layout == 2 && d->dose.slice_lanes != ddcs[0]->dose.slice_lanes) ||
+            (d->price.layout == 2 && d->price.slice_lanes != ddcs[0]->price.slice_lanes))
+            return set_error(DVMAT_E_ARG, "dvmat_batch_create: plan %d has different lanes per row of its slices", i);
         auto plan = [](const CsrDev& c, const float* scale, int64_t base) {
             PlanDev q{};
             q.rowptr = c.rowptr;
@@ -680,7 +683,7 @@ dvmat_status dvmat_batch_create(const dvmat_ddc* ddcs, int32_t n, void* ws, size
             q.perm_runs = c.perm_runs;
             q.n_rows = c.n_rows;
             q.block_base = base;
-            q.n_blocks = c.layout == 1 ? c.n_parts : c.n_blocks;
+            q.n_blocks = c.layout >= 1 ? c.n_parts : c.n_blocks;
             q.col16 = c.col16;
             q.ulist = c.ulist;
             q.panel_u = c.panel_u;
@@ -708,12 +711,14 @@ dvmat_status dvmat_batch_create(const dvmat_ddc* ddcs, int32_t n, void* ws, size
     bt->price_blocks = bp;
     bt->dose_layout = ddcs[0]->dose.layout;
     bt->price_layout = ddcs[0]->price.layout;
+    bt->dose_W = ddcs[0]->dose.slice_lanes;
+    bt->price_W = ddcs[0]->price.slice_lanes;
     bt->dose_max_cols = max_cols_d;
     bt->price_max_cols = max_cols_p;
     bt->dose_cfg = default_cfg();
     bt->price_cfg = default_cfg();
-    if (bt->dose_layout == 1) bt->dose_cfg.kind = KIND_PANEL;
-    if (bt->price_layout == 1) bt->price_cfg.kind = KIND_PANEL;
+    if (bt->dose_layout >= 1) bt->dose_cfg.kind = KIND_PANEL;
+    if (bt->price_layout >= 1) bt->price_cfg.kind = KIND_PANEL;
     for (int i = 0; i < n; ++i) {
         bt->n_vox.push_back(ddcs[i]->n_vox);
         bt->n_bl.push_back(ddcs[i]->n_bl);
@@ -751,11 +756,11 @@ dvmat_status dvmat_batch_autotune(dvmat_batch b, const float* const* xs, float* 
     KernelCfg best{};
     float ms = 0.0f;
     dvmat_status st = tune([&](const KernelCfg& c) { return batch_call(b, true, c, xs, nrhs, zs, s, "dvmat_batch_autotune"); },
-                           reps, s, &best, &ms, b->dose_B, false, b->dose_layout == 1);
+                           reps, s, &best, &ms, b->dose_B, false, b->dose_layout >= 1);
     if (st) return st;
     b->dose_cfg = best;
     st = tune([&](const KernelCfg& c) { return batch_call(b, false, c, gs, nrhs, ps, s, "dvmat_batch_autotune"); },
-              reps, s, &best, &ms, b->price_B, false, b->price_layout == 1);
+              reps, s, &best, &ms, b->price_B, false, b->price_layout >= 1);
     if (st) return st;
     b->price_cfg = best;
     return DVMAT_OK;
@@ -769,7 +774,7 @@ dvmat_status dvmat_batch_set_kernel(dvmat_batch b, int32_t orientation, int32_t 
         return set_error(DVMAT_E_ARG, "dvmat_batch_set_kernel: workgroups %d not in [8, 8192]", workgroups);
     if (orientation == 0 || orientation == 1) {
         const int layout = orientation == 0 ? b->dose_layout : b->price_layout;
-        if ((kind == KIND_PANEL) != (layout == 1))
+        if ((kind == KIND_PANEL) != (layout >= 1))
             return set_error(DVMAT_E_ARG, "dvmat_batch_set_kernel: kind 3 (panel) goes with the panel layout and only there");
         if (kind == KIND_STREAM && (orientation == 0 ? b->dose_B : b->price_B) != 1)
             return set_error(DVMAT_E_ARG, "dvmat_batch_set_kernel: the stream kernel needs one row per block row");

@@ -651,9 +651,10 @@ struct BatchParams {
     float* y[kMaxBatch];
 };
 
-// Batched products on the panel layout (spmv_panel.hip): right-hand sides
+// Batched products on the panel layouts (spmv_panel.hip): right-hand sides
 // [h0, h0 + chunk) of nrhs, chunk by chunk; scale_stage multiplies the staged
-// slice by the per-beamlet scale (16-bit dose).
+// slice by the per-beamlet scale (16-bit dose).  B: rows per block row of the
+// panel layout, or minus the lanes per row of the sliced layout.
 dvmat_status launch_batch_panel(int storage, int B, int epi_scale, bool scale_stage, int64_t max_panel_cols,
                                 const BatchParams& Bp, int nrhs, int workgroups, hipStream_t s);
 

@@ -294,12 +294,54 @@ __device__ __forceinline__ void slice_rows(const SpmvParams& P, const SliceDesc&
     if (act && lane % W == 0) row_epilogue<R, EPI>(P, nat, e, tab, sum, fpart, cpart);
 }
 
-// Parts of sliced panels: the staging of the panel kernel, then the part's
-// slices in a fixed order: a part's slices are sorted longest first, and wave w
-// takes slice w of each round of eight, in reverse order every second round,
-// so that each wave's share of a part comes out about even.  The descriptors
-// of a wave's next 64 slices are read one per lane (during the staging for
-// the first 64), so a slice starts without a round trip for them.
+// A part of sliced panels after its staging: the part's slices in a fixed
+// order: a part's slices are sorted longest first, and wave w takes slice w
+// of each round of NW, in reverse order every second round, so that each
+// wave's share of a part comes out about even.  The descriptors of a wave's
+// next 64 slices are read one per lane (SliceLanes; the caller reads the
+// first 64 before the staging), so a slice starts without a round trip for
+// them.
+struct SliceLanes {
+    int p0 = 0, p1 = 0;
+    int64_t b0 = 0, b1 = 0;
+};
+
+template <int NW>
+__device__ __forceinline__ int slice_of(int q0, int r, int wid) {
+    return q0 + r * NW + ((r & 1) ? NW - 1 - wid : wid);
+}
+
+template <int NW>
+__device__ __forceinline__ SliceLanes slice_lanes(const SpmvParams& P, int q0, int q1, int wid, int lane, int rb) {
+    SliceLanes l;
+    const int qj = slice_of<NW>(q0, rb + lane, wid);
+    if (qj < q1) {
+        l.p0 = P.blocks[qj];
+        l.p1 = P.blocks[qj + 1];
+        l.b0 = P.rowptr[qj];
+        l.b1 = P.rowptr[qj + 1];
+    }
+    return l;
+}
+
+template <int ST, int R, int EPI, int W, int NW>
+__device__ __forceinline__ void slice_part(const SpmvParams& P, const uint16_t* col16, int q0, int q1, int wid,
+                                           int lane, SliceLanes dl, const f32x4* tab, float (&fpart)[R],
+                                           double& cpart, const float* xs) {
+    for (int rb = 0; slice_of<NW>(q0, rb, wid) < q1; rb += kWaveSize) {
+        if (rb > 0) dl = slice_lanes<NW>(P, q0, q1, wid, lane, rb);
+        for (int j = 0; j < kWaveSize && slice_of<NW>(q0, rb + j, wid) < q1; ++j) {
+            SliceDesc d;
+            d.p0 = __builtin_amdgcn_readlane(dl.p0, j);
+            d.nr = __builtin_amdgcn_readlane(dl.p1, j) - d.p0;
+            const int64_t b0 = readlane64(dl.b0, j);
+            d.base = b0;
+            d.len = (int)(readlane64(dl.b1, j) - b0);
+            slice_rows<ST, R, EPI, W>(P, d, lane, tab, fpart, cpart, xs, col16);
+        }
+    }
+}
+
 template <int ST, int R, int EPI, int W>
 __global__ __launch_bounds__(kPanelThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void spmv_slice_kernel(
     SpmvParams P, PanelParams Q) {
@@ -320,37 +362,12 @@ __global__ __launch_bounds__(kPanelThreads) __attribute__((amdgpu_waves_per_eu(8
         const int64_t u0 = Q.panel_u[p];
         const int nu = (int)(Q.panel_u[p + 1] - u0);
         const int q0 = Q.part_units[t], q1 = Q.part_units[t + 1];
-        auto slice_of = [&](int r) { return q0 + r * kWaves + ((r & 1) ? kWaves - 1 - wid : wid); };
-        int dp0 = 0, dp1 = 0;
-        int64_t db0 = 0, db1 = 0;
-        auto lane_desc = [&](int rb) {
-            const int qj = slice_of(rb + lane);
-            dp0 = dp1 = 0;
-            db0 = db1 = 0;
-            if (qj < q1) {
-                dp0 = P.blocks[qj];
-                dp1 = P.blocks[qj + 1];
-                db0 = P.rowptr[qj];
-                db1 = P.rowptr[qj + 1];
-            }
-        };
         __syncthreads();                              // the previous panel's gathers are done
-        lane_desc(0);
+        const SliceLanes dl = slice_lanes<kWaves>(P, q0, q1, wid, lane, 0);
         // a part of rows without entries (outside the body) needs no slice
         if (P.rowptr[q1] > P.rowptr[q0]) stage_slice<R, false>(xs, Q.ulist + u0, nu, Q.x, Q.ldx, nullptr);
         __syncthreads();
-        for (int rb = 0; slice_of(rb) < q1; rb += kWaveSize) {
-            if (rb > 0) lane_desc(rb);
-            for (int j = 0; j < kWaveSize && slice_of(rb + j) < q1; ++j) {
-                SliceDesc d;
-                d.p0 = __builtin_amdgcn_readlane(dp0, j);
-                d.nr = __builtin_amdgcn_readlane(dp1, j) - d.p0;
-                const int64_t b0 = readlane64(db0, j);
-                d.base = b0;
-                d.len = (int)(readlane64(db1, j) - b0);
-                slice_rows<ST, R, EPI, W>(P, d, lane, s_tab, fpart, cpart, xs, Q.col16);
-            }
-        }
+        slice_part<ST, R, EPI, W, kWaves>(P, Q.col16, q0, q1, wid, lane, dl, s_tab, fpart, cpart, xs);
     }
     workgroup_partials_n<R, EPI, kWaves>(P, lane, wid, fpart, cpart);
 }
@@ -484,15 +501,67 @@ __global__ __launch_bounds__(kBatchPanelThreads) __attribute__((amdgpu_waves_per
     }
 }
 
+// The batched launch over plans in the sliced panel layout: the same part
+// walk, each part's slices as in spmv_slice_kernel (sixteen waves).
+template <int ST, int R, int EPI, int W, bool SCALE_STAGE>
+__global__ __launch_bounds__(kBatchPanelThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void spmv_batch_slice_kernel(
+    BatchParams Bp, int h0, int nrhs) {
+    constexpr int kWaves = kBatchPanelThreads / kWaveSize;
+    static_assert(EPI == EPI_PLAIN || EPI == EPI_SCALE, "the batched launch has no objective epilogue");
+    extern __shared__ float xs[];
+    const int lane = threadIdx.x & (kWaveSize - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWaveSize);
+    float fpart[R];
+#pragma unroll
+    for (int h = 0; h < R; ++h) fpart[h] = 0.0f;
+    double cpart = 0.0;
+    int p = 0;
+    for (int64_t t = blockIdx.x; t < Bp.total_blocks; t += gridDim.x) {
+        while (p + 1 < Bp.n_plans && Bp.plans[p + 1].block_base <= t) ++p;      // t only grows
+        const PlanDev& pd = Bp.plans[p];
+        const int64_t tl = t - pd.block_base;
+        const int pan = pd.part_panel[tl];
+        const int64_t u0 = pd.panel_u[pan];
+        const int nu = (int)(pd.panel_u[pan + 1] - u0);
+        SpmvParams P{};
+        P.n_rows = pd.n_rows;
+        P.perm = pd.perm;
+        P.rowptr = pd.rowptr;
+        P.val = pd.val;
+        P.blocks = pd.blocks;
+        P.y = Bp.y[p] + h0;
+        P.ld = nrhs;
+        P.row_scale = pd.scale;
+        const int q0 = pd.part_units[tl], q1 = pd.part_units[tl + 1];
+        __syncthreads();                              // the previous part's gathers are done
+        const SliceLanes dl = slice_lanes<kWaves>(P, q0, q1, wid, lane, 0);
+        if (P.rowptr[q1] > P.rowptr[q0])
+            stage_slice<R, SCALE_STAGE, kBatchPanelThreads>(xs, pd.ulist + u0, nu, Bp.x[p] + h0, nrhs, pd.scale);
+        __syncthreads();
+        slice_part<ST, R, EPI, W, kWaves>(P, pd.col16, q0, q1, wid, lane, dl, nullptr, fpart, cpart, xs);
+    }
+}
+
 template <int ST, int R, int EPI, int B, bool SCALE_STAGE>
 static void launch_batch_one(int nwg, size_t lds, const BatchParams& Bp, int h0, int nrhs, hipStream_t s) {
     hipLaunchKernelGGL((spmv_batch_panel_kernel<ST, R, EPI, B, SCALE_STAGE>), dim3(nwg), dim3(kBatchPanelThreads),
                        lds, s, Bp, h0, nrhs);
 }
 
+template <int ST, int R, int EPI, int W, bool SCALE_STAGE>
+static void launch_batch_slice(int nwg, size_t lds, const BatchParams& Bp, int h0, int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL((spmv_batch_slice_kernel<ST, R, EPI, W, SCALE_STAGE>), dim3(nwg), dim3(kBatchPanelThreads),
+                       lds, s, Bp, h0, nrhs);
+}
+
+// B > 0: rows per block row of the panel layout; B < 0: -B lanes per row of
+// the sliced layout.
 template <int ST, int R, int EPI, bool SCALE_STAGE>
 static void launch_batch_chunk(int B, int nwg, size_t lds, const BatchParams& Bp, int h0, int nrhs, hipStream_t s) {
-    if (B == 4) launch_batch_one<ST, R, EPI, 4, SCALE_STAGE>(nwg, lds, Bp, h0, nrhs, s);
+    if (B == -16) launch_batch_slice<ST, R, EPI, 16, SCALE_STAGE>(nwg, lds, Bp, h0, nrhs, s);
+    else if (B == -8) launch_batch_slice<ST, R, EPI, 8, SCALE_STAGE>(nwg, lds, Bp, h0, nrhs, s);
+    else if (B < 0) launch_batch_slice<ST, R, EPI, 4, SCALE_STAGE>(nwg, lds, Bp, h0, nrhs, s);
+    else if (B == 4) launch_batch_one<ST, R, EPI, 4, SCALE_STAGE>(nwg, lds, Bp, h0, nrhs, s);
     else if (B == 2) launch_batch_one<ST, R, EPI, 2, SCALE_STAGE>(nwg, lds, Bp, h0, nrhs, s);
     else launch_batch_one<ST, R, EPI, 1, SCALE_STAGE>(nwg, lds, Bp, h0, nrhs, s);
 }

@@ -110,10 +110,11 @@ def test_batch_graph_capture_replays(plans):
             assert torch.equal(a, b), rep
 
 
-def _panel_ddcs(storage, cap=3584):
-    """The same plans in the panel layout: tiles of the plans' grids, greedy
-    panels in natural order for the unstructured matrix; a column budget that
-    lets 4 right-hand sides share LDS (8 go in two chunks)."""
+def _panel_ddcs(storage, cap=3584, layout="panel"):
+    """The same plans in the panel layout (or sliced panels): tiles of the
+    plans' grids, greedy panels in natural order for the unstructured matrix;
+    a column budget that lets 4 right-hand sides share LDS (8 go in two
+    chunks)."""
     from paper_1503_01721_amd import dvmat
     names = ["tiny_cp4_bl3x4_vox8", "small_cp8_bl6x6_vox16", "cp20_bl20x20_vox32", "cp64_bl12x12_vox40"]
     out = []
@@ -122,20 +123,22 @@ def _panel_ddcs(storage, cap=3584):
         d = synth.generate_ddc(pl)
         out.append((pl.n_vox, pl.n_bl, d, dvmat.DDC(d["row"], d["col"], d["val"], pl.n_vox, pl.n_bl, storage=storage,
                                                      dose_block_rows=1, price_block_rows=1, panel_cols=cap,
-                                                     dose_layout="panel", price_layout="panel", **pl.grids)))
+                                                     dose_layout=layout, price_layout=layout, **pl.grids)))
     d = synth.random_sparse(3001, 517, 0.02, 5, empty_rows=300, empty_cols=40)
     out.append((3001, 517, d, dvmat.DDC(d["row"], d["col"], d["val"], 3001, 517, storage=storage, dose_block_rows=1,
-                                        price_block_rows=1, dose_layout="panel", price_layout="panel", panel_cols=cap)))
+                                        price_block_rows=1, dose_layout=layout, price_layout=layout, panel_cols=cap)))
     return out
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 @pytest.mark.parametrize("nrhs", [1, 2, 8])
-def test_batch_panel_layout_matches_oracle(storage, nrhs):
+@pytest.mark.parametrize("layout", ["panel", "sliced"])
+def test_batch_panel_layout_matches_oracle(storage, nrhs, layout):
     from paper_1503_01721_amd import dvmat
-    items = _panel_ddcs(storage)
+    items = _panel_ddcs(storage, layout=layout)
+    want = 1 if layout == "panel" else 2
     for _, _, _, x in items:
-        assert (x.info.dose_layout, x.info.price_layout) == (1, 1)
+        assert (x.info.dose_layout, x.info.price_layout) == (want, want)
     batch = dvmat.Batch([x for *_, x in items])
     info = batch.info()
     assert info["dose_kernel"] == 3 and info["price_kernel"] == 3
@@ -166,9 +169,10 @@ def test_batch_panel_layout_matches_oracle(storage, nrhs):
         dvmat.Batch([items[1][3], csr])
 
 
-def test_batch_panel_graph_capture_replays():
+@pytest.mark.parametrize("layout", ["panel", "sliced"])
+def test_batch_panel_graph_capture_replays(layout):
     from paper_1503_01721_amd import dvmat
-    items = _panel_ddcs("f16")
+    items = _panel_ddcs("f16", layout=layout)
     batch = dvmat.Batch([x for *_, x in items])
     rng = np.random.default_rng(8)
     xt = [torch.from_numpy(rng.random((nb, 8)).astype(np.float32)).cuda() for nv, nb, _, _ in items]

@@ -138,7 +138,7 @@ def test_sliced_layout_unstructured(dv, wg, W):
             assert np.abs(p - p_ref).max() <= TOL * oprod.price(r, c, v, np.abs(g), n_bl).max()
 
 
-def test_sliced_layout_edges_and_batch_refusal(dv, plan1):
+def test_sliced_layout_edges_and_batch_lanes(dv, plan1):
     # an empty matrix, and a single entry
     for r, c, v in ((np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32)),
                     (np.array([7], np.int32), np.array([3], np.int32), np.array([0.5], np.float32))):
@@ -148,8 +148,12 @@ def test_sliced_layout_edges_and_batch_refusal(dv, plan1):
         assert np.array_equal(z, oprod.dose(r, c, v, np.ones(30), 100).astype(np.float32))
         assert np.array_equal(p, oprod.price(r, c, v, np.ones(100), 30).astype(np.float32))
     d, _, _, _ = plan1
-    sl = dv.DDC(d["row"], d["col"], d["val"], PLAN1.n_vox, PLAN1.n_bl, dose_layout="sliced", **PLAN1.grids)
-    with pytest.raises(dv.DvmatError):
-        dv.Batch([sl])
+    sl = dv.DDC(d["row"], d["col"], d["val"], PLAN1.n_vox, PLAN1.n_bl, dose_layout="sliced", price_layout="sliced",
+                slice_lanes=8, **PLAN1.grids)
+    sl4 = dv.DDC(d["row"], d["col"], d["val"], PLAN1.n_vox, PLAN1.n_bl, dose_layout="sliced", price_layout="sliced",
+                 slice_lanes=4, **PLAN1.grids)
+    with pytest.raises(dv.DvmatError):                  # a batch's sliced plans share their lanes per row
+        dv.Batch([sl, sl4])
+    dv.Batch([sl, sl])
     with pytest.raises(dv.DvmatError):
         sl.set_kernel("dose", "row", 1024)
