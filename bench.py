@@ -366,9 +366,12 @@ def bench_shard(args):
     log(f"generated slab {s} of {G} (slices {z0}..{z1 - 1}) of {plan.name}: nnz={len(d['val'])} in {t_gen:.1f} s")
     t = time.perf_counter()
     layout = grid_layout(args, {"dose_grid": (N, N, z1 - z0), "price_grid": plan.grids["price_grid"]})
-    # a thin slab leaves each beamlet row a few hundred entries: two rows per
-    # block row halve the reductions (partial price 0.560 against 0.666 ms)
-    ddc = dvmat.DDC(d["row"], d["col"], d["val"], n_vox, plan.n_bl, storage=storage, price_block_rows=2, **layout)
+    # a thin slab leaves each beamlet row a few hundred entries: the sliced
+    # layout (the default with grids) runs such short rows in lock step; in
+    # CSR two rows per block row halve the reductions
+    if args.layout == "csr":
+        layout["price_block_rows"] = 2
+    ddc = dvmat.DDC(d["row"], d["col"], d["val"], n_vox, plan.n_bl, storage=storage, **layout)
     del d
     obj = dvmat.Objective(sid, table)
     t_build = time.perf_counter() - t

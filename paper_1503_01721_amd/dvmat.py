@@ -234,7 +234,8 @@ class DDC:
         (columns, MLC rows, control points), fastest axis first.  With a grid
         the orientation defaults to the sliced panel layout, the fastest
         measured (tiles DOSE_TILE, or DOSE_TILE_16BIT at 16-bit storage, and
-        PRICE_TILE); without one, to CSR.  *_layout: "csr", "panel" or "sliced" (panels whose rows, sorted
+        PRICE_TILE), or to panels when block rows of several rows are asked
+        for; without one, to CSR.  *_layout: "csr", "panel" or "sliced" (panels whose rows, sorted
         by length, run in slices of 64 / W rows with W lanes per row: W from
         dose_slice_lanes / price_slice_lanes, or slice_lanes for both)."""
         row = np.ascontiguousarray(row, dtype=np.int32)
@@ -255,10 +256,12 @@ class DDC:
             if v is not None:
                 setattr(opts, name, int(v))
         dose_dflt = DOSE_TILE if storage == "f32" else DOSE_TILE_16BIT
-        for side, grid, lay, tile, dflt in (("dose", dose_grid, dose_layout, dose_tile, dose_dflt),
-                                            ("price", price_grid, price_layout, price_tile, PRICE_TILE)):
+        for side, grid, lay, tile, dflt, B in (
+                ("dose", dose_grid, dose_layout, dose_tile, dose_dflt, dose_block_rows),
+                ("price", price_grid, price_layout, price_tile, PRICE_TILE, price_block_rows)):
             if lay is None:
-                lay = "sliced" if grid is not None else "csr"
+                # block rows of several rows exist in panels and CSR only
+                lay = ("panel" if B is not None and B > 1 else "sliced") if grid is not None else "csr"
             setattr(opts, side + "_layout", LAYOUTS[lay])
             if grid is not None:
                 getattr(opts, side + "_grid")[:] = [int(v) for v in grid]
