@@ -67,6 +67,11 @@ def grid_layout(args, grids):
     out = dict(grids)
     if args.layout in ("panel", "sliced"):
         out.update(dose_layout=args.layout, price_layout=args.layout)
+    if args.layout != "panel":
+        if args.dose_lanes:
+            out["dose_slice_lanes"] = args.dose_lanes
+        if args.price_lanes:
+            out["price_slice_lanes"] = args.price_lanes
     return out
 
 
@@ -559,6 +564,10 @@ def main():
                     help="device layout of both orientations: grid (default: the tuner's cached choice of "
                          "panel layouts, else the library's default, sliced panels), sliced or panel forced "
                          "(vector slices staged in LDS), or CSR (gathers from global memory)")
+    ap.add_argument("--dose-lanes", type=int, default=0, choices=[0, 4, 8, 16],
+                    help="sliced layout: lanes per dose row (0: the library's default)")
+    ap.add_argument("--price-lanes", type=int, default=0, choices=[0, 4, 8, 16],
+                    help="sliced layout: lanes per price row (0: the library's default)")
     ap.add_argument("--tune", action="store_true",
                     help="time the candidate layouts first and cache the fastest (DVMAT_TUNE_CACHE)")
     ap.add_argument("--no-tuned-layout", action="store_true", help="ignore the tuner cache: library defaults")

@@ -138,8 +138,10 @@ typedef struct {
  * partial step each.  Rows shorter than their slice's longest are padded
  * with zeros to its step count.  Rows without entries form slices of up to
  * 64 rows with no steps.  A slice is the work unit (n_blocks counts slices).
- * W in {4, 8, 16} (0: the fastest measured, 8 but 4 for the dose at 16-bit
- * storage); layout 2 needs block_rows 1 (0 resolves to 1). */
+ * W in {4, 8, 16}; 0 chooses W from the orientation's mean non-empty row
+ * length (the W whose slices take closest to 32 steps for such a row: more
+ * lanes per row for longer rows); layout 2 needs block_rows 1 (0 resolves to
+ * 1).  dvmat_ddc_info reports the lanes built. */
 typedef struct {
     int32_t dose_block_rows;
     int32_t price_block_rows;
