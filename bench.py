@@ -191,6 +191,11 @@ def bench_batched(args):
                                                        price_layout=args.batch_price_layout, **p.grids)
         if args.layout != "csr" and args.batch_dose_layout == "panel":
             layout["dose_block_rows"] = args.batch_dose_b
+        # the plans of a batch share their lanes per row (the library would
+        # choose them per plan from the rows' lengths)
+        if args.layout != "csr":
+            layout["dose_slice_lanes"] = args.dose_lanes or 4
+            layout["price_slice_lanes"] = args.price_lanes or 8
         if args.batch_price_b and args.batch_price_layout != "sliced":
             layout["price_block_rows"] = args.batch_price_b
         ddcs.append(dvmat.DDC(d["row"], d["col"], d["val"], p.n_vox, p.n_bl, storage=storage, **layout))

@@ -492,7 +492,8 @@ dvmat_status dvmat_bb_get_y(dvmat_bb bb, float* y, dvmat_stream stream);
  * suggests lending idle GPUs to another plan, Sec. 4; here the plans share
  * one GPU.)  All plans must be bound and share a storage type, the block
  * rows and, per orientation, the layout (and, for sliced panels, the lanes
- * per row); n <= 64.  With panels the work list
+ * per row: build such plans with explicit lanes, since lanes left at 0 follow
+ * each plan's row lengths); n <= 64.  With panels the work list
  * is the plans' panel parts, each staging its panel's slice of the input
  * vectors in LDS (a sliced plan's slices run as in the single-plan product);
  * right-hand sides beyond what LDS holds go in chunks, one launch each (plans

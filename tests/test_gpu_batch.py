@@ -123,10 +123,12 @@ def _panel_ddcs(storage, cap=3584, layout="panel"):
         d = synth.generate_ddc(pl)
         out.append((pl.n_vox, pl.n_bl, d, dvmat.DDC(d["row"], d["col"], d["val"], pl.n_vox, pl.n_bl, storage=storage,
                                                      dose_block_rows=1, price_block_rows=1, panel_cols=cap,
-                                                     dose_layout=layout, price_layout=layout, **pl.grids)))
+                                                     dose_layout=layout, price_layout=layout, slice_lanes=4,
+                                                     **pl.grids)))
     d = synth.random_sparse(3001, 517, 0.02, 5, empty_rows=300, empty_cols=40)
     out.append((3001, 517, d, dvmat.DDC(d["row"], d["col"], d["val"], 3001, 517, storage=storage, dose_block_rows=1,
-                                        price_block_rows=1, dose_layout=layout, price_layout=layout, panel_cols=cap)))
+                                        price_block_rows=1, dose_layout=layout, price_layout=layout, slice_lanes=4,
+                                        panel_cols=cap)))
     return out
 
 
