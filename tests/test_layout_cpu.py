@@ -323,6 +323,25 @@ def test_sliced_panels_unstructured_and_options(dv):
                                           v.ctypes.data_as(P), 0, ctypes.byref(o), ctypes.byref(h)) == -1
 
 
+@pytest.mark.parametrize("row_len,storage,want", [(100, 0, 4), (900, 0, 8), (1800, 0, 16), (900, 1, 4),
+                                                  (1800, 1, 8), (4000, 1, 16)])
+def test_sliced_lanes_follow_the_mean_row_length(dv, row_len, storage, want):
+    """Lanes left open: the W in {4, 8, 16} whose slices need closest to 32
+    steps of W lanes x E entries (E = 4 at FP32, 8 at 16 bits) for a row of
+    the mean non-empty length."""
+    rng = np.random.default_rng(row_len)
+    n_rows, n_cols = 40, 5000
+    r = np.repeat(np.arange(n_rows), row_len)
+    c = np.concatenate([rng.choice(n_cols, row_len, replace=False) for _ in range(n_rows)])
+    v = rng.uniform(0.1, 1.0, len(r)).astype(np.float32)
+    o = _opts(dv, (1, 1), (2, 0), panel_cols=8192)
+    h, info = _create(dv, r, c, v, n_rows, n_cols, o, storage=storage)
+    try:
+        assert info.dose_layout == 2 and info.dose_slice_lanes == want
+    finally:
+        dv.lib.dvmat_ddc_destroy(h)
+
+
 def test_grid_must_match_rows(dv, small):
     row, col, val = small
     o = _opts(dv, (2, 1), (1, 1), {"dose_grid": (16, 16, 15), "price_grid": PLAN.grids["price_grid"]},
