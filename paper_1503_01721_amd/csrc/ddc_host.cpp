@@ -425,18 +425,18 @@ static dvmat_status build_panels(CsrHost& out, int64_t n_cols, const std::vector
 // line then share a workgroup, so its stores meet in one L2).  Inside each
 // part the rows are sorted by length, longest first (stable), and cut into
 // slices of C = 64 / W rows; a wave runs a slice with W lanes per row, all
-// rows advancing together.  A slice of n_r
-// rows and S steps stores, for step t, row i and lane w of that row, four
-// entries at slice offset ((t*n_r + i)*W + w)*4 + q, q = 0..3: the row's sorted
-// entry 4Wt + qW + w, or a zero with local column 0 past the row's end.  One
-// 16-byte load per lane and step thus streams the slice, and each gather
-// instruction of a row's W lanes covers W consecutive sorted columns.  Rows
-// without entries close each part in slices of up to 64 rows and no steps.
-// Afterwards rowptr holds each slice's first entry (int64, n_slices + 1),
-// blocks each slice's first row position, perm the natural row of each
-// position, panel_units each panel's first slice, part_units each part's
-// first slice.  len_of_pos: entries of the row at each old position (before
-// the padding to a multiple of 4).
+// rows advancing together.  A slice of n_r rows and S steps stores, for step
+// t, row i and lane w of that row, E entries (4 at FP32, 8 at 16 bits) at
+// slice offset ((t*n_r + i)*W + w)*E + q, q = 0..E-1: the row's sorted entry
+// EWt + qW + w, or a zero (local column 0, the row's first beamlet) past the
+// row's end.  One 16-byte value load per lane and step thus streams the
+// slice, and each gather instruction of a row's W lanes covers W consecutive
+// sorted columns.  Rows without entries close each part in slices of up to
+// 64 rows and no steps.  Afterwards rowptr holds each slice's first entry
+// (int64, n_slices + 1), blocks each slice's first row position, perm the
+// natural row of each position, panel_units each panel's first slice,
+// part_units each part's first slice.  len_of_pos: entries of the row at
+// each old position (before the panel layout's padding to a multiple of 4).
 static dvmat_status build_slices(CsrHost& out, std::vector<float>& fvalb, const std::vector<int64_t>& pstart,
                                  const std::vector<int64_t>& len_of_pos, int W, int E, int64_t part_cap,
                                  int64_t line_rows) {

@@ -117,9 +117,11 @@ __global__ __launch_bounds__(kPanelThreads) __attribute__((amdgpu_waves_per_eu(8
 // ---- sliced panels (layout 2) ------------------------------------------------
 //
 // A slice holds up to 64 / W rows of one panel, sorted by length; the wave's
-// lanes i*W .. i*W + W-1 share row i and all rows advance together, four
-// entries per lane and step (one 16-byte value load at FP32, one 8-byte index
-// load), four steps in flight.  The step count is the slice's (uniform), so
+// lanes i*W .. i*W + W-1 share row i and all rows advance together, E
+// entries per lane and step (one 16-byte value load: 4 entries at FP32 with
+// an 8-byte index load, 8 at 16 bits with a 16-byte one), four steps in flight
+// (two for several right-hand sides, the curvature and bfloat16, whose
+// registers would not hold four).  The step count is the slice's (uniform), so
 // the loop has no per-lane exit and no partial step per row; the W lanes of a
 // row are summed by DPP permutes at the end (two to four per slice instead of
 // a whole-wave reduction per row).  Lanes past the slice's rows re-read an

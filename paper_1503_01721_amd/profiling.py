@@ -14,8 +14,9 @@ plain 1 GiB device copy, into HBM bytes per launch of one kernel: the
 counters' KiB are scaled by what they read for the copy of known size.
 `counters` tabulates the mean of every counter of one or more `--pmc` runs per
 launch of each named kernel.  The
-traffic file carries the hash of the product kernels' sources; bench.py
-reports its figure only while the sources are unchanged.
+traffic file carries the hash of the product kernels' sources (their code:
+comments and the layout of white space do not enter it); bench.py reports
+its figure only while that code is unchanged.
 """
 from __future__ import annotations
 
@@ -30,10 +31,38 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PRODUCT_SOURCES = ("spmv_device.hpp", "spmv.hip", "spmv_panel.hip", "common.hpp", "ddc_host.cpp")
 
 
+def code_only(text: str) -> str:
+    """C++ source without its comments, runs of white space as one blank
+    (string and character literals kept whole)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def products_source_sha() -> str:
+    """Hash of the product kernels' code (comments excluded)."""
     h = hashlib.sha256()
     for name in PRODUCT_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_1503_01721_amd", "csrc", name), "rb").read())
+        with open(os.path.join(ROOT, "paper_1503_01721_amd", "csrc", name), encoding="utf-8") as f:
+            h.update(code_only(f.read()).encode())
+        h.update(b"\0")
     return h.hexdigest()[:16]
 
 

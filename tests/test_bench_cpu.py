@@ -45,3 +45,14 @@ def test_algorithmic_bytes_count_the_layouts_own_index_width():
     assert d16 == nnz * 3 + 8 * (n_vox + 1) + 32 * (n_bl + n_vox) + 4 * n_bl
     assert p16 == nnz * 4 + 8 * (n_bl + 1) + 32 * (n_vox + n_bl) + 4 * n_bl
     assert not b.check_peak("test", 8001.0) and b.check_peak("test", 7999.0)
+
+
+def test_source_hash_ignores_comments_only():
+    """The counters' validity key: comments and white-space layout do not
+    change it, code does; string and character literals stay whole."""
+    from paper_1503_01721_amd.profiling import code_only
+    a = 'int a = 1; // one\n/* block "x" */ const char* s = "// kept"; char q = \'/\';\n'
+    b = 'int   a = 1;\n\n// another comment\nconst char* s = "// kept"; /* c */ char q = \'/\';'
+    assert code_only(a) == code_only(b) == 'int a = 1; const char* s = "// kept"; char q = \'/\';'
+    assert code_only("int a = 1;") != code_only("int a = 2;")
+    assert code_only('x = "a\\"b // c"; y;') == 'x = "a\\"b // c"; y;'
