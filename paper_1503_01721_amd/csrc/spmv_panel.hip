@@ -35,9 +35,10 @@ struct PanelParams {
     int xcd_runs;               // 1: each XCD takes a contiguous eighth of the parts
 };
 
-// Eight waves share one LDS slice.  Slices up to 36 KB (the dose of the
-// full-scale single-arc workload has 9,114 columns) let four workgroups fill
-// a CU's 160 KB of LDS and all of its 32 wave slots.
+// Eight waves share one LDS slice.  Slices up to 36 KB (the widest dose
+// panel of the full-scale single-arc workload has 9,114 columns under the
+// default 12,288-column budget, 8,192 under the tuned one) let four
+// workgroups fill a CU's 160 KB of LDS and all of its 32 wave slots.
 constexpr int kPanelThreads = 512;
 
 // Copy a panel's slice of the input into LDS: xs[i*R + h] = x[list[i]*ldx + h]
