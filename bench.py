@@ -112,19 +112,26 @@ def read_traffic(kernel, workload, storage, layout):
         return None
 
 
-def cpu_baseline(d, plan, bytes_dose_plain, bytes_price):
-    """The FP64 oracle (NumPy bincount over COO, single-threaded) on one dose and
-    one price product over the whole matrix."""
+def cpu_baseline(d, plan, bytes_dose_plain, bytes_price, min_seconds=10.0, max_pairs=6):
+    """The FP64 oracle (NumPy bincount over COO, single-threaded) on pairs of one
+    dose and one price product over the whole matrix, repeated until at least
+    min_seconds of CPU work (at most max_pairs pairs)."""
     import numpy as np
     from oracle import products as oprod
     from paper_1503_01721_amd import synth
     x, g = synth.bench_vectors(plan.n_bl, plan.n_vox, 1002)
-    t0 = time.perf_counter()
-    oprod.dose(d["row"], d["col"], d["val"], x, plan.n_vox)
-    t1 = time.perf_counter()
-    oprod.price(d["row"], d["col"], d["val"], g, plan.n_bl)
-    t2 = time.perf_counter()
-    gbs = (bytes_dose_plain + bytes_price) / (t2 - t0) / 1e9
+    t_dose = t_price = 0.0
+    pairs = 0
+    while pairs < max_pairs and (pairs == 0 or t_dose + t_price < min_seconds):
+        t0 = time.perf_counter()
+        oprod.dose(d["row"], d["col"], d["val"], x, plan.n_vox)
+        t1 = time.perf_counter()
+        oprod.price(d["row"], d["col"], d["val"], g, plan.n_bl)
+        t2 = time.perf_counter()
+        t_dose += t1 - t0
+        t_price += t2 - t1
+        pairs += 1
+    gbs = pairs * (bytes_dose_plain + bytes_price) / (t_dose + t_price) / 1e9
     model = platform.processor() or platform.machine()
     try:
         with open("/proc/cpuinfo") as fh:
@@ -133,10 +140,11 @@ def cpu_baseline(d, plan, bytes_dose_plain, bytes_price):
         pass
     affinity = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     return {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": (f"one FP64 dose and one FP64 price product over the whole {plan.name} matrix "
-                       f"(NumPy bincount over COO, single-threaded; dose {t1 - t0:.2f} s, price {t2 - t1:.2f} s); "
+            "sample": (f"{pairs} pair{'s' if pairs != 1 else ''} of one FP64 dose and one FP64 price product over the whole {plan.name} "
+                       f"matrix (NumPy bincount over COO, single-threaded; dose {t_dose / pairs:.2f} s, "
+                       f"price {t_price / pairs:.2f} s per product); "
                        f"host {model}, os.cpu_count()={os.cpu_count()}, affinity {affinity} CPUs"),
-            "seconds": round(t2 - t0, 3)}
+            "seconds": round(t_dose + t_price, 3)}
 
 
 def copy_calibration():
