@@ -133,9 +133,10 @@ typedef struct {
  * tile, or one row without a grid) holding up to part_entries stored values;
  * the rows of each part are sorted by length, longest first, and cut into
  * slices of 64 / W rows (W = dose_slice_lanes or price_slice_lanes); a wave
- * streams a slice with W lanes per row, all rows advancing together, four entries per lane and
- * step, so short rows pay neither a reduction over the whole wave nor a
- * partial step each.  Rows shorter than their slice's longest are padded
+ * streams a slice with W lanes per row, all rows advancing together, 16
+ * bytes of values per lane and step (4 entries at FP32, 8 at 16 bits), so
+ * short rows pay neither a reduction over the whole wave nor a partial step
+ * each.  Rows shorter than their slice's longest are padded
  * with zeros to its step count.  Rows without entries form slices of up to
  * 64 rows with no steps.  A slice is the work unit (n_blocks counts slices).
  * W in {4, 8, 16}; 0 chooses W from the orientation's mean non-empty row
