@@ -56,3 +56,16 @@ def test_source_hash_ignores_comments_only():
     assert code_only(a) == code_only(b) == 'int a = 1; const char* s = "// kept"; char q = \'/\';'
     assert code_only("int a = 1;") != code_only("int a = 2;")
     assert code_only('x = "a\\"b // c"; y;') == 'x = "a\\"b // c"; y;'
+
+
+def test_cpu_baseline_repeats_the_oracle_pairs_to_its_time_floor():
+    """The oracle leg: at least one dose + price pair, more until min_seconds
+    of host work, never more than max_pairs; the rate counts every pair."""
+    b = _bench_module()
+    from paper_1503_01721_amd import synth
+    plan = synth.PLANS["small_cp8_bl6x6_vox16"]
+    d = synth.generate_ddc(plan)
+    one = b.cpu_baseline(d, plan, 1e12, 1e12, min_seconds=0.0)
+    assert one["sample"].startswith("1 pair of") and one["kind"] == "oracle" and one["cores"] == 1
+    two = b.cpu_baseline(d, plan, 1e12, 1e12, min_seconds=1e9, max_pairs=2)
+    assert two["sample"].startswith("2 pairs of") and two["value"] > 0 and two["seconds"] > 0
