@@ -69,3 +69,13 @@ def test_cpu_baseline_repeats_the_oracle_pairs_to_its_time_floor():
     assert one["sample"].startswith("1 pair of") and one["kind"] == "oracle" and one["cores"] == 1
     two = b.cpu_baseline(d, plan, 1e12, 1e12, min_seconds=1e9, max_pairs=2)
     assert two["sample"].startswith("2 pairs of") and two["value"] > 0 and two["seconds"] > 0
+
+
+def test_committed_traffic_matches_the_product_code():
+    """The HBM counters committed for the benchmark's kernels were taken on the
+    product code as it stands (comments aside), so the benchmark reports them."""
+    b = _bench_module()
+    for kernel in ("dose", "price"):
+        for storage in ("f32", "f16"):
+            v = b.read_traffic(kernel, "cp180_bl40x40_vox128", storage, "sliced")
+            assert v is not None and v > 1e9, (kernel, storage)
