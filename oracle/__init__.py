@@ -16,6 +16,8 @@ aperture   aperture selection by exhaustive interval enumeration (Sec. 2.2.2)
 bb         Barzilai-Borwein master-problem solver with the subspace bound
            handling of Eqs. (7)-(10), in D-form and in DA-form (Eq. 6)
 colgen     the column-generation loop (Sec. 2.1)
+machine    gantry-speed bounds from leaf motion and speed change, and the
+           rate box of every aperture (Eq. 2, Eq. 6)
 
 All floating point is float64.
 """
