@@ -782,7 +782,7 @@ def main():
         },
     }
     if not args.no_cpu_baseline:
-        log("timing the FP64 oracle on one dose and one price product (CPU baseline)")
+        log("timing the FP64 oracle on dose and price product pairs (CPU baseline)")
         bplain = ab["dose"] - info.n_vox * (1 + 4)
         out["cpu_baseline"] = cpu_baseline(d, plan, bplain, ab["price"])
         log(f"cpu baseline {out['cpu_baseline']['value']} GB/s in {out['cpu_baseline']['seconds']} s")
